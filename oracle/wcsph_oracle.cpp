@@ -1,0 +1,860 @@
+// wcsph_oracle.cpp -- FP64 CPU oracle of the planar WCSPH step.
+//
+// TEST INFRASTRUCTURE ONLY: the plain, slow, obviously correct reference the
+// GPU path is checked against. Only the tests, the smoke check and the CPU
+// baseline of the benchmark load it; it shares no code with the GPU library.
+//
+// What it computes, step by step, in the paper's order and notation
+// (planar WCSPH model for hydrodynamic ram, Numerical Methodology section),
+// with the scheme choices of the hot path where they differ from the paper:
+//  * SPH interpolant with a compact kernel of support 2h, h = 1.3 dx
+//    (eq. sph-approx); kernel = Wendland C2 in 2D instead of the paper's
+//    cubic B-spline (eq. cubic-kernel).
+//  * momentum in the symmetric form (eq. momentum) with the Monaghan
+//    artificial viscosity, linear term only (eq. artificial-viscosity), plus
+//    a laminar term in the Lo-Shao form for the physical viscosity
+//    (the viscosity paragraph of Governing Equations).
+//  * XSPH-smoothed advection velocity over fluid neighbours (eq. xsph).
+//  * density from the continuity equation with the Molteni-Colagrossi
+//    delta-diffusion term (named as the alternative in Density Summation),
+//    clamped to the band [0.5, 1.5] rho0 after every update.
+//  * Tait EOS p = B((rho/rho0)^gamma - 1), B = rho0 c0^2 / gamma, with the
+//    cavitation cutoff p >= p_cav (eq. eos text).
+//  * predictor-corrector (explicit midpoint) update with the CFL step of
+//    eq. cfl, v_max over fluid and ghosts (CFL gate paragraph of GPU
+//    Implementation).
+//  * Adami ghost state on the disk ring and on three lattice layers of wall
+//    ghosts (eq. adami-p, eq. adami-v), body-force term (g - a_w) as in
+//    Adami 2012; ring of N_g ghosts with m_g = rho0 dx 2 pi R / N_g.
+//  * hard wall reflection (Channel Walls section) and a radial pull-out plus
+//    reflection of the inward relative velocity for the disk.
+//  * prescribed kinematics: ramp (eq. velocity-ramp) then constant
+//    deceleration k v0^2, or the quadratic drag of eq. drag.
+//  * cell-linked list of cell size >= 2h, rebuilt at every evaluation by a
+//    stable sort of the particles by cell key.
+// Ghost state and rates are re-evaluated at both evaluations of a step
+// (operator split of the Pipeline Provenance section).
+
+#include "oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Dual numbers with N tangent directions (forward-mode derivative).
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+  Dual() : v(0) { for (int k = 0; k < N; ++k) d[k] = 0; }
+  Dual(double x) : v(x) { for (int k = 0; k < N; ++k) d[k] = 0; }  // NOLINT
+};
+template <int N> Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v + b.v; for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+template <int N> Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v - b.v; for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+template <int N> Dual<N> operator-(const Dual<N>& a) { Dual<N> r; r.v = -a.v; for (int k = 0; k < N; ++k) r.d[k] = -a.d[k]; return r; }
+template <int N> Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v * b.v; for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+template <int N> Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v / b.v; for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v); return r; }
+template <int N> Dual<N> operator+(const Dual<N>& a, double b) { return a + Dual<N>(b); }
+template <int N> Dual<N> operator+(double a, const Dual<N>& b) { return Dual<N>(a) + b; }
+template <int N> Dual<N> operator-(const Dual<N>& a, double b) { return a - Dual<N>(b); }
+template <int N> Dual<N> operator-(double a, const Dual<N>& b) { return Dual<N>(a) - b; }
+template <int N> Dual<N> operator*(const Dual<N>& a, double b) { Dual<N> r; r.v = a.v * b; for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b; return r; }
+template <int N> Dual<N> operator*(double a, const Dual<N>& b) { return b * a; }
+template <int N> Dual<N> operator/(const Dual<N>& a, double b) { return a * (1.0 / b); }
+template <int N> Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
+template <int N> Dual<N>& operator+=(Dual<N>& a, const Dual<N>& b) { a = a + b; return a; }
+template <int N> Dual<N>& operator-=(Dual<N>& a, const Dual<N>& b) { a = a - b; return a; }
+template <int N> Dual<N> sqrt(const Dual<N>& a) { Dual<N> r; r.v = std::sqrt(a.v); for (int k = 0; k < N; ++k) r.d[k] = a.d[k] / (2.0 * r.v); return r; }
+template <int N> Dual<N> pow(const Dual<N>& a, double e) { Dual<N> r; r.v = std::pow(a.v, e); double g = e * std::pow(a.v, e - 1.0); for (int k = 0; k < N; ++k) r.d[k] = g * a.d[k]; return r; }
+
+inline double val(double x) { return x; }
+template <int N> double val(const Dual<N>& x) { return x.v; }
+using std::pow;
+using std::sqrt;
+
+// ---------------------------------------------------------------------------
+// Geometry and constants derived from the parameters.
+struct Geom {
+  double dx, h, dc, x_lo, y_lo;
+  int nx, ny, ncx, ncy;
+  double sigma;  // Wendland C2 2D normalisation 7 / (4 pi h^2)
+  double fgrad;  // gradient factor 35 / (4 pi h^4)
+  double m_fluid, m_wall, m_disk, nu0;
+};
+
+Geom make_geom(const orc_params& p) {
+  Geom g;
+  g.dx = p.dx;
+  g.h = p.h_over_dx * p.dx;
+  g.dc = p.cell_size > 0 ? p.cell_size : 2.0 * g.h;
+  g.x_lo = -p.ghost_layers * p.dx;
+  g.y_lo = -p.ghost_layers * p.dx;
+  g.nx = (int)std::lround(p.L / p.dx);
+  g.ny = (int)std::lround(p.W / p.dx);
+  g.ncx = (int)std::ceil((p.L + 2.0 * p.ghost_layers * p.dx) / g.dc);
+  g.ncy = (int)std::ceil((p.W + 2.0 * p.ghost_layers * p.dx) / g.dc);
+  g.sigma = 7.0 / (4.0 * M_PI * g.h * g.h);
+  g.fgrad = 35.0 / (4.0 * M_PI * g.h * g.h * g.h * g.h);
+  g.m_fluid = p.rho0 * p.dx * p.dx;
+  g.m_wall = p.rho0 * p.dx * p.dx;
+  g.m_disk = p.n_disk_ghosts > 0 ? p.rho0 * p.dx * 2.0 * M_PI * p.disk_R / p.n_disk_ghosts : 0.0;
+  g.nu0 = p.mu_dyn / p.rho0;
+  return g;
+}
+
+int cell_coord(double x, double lo, double dc, int n) {
+  int c = (int)std::floor((x - lo) / dc);
+  return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+// Wendland C2 in 2D: W = sigma (1 - q/2)^4 (2q + 1) for q < 2; grad_i W = F r_ij
+// with F = -(35 / (4 pi h^4)) (1 - q/2)^3 (derivative of W divided by r).
+template <class T>
+void kernel_WF(const T& q, const Geom& g, T& W, T& F) {
+  T s = 1.0 - 0.5 * q;
+  T s2 = s * s;
+  W = g.sigma * s2 * s2 * (2.0 * q + 1.0);
+  F = -g.fgrad * s2 * s;
+}
+
+// Coefficients that the tangent build differentiates (alpha, delta, c0) and
+// the ones that follow from them.
+template <class T>
+struct Coef {
+  T alpha, delta, c0, B;
+};
+
+// Tait EOS with cavitation cutoff; sound speed c = c0 (rho/rho0)^((gamma-1)/2).
+template <class T>
+T eos_p(const T& rho, const orc_params& p, const Coef<T>& k) {
+  T pr = k.B * (pow(rho / p.rho0, p.gamma) - 1.0);
+  return val(pr) < p.p_cav ? T(p.p_cav) : pr;
+}
+template <class T>
+T eos_c(const T& rho, const orc_params& p, const Coef<T>& k) {
+  return k.c0 * pow(rho / p.rho0, 0.5 * (p.gamma - 1.0));
+}
+
+// A particle as seen by the pair law.
+template <class T>
+struct PV {
+  T x, y, vx, vy, rho, P, c;  // P = p / rho^2
+  double m;
+  int kind;  // 0 fluid, 1 wall ghost, 2 disk ghost
+};
+
+template <class T>
+struct Acc {
+  T D, ax, ay, Vx, Vy, fdx;
+  Acc() : D(0.0), ax(0.0), ay(0.0), Vx(0.0), Vy(0.0), fdx(0.0) {}
+};
+
+// Contribution of neighbour b to the rates of fluid particle a.
+template <class T>
+void pair_law(const PV<T>& a, const PV<T>& b, const orc_params& p, const Geom& g,
+              const Coef<T>& k, Acc<T>& acc) {
+  T rx = a.x - b.x, ry = a.y - b.y;
+  T r2 = rx * rx + ry * ry;
+  if (!(val(r2) < 4.0 * g.h * g.h)) return;
+  T r = sqrt(r2);
+  T q = r / g.h;
+  T W, F;
+  kernel_WF(q, g, W, F);
+  T vxij = a.vx - b.vx, vyij = a.vy - b.vy;
+  T vr = vxij * rx + vyij * ry;
+  T rbar = 0.5 * (a.rho + b.rho);
+  T cbar = 0.5 * (a.c + b.c);
+  T denom = r2 + p.eta2 * g.h * g.h;
+  T Pi(0.0);
+  if (val(vr) < 0.0) {
+    T mu = g.h * vr / denom;
+    Pi = -1.0 * k.alpha * cbar * mu / rbar;
+  }
+  // continuity: d rho_i/dt = sum_j m_j v_ij . grad_i W_ij
+  acc.D += b.m * vr * F;
+  // delta diffusion (fluid pairs): delta h c0 sum_j V_j psi_ij . grad_i W_ij,
+  // psi_ij = 2 (rho_j - rho_i) (r_j - r_i) / |r_ij|^2
+  if (b.kind == 0) acc.D += 2.0 * k.delta * g.h * k.c0 * (b.m / b.rho) * (a.rho - b.rho) * F;
+  // pressure + artificial viscosity, symmetric form
+  T s = a.P + b.P + Pi;
+  acc.ax -= b.m * s * F * rx;
+  acc.ay -= b.m * s * F * ry;
+  if (b.kind == 2) acc.fdx -= b.m * s * F * rx;
+  // laminar viscosity (Lo-Shao): sum_j 4 nu0 m_j (r_ij . grad W) / ((rho_i + rho_j)(r^2 + eta^2 h^2)) v_ij
+  T lam = b.m * 4.0 * g.nu0 * F * r2 / ((a.rho + b.rho) * denom);
+  acc.ax += lam * vxij;
+  acc.ay += lam * vyij;
+  // XSPH over fluid neighbours
+  if (b.kind == 0) {
+    T w = p.eps_xsph * (b.m / rbar) * W;
+    acc.Vx += w * (b.vx - a.vx);
+    acc.Vy += w * (b.vy - a.vy);
+  }
+}
+
+// Prescribed disk kinematics (centre x, velocity, acceleration along +x).
+void kinematics(int mode, double v0, double t_ramp, double coef, double x0, double t, double* xo,
+                double* vo, double* ao) {
+  if (t < t_ramp) {
+    *vo = v0 * t / t_ramp;
+    *ao = v0 / t_ramp;
+    *xo = x0 + 0.5 * v0 * t * t / t_ramp;
+    return;
+  }
+  double tau = t - t_ramp;
+  double xr = x0 + 0.5 * v0 * t_ramp;
+  if (mode == 1) {  // quadratic drag dv/dt = -k v^2
+    double k = coef;
+    double v = v0 / (1.0 + k * v0 * tau);
+    *vo = v;
+    *ao = -k * v * v;
+    *xo = k > 0 ? xr + std::log1p(k * v0 * tau) / k : xr + v0 * tau;
+    return;
+  }
+  double ad = coef;  // constant deceleration, stops at v = 0
+  if (ad > 0 && tau >= v0 / ad) {
+    *vo = 0;
+    *ao = 0;
+    *xo = xr + 0.5 * v0 * v0 / ad;
+    return;
+  }
+  *vo = v0 - ad * tau;
+  *ao = -ad;
+  *xo = xr + v0 * tau - 0.5 * ad * tau * tau;
+}
+
+// ---------------------------------------------------------------------------
+template <class T>
+struct Sim {
+  orc_params P;
+  Geom G;
+  Coef<T> K;
+  int Nf = 0, Nw = 0, Nd = 0;
+  // fluid state by fluid id
+  std::vector<T> x, y, vx, vy, rho;
+  // ghosts by ghost index: walls first, then the disk ring
+  std::vector<double> gx, gy, gm;
+  std::vector<T> gp, grho, gvx, gvy;
+  // cell list: storage order (global ids) and cell ranges
+  std::vector<int> order, cell_start, key;
+  double t = 0.0;
+  long step = 0;
+  std::vector<double> dt_table;
+  std::vector<double> probe_rows;  // per row: t, dt, then probes
+  std::vector<T> probe_vals;
+  std::vector<double> diag_rows;
+  T J = T(0.0);
+  double w_boundary = 0.0;
+  long n_clamp = 0, n_enforce = 0;
+  // disk state at the current evaluation
+  double dx_c = 0, dv = 0, da = 0;
+
+  int N() const { return Nf + Nw + Nd; }
+
+  void setup(const orc_params& p, int n_init, const double* init) {
+    P = p;
+    G = make_geom(p);
+    // fluid (S1): lattice points ((i+1/2)dx, (j+1/2)dx), id = j nx + i, disk interior removed
+    if (init == nullptr) {
+      const double cx = p.disk_x0, cy = p.disk_y0, R = p.disk_R;
+      for (int j = 0; j < G.ny; ++j)
+        for (int i = 0; i < G.nx; ++i) {
+          double xx = (i + 0.5) * p.dx, yy = (j + 0.5) * p.dx;
+          if (R > 0 && (xx - cx) * (xx - cx) + (yy - cy) * (yy - cy) < R * R) continue;
+          double r0 = p.rho0;
+          if (p.init_mode == 1) {  // hydrostatic: Tait inverse of rho0 |g| (W - y)
+            double ph = p.rho0 * std::fabs(p.gravity_y) * (p.W - yy);
+            double B = p.rho0 * p.c0 * p.c0 / p.gamma;
+            r0 = p.rho0 * std::pow(1.0 + ph / B, 1.0 / p.gamma);
+          }
+          x.push_back(xx); y.push_back(yy); vx.push_back(0.0); vy.push_back(0.0); rho.push_back(r0);
+        }
+    } else {
+      for (int k = 0; k < n_init; ++k) {
+        x.push_back(init[5 * k]); y.push_back(init[5 * k + 1]);
+        vx.push_back(init[5 * k + 2]); vy.push_back(init[5 * k + 3]); rho.push_back(init[5 * k + 4]);
+      }
+    }
+    Nf = (int)x.size();
+    // wall ghosts (S2): the lattice continued ghost_layers deep around the box, j outer
+    const int Lg = p.ghost_layers;
+    for (int j = -Lg; j < G.ny + Lg; ++j)
+      for (int i = -Lg; i < G.nx + Lg; ++i) {
+        if (i >= 0 && i < G.nx && j >= 0 && j < G.ny) continue;
+        gx.push_back((i + 0.5) * p.dx); gy.push_back((j + 0.5) * p.dx); gm.push_back(G.m_wall);
+      }
+    Nw = (int)gx.size();
+    // disk ring (S3)
+    Nd = p.disk_R > 0 ? p.n_disk_ghosts : 0;
+    for (int k = 0; k < Nd; ++k) { gx.push_back(0); gy.push_back(0); gm.push_back(G.m_disk); }
+    gp.assign(Nw + Nd, T(0.0)); grho.assign(Nw + Nd, T(p.rho0));
+    gvx.assign(Nw + Nd, T(0.0)); gvy.assign(Nw + Nd, T(0.0));
+    order.resize(N());
+    for (int k = 0; k < N(); ++k) order[k] = k;
+    key.assign(N(), 0);
+    cell_start.assign(G.ncx * G.ncy + 1, 0);
+    probe_vals.assign(P.n_probes, T(0.0));
+    record_diag(0.0, 0.0);
+  }
+
+  void set_coef(const T& alpha, const T& delta, const T& c0) {
+    K.alpha = alpha; K.delta = delta; K.c0 = c0;
+    K.B = P.rho0 * c0 * c0 / P.gamma;
+  }
+
+  void disk_state(double tt) {
+    kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, tt, &dx_c, &dv, &da);
+  }
+
+  // disk ghosts at angle 2 pi k / N_g around the centre (eq. adami-p text)
+  void place_disk(double tt) {
+    disk_state(tt);
+    for (int k = 0; k < Nd; ++k) {
+      double th = 2.0 * M_PI * k / Nd;
+      gx[Nw + k] = dx_c + P.disk_R * std::cos(th);
+      gy[Nw + k] = P.disk_y0 + P.disk_R * std::sin(th);
+    }
+  }
+
+  double px(int id) const { return id < Nf ? val(x[id]) : gx[id - Nf]; }
+  double py(int id) const { return id < Nf ? val(y[id]) : gy[id - Nf]; }
+
+  // keys for every particle and a stable re-sort of the storage order by key
+  void build_cells() {
+    for (int id = 0; id < N(); ++id) {
+      int cx = cell_coord(px(id), G.x_lo, G.dc, G.ncx);
+      int cy = cell_coord(py(id), G.y_lo, G.dc, G.ncy);
+      key[id] = cy * G.ncx + cx;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::fill(cell_start.begin(), cell_start.end(), 0);
+    for (int id = 0; id < N(); ++id) cell_start[key[id] + 1]++;
+    for (size_t k = 1; k < cell_start.size(); ++k) cell_start[k] += cell_start[k - 1];
+  }
+
+  // visit ids in the 3x3 block of cells around (xx, yy): rows bottom to top,
+  // cells left to right, storage order inside a cell
+  template <class Fn>
+  void for_neighbours(double xx, double yy, Fn&& fn) const {
+    int cx = cell_coord(xx, G.x_lo, G.dc, G.ncx);
+    int cy = cell_coord(yy, G.y_lo, G.dc, G.ncy);
+    for (int dy = -1; dy <= 1; ++dy) {
+      int yy2 = cy + dy;
+      if (yy2 < 0 || yy2 >= G.ncy) continue;
+      for (int dxx = -1; dxx <= 1; ++dxx) {
+        int xx2 = cx + dxx;
+        if (xx2 < 0 || xx2 >= G.ncx) continue;
+        int K2 = yy2 * G.ncx + xx2;
+        for (int k = cell_start[K2]; k < cell_start[K2 + 1]; ++k) fn(order[k]);
+      }
+    }
+  }
+
+  // Shepard sums over fluid within 2h of point (xx, yy)
+  void shepard(double xx, double yy, const std::vector<T>& pf, T& SW, T& Sp, T& Srx, T& Sry,
+               T& Svx, T& Svy) const {
+    SW = Sp = Srx = Sry = Svx = Svy = T(0.0);
+    for_neighbours(xx, yy, [&](int j) {
+      if (j >= Nf) return;
+      T rx = xx - x[j], ry = yy - y[j];
+      T r2 = rx * rx + ry * ry;
+      if (!(val(r2) < 4.0 * G.h * G.h)) return;
+      T W, F;
+      kernel_WF(sqrt(r2) / G.h, G, W, F);
+      SW += W;
+      Sp += pf[j] * W;
+      Srx += rho[j] * rx * W;
+      Sry += rho[j] * ry * W;
+      Svx += vx[j] * W;
+      Svy += vy[j] * W;
+    });
+  }
+
+  // Adami ghost state (eq. adami-p, eq. adami-v) for every ghost
+  void ghosts(const std::vector<T>& pf) {
+    const int NG = Nw + Nd;
+#pragma omp parallel for schedule(static)
+    for (int g = 0; g < NG; ++g) {
+      double vwx = 0, awx = 0;
+      if (g >= Nw) { vwx = dv; awx = da; }
+      T SW, Sp, Srx, Sry, Svx, Svy;
+      shepard(gx[g], gy[g], pf, SW, Sp, Srx, Sry, Svx, Svy);
+      T pg, vgx, vgy;
+      if (val(SW) > 0.0) {
+        // body-force term (g - a_w) . sum_j rho_j (r_g - r_j) W_gj
+        pg = (Sp + (0.0 - awx) * Srx + (P.gravity_y - 0.0) * Sry) / SW;
+        vgx = 2.0 * vwx - Svx / SW;
+        vgy = 0.0 - Svy / SW;
+      } else {
+        pg = T(0.0);
+        vgx = T(vwx);
+        vgy = T(0.0);
+      }
+      if (val(pg) < P.p_cav) pg = T(P.p_cav);
+      T rg;
+      if (P.ghost_rho_mode == 0) rg = P.rho0 * (1.0 + pg / (P.rho0 * K.c0 * K.c0));  // linear branch
+      else rg = P.rho0 * pow(1.0 + pg / K.B, 1.0 / P.gamma);
+      gp[g] = pg; grho[g] = rg; gvx[g] = vgx; gvy[g] = vgy;
+    }
+  }
+
+  // particle view for the pair law
+  PV<T> view(int id, const std::vector<T>& pf) const {
+    PV<T> v;
+    if (id < Nf) {
+      v.x = x[id]; v.y = y[id]; v.vx = vx[id]; v.vy = vy[id]; v.rho = rho[id];
+      v.P = pf[id] / (rho[id] * rho[id]);
+      v.c = eos_c(rho[id], P, K);
+      v.m = G.m_fluid; v.kind = 0;
+    } else {
+      int g = id - Nf;
+      v.x = T(gx[g]); v.y = T(gy[g]); v.vx = gvx[g]; v.vy = gvy[g]; v.rho = grho[g];
+      v.P = gp[g] / (grho[g] * grho[g]);
+      v.c = eos_c(grho[g], P, K);
+      v.m = gm[g]; v.kind = g < Nw ? 1 : 2;
+    }
+    return v;
+  }
+
+  // rates of every fluid particle; returns the x force of the disk on the fluid
+  T rates(const std::vector<T>& pf, std::vector<T>& D, std::vector<T>& ax, std::vector<T>& ay,
+          std::vector<T>& Vx, std::vector<T>& Vy) const {
+    std::vector<T> fdx(Nf);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < Nf; ++i) {
+      PV<T> a = view(i, pf);
+      Acc<T> acc;
+      for_neighbours(val(x[i]), val(y[i]), [&](int j) {
+        if (j == i) return;
+        pair_law(a, view(j, pf), P, G, K, acc);
+      });
+      D[i] = acc.D;
+      ax[i] = acc.ax;
+      ay[i] = acc.ay + P.gravity_y;
+      Vx[i] = vx[i] + acc.Vx;
+      Vy[i] = vy[i] + acc.Vy;
+      fdx[i] = G.m_fluid * acc.fdx;
+    }
+    T f(0.0);
+    for (int i = 0; i < Nf; ++i) f += fdx[i];
+    return f;
+  }
+
+  void fluid_pressure(std::vector<T>& pf) const {
+    pf.resize(Nf);
+    for (int i = 0; i < Nf; ++i) pf[i] = eos_p(rho[i], P, K);
+  }
+
+  // hard walls (Channel Walls section) then the disk: radial pull-out to
+  // R + eps and reflection of the inward normal velocity relative to the disk
+  bool enforce(T& xx, T& yy, T& ux, T& uy, double cx, double cy, double vd) const {
+    bool hit = false;
+    const double e = P.eps_wall;
+    if (val(xx) < e) { xx = T(e); ux = -1.0 * ux; hit = true; }
+    if (val(xx) > P.L - e) { xx = T(P.L - e); ux = -1.0 * ux; hit = true; }
+    if (val(yy) < e) { yy = T(e); uy = -1.0 * uy; hit = true; }
+    if (val(yy) > P.W - e) { yy = T(P.W - e); uy = -1.0 * uy; hit = true; }
+    if (Nd > 0) {
+      T rx = xx - cx, ry = yy - cy;
+      T d2 = rx * rx + ry * ry;
+      if (val(d2) < P.disk_R * P.disk_R) {
+        T nx(-1.0), ny(0.0);
+        if (val(d2) > 0.0) { T d = sqrt(d2); nx = rx / d; ny = ry / d; }
+        xx = cx + (P.disk_R + e) * nx;
+        yy = cy + (P.disk_R + e) * ny;
+        T w = (ux - vd) * nx + uy * ny;
+        if (val(w) < 0.0) { ux = ux - 2.0 * w * nx; uy = uy - 2.0 * w * ny; }
+        hit = true;
+      }
+    }
+    return hit;
+  }
+
+  // phi = clamp(phi0 + h D), v = v0 + h a, r = r0 + h V, then enforcement at time te
+  void advance(const std::vector<T>& x0, const std::vector<T>& y0, const std::vector<T>& vx0,
+               const std::vector<T>& vy0, const std::vector<T>& rho0, double hdt,
+               const std::vector<T>& D, const std::vector<T>& ax, const std::vector<T>& ay,
+               const std::vector<T>& Vx, const std::vector<T>& Vy, double te) {
+    double cx, vd, ad;
+    kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, te, &cx, &vd, &ad);
+    const double lo = P.rho_lo * P.rho0, hi = P.rho_hi * P.rho0;
+    for (int i = 0; i < Nf; ++i) {
+      T r = rho0[i] + hdt * D[i];
+      if (val(r) < lo) { r = T(lo); n_clamp++; }
+      if (val(r) > hi) { r = T(hi); n_clamp++; }
+      T ux = vx0[i] + hdt * ax[i], uy = vy0[i] + hdt * ay[i];
+      T xx = x0[i] + hdt * Vx[i], yy = y0[i] + hdt * Vy[i];
+      if (enforce(xx, yy, ux, uy, cx, P.disk_y0, vd)) n_enforce++;
+      x[i] = xx; y[i] = yy; vx[i] = ux; vy[i] = uy; rho[i] = r;
+    }
+  }
+
+  // Shepard average of fluid pressure at the probe points
+  void probes(const std::vector<T>& pf) {
+    for (int k = 0; k < P.n_probes; ++k) {
+      T SW, Sp, a, b, c, d;
+      shepard(P.probe_xy[2 * k], P.probe_xy[2 * k + 1], pf, SW, Sp, a, b, c, d);
+      probe_vals[k] = val(SW) > 0.0 ? Sp / SW : T(0.0);
+    }
+  }
+
+  double vmax_now() const {
+    double m = 0.0;
+    for (int i = 0; i < Nf; ++i) m = std::max(m, std::hypot(val(vx[i]), val(vy[i])));
+    for (int g = 0; g < Nw + Nd; ++g) m = std::max(m, std::hypot(val(gvx[g]), val(gvy[g])));
+    return m;
+  }
+
+  // one evaluation at time te on the current fluid state: disk placement,
+  // cell list, ghost state
+  void prepare(double te, std::vector<T>& pf) {
+    place_disk(te);
+    build_cells();
+    fluid_pressure(pf);
+    ghosts(pf);
+  }
+
+  void one_step() {
+    std::vector<T> pf, D(Nf), ax(Nf), ay(Nf), Vx(Nf), Vy(Nf);
+    const std::vector<T> x0 = x, y0 = y, vx0 = vx, vy0 = vy, rho0 = rho;
+    // evaluation at state n
+    prepare(t, pf);
+    probes(pf);
+    double vmax = vmax_now();
+    double dt = (step < (long)dt_table.size()) ? dt_table[step]
+                                               : P.cfl * G.h / (val(K.c0) + vmax);
+    probe_rows.push_back(t);
+    probe_rows.push_back(dt);
+    for (int k = 0; k < P.n_probes; ++k) {
+      probe_rows.push_back(val(probe_vals[k]));
+      J += probe_vals[k] * dt;
+    }
+    rates(pf, D, ax, ay, Vx, Vy);
+    // predictor to t + dt/2
+    advance(x0, y0, vx0, vy0, rho0, 0.5 * dt, D, ax, ay, Vx, Vy, t + 0.5 * dt);
+    // evaluation at the midpoint state
+    prepare(t + 0.5 * dt, pf);
+    T fdx = rates(pf, D, ax, ay, Vx, Vy);
+    w_boundary += dt * val(fdx) * dv;
+    // corrector from state n with the midpoint rates
+    advance(x0, y0, vx0, vy0, rho0, dt, D, ax, ay, Vx, Vy, t + dt);
+    t += dt;
+    step++;
+    if (P.diag_every > 0 && step % P.diag_every == 0) record_diag(dt, vmax);
+  }
+
+  // specific elastic energy of the Tait law with the cutoff branch
+  double e_el(double r) const {
+    const double g = P.gamma, r0 = P.rho0, B = val(K.B);
+    auto e_tait = [&](double q) {
+      return B * ((std::pow(q, g - 1.0) - std::pow(r0, g - 1.0)) / ((g - 1.0) * std::pow(r0, g)) +
+                  1.0 / q - 1.0 / r0);
+    };
+    double rc = r0 * std::pow(1.0 + P.p_cav / B, 1.0 / g);
+    if (r >= rc) return e_tait(r);
+    return e_tait(rc) + P.p_cav * (1.0 / rc - 1.0 / r);
+  }
+
+  void record_diag(double dt, double vmax) {
+    double M = 0, px_ = 0, py_ = 0, ke = 0, eel = 0, epot = 0;
+    long ncav = 0;
+    for (int i = 0; i < Nf; ++i) {
+      double m = G.m_fluid, u = val(vx[i]), w = val(vy[i]), r = val(rho[i]);
+      M += m;
+      px_ += m * u;
+      py_ += m * w;
+      ke += 0.5 * m * (u * u + w * w);
+      epot += m * (-P.gravity_y) * val(y[i]);
+      eel += m * e_el(r);
+      if (val(K.B) * (std::pow(r / P.rho0, P.gamma) - 1.0) <= P.p_cav) ncav++;
+    }
+    double xd, vd, ad;
+    kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, t, &xd, &vd, &ad);
+    double row[ORC_NDIAG] = {t, dt, vmax, M, px_, py_, ke, eel, epot, 0.5 * P.disk_mass * vd * vd,
+                             w_boundary, (double)step, (double)n_clamp, (double)ncav,
+                             (double)n_enforce};
+    diag_rows.insert(diag_rows.end(), row, row + ORC_NDIAG);
+  }
+};
+
+using SimD = Sim<double>;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void* orc_create(const orc_params* p, int n_init, const double* init) {
+  SimD* s = new SimD();
+  s->P = *p;
+  s->set_coef(p->alpha, p->delta, p->c0);
+  s->setup(*p, n_init, init);
+  return s;
+}
+void orc_destroy(void* s) { delete static_cast<SimD*>(s); }
+int orc_num_fluid(void* s) { return static_cast<SimD*>(s)->Nf; }
+int orc_num_ghost(void* s) { auto* q = static_cast<SimD*>(s); return q->Nw + q->Nd; }
+int orc_num_cells(void* s) { auto* q = static_cast<SimD*>(s); return q->G.ncx * q->G.ncy; }
+void orc_set_dt_table(void* s, int n, const double* dt) {
+  static_cast<SimD*>(s)->dt_table.assign(dt, dt + (n > 0 ? n : 0));
+}
+int orc_step(void* s, int n) {
+  auto* q = static_cast<SimD*>(s);
+  for (int k = 0; k < n; ++k) q->one_step();
+  return 0;
+}
+void orc_get_fluid(void* s, double* t, double* x, double* y, double* vx, double* vy, double* rho) {
+  auto* q = static_cast<SimD*>(s);
+  if (t) *t = q->t;
+  for (int i = 0; i < q->Nf; ++i) {
+    x[i] = q->x[i]; y[i] = q->y[i]; vx[i] = q->vx[i]; vy[i] = q->vy[i]; rho[i] = q->rho[i];
+  }
+}
+void orc_set_fluid(void* s, double t, const double* x, const double* y, const double* vx,
+                   const double* vy, const double* rho) {
+  auto* q = static_cast<SimD*>(s);
+  q->t = t;
+  for (int i = 0; i < q->Nf; ++i) {
+    q->x[i] = x[i]; q->y[i] = y[i]; q->vx[i] = vx[i]; q->vy[i] = vy[i]; q->rho[i] = rho[i];
+  }
+  for (int k = 0; k < q->N(); ++k) q->order[k] = k;
+}
+int orc_probe_rows(void* s) {
+  auto* q = static_cast<SimD*>(s);
+  return (int)(q->probe_rows.size() / (2 + q->P.n_probes));
+}
+void orc_get_probes(void* s, double* t, double* dt, double* p) {
+  auto* q = static_cast<SimD*>(s);
+  const int w = 2 + q->P.n_probes, rows = orc_probe_rows(s);
+  for (int r = 0; r < rows; ++r) {
+    t[r] = q->probe_rows[r * w];
+    dt[r] = q->probe_rows[r * w + 1];
+    for (int k = 0; k < q->P.n_probes; ++k) p[r * q->P.n_probes + k] = q->probe_rows[r * w + 2 + k];
+  }
+}
+int orc_diag_rows(void* s) { return (int)(static_cast<SimD*>(s)->diag_rows.size() / ORC_NDIAG); }
+void orc_get_diags(void* s, double* rows) {
+  auto* q = static_cast<SimD*>(s);
+  std::copy(q->diag_rows.begin(), q->diag_rows.end(), rows);
+}
+double orc_impulse(void* s) { return static_cast<SimD*>(s)->J; }
+
+void orc_eval_rates(void* s, double* drho, double* ax, double* ay, double* Vx, double* Vy,
+                    double* gp, double* grho, double* gvx, double* gvy, double* vmax) {
+  auto* q = static_cast<SimD*>(s);
+  std::vector<double> pf, D(q->Nf), a(q->Nf), b(q->Nf), c(q->Nf), d(q->Nf);
+  q->prepare(q->t, pf);
+  q->rates(pf, D, a, b, c, d);
+  for (int i = 0; i < q->Nf; ++i) { drho[i] = D[i]; ax[i] = a[i]; ay[i] = b[i]; Vx[i] = c[i]; Vy[i] = d[i]; }
+  const int NG = q->Nw + q->Nd;
+  for (int g = 0; g < NG; ++g) {
+    if (gp) gp[g] = q->gp[g];
+    if (grho) grho[g] = q->grho[g];
+    if (gvx) gvx[g] = q->gvx[g];
+    if (gvy) gvy[g] = q->gvy[g];
+  }
+  if (vmax) *vmax = q->vmax_now();
+}
+void orc_get_ghosts(void* s, double* gx, double* gy, double* gm) {
+  auto* q = static_cast<SimD*>(s);
+  for (int g = 0; g < q->Nw + q->Nd; ++g) { gx[g] = q->gx[g]; gy[g] = q->gy[g]; gm[g] = q->gm[g]; }
+}
+void orc_get_order(void* s, int* order, int* cell_start) {
+  auto* q = static_cast<SimD*>(s);
+  std::copy(q->order.begin(), q->order.end(), order);
+  std::copy(q->cell_start.begin(), q->cell_start.end(), cell_start);
+}
+void orc_kinematics(void* s, double t, double* x, double* v, double* a) {
+  auto* q = static_cast<SimD*>(s);
+  kinematics(q->P.kin_mode, q->P.kin_v0, q->P.kin_t_ramp, q->P.kin_coef, q->P.disk_x0, t, x, v, a);
+}
+
+// ---- building blocks --------------------------------------------------------
+void orc_kernel(double q, double h, double* W, double* F) {
+  orc_params p;
+  std::memset(&p, 0, sizeof p);
+  p.dx = h; p.h_over_dx = 1.0; p.rho0 = 1.0; p.L = p.W = 1.0;
+  Geom g = make_geom(p);
+  if (!(q < 2.0)) { *W = 0; *F = 0; return; }
+  kernel_WF(q, g, *W, *F);
+}
+
+void orc_eos(const orc_params* p, double rho, double* pres, double* c) {
+  Coef<double> k;
+  k.c0 = p->c0; k.B = p->rho0 * p->c0 * p->c0 / p->gamma; k.alpha = p->alpha; k.delta = p->delta;
+  *pres = eos_p(rho, *p, k);
+  *c = eos_c(rho, *p, k);
+}
+
+double orc_elastic_energy(const orc_params* p, double rho) {
+  SimD s;
+  s.P = *p;
+  s.set_coef(p->alpha, p->delta, p->c0);
+  return s.e_el(rho);
+}
+
+double orc_cfl_dt(double cfl, double h, double c0, double vmax) { return cfl * h / (c0 + vmax); }
+
+int orc_cell_list(const orc_params* p, int n, const double* x, const double* y, int* keys,
+                  int* perm, int* cell_start) {
+  Geom g = make_geom(*p);
+  const int nc = g.ncx * g.ncy;
+  std::vector<int> k(n), ord(n);
+  for (int i = 0; i < n; ++i) {
+    k[i] = cell_coord(y[i], g.y_lo, g.dc, g.ncy) * g.ncx + cell_coord(x[i], g.x_lo, g.dc, g.ncx);
+    ord[i] = i;
+    if (keys) keys[i] = k[i];
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return k[a] < k[b]; });
+  if (perm) std::copy(ord.begin(), ord.end(), perm);
+  if (cell_start) {
+    std::fill(cell_start, cell_start + nc + 1, 0);
+    for (int i = 0; i < n; ++i) cell_start[k[i] + 1]++;
+    for (int c = 1; c <= nc; ++c) cell_start[c] += cell_start[c - 1];
+  }
+  return nc;
+}
+
+long orc_brute_pairs(const orc_params* p, int n, const double* x, const double* y, int* out, long cap) {
+  const double h = p->h_over_dx * p->dx, s2 = 4.0 * h * h;
+  long m = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      double rx = x[i] - x[j], ry = y[i] - y[j];
+      if (rx * rx + ry * ry < s2) {
+        if (out && m < cap) { out[2 * m] = i; out[2 * m + 1] = j; }
+        ++m;
+      }
+    }
+  return m;
+}
+
+long orc_cell_pairs(const orc_params* p, int n, const double* x, const double* y, int* out, long cap) {
+  Geom g = make_geom(*p);
+  const double s2 = 4.0 * g.h * g.h;
+  std::vector<int> keys(n), perm(n), cs(g.ncx * g.ncy + 1);
+  orc_cell_list(p, n, x, y, keys.data(), perm.data(), cs.data());
+  long m = 0;
+  for (int i = 0; i < n; ++i) {
+    int cx = keys[i] % g.ncx, cy = keys[i] / g.ncx;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dxx = -1; dxx <= 1; ++dxx) {
+        int xx = cx + dxx, yy = cy + dy;
+        if (xx < 0 || xx >= g.ncx || yy < 0 || yy >= g.ncy) continue;
+        int K = yy * g.ncx + xx;
+        for (int k = cs[K]; k < cs[K + 1]; ++k) {
+          int j = perm[k];
+          if (j <= i) continue;
+          double rx = x[i] - x[j], ry = y[i] - y[j];
+          if (rx * rx + ry * ry < s2) {
+            if (out && m < cap) { out[2 * m] = i; out[2 * m + 1] = j; }
+            ++m;
+          }
+        }
+      }
+  }
+  return m;
+}
+
+void orc_neighbour_stats(const orc_params* p, int n, const double* x, const double* y,
+                         const int* ids, double tol, int* count, long long* idsum, int* border) {
+  Geom g = make_geom(*p);
+  const double s2 = 4.0 * g.h * g.h;
+  std::vector<int> keys(n), perm(n), cs(g.ncx * g.ncy + 1);
+  orc_cell_list(p, n, x, y, keys.data(), perm.data(), cs.data());
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n; ++i) {
+    int cx = keys[i] % g.ncx, cy = keys[i] / g.ncx;
+    int c = 0, b = 0;
+    long long sm = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dxx = -1; dxx <= 1; ++dxx) {
+        int xx = cx + dxx, yy = cy + dy;
+        if (xx < 0 || xx >= g.ncx || yy < 0 || yy >= g.ncy) continue;
+        int K = yy * g.ncx + xx;
+        for (int k = cs[K]; k < cs[K + 1]; ++k) {
+          int j = perm[k];
+          if (j == i) continue;
+          double rx = x[i] - x[j], ry = y[i] - y[j], r2 = rx * rx + ry * ry;
+          if (std::fabs(r2 - s2) < tol * s2) ++b;
+          if (r2 < s2) { ++c; sm += ids[j]; }
+        }
+      }
+    count[i] = c; idsum[i] = sm; border[i] = b;
+  }
+}
+
+void orc_ghost_point(const orc_params* p, double gx, double gy, const double* vw, const double* aw,
+                     int nf, const double* x, const double* y, const double* vx, const double* vy,
+                     const double* rho, const double* pres, double* pg, double* rhog, double* vg) {
+  Geom g = make_geom(*p);
+  double SW = 0, Sp = 0, Srx = 0, Sry = 0, Svx = 0, Svy = 0;
+  for (int j = 0; j < nf; ++j) {
+    double rx = gx - x[j], ry = gy - y[j], r2 = rx * rx + ry * ry;
+    if (!(r2 < 4.0 * g.h * g.h)) continue;
+    double W, F;
+    kernel_WF(std::sqrt(r2) / g.h, g, W, F);
+    SW += W; Sp += pres[j] * W; Srx += rho[j] * rx * W; Sry += rho[j] * ry * W;
+    Svx += vx[j] * W; Svy += vy[j] * W;
+  }
+  double q, ux, uy;
+  if (SW > 0) {
+    q = (Sp + (0.0 - aw[0]) * Srx + (p->gravity_y - aw[1]) * Sry) / SW;
+    ux = 2.0 * vw[0] - Svx / SW;
+    uy = 2.0 * vw[1] - Svy / SW;
+  } else {
+    q = 0; ux = vw[0]; uy = vw[1];
+  }
+  if (q < p->p_cav) q = p->p_cav;
+  double B = p->rho0 * p->c0 * p->c0 / p->gamma;
+  *pg = q;
+  *rhog = p->ghost_rho_mode == 0 ? p->rho0 * (1.0 + q / (p->rho0 * p->c0 * p->c0))
+                                 : p->rho0 * std::pow(1.0 + q / B, 1.0 / p->gamma);
+  vg[0] = ux; vg[1] = uy;
+}
+
+void orc_pair_rates(const orc_params* p, int n, const double* x, const double* y, const double* vx,
+                    const double* vy, const double* rho, const double* pres, const double* m,
+                    const int* kind, double* drho, double* ax, double* ay, double* Vx, double* Vy) {
+  Geom g = make_geom(*p);
+  Coef<double> k;
+  k.alpha = p->alpha; k.delta = p->delta; k.c0 = p->c0; k.B = p->rho0 * p->c0 * p->c0 / p->gamma;
+  auto view = [&](int j) {
+    PV<double> v;
+    v.x = x[j]; v.y = y[j]; v.vx = vx[j]; v.vy = vy[j]; v.rho = rho[j];
+    v.P = pres[j] / (rho[j] * rho[j]);
+    v.c = eos_c(rho[j], *p, k);
+    v.m = m[j]; v.kind = kind[j];
+    return v;
+  };
+  for (int i = 0; i < n; ++i) {
+    if (kind[i] != 0) continue;
+    PV<double> a = view(i);
+    Acc<double> acc;
+    for (int j = 0; j < n; ++j)
+      if (j != i) pair_law(a, view(j), *p, g, k, acc);
+    drho[i] = acc.D; ax[i] = acc.ax; ay[i] = acc.ay + p->gravity_y;
+    Vx[i] = vx[i] + acc.Vx; Vy[i] = vy[i] + acc.Vy;
+  }
+}
+
+void orc_tangent_J(const orc_params* p, int n_steps, const double* dt, double* J, double* dJ) {
+  using D3 = Dual<3>;
+  Sim<D3> s;
+  s.P = *p;
+  D3 a(p->alpha), d(p->delta), c(p->c0);
+  a.d[0] = 1.0; d.d[1] = 1.0; c.d[2] = 1.0;
+  s.set_coef(a, d, c);
+  s.setup(*p, 0, nullptr);
+  s.dt_table.assign(dt, dt + n_steps);
+  for (int k = 0; k < n_steps; ++k) s.one_step();
+  *J = s.J.v;
+  for (int k = 0; k < 3; ++k) dJ[k] = s.J.d[k];
+}
+
+}  // extern "C"
