@@ -1,0 +1,156 @@
+"""Benchmark of the planar WCSPH hot path on one MI355X.
+
+Workload: the 300x150 mm channel at dx = 0.5 mm (179,552 fluid particles,
+5,536 ghosts), disk R = 6 mm at 900 m/s decelerating, four wall probes
+recorded every step, 2,000 predictor-corrector steps from t = 0.
+
+value = fluid particle-steps per second over the timed steps, with the
+state already resident in HBM. The roofline block prices the pair-sum
+kernel (the dominant kernel) with its algorithmic flops against the FP32
+vector peak, timed with HIP events on the library's stream. cpu_baseline
+times the FP64 oracle on the host cores on a bounded sample of the same
+workload (its first steps).
+
+python bench.py [--gpus 1] [--steps 2000] [--warmup 50]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic work of one pair-kernel launch (roofline)
+FLOP_PER_CANDIDATE = 7     # r_ij from cell-relative offsets, |r|^2, compare
+FLOP_PER_PAIR = 60         # kernel, continuity + delta, pressure + AV, laminar, XSPH
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (published)
+PEAK_HBM_GBS = 8000.0
+
+
+def pair_flops(s) -> float:
+    """Algorithmic flops of one pair-kernel launch on the solver's current
+    state: per fluid particle, the candidates in its 3x3 cells and the
+    in-support neighbours."""
+    nb = s.export_neighbours()
+    ex = s.export_cells()
+    cs = ex["cell_start"].astype(np.int64)
+    occ = np.diff(cs)
+    nf = s.nf
+    fluid = nb["ids"] < nf
+    cfg = s.cfgs[0]
+    ncx = int(np.ceil((cfg["L"] + 6 * cfg["dx"]) / cfg["cell_size"]))
+    ncy = occ.size // ncx
+    grid = occ.reshape(ncy, ncx)
+    pad = np.pad(grid, 1)
+    cand = sum(pad[1 + dy:1 + dy + ncy, 1 + dx:1 + dx + ncx] for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+    cand_per_cell = cand.ravel()
+    # candidates of each fluid particle = occupancy of its 3x3 block (minus itself)
+    keys = np.repeat(np.arange(occ.size), occ)  # key of each sorted slot
+    n_cand = (cand_per_cell[keys] - 1)[fluid]
+    n_pair = nb["count"][fluid]
+    return float(n_cand.sum() * FLOP_PER_CANDIDATE + n_pair.sum() * FLOP_PER_PAIR), \
+        float(n_cand.mean()), float(n_pair.mean())
+
+
+def cpu_baseline(cfg, budget_s: float = 15.0):
+    import oracle
+    o = oracle.Oracle(cfg)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        o.step(5)
+        n += 5
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=o.nf * n / dt, unit="fluid particle-steps/s", cores=threads, kind="oracle",
+                sample=f"first {n} steps of the same 300x150 mm / dx 0.5 mm workload from t = 0, "
+                       f"FP64 oracle (C++17, OpenMP), {dt:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--reps", type=int, default=50, help="pair-kernel timing launches")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    import paper_2609_05494_amd as wc
+
+    cfg = workloads.C2()
+    s = wc.Solver(cfg, "cuda:0")
+    blob0 = s.save_state()
+    s.step(args.warmup)
+    s.synchronize()
+    s.load_state(blob0)
+    s.read_probes()
+    s.read_diagnostics()
+    print(f"[bench] C2 nf={s.nf} slots={s.n_slots} cells={s.n_cells}: timing {args.steps} steps",
+          file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    s.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    value = s.nf * args.steps / elapsed
+    d = s.read_diagnostics()
+    unstable = bool(d.get("unstable", False))
+    _, _, p = s.read_probes()
+
+    # roofline of the pair kernel, timed on the final state of the timed run
+    flops, mean_cand, mean_pair = pair_flops(s)
+    pair_ms = s.time_pair_kernel(args.reps)
+    achieved = flops / (pair_ms * 1e-3) / 1e12
+    roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
+                kernel="k_pair<EV_A>", kernel_ms=round(pair_ms, 5),
+                flop_per_launch=flops, mean_candidates=round(mean_cand, 2),
+                mean_pairs=round(mean_pair, 2))
+    nf = s.nf
+    s.close()
+
+    cpu = None if args.no_cpu else cpu_baseline(cfg)
+    out = {
+        "metric": "WCSPH fluid particle-steps/s at 180k particles",
+        "value": value,
+        "unit": "fluid particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "300x150 mm channel, dx 0.5 mm, 179,552 fluid + 5,536 ghosts, "
+                               "disk R 6 mm at 900 m/s, 4 wall probes, predictor-corrector",
+                   "n_fluid": nf, "steps": args.steps, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "unstable": unstable,
+        "probe_peak_pa": float(np.abs(p).max()) if p.size else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

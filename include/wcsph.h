@@ -1,0 +1,218 @@
+/*
+ * wcsph.h -- C ABI of the MI355X planar WCSPH hot path (libwcsph.so).
+ *
+ * The library advances the per-step particle pipeline of a planar
+ * weakly-compressible SPH model of hydrodynamic ram (a rigid disk driven
+ * through a water channel): cell-linked-list neighbour search, Wendland C2
+ * continuity (with delta diffusion) and momentum sums, Tait EOS with a
+ * cavitation cutoff, Monaghan artificial viscosity, Adami ghost particles on
+ * the channel walls and the moving disk, and a predictor-corrector update.
+ * Section / equation names below refer to the paper "Verification,
+ * Sensitivity, and Operating Limits of a GPU-Accelerated Planar WCSPH Model
+ * for Hydrodynamic Ram".
+ *
+ * Conventions
+ *  - SI units. The fluid box is [0,L]x[0,W]; the disk moves along +x.
+ *  - Every function returns wcsph_status; nothing throws across the ABI.
+ *  - Host pointers are caller-owned and only read/written during the call.
+ *    Device memory is owned by the context; it is obtained through the
+ *    caller's allocator (or hipMalloc when none is given) at create time.
+ *  - Work is queued on the stream given at create (it must not be the
+ *    legacy NULL stream: the step is captured into a HIP graph on it).
+ *    wcsph_step returns without waiting; every read_* / get_* / export_*
+ *    call synchronises the stream first.
+ *  - A context is not thread-safe; use one context per host thread.
+ *  - On error the context keeps its previous state when possible and
+ *    wcsph_last_error() describes the failure. After WCSPH_E_HIP the
+ *    context must only be destroyed.
+ */
+#ifndef WCSPH_H
+#define WCSPH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WCSPH_OK = 0,
+  WCSPH_E_INVALID = 1,  /* bad argument or parameter; nothing was changed */
+  WCSPH_E_OOM = 2,      /* an allocation failed; the context is still destroyable */
+  WCSPH_E_HIP = 3,      /* a HIP runtime call failed */
+  WCSPH_E_STATE = 4,    /* call not valid in the current state (NULL / destroyed ctx) */
+  WCSPH_E_UNSTABLE = 5, /* a diagnostic found a non-finite value or an escaped particle */
+  WCSPH_E_RANGE = 6     /* a size argument is too small for the data */
+} wcsph_status;
+
+#define WCSPH_MAX_PROBES 16
+
+typedef struct wcsph_ctx wcsph_ctx;
+
+/* Optional device allocator (e.g. a framework's caching allocator).
+ * alloc returns device memory of at least `bytes` bytes or NULL; free
+ * releases it. `stream` is the context's stream. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* stream, void* user);
+  void* user;
+} wcsph_allocator;
+
+/* Problem and scheme parameters (copied at create).
+ *  geometry   : channel [0,L]x[0,W], lattice spacing dx, h = h_over_dx dx
+ *               (1.3: SPH Fundamentals), cell edge cell_size >= 2h (<= 0 -> the
+ *               smallest float >= 2h), ghost_layers wall-ghost lattice rows.
+ *  material   : rho0, Tait c0 and gamma (B = rho0 c0^2 / gamma), cavitation
+ *               cutoff p_cav (< 0, eq. eos text).
+ *  scheme     : Monaghan alpha and eta2 (eq. artificial-viscosity), delta
+ *               diffusion coefficient, eps_xsph (eq. xsph), dynamic viscosity
+ *               mu_dyn (laminar term), CFL number (eq. cfl), gravity_y,
+ *               density band [rho_lo, rho_hi] rho0 (Density Summation),
+ *               wall pull-back eps_wall (Channel Walls).
+ *  disk       : radius disk_R (0 -> no disk) starting at (disk_x0, disk_y0),
+ *               n_disk_ghosts ring ghosts of mass rho0 dx 2 pi R / N_g
+ *               (eq. adami-p text), ghost_rho_mode 0 = linear acoustic branch
+ *               rho0 (1 + p / (rho0 c0^2)) (eq. adami-v), 1 = Tait inverse,
+ *               disk_mass for the disk kinetic energy diagnostic.
+ *  kinematics : kin_mode 0 = ramp (eq. velocity-ramp) over kin_t_ramp to kin_v0
+ *               then constant deceleration kin_coef (m/s^2); 1 = ramp then
+ *               quadratic drag dv/dt = -kin_coef v^2 (eq. drag).
+ *  probes     : n_probes points (x, y) where the Shepard-averaged fluid
+ *               pressure is recorded every step.
+ *  output     : diag_every steps between diagnostic records; init_mode 0 =
+ *               fluid at rest at rho0, 1 = hydrostatic density. */
+typedef struct {
+  double L, W, dx, h_over_dx, cell_size;
+  double rho0, c0, gamma, p_cav;
+  double alpha, delta, eps_xsph, mu_dyn, eta2;
+  double cfl, gravity_y;
+  double rho_lo, rho_hi, eps_wall;
+  int ghost_layers, n_disk_ghosts, ghost_rho_mode, init_mode;
+  double disk_R, disk_x0, disk_y0, disk_mass;
+  int n_probes;
+  double probe_xy[2 * WCSPH_MAX_PROBES];
+  int diag_every;
+  int kin_mode;
+  double kin_v0, kin_t_ramp, kin_coef;
+} wcsph_params;
+
+/* One diagnostic record (FP64 reductions over the fluid of one instance).
+ * ke, e_el (Tait elastic energy with the cutoff branch), e_pot (gravity),
+ * e_disk = disk_mass v_d^2 / 2, w_boundary = integrated work of the disk
+ * ghosts on the fluid (eq. energy-audit), n_clamp / n_enforce = cumulative
+ * density-band and enforcement hits, n_cav = particles at the cutoff now. */
+typedef struct {
+  double t, dt, vmax, mass, mom[2], ke, e_el, e_pot, e_disk, w_boundary;
+  long long step, n_clamp, n_cav, n_enforce;
+} wcsph_diag;
+
+typedef struct {
+  int n_inst;          /* instances in the context (1 unless batched) */
+  long long n_fluid;   /* fluid particles over all instances */
+  long long n_ghost;   /* wall + disk ghosts over all instances */
+  long long n_slots;   /* particles stored (fluid + ghosts) */
+  long long n_cells;   /* cells over all instances */
+  long long steps;     /* completed steps */
+} wcsph_info;
+
+/* ---- life cycle ---------------------------------------------------------- */
+
+/* Build the initial state of the paper's problem set-up (Validation Problem
+ * Setup; fluid lattice at ((i+1/2)dx, (j+1/2)dx) with the disk interior
+ * removed, wall ghosts continuing the lattice ghost_layers deep, disk ring)
+ * and capture one step as a HIP graph on `stream`.
+ * alloc: NULL -> hipMalloc/hipFree. stream: a hipStream_t, not NULL.
+ * Errors: E_INVALID (dx <= 0, h_over_dx outside [1,2], cell_size < 2h,
+ * disk outside the box, n_probes > 16, ...) before any allocation;
+ * E_OOM / E_HIP afterwards (the partially built context is released). */
+wcsph_status wcsph_create(const wcsph_params* p, const wcsph_allocator* alloc, void* stream,
+                          wcsph_ctx** out);
+
+/* Batched coefficient sweep: n_inst independent instances (params[k] each,
+ * sizes may differ) advanced together by the same kernels; every launch
+ * covers all instances, with per-instance time step, clock and probes. */
+wcsph_status wcsph_batch_create(const wcsph_params* params, int n_inst,
+                                const wcsph_allocator* alloc, void* stream, wcsph_ctx** out);
+
+wcsph_status wcsph_destroy(wcsph_ctx* ctx);
+const char* wcsph_last_error(const wcsph_ctx* ctx);
+wcsph_status wcsph_get_info(const wcsph_ctx* ctx, wcsph_info* out);
+/* Per-instance sizes: fluid, ghosts (walls + ring), cells. */
+wcsph_status wcsph_instance_info(const wcsph_ctx* ctx, int inst, int* n_fluid, int* n_ghost,
+                                 int* n_cells);
+
+/* ---- driving --------------------------------------------------------------- */
+
+/* Prescribed disk kinematics of instance `inst` (Velocity Ramp, Projectile
+ * Dynamics). mode 0: coeffs = {v0, t_ramp, a_d}; mode 1: {v0, t_ramp, k}.
+ * n = number of coefficients (3). Takes effect at the next step. */
+wcsph_status wcsph_set_disk_kinematics(wcsph_ctx* ctx, int inst, int mode, const double* coeffs,
+                                       int n);
+
+/* Fixed time-step table: when n > 0, step k (counted from the current
+ * state) uses dt[k] for every instance instead of the CFL gate; n = 0
+ * returns to the CFL gate. The table is copied. */
+wcsph_status wcsph_set_dt_table(wcsph_ctx* ctx, const double* dt, int n);
+
+/* Advance every instance by n_steps predictor-corrector steps (asynchronous
+ * on the context stream). Each step: kinematics, cell list (stable sort by
+ * cell key), Adami ghosts, probes, CFL step, pair sums + predictor; then the
+ * same at the midpoint state + corrector (Pipeline Provenance section).
+ * A diagnostic record is taken every diag_every steps. */
+wcsph_status wcsph_step(wcsph_ctx* ctx, int n_steps);
+wcsph_status wcsph_synchronize(wcsph_ctx* ctx);
+
+/* ---- reading results ------------------------------------------------------- */
+
+/* Probe history of instance `inst` since the last read: per step n, the time
+ * t_n, the step dt_n and n_probes pressures (row-major). The device ring holds
+ * the last 65536 steps; older rows are dropped. */
+wcsph_status wcsph_read_probes(wcsph_ctx* ctx, int inst, double* t, double* dt, float* p,
+                               int max_rows, int* rows_out);
+/* Diagnostic records of instance `inst` since the last read (ring of 4096).
+ * Returns E_UNSTABLE if a record found a non-finite value. */
+wcsph_status wcsph_read_diagnostics(wcsph_ctx* ctx, int inst, wcsph_diag* out, int max, int* n_out);
+
+/* Fluid state of instance `inst` in particle-id order (id = j nx + i of the
+ * lattice, disk interior skipped), decoded to FP64; n = its fluid count. */
+wcsph_status wcsph_get_fluid(wcsph_ctx* ctx, int inst, double* t, double* x, double* y, double* vx,
+                             double* vy, double* rho, int n);
+/* Replace the fluid state of every instance (single-instance contexts only):
+ * positions are encoded as (cell, FP32 offset), velocities and density to
+ * FP32; storage order is reset to id order and the clock set to t. */
+wcsph_status wcsph_set_fluid(wcsph_ctx* ctx, double t, const double* x, const double* y,
+                             const double* vx, const double* vy, const double* rho, int n);
+
+/* Opaque checkpoint of the whole device state (clock, encoded particles,
+ * storage order). need returns the size; cap too small -> E_RANGE. */
+wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* need);
+wcsph_status wcsph_load_state(wcsph_ctx* ctx, const void* buf, size_t n);
+
+/* ---- test hooks -------------------------------------------------------------- */
+
+/* One cell-list build on the current state (single instance): per slot of
+ * the pre-sort order the key, particle id and decoded position; the stable
+ * permutation perm[new] = old; the ids in sorted order; cell_start[ncells+1].
+ * The state is left unchanged. */
+wcsph_status wcsph_export_cells(wcsph_ctx* ctx, unsigned* keys, unsigned* ids_pre, double* x,
+                                double* y, unsigned* perm, unsigned* ids_post, unsigned* cell_start,
+                                size_t cap_slots, size_t cap_cells);
+/* One evaluation on the current state (ghosts then pair sums, single
+ * instance): density rate, acceleration and XSPH velocity per fluid id, ghost
+ * pressure / density / velocity per ghost index (walls then ring). */
+wcsph_status wcsph_export_rates(wcsph_ctx* ctx, float* drho, float* ax, float* ay, float* Vx,
+                                float* Vy, float* gp, float* grho, float* gvx, float* gvy,
+                                int n_fluid, int n_ghost);
+/* In-support neighbour count and neighbour-id sum per particle (ids in
+ * sorted order), plus decoded positions; single instance. */
+wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, long long* idsum,
+                                     double* x, double* y, size_t cap_slots);
+/* Measurement hook: average duration (ms) of the pair-sum kernel of the
+ * first evaluation, re-launched `reps` times on the current sorted state
+ * between two HIP events on the context stream. The state is restored. */
+wcsph_status wcsph_time_pair_kernel(wcsph_ctx* ctx, int reps, float* avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WCSPH_H */

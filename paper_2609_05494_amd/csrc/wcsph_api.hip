@@ -1,0 +1,998 @@
+// wcsph_api.hip -- host runtime and C ABI of libwcsph.so.
+//
+// Builds the paper's problem set-up on the host in FP64 (fluid lattice with
+// the disk interior removed, wall-ghost lattice, disk ring, probe points,
+// cell grid), encodes it into the device layout, captures one
+// predictor-corrector step into a HIP graph and replays it.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wcsph.h"
+#include "wcsph_launch.h"
+
+namespace {
+
+struct WcError {
+  wcsph_status st;
+  std::string msg;
+};
+
+thread_local std::string g_create_error;
+
+#define HC(call)                                                                           \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw WcError{WCSPH_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)};       \
+  } while (0)
+
+void require(bool ok, const std::string& msg) {
+  if (!ok) throw WcError{WCSPH_E_INVALID, msg};
+}
+
+// Host-side geometry of one instance (FP64).
+struct HostInst {
+  std::vector<double> fx, fy, frho;  // fluid lattice (id order)
+  std::vector<double> wx, wy;        // wall ghosts (id order)
+  int nd = 0;
+};
+
+}  // namespace
+
+struct wcsph_ctx {
+  std::string err;
+  hipStream_t st = nullptr;
+  wcsph_allocator al{};
+  bool custom_alloc = false;
+  std::vector<void*> blocks;
+  bool batch = false;
+  int n_inst = 0;
+  std::vector<wcsph_params> pin;
+  std::vector<InstParams> hp;
+  std::vector<HostInst> geo;
+  long long n_fluid = 0;
+  int n_slots = 0, n_cells = 0, n_ghost = 0, n_gblk = 0;
+  int diag_every = 0;
+  Dev d{};
+  Bufs b{};
+  InstParams* d_prm = nullptr;
+  Clock* d_clk = nullptr;
+  uint32_t* d_wallcount = nullptr;
+  uint32_t* d_gslot_save = nullptr;
+  std::vector<uint32_t> h_wallcount, h_wrank;
+  std::vector<int4> h_gblk;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  long long steps = 0;
+  std::vector<long long> hist_read, diag_rows, diag_read;
+  double* d_dt = nullptr;
+  size_t d_dt_cap = 0;
+  bool dead = false;
+};
+
+namespace {
+
+void* dalloc(wcsph_ctx* c, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  void* p = nullptr;
+  if (c->custom_alloc) {
+    p = c->al.alloc(bytes, (void*)c->st, c->al.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (!p) throw WcError{WCSPH_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+  c->blocks.push_back(p);
+  return p;
+}
+
+template <class T>
+T* dalloc_n(wcsph_ctx* c, size_t n) {
+  return static_cast<T*>(dalloc(c, n * sizeof(T)));
+}
+
+float cell_edge(const wcsph_params& p) {
+  const double two_h = 2.0 * p.h_over_dx * p.dx;
+  if (p.cell_size > 0) return (float)p.cell_size;
+  float c = (float)two_h;
+  if ((double)c < two_h) c = std::nextafter(c, INFINITY);
+  return c;
+}
+
+void validate(const wcsph_params& p) {
+  require(p.dx > 0 && std::isfinite(p.dx), "dx must be positive");
+  require(p.L > 0 && p.W > 0, "L and W must be positive");
+  require(p.h_over_dx >= 1.0 && p.h_over_dx <= 2.0, "h_over_dx must lie in [1, 2]");
+  const double two_h = 2.0 * p.h_over_dx * p.dx;
+  if (p.cell_size > 0) {
+    require((double)(float)p.cell_size == p.cell_size, "cell_size must be a float32 value");
+    require(p.cell_size >= two_h, "cell_size must be >= 2h");
+  }
+  require(p.rho0 > 0 && p.c0 > 0 && p.gamma > 1.0, "rho0, c0 must be positive and gamma > 1");
+  require(p.p_cav <= 0, "p_cav must be <= 0");
+  require(p.alpha >= 0 && p.delta >= 0 && p.eps_xsph >= 0 && p.mu_dyn >= 0 && p.eta2 > 0,
+          "scheme coefficients must be non-negative (eta2 > 0)");
+  require(p.cfl > 0 && p.cfl <= 1.0, "cfl must lie in (0, 1]");
+  require(p.rho_lo > 0 && p.rho_hi > p.rho_lo, "density band must satisfy 0 < rho_lo < rho_hi");
+  require(p.eps_wall >= 0 && p.eps_wall < 0.5 * p.dx, "eps_wall must lie in [0, dx/2)");
+  require(p.ghost_layers >= 1 && p.ghost_layers <= 8, "ghost_layers must lie in [1, 8]");
+  require(p.n_disk_ghosts >= 0 && p.n_disk_ghosts <= 200, "n_disk_ghosts must lie in [0, 200]");
+  require(p.ghost_rho_mode == 0 || p.ghost_rho_mode == 1, "ghost_rho_mode must be 0 or 1");
+  require(p.init_mode == 0 || p.init_mode == 1, "init_mode must be 0 or 1");
+  require(p.disk_R >= 0, "disk_R must be >= 0");
+  if (p.disk_R > 0) {
+    require(p.disk_x0 - p.disk_R >= -1e-12 && p.disk_x0 + p.disk_R <= p.L + 1e-12 &&
+                p.disk_y0 - p.disk_R >= -1e-12 && p.disk_y0 + p.disk_R <= p.W + 1e-12,
+            "disk must lie inside the channel");
+    require(p.kin_t_ramp > 0 && p.kin_v0 >= 0 && p.kin_coef >= 0, "kinematics coefficients invalid");
+  }
+  require(p.kin_mode == 0 || p.kin_mode == 1, "kin_mode must be 0 or 1");
+  require(p.n_probes >= 0 && p.n_probes <= WCSPH_MAX_PROBES, "n_probes must lie in [0, 16]");
+  const double m = p.ghost_layers * p.dx;
+  for (int k = 0; k < p.n_probes; ++k)
+    require(p.probe_xy[2 * k] >= -m && p.probe_xy[2 * k] <= p.L + m && p.probe_xy[2 * k + 1] >= -m &&
+                p.probe_xy[2 * k + 1] <= p.W + m,
+            "probe outside the grid");
+  require(p.diag_every >= 0, "diag_every must be >= 0");
+  const long long nx = std::llround(p.L / p.dx), ny = std::llround(p.W / p.dx);
+  require(nx >= 1 && ny >= 1 && nx * ny < (1ll << 28), "lattice size out of range");
+}
+
+// Problem set-up of one instance: fluid lattice ((i+1/2)dx, (j+1/2)dx) with
+// id = j nx + i and the disk interior removed; wall ghosts continuing the
+// lattice ghost_layers deep around the box (j outer); the disk ring.
+HostInst build_geometry(const wcsph_params& p) {
+  HostInst g;
+  const int nx = (int)std::lround(p.L / p.dx), ny = (int)std::lround(p.W / p.dx);
+  const double B = p.rho0 * p.c0 * p.c0 / p.gamma;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double x = (i + 0.5) * p.dx, y = (j + 0.5) * p.dx;
+      if (p.disk_R > 0) {
+        const double ux = x - p.disk_x0, uy = y - p.disk_y0;
+        if (ux * ux + uy * uy < p.disk_R * p.disk_R) continue;
+      }
+      double r = p.rho0;
+      if (p.init_mode == 1) r = p.rho0 * std::pow(1.0 + p.rho0 * std::fabs(p.gravity_y) * (p.W - y) / B, 1.0 / p.gamma);
+      g.fx.push_back(x);
+      g.fy.push_back(y);
+      g.frho.push_back(r);
+    }
+  const int Lg = p.ghost_layers;
+  for (int j = -Lg; j < ny + Lg; ++j)
+    for (int i = -Lg; i < nx + Lg; ++i) {
+      if (i >= 0 && i < nx && j >= 0 && j < ny) continue;
+      g.wx.push_back((i + 0.5) * p.dx);
+      g.wy.push_back((j + 0.5) * p.dx);
+    }
+  g.nd = p.disk_R > 0 ? p.n_disk_ghosts : 0;
+  return g;
+}
+
+InstParams derive(const wcsph_params& p) {
+  InstParams q;
+  std::memset(&q, 0, sizeof q);
+  const double h = p.h_over_dx * p.dx;
+  q.dc = cell_edge(p);
+  q.dcd = (double)q.dc;
+  q.x_lo = -p.ghost_layers * p.dx;
+  q.y_lo = -p.ghost_layers * p.dx;
+  q.ncx = (int)std::ceil((p.L + 2.0 * p.ghost_layers * p.dx) / q.dcd);
+  q.ncy = (int)std::ceil((p.W + 2.0 * p.ghost_layers * p.dx) / q.dcd);
+  q.ncell = q.ncx * q.ncy;
+  q.h = (float)h;
+  q.inv_h = (float)(1.0 / h);
+  q.four_h2 = (float)(4.0 * h * h);
+  q.sigma = (float)(7.0 / (4.0 * M_PI * h * h));
+  q.fgrad = (float)(35.0 / (4.0 * M_PI * h * h * h * h));
+  q.eta2h2 = (float)(p.eta2 * h * h);
+  const double B = p.rho0 * p.c0 * p.c0 / p.gamma;
+  q.rho0 = (float)p.rho0;
+  q.c0 = (float)p.c0;
+  q.B = (float)B;
+  q.p_cav = (float)p.p_cav;
+  q.alpha = (float)p.alpha;
+  q.eps_xsph = (float)p.eps_xsph;
+  q.gy = (float)p.gravity_y;
+  q.two_delta_h_c0 = (float)(2.0 * p.delta * h * p.c0);
+  q.four_nu0 = (float)(4.0 * p.mu_dyn / p.rho0);
+  q.m_fluid = (float)(p.rho0 * p.dx * p.dx);
+  q.m_wall = (float)(p.rho0 * p.dx * p.dx);
+  q.m_disk = p.n_disk_ghosts > 0 ? (float)(p.rho0 * p.dx * 2.0 * M_PI * p.disk_R / p.n_disk_ghosts) : 0.0f;
+  q.rho_lo = (float)(p.rho_lo * p.rho0);
+  q.rho_hi = (float)(p.rho_hi * p.rho0);
+  q.inv_rho0c02 = (float)(1.0 / (p.rho0 * p.c0 * p.c0));
+  q.c_exp = (float)(0.5 * (p.gamma - 1.0));
+  q.gamma = (float)p.gamma;
+  q.inv_gamma = (float)(1.0 / p.gamma);
+  q.ghost_rho_mode = p.ghost_rho_mode;
+  q.L = p.L;
+  q.W = p.W;
+  q.eps_wall = p.eps_wall;
+  q.R = p.disk_R;
+  q.disk_x0 = p.disk_x0;
+  q.disk_y0 = p.disk_y0;
+  q.disk_mass = p.disk_mass;
+  q.cfl = p.cfl;
+  q.hd = h;
+  q.c0d = p.c0;
+  q.Bd = B;
+  q.rho0d = p.rho0;
+  q.gammad = p.gamma;
+  q.p_cavd = p.p_cav;
+  q.m_fluidd = p.rho0 * p.dx * p.dx;
+  q.kin_mode = p.kin_mode;
+  q.kin_v0 = p.kin_v0;
+  q.kin_t_ramp = p.kin_t_ramp;
+  q.kin_coef = p.kin_coef;
+  return q;
+}
+
+void encode(const InstParams& q, double x, double y, uint32_t& key, float& ox, float& oy) {
+  auto axis = [&](double v, double lo, int n, int& c, float& o) {
+    const double u = v - lo;
+    c = (int)std::floor(u / q.dcd);
+    c = std::min(std::max(c, 0), n - 1);
+    o = (float)(u - (double)c * q.dcd);
+    if (o >= q.dc && c < n - 1) {
+      o -= q.dc;
+      c += 1;
+    }
+  };
+  int cx, cy;
+  axis(x, q.x_lo, q.ncx, cx, ox);
+  axis(y, q.y_lo, q.ncy, cy, oy);
+  key = (uint32_t)(q.cell_off + cy * q.ncx + cx);
+}
+
+void decode(const InstParams& q, uint32_t key, float ox, float oy, double& x, double& y) {
+  const int local = (int)key - q.cell_off;
+  const int cy = local / q.ncx, cx = local - cy * q.ncx;
+  x = q.x_lo + (double)cx * q.dcd + (double)ox;
+  y = q.y_lo + (double)cy * q.dcd + (double)oy;
+}
+
+void alloc_buf(wcsph_ctx* c, Buf& b) {
+  const size_t n = c->n_slots;
+  b.cell = dalloc_n<uint32_t>(c, n);
+  b.id = dalloc_n<uint32_t>(c, n);
+  b.pv = dalloc_n<float4>(c, n);
+  b.aux = dalloc_n<float4>(c, n);
+  b.bslot = dalloc_n<uint32_t>(c, n);
+  b.inst = c->batch ? dalloc_n<uint16_t>(c, n) : nullptr;
+}
+
+void sync(wcsph_ctx* c) { HC(hipStreamSynchronize(c->st)); }
+
+// Write the set-up (or a given fluid state for instance 0) into X in id
+// order, re-arm the sort counters and reset the clocks.
+void upload_state(wcsph_ctx* c, double t0, const double* fx, const double* fy, const double* fvx,
+                  const double* fvy, const double* frho) {
+  const size_t n = c->n_slots;
+  std::vector<uint32_t> cell(n), id(n);
+  std::vector<float4> pv(n), aux(n);
+  std::vector<uint16_t> inst(n);
+  std::vector<uint32_t> gslot(c->n_ghost);
+  for (int i = 0; i < c->n_inst; ++i) {
+    const InstParams& q = c->hp[i];
+    const HostInst& g = c->geo[i];
+    const wcsph_params& p = c->pin[i];
+    for (int k = 0; k < q.nf; ++k) {
+      const size_t s = q.id0 + k;
+      const bool given = fx != nullptr && i == 0;
+      const double x = given ? fx[k] : g.fx[k], y = given ? fy[k] : g.fy[k];
+      float ox, oy;
+      encode(q, x, y, cell[s], ox, oy);
+      pv[s] = make_float4(ox, oy, given ? (float)fvx[k] : 0.0f, given ? (float)fvy[k] : 0.0f);
+      aux[s] = make_float4(given ? (float)frho[k] : (float)g.frho[k], 0, 0, 0);
+      id[s] = (uint32_t)s;
+      inst[s] = (uint16_t)i;
+    }
+    for (int k = 0; k < q.nw; ++k) {
+      const size_t s = q.id0 + q.nf + k;
+      float ox, oy;
+      encode(q, g.wx[k], g.wy[k], cell[s], ox, oy);
+      pv[s] = make_float4(ox, oy, 0, 0);
+      aux[s] = make_float4((float)p.rho0, 0, 0, 0);
+      id[s] = (uint32_t)s;
+      inst[s] = (uint16_t)i;
+      gslot[q.gmap0 + k] = (uint32_t)s;
+    }
+    for (int k = 0; k < q.nd; ++k) {
+      const size_t s = q.id0 + q.nf + q.nw + k;
+      float ox, oy;
+      encode(q, p.disk_x0, p.disk_y0, cell[s], ox, oy);  // placed by the first evaluation
+      pv[s] = make_float4(ox, oy, 0, 0);
+      aux[s] = make_float4((float)p.rho0, 0, 0, 0);
+      id[s] = (uint32_t)s;
+      inst[s] = (uint16_t)i;
+      gslot[q.gmap0 + q.nw + k] = (uint32_t)s;
+    }
+  }
+  HC(hipMemcpyAsync(c->b.X.cell, cell.data(), n * 4, hipMemcpyHostToDevice, c->st));
+  HC(hipMemcpyAsync(c->b.X.id, id.data(), n * 4, hipMemcpyHostToDevice, c->st));
+  HC(hipMemcpyAsync(c->b.X.pv, pv.data(), n * 16, hipMemcpyHostToDevice, c->st));
+  HC(hipMemcpyAsync(c->b.X.aux, aux.data(), n * 16, hipMemcpyHostToDevice, c->st));
+  if (c->batch) HC(hipMemcpyAsync(c->b.X.inst, inst.data(), n * 2, hipMemcpyHostToDevice, c->st));
+  HC(hipMemcpyAsync(c->d.gslot, gslot.data(), gslot.size() * 4, hipMemcpyHostToDevice, c->st));
+  HC(hipMemcpyAsync(c->d.count, c->d_wallcount, (size_t)c->n_cells * 4, hipMemcpyDeviceToDevice, c->st));
+  std::vector<Clock> clk(c->n_inst);
+  for (auto& k : clk) {
+    std::memset(&k, 0, sizeof k);
+    k.t = t0;
+    k.t_next = t0;
+    k.step = -1;
+  }
+  HC(hipMemcpyAsync(c->d_clk, clk.data(), clk.size() * sizeof(Clock), hipMemcpyHostToDevice, c->st));
+  wc_enqueue_init(c->d, c->b, c->batch, c->st);
+  HC(hipGetLastError());
+  c->steps = 0;
+  for (int i = 0; i < c->n_inst; ++i) {
+    c->hist_read[i] = 0;
+    c->diag_rows[i] = 0;
+    c->diag_read[i] = 0;
+  }
+  wc_enqueue_diag(c->d, c->b, 0, false, c->st);
+  HC(hipGetLastError());
+  for (int i = 0; i < c->n_inst; ++i) c->diag_rows[i] = 1;
+  sync(c);
+}
+
+void capture(wcsph_ctx* c) {
+  if (c->gexec) {
+    HC(hipGraphExecDestroy(c->gexec));
+    c->gexec = nullptr;
+  }
+  if (c->graph) {
+    HC(hipGraphDestroy(c->graph));
+    c->graph = nullptr;
+  }
+  HC(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+  wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, c->st);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->st, &g);
+  HC(e);
+  c->graph = g;
+  HC(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+}
+
+void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
+  c->n_inst = n_inst;
+  c->pin.assign(params, params + n_inst);
+  c->diag_every = params[0].diag_every;
+  int id0 = 0, gmap0 = 0, cell_off = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const wcsph_params& p = params[i];
+    HostInst g = build_geometry(p);
+    InstParams q = derive(p);
+    q.nf = (int)g.fx.size();
+    q.nw = (int)g.wx.size();
+    q.nd = g.nd;
+    q.id0 = id0;
+    q.gmap0 = gmap0;
+    q.cell_off = cell_off;
+    q.n_probes = p.n_probes;
+    for (int k = 0; k < p.n_probes; ++k) {
+      encode(q, p.probe_xy[2 * k], p.probe_xy[2 * k + 1], q.probe_cell[k], q.probe_ox[k], q.probe_oy[k]);
+    }
+    id0 += q.nf + q.nw + q.nd;
+    gmap0 += q.nw + q.nd;
+    cell_off += q.ncell;
+    require((long long)id0 < (1ll << 30) && (long long)cell_off < (1ll << 30), "problem too large");
+    c->n_fluid += q.nf;
+    c->hp.push_back(q);
+    c->geo.push_back(std::move(g));
+  }
+  c->n_slots = id0;
+  c->n_ghost = gmap0;
+  c->n_cells = cell_off;
+  // static wall-ghost occupancy and bucket ranks; ghost-kernel block table
+  c->h_wallcount.assign(c->n_cells, 0);
+  c->h_wrank.assign(c->n_ghost, 0);
+  for (int i = 0; i < n_inst; ++i) {
+    const InstParams& q = c->hp[i];
+    for (int k = 0; k < q.nw; ++k) {
+      uint32_t key;
+      float ox, oy;
+      encode(q, c->geo[i].wx[k], c->geo[i].wy[k], key, ox, oy);
+      c->h_wrank[q.gmap0 + k] = c->h_wallcount[key]++;
+    }
+    for (int g0 = 0; g0 < q.nw; g0 += WC_GHOST_BLOCK)
+      c->h_gblk.push_back(make_int4(i, g0, std::min(WC_GHOST_BLOCK, q.nw - g0), 0));
+    c->h_gblk.push_back(make_int4(i, q.nw, q.nd, 1));
+  }
+  c->n_gblk = (int)c->h_gblk.size();
+  // device memory
+  alloc_buf(c, c->b.X);
+  alloc_buf(c, c->b.Y);
+  alloc_buf(c, c->b.Z);
+  alloc_buf(c, c->b.W);
+  Dev& d = c->d;
+  c->d_prm = dalloc_n<InstParams>(c, n_inst);
+  c->d_clk = dalloc_n<Clock>(c, n_inst);
+  d.prm = c->d_prm;
+  d.clk = c->d_clk;
+  d.n_inst = n_inst;
+  d.n_slots = c->n_slots;
+  d.n_cells = c->n_cells;
+  d.n_ghost = c->n_ghost;
+  d.count = dalloc_n<uint32_t>(c, c->n_cells);
+  d.start = dalloc_n<uint32_t>(c, c->n_cells + 1);
+  c->d_wallcount = dalloc_n<uint32_t>(c, c->n_cells);
+  d.wallcount = c->d_wallcount;
+  d.tmp = dalloc_n<uint32_t>(c, c->n_slots);
+  d.perm = dalloc_n<uint32_t>(c, c->n_slots);
+  d.gslot = dalloc_n<uint32_t>(c, c->n_ghost);
+  c->d_gslot_save = dalloc_n<uint32_t>(c, c->n_ghost);
+  uint32_t* wrank = dalloc_n<uint32_t>(c, c->n_ghost);
+  d.wrank = wrank;
+  int4* gblk = dalloc_n<int4>(c, c->n_gblk);
+  d.gblk = gblk;
+  d.hist_t = dalloc_n<double>(c, (size_t)n_inst * WC_HIST_CAP);
+  d.hist_dt = dalloc_n<double>(c, (size_t)n_inst * WC_HIST_CAP);
+  d.hist_p = dalloc_n<float>(c, (size_t)n_inst * WC_HIST_CAP * WC_MAX_PROBES);
+  d.diag = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_CAP * WC_NDIAG);
+  d.xr = dalloc_n<float>(c, (size_t)5 * c->n_slots);
+  d.nb_count = dalloc_n<int>(c, c->n_slots);
+  d.nb_idsum = dalloc_n<long long>(c, c->n_slots);
+  d.n_dt = 0;
+  d.dt_step0 = 0;
+  d.dt_table = nullptr;
+  HC(hipMemcpyAsync(c->d_prm, c->hp.data(), n_inst * sizeof(InstParams), hipMemcpyHostToDevice, c->st));
+  HC(hipMemcpyAsync(c->d_wallcount, c->h_wallcount.data(), (size_t)c->n_cells * 4, hipMemcpyHostToDevice, c->st));
+  HC(hipMemcpyAsync(wrank, c->h_wrank.data(), (size_t)c->n_ghost * 4, hipMemcpyHostToDevice, c->st));
+  HC(hipMemcpyAsync(gblk, c->h_gblk.data(), (size_t)c->n_gblk * sizeof(int4), hipMemcpyHostToDevice, c->st));
+  HC(hipMemsetAsync(d.hist_p, 0, (size_t)n_inst * WC_HIST_CAP * WC_MAX_PROBES * 4, c->st));
+  c->hist_read.assign(n_inst, 0);
+  c->diag_rows.assign(n_inst, 0);
+  c->diag_read.assign(n_inst, 0);
+  upload_state(c, 0.0, nullptr, nullptr, nullptr, nullptr, nullptr);
+  capture(c);
+}
+
+void release(wcsph_ctx* c) {
+  if (c->st) hipStreamSynchronize(c->st);
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  for (void* p : c->blocks) {
+    if (c->custom_alloc) c->al.free(p, (void*)c->st, c->al.user);
+    else hipFree(p);
+  }
+  c->blocks.clear();
+}
+
+wcsph_status create_impl(const wcsph_params* params, int n_inst, const wcsph_allocator* alloc,
+                         void* stream, wcsph_ctx** out, bool batch) {
+  if (!out) return WCSPH_E_INVALID;
+  *out = nullptr;
+  g_create_error.clear();
+  if (!params || n_inst < 1 || n_inst > 256) {
+    g_create_error = "params must be non-NULL and 1 <= n_inst <= 256";
+    return WCSPH_E_INVALID;
+  }
+  if (!stream) {
+    g_create_error = "a non-NULL hipStream_t is required (the step is graph-captured on it)";
+    return WCSPH_E_INVALID;
+  }
+  if (alloc && (!alloc->alloc || !alloc->free)) {
+    g_create_error = "allocator needs both alloc and free";
+    return WCSPH_E_INVALID;
+  }
+  try {
+    for (int i = 0; i < n_inst; ++i) validate(params[i]);
+    for (int i = 1; i < n_inst; ++i)
+      require(params[i].diag_every == params[0].diag_every, "batched instances share diag_every");
+  } catch (const WcError& e) {
+    g_create_error = e.msg;
+    return e.st;
+  }
+  wcsph_ctx* c = new wcsph_ctx();
+  c->st = (hipStream_t)stream;
+  c->batch = batch;
+  if (alloc) {
+    c->al = *alloc;
+    c->custom_alloc = true;
+  }
+  try {
+    build(c, params, n_inst);
+  } catch (const WcError& e) {
+    g_create_error = e.msg;
+    release(c);
+    delete c;
+    return e.st;
+  }
+  *out = c;
+  return WCSPH_OK;
+}
+
+// Save / restore what the test hooks disturb: sort counters, ghost slots
+// and clocks (the state in X itself is left untouched by the hooks).
+struct HookGuard {
+  wcsph_ctx* c;
+  std::vector<Clock> clk;
+  explicit HookGuard(wcsph_ctx* cc) : c(cc), clk(cc->n_inst) {
+    sync(c);
+    HC(hipMemcpy(clk.data(), c->d_clk, clk.size() * sizeof(Clock), hipMemcpyDeviceToHost));
+    HC(hipMemcpyAsync(c->d_gslot_save, c->d.gslot, (size_t)c->n_ghost * 4, hipMemcpyDeviceToDevice, c->st));
+  }
+  void restore() {
+    HC(hipMemcpyAsync(c->d.gslot, c->d_gslot_save, (size_t)c->n_ghost * 4, hipMemcpyDeviceToDevice, c->st));
+    HC(hipMemcpyAsync(c->d.count, c->d_wallcount, (size_t)c->n_cells * 4, hipMemcpyDeviceToDevice, c->st));
+    std::vector<Clock> k = clk;
+    for (auto& q : k) q.vmax_bits = 0u;
+    HC(hipMemcpyAsync(c->d_clk, k.data(), k.size() * sizeof(Clock), hipMemcpyHostToDevice, c->st));
+    wc_enqueue_init(c->d, c->b, c->batch, c->st);
+    HC(hipGetLastError());
+    sync(c);
+    // the fluid |v| max is recomputed; keep the larger of it and the saved value
+    std::vector<Clock> now(c->n_inst);
+    HC(hipMemcpy(now.data(), c->d_clk, now.size() * sizeof(Clock), hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->n_inst; ++i) now[i].vmax_bits = std::max(now[i].vmax_bits, clk[i].vmax_bits);
+    HC(hipMemcpy(c->d_clk, now.data(), now.size() * sizeof(Clock), hipMemcpyHostToDevice));
+  }
+};
+
+template <class T>
+std::vector<T> d2h(wcsph_ctx* c, const T* p, size_t n) {
+  std::vector<T> v(n);
+  if (n) HC(hipMemcpy(v.data(), p, n * sizeof(T), hipMemcpyDeviceToHost));
+  return v;
+}
+
+}  // namespace
+
+#define API_BEGIN(ctx)                                   \
+  if (!(ctx)) return WCSPH_E_STATE;                      \
+  if ((ctx)->dead) {                                     \
+    (ctx)->err = "context unusable after a HIP error";   \
+    return WCSPH_E_STATE;                                \
+  }                                                      \
+  try {
+#define API_END(ctx)                                     \
+  }                                                      \
+  catch (const WcError& e) {                             \
+    (ctx)->err = e.msg;                                  \
+    if (e.st == WCSPH_E_HIP) (ctx)->dead = true;         \
+    return e.st;                                         \
+  }                                                      \
+  catch (const std::exception& e) {                      \
+    (ctx)->err = e.what();                               \
+    return WCSPH_E_INVALID;                              \
+  }                                                      \
+  return WCSPH_OK;
+
+extern "C" {
+
+wcsph_status wcsph_create(const wcsph_params* p, const wcsph_allocator* alloc, void* stream,
+                          wcsph_ctx** out) {
+  return create_impl(p, 1, alloc, stream, out, false);
+}
+
+wcsph_status wcsph_batch_create(const wcsph_params* params, int n_inst, const wcsph_allocator* alloc,
+                                void* stream, wcsph_ctx** out) {
+  return create_impl(params, n_inst, alloc, stream, out, true);
+}
+
+wcsph_status wcsph_destroy(wcsph_ctx* ctx) {
+  if (!ctx) return WCSPH_E_STATE;
+  release(ctx);
+  delete ctx;
+  return WCSPH_OK;
+}
+
+const char* wcsph_last_error(const wcsph_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+wcsph_status wcsph_get_info(const wcsph_ctx* ctx, wcsph_info* out) {
+  if (!ctx) return WCSPH_E_STATE;
+  if (!out) return WCSPH_E_INVALID;
+  out->n_inst = ctx->n_inst;
+  out->n_fluid = ctx->n_fluid;
+  out->n_ghost = ctx->n_ghost;
+  out->n_slots = ctx->n_slots;
+  out->n_cells = ctx->n_cells;
+  out->steps = ctx->steps;
+  return WCSPH_OK;
+}
+
+wcsph_status wcsph_instance_info(const wcsph_ctx* ctx, int inst, int* n_fluid, int* n_ghost, int* n_cells) {
+  if (!ctx) return WCSPH_E_STATE;
+  if (inst < 0 || inst >= ctx->n_inst) return WCSPH_E_INVALID;
+  const InstParams& q = ctx->hp[inst];
+  if (n_fluid) *n_fluid = q.nf;
+  if (n_ghost) *n_ghost = q.nw + q.nd;
+  if (n_cells) *n_cells = q.ncell;
+  return WCSPH_OK;
+}
+
+wcsph_status wcsph_set_disk_kinematics(wcsph_ctx* ctx, int inst, int mode, const double* coeffs, int n) {
+  API_BEGIN(ctx)
+  require(inst >= 0 && inst < ctx->n_inst, "instance out of range");
+  require(mode == 0 || mode == 1, "mode must be 0 or 1");
+  require(coeffs != nullptr && n == 3, "three coefficients expected");
+  require(coeffs[0] >= 0 && coeffs[1] > 0 && coeffs[2] >= 0, "coefficients must be non-negative, t_ramp > 0");
+  InstParams& q = ctx->hp[inst];
+  q.kin_mode = mode;
+  q.kin_v0 = coeffs[0];
+  q.kin_t_ramp = coeffs[1];
+  q.kin_coef = coeffs[2];
+  ctx->pin[inst].kin_mode = mode;
+  ctx->pin[inst].kin_v0 = coeffs[0];
+  ctx->pin[inst].kin_t_ramp = coeffs[1];
+  ctx->pin[inst].kin_coef = coeffs[2];
+  HC(hipMemcpyAsync(ctx->d_prm + inst, &q, sizeof(InstParams), hipMemcpyHostToDevice, ctx->st));
+  sync(ctx);
+  API_END(ctx)
+}
+
+wcsph_status wcsph_set_dt_table(wcsph_ctx* ctx, const double* dt, int n) {
+  API_BEGIN(ctx)
+  require(n >= 0 && (n == 0 || dt != nullptr), "dt table invalid");
+  for (int k = 0; k < n; ++k) require(dt[k] > 0 && std::isfinite(dt[k]), "dt entries must be positive");
+  sync(ctx);
+  if ((size_t)n > ctx->d_dt_cap) {
+    ctx->d_dt = dalloc_n<double>(ctx, n);
+    ctx->d_dt_cap = n;
+  }
+  if (n) HC(hipMemcpy(ctx->d_dt, dt, (size_t)n * 8, hipMemcpyHostToDevice));
+  ctx->d.dt_table = ctx->d_dt;
+  ctx->d.n_dt = n;
+  ctx->d.dt_step0 = ctx->steps;
+  capture(ctx);
+  API_END(ctx)
+}
+
+wcsph_status wcsph_step(wcsph_ctx* ctx, int n_steps) {
+  API_BEGIN(ctx)
+  require(n_steps >= 0, "n_steps must be >= 0");
+  for (int k = 0; k < n_steps; ++k) {
+    HC(hipGraphLaunch(ctx->gexec, ctx->st));
+    ctx->steps++;
+    if (ctx->diag_every > 0 && ctx->steps % ctx->diag_every == 0) {
+      wc_enqueue_diag(ctx->d, ctx->b, (int)(ctx->diag_rows[0] % WC_DIAG_CAP), true, ctx->st);
+      HC(hipGetLastError());
+      for (int i = 0; i < ctx->n_inst; ++i) ctx->diag_rows[i]++;
+    }
+  }
+  API_END(ctx)
+}
+
+wcsph_status wcsph_synchronize(wcsph_ctx* ctx) {
+  API_BEGIN(ctx)
+  sync(ctx);
+  API_END(ctx)
+}
+
+wcsph_status wcsph_read_probes(wcsph_ctx* ctx, int inst, double* t, double* dt, float* p, int max_rows,
+                               int* rows_out) {
+  API_BEGIN(ctx)
+  require(inst >= 0 && inst < ctx->n_inst, "instance out of range");
+  require(max_rows >= 0 && rows_out != nullptr, "rows_out required");
+  sync(ctx);
+  long long& rd = ctx->hist_read[inst];
+  if (ctx->steps - rd > WC_HIST_CAP) rd = ctx->steps - WC_HIST_CAP;
+  const long long rows = std::min<long long>(ctx->steps - rd, max_rows);
+  const int np = ctx->hp[inst].n_probes;
+  const size_t base = (size_t)inst * WC_HIST_CAP;
+  std::vector<float> row(WC_MAX_PROBES);
+  for (long long r = 0; r < rows; ++r) {
+    const size_t k = base + (size_t)((rd + r) % WC_HIST_CAP);
+    if (t) HC(hipMemcpy(t + r, ctx->d.hist_t + k, 8, hipMemcpyDeviceToHost));
+    if (dt) HC(hipMemcpy(dt + r, ctx->d.hist_dt + k, 8, hipMemcpyDeviceToHost));
+    if (p && np) {
+      HC(hipMemcpy(row.data(), ctx->d.hist_p + k * WC_MAX_PROBES, WC_MAX_PROBES * 4, hipMemcpyDeviceToHost));
+      std::copy(row.begin(), row.begin() + np, p + r * np);
+    }
+  }
+  rd += rows;
+  *rows_out = (int)rows;
+  API_END(ctx)
+}
+
+wcsph_status wcsph_read_diagnostics(wcsph_ctx* ctx, int inst, wcsph_diag* out, int max, int* n_out) {
+  API_BEGIN(ctx)
+  require(inst >= 0 && inst < ctx->n_inst, "instance out of range");
+  require(max >= 0 && n_out != nullptr, "n_out required");
+  sync(ctx);
+  long long& rd = ctx->diag_read[inst];
+  if (ctx->diag_rows[inst] - rd > WC_DIAG_CAP) rd = ctx->diag_rows[inst] - WC_DIAG_CAP;
+  const long long rows = std::min<long long>(ctx->diag_rows[inst] - rd, max);
+  double v[WC_NDIAG];
+  for (long long r = 0; r < rows; ++r) {
+    const size_t k = ((size_t)inst * WC_DIAG_CAP + (size_t)((rd + r) % WC_DIAG_CAP)) * WC_NDIAG;
+    HC(hipMemcpy(v, ctx->d.diag + k, sizeof v, hipMemcpyDeviceToHost));
+    wcsph_diag& o = out[r];
+    o.t = v[0];
+    o.dt = v[1];
+    o.vmax = v[2];
+    o.mass = v[3];
+    o.mom[0] = v[4];
+    o.mom[1] = v[5];
+    o.ke = v[6];
+    o.e_el = v[7];
+    o.e_pot = v[8];
+    o.e_disk = v[9];
+    o.w_boundary = v[10];
+    o.step = (long long)v[11];
+    o.n_clamp = (long long)v[12];
+    o.n_cav = (long long)v[13];
+    o.n_enforce = (long long)v[14];
+  }
+  rd += rows;
+  *n_out = (int)rows;
+  Clock k;
+  HC(hipMemcpy(&k, ctx->d_clk + inst, sizeof k, hipMemcpyDeviceToHost));
+  if (k.bad) {
+    ctx->err = "non-finite value or corrupted cell list detected (flags " + std::to_string(k.bad) + ")";
+    return WCSPH_E_UNSTABLE;
+  }
+  API_END(ctx)
+}
+
+wcsph_status wcsph_get_fluid(wcsph_ctx* ctx, int inst, double* t, double* x, double* y, double* vx, double* vy,
+                             double* rho, int n) {
+  API_BEGIN(ctx)
+  require(inst >= 0 && inst < ctx->n_inst, "instance out of range");
+  const InstParams& q = ctx->hp[inst];
+  if (n < q.nf) throw WcError{WCSPH_E_RANGE, "output arrays shorter than the fluid count"};
+  sync(ctx);
+  const size_t N = ctx->n_slots;
+  auto cell = d2h(ctx, ctx->b.X.cell, N);
+  auto id = d2h(ctx, ctx->b.X.id, N);
+  auto pv = d2h(ctx, ctx->b.X.pv, N);
+  auto aux = d2h(ctx, ctx->b.X.aux, N);
+  for (size_t s = 0; s < N; ++s) {
+    const int k = (int)id[s] - q.id0;
+    if (k < 0 || k >= q.nf) continue;
+    double xx, yy;
+    decode(q, cell[s], pv[s].x, pv[s].y, xx, yy);
+    if (x) x[k] = xx;
+    if (y) y[k] = yy;
+    if (vx) vx[k] = pv[s].z;
+    if (vy) vy[k] = pv[s].w;
+    if (rho) rho[k] = aux[s].x;
+  }
+  if (t) {
+    Clock k;
+    HC(hipMemcpy(&k, ctx->d_clk + inst, sizeof k, hipMemcpyDeviceToHost));
+    *t = k.t_next;
+  }
+  API_END(ctx)
+}
+
+wcsph_status wcsph_set_fluid(wcsph_ctx* ctx, double t, const double* x, const double* y, const double* vx,
+                             const double* vy, const double* rho, int n) {
+  API_BEGIN(ctx)
+  require(ctx->n_inst == 1, "set_fluid needs a single-instance context");
+  require(x && y && vx && vy && rho, "all arrays required");
+  require(n == ctx->hp[0].nf, "n must equal the fluid count");
+  for (int k = 0; k < n; ++k)
+    require(std::isfinite(x[k]) && std::isfinite(y[k]) && std::isfinite(vx[k]) && std::isfinite(vy[k]) &&
+                rho[k] > 0,
+            "non-finite or non-positive input");
+  sync(ctx);
+  upload_state(ctx, t, x, y, vx, vy, rho);
+  if (ctx->d.n_dt > 0 && ctx->d.dt_step0 != 0) {
+    ctx->d.dt_step0 = 0;
+    capture(ctx);
+  }
+  API_END(ctx)
+}
+
+namespace {
+struct BlobHeader {
+  char magic[8];
+  long long n_inst, n_slots, n_cells, n_ghost, steps, batch;
+};
+}  // namespace
+
+wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* need) {
+  API_BEGIN(ctx)
+  const size_t N = ctx->n_slots;
+  const size_t sz = sizeof(BlobHeader) + ctx->n_inst * sizeof(Clock) + N * (4 + 4 + 16 + 16 + 4 + 2) +
+                    (size_t)ctx->n_ghost * 4 + (size_t)ctx->n_cells * 4;
+  if (need) *need = sz;
+  if (!buf) return WCSPH_OK;
+  if (cap < sz) throw WcError{WCSPH_E_RANGE, "buffer too small for the state"};
+  sync(ctx);
+  char* o = static_cast<char*>(buf);
+  BlobHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, "WCSPHST1", 8);
+  h.n_inst = ctx->n_inst;
+  h.n_slots = N;
+  h.n_cells = ctx->n_cells;
+  h.n_ghost = ctx->n_ghost;
+  h.steps = ctx->steps;
+  h.batch = ctx->batch;
+  std::memcpy(o, &h, sizeof h);
+  o += sizeof h;
+  auto put = [&](const void* dev, size_t bytes) {
+    HC(hipMemcpy(o, dev, bytes, hipMemcpyDeviceToHost));
+    o += bytes;
+  };
+  put(ctx->d_clk, ctx->n_inst * sizeof(Clock));
+  put(ctx->b.X.cell, N * 4);
+  put(ctx->b.X.id, N * 4);
+  put(ctx->b.X.pv, N * 16);
+  put(ctx->b.X.aux, N * 16);
+  put(ctx->b.X.bslot, N * 4);
+  if (ctx->batch) put(ctx->b.X.inst, N * 2);
+  else {
+    std::memset(o, 0, N * 2);
+    o += N * 2;
+  }
+  put(ctx->d.gslot, (size_t)ctx->n_ghost * 4);
+  put(ctx->d.count, (size_t)ctx->n_cells * 4);
+  API_END(ctx)
+}
+
+wcsph_status wcsph_load_state(wcsph_ctx* ctx, const void* buf, size_t n) {
+  API_BEGIN(ctx)
+  require(buf != nullptr && n >= sizeof(BlobHeader), "buffer too small");
+  BlobHeader h;
+  std::memcpy(&h, buf, sizeof h);
+  require(std::memcmp(h.magic, "WCSPHST1", 8) == 0, "not a state blob");
+  require(h.n_inst == ctx->n_inst && h.n_slots == ctx->n_slots && h.n_cells == ctx->n_cells &&
+              h.n_ghost == ctx->n_ghost && h.batch == (long long)ctx->batch,
+          "state blob does not match this context");
+  const size_t N = ctx->n_slots;
+  const size_t sz = sizeof(BlobHeader) + ctx->n_inst * sizeof(Clock) + N * (4 + 4 + 16 + 16 + 4 + 2) +
+                    (size_t)ctx->n_ghost * 4 + (size_t)ctx->n_cells * 4;
+  require(n >= sz, "state blob truncated");
+  sync(ctx);
+  const char* o = static_cast<const char*>(buf) + sizeof h;
+  auto get = [&](void* dev, size_t bytes) {
+    HC(hipMemcpy(dev, o, bytes, hipMemcpyHostToDevice));
+    o += bytes;
+  };
+  get(ctx->d_clk, ctx->n_inst * sizeof(Clock));
+  get(ctx->b.X.cell, N * 4);
+  get(ctx->b.X.id, N * 4);
+  get(ctx->b.X.pv, N * 16);
+  get(ctx->b.X.aux, N * 16);
+  get(ctx->b.X.bslot, N * 4);
+  if (ctx->batch) get(ctx->b.X.inst, N * 2);
+  else o += N * 2;
+  get(ctx->d.gslot, (size_t)ctx->n_ghost * 4);
+  get(ctx->d.count, (size_t)ctx->n_cells * 4);
+  ctx->steps = h.steps;
+  for (int i = 0; i < ctx->n_inst; ++i) {
+    ctx->hist_read[i] = ctx->steps;
+    ctx->diag_read[i] = ctx->diag_rows[i];
+  }
+  API_END(ctx)
+}
+
+wcsph_status wcsph_export_cells(wcsph_ctx* ctx, unsigned* keys, unsigned* ids_pre, double* x, double* y,
+                                unsigned* perm, unsigned* ids_post, unsigned* cell_start, size_t cap_slots,
+                                size_t cap_cells) {
+  API_BEGIN(ctx)
+  require(!ctx->batch, "single-instance contexts only");
+  if (cap_slots < (size_t)ctx->n_slots || cap_cells < (size_t)ctx->n_cells + 1)
+    throw WcError{WCSPH_E_RANGE, "output arrays too small"};
+  HookGuard guard(ctx);
+  wc_enqueue_export_sort(ctx->d, ctx->b, false, ctx->st);
+  HC(hipGetLastError());
+  sync(ctx);
+  const size_t N = ctx->n_slots;
+  auto cell = d2h(ctx, ctx->b.X.cell, N);
+  auto pv = d2h(ctx, ctx->b.X.pv, N);
+  auto idp = d2h(ctx, ctx->b.X.id, N);
+  auto pm = d2h(ctx, ctx->d.perm, N);
+  auto idq = d2h(ctx, ctx->b.Y.id, N);
+  auto cs = d2h(ctx, ctx->d.start, (size_t)ctx->n_cells + 1);
+  for (size_t s = 0; s < N; ++s) {
+    if (keys) keys[s] = cell[s];
+    if (ids_pre) ids_pre[s] = idp[s];
+    double xx, yy;
+    decode(ctx->hp[0], cell[s], pv[s].x, pv[s].y, xx, yy);
+    if (x) x[s] = xx;
+    if (y) y[s] = yy;
+    if (perm) perm[s] = pm[s];
+    if (ids_post) ids_post[s] = idq[s];
+  }
+  if (cell_start) std::copy(cs.begin(), cs.end(), cell_start);
+  guard.restore();
+  API_END(ctx)
+}
+
+wcsph_status wcsph_export_rates(wcsph_ctx* ctx, float* drho, float* ax, float* ay, float* Vx, float* Vy,
+                                float* gp, float* grho, float* gvx, float* gvy, int n_fluid, int n_ghost) {
+  API_BEGIN(ctx)
+  require(!ctx->batch, "single-instance contexts only");
+  const InstParams& q = ctx->hp[0];
+  if (n_fluid < q.nf || n_ghost < q.nw + q.nd) throw WcError{WCSPH_E_RANGE, "output arrays too small"};
+  HookGuard guard(ctx);
+  wc_enqueue_export_sort(ctx->d, ctx->b, false, ctx->st);
+  wc_enqueue_export_ghosts(ctx->d, ctx->b, ctx->n_gblk, ctx->st);
+  wc_enqueue_export_pair(ctx->d, ctx->b, ctx->st);
+  HC(hipGetLastError());
+  sync(ctx);
+  const size_t N = ctx->n_slots;
+  auto xr = d2h(ctx, ctx->d.xr, 5 * N);
+  auto id = d2h(ctx, ctx->b.Y.id, N);
+  auto pv = d2h(ctx, ctx->b.Y.pv, N);
+  auto aux = d2h(ctx, ctx->b.Y.aux, N);
+  for (size_t s = 0; s < N; ++s) {
+    const int k = (int)id[s] - q.id0;
+    if (k >= 0 && k < q.nf) {
+      if (drho) drho[k] = xr[s];
+      if (ax) ax[k] = xr[N + s];
+      if (ay) ay[k] = xr[2 * N + s];
+      if (Vx) Vx[k] = xr[3 * N + s];
+      if (Vy) Vy[k] = xr[4 * N + s];
+    } else if (k >= q.nf && k < q.nf + q.nw + q.nd) {
+      const int g = k - q.nf;
+      if (gp) gp[g] = aux[s].y * aux[s].x * aux[s].x;
+      if (grho) grho[g] = aux[s].x;
+      if (gvx) gvx[g] = pv[s].z;
+      if (gvy) gvy[g] = pv[s].w;
+    }
+  }
+  guard.restore();
+  API_END(ctx)
+}
+
+wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, long long* idsum, double* x,
+                                     double* y, size_t cap_slots) {
+  API_BEGIN(ctx)
+  require(!ctx->batch, "single-instance contexts only");
+  if (cap_slots < (size_t)ctx->n_slots) throw WcError{WCSPH_E_RANGE, "output arrays too small"};
+  HookGuard guard(ctx);
+  wc_enqueue_export_sort(ctx->d, ctx->b, false, ctx->st);
+  wc_enqueue_neigh(ctx->d, ctx->b, ctx->st);
+  HC(hipGetLastError());
+  sync(ctx);
+  const size_t N = ctx->n_slots;
+  auto id = d2h(ctx, ctx->b.Y.id, N);
+  auto cell = d2h(ctx, ctx->b.Y.cell, N);
+  auto pv = d2h(ctx, ctx->b.Y.pv, N);
+  auto nc = d2h(ctx, ctx->d.nb_count, N);
+  auto ns = d2h(ctx, ctx->d.nb_idsum, N);
+  for (size_t s = 0; s < N; ++s) {
+    if (ids) ids[s] = id[s];
+    if (count) count[s] = nc[s];
+    if (idsum) idsum[s] = ns[s];
+    double xx, yy;
+    decode(ctx->hp[0], cell[s], pv[s].x, pv[s].y, xx, yy);
+    if (x) x[s] = xx;
+    if (y) y[s] = yy;
+  }
+  guard.restore();
+  API_END(ctx)
+}
+
+wcsph_status wcsph_time_pair_kernel(wcsph_ctx* ctx, int reps, float* avg_ms) {
+  API_BEGIN(ctx)
+  require(reps >= 1 && reps <= 10000 && avg_ms != nullptr, "reps must lie in [1, 10000]");
+  HookGuard guard(ctx);
+  wc_enqueue_export_sort(ctx->d, ctx->b, ctx->batch, ctx->st);
+  if (!ctx->batch) wc_enqueue_export_ghosts(ctx->d, ctx->b, ctx->n_gblk, ctx->st);
+  HC(hipGetLastError());
+  hipEvent_t e0, e1;
+  HC(hipEventCreate(&e0));
+  HC(hipEventCreate(&e1));
+  HC(hipEventRecord(e0, ctx->st));
+  for (int r = 0; r < reps; ++r) wc_enqueue_pair_a(ctx->d, ctx->b, ctx->batch, ctx->st);
+  HC(hipEventRecord(e1, ctx->st));
+  HC(hipEventSynchronize(e1));
+  float ms = 0;
+  HC(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  guard.restore();
+  API_END(ctx)
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// wcsph_dev.h -- device-side data layout shared by the kernels and the host
+// runtime of libwcsph.so (internal; not part of the C ABI).
+//
+// Particles (fluid, wall ghosts, disk ghosts of every instance) live in one
+// slot space. Each buffer is a structure of arrays in slot order; after a
+// sort the slots are ordered by global cell key, so the particles of a cell
+// (and of an instance) are contiguous. Positions are encoded as the cell key
+// plus an FP32 offset inside the cell, so pair distances are formed from
+// cell-relative coordinates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define WC_MAX_PROBES 16
+#define WC_HIST_CAP 65536
+#define WC_DIAG_CAP 4096
+#define WC_NDIAG 15
+#define WC_BLOCK 256
+#define WC_GHOST_BLOCK 256
+
+// Per-instance constants (read-only in kernels).
+struct InstParams {
+  // grid: cell key = cell_off + cy * ncx + cx; origin (x_lo, y_lo); edge dc
+  double x_lo, y_lo, dcd;
+  float dc;
+  int ncx, ncy, cell_off, ncell;
+  // ids: [id0, id0+nf) fluid, then nw wall ghosts, then nd disk ghosts;
+  // ghost g of this instance is tracked at gslot[gmap0 + g]
+  int id0, nf, nw, nd, gmap0;
+  // pair arithmetic (FP32)
+  float h, inv_h, four_h2, sigma, fgrad, eta2h2;
+  float rho0, c0, B, p_cav, alpha, eps_xsph, gy;
+  float two_delta_h_c0, four_nu0;
+  float m_fluid, m_wall, m_disk;
+  float rho_lo, rho_hi, inv_rho0c02, c_exp, gamma, inv_gamma;
+  int ghost_rho_mode;
+  // FP64 geometry, kinematics and step control
+  double L, W, eps_wall, R, disk_x0, disk_y0, disk_mass, cfl, hd, c0d, Bd, rho0d, gammad, p_cavd;
+  double m_fluidd;  // rho0 dx^2 for the FP64 diagnostics
+  int kin_mode;
+  double kin_v0, kin_t_ramp, kin_coef;
+  // probes: encoded positions
+  int n_probes;
+  uint32_t probe_cell[WC_MAX_PROBES];
+  float probe_ox[WC_MAX_PROBES], probe_oy[WC_MAX_PROBES];
+};
+
+// Per-instance clock and accumulators (device-resident, FP64 time).
+struct Clock {
+  double t;        // time of the current step's state n
+  double t_next;   // t + dt once the step has completed (the time of the newest state)
+  double dt;       // dt of the current step
+  double t_eval;   // time of the current evaluation
+  double xd, vd, ad;  // disk centre x, velocity, acceleration at t_eval
+  double w_boundary;  // integrated work of the disk ghosts on the fluid
+  double vmax_used;   // v_max that set dt
+  long long step;     // index of the current step (-1 before the first)
+  unsigned long long n_clamp, n_enforce;
+  unsigned int vmax_bits;  // running max of |v| (float bits) for the next dt
+  unsigned int bad;        // non-finite / escaped-particle flag
+};
+
+// One particle buffer (structure of arrays in slot order).
+struct Buf {
+  uint32_t* cell;   // global cell key
+  uint32_t* id;     // global particle id
+  float4* pv;       // (ox, oy, vx, vy): offset inside the cell, velocity
+  float4* aux;      // (rho, P = p / rho^2, c, m) ; m < 0 marks a ghost
+  uint32_t* bslot;  // slot inside the cell bucket for the next sort
+  uint16_t* inst;   // instance (batched contexts only)
+};
+
+// Everything a kernel may touch (passed by value).
+struct Dev {
+  const InstParams* prm;
+  Clock* clk;
+  int n_inst, n_slots, n_cells, n_ghost;
+  uint32_t* count;            // per cell: bucket fill for the next sort
+  uint32_t* start;            // per cell + 1: exclusive scan of count
+  const uint32_t* wallcount;  // per cell: static wall ghosts (pre-fill of count)
+  uint32_t* tmp;              // per slot: bucket contents (old slots)
+  uint32_t* perm;             // per slot: perm[new] = old of the last sort
+  uint32_t* gslot;            // per ghost: current slot
+  const uint32_t* wrank;      // per ghost: static bucket rank of a wall ghost
+  const int4* gblk;           // ghost-kernel block table: (inst, first ghost, count, kind)
+  double* hist_t;             // [n_inst][WC_HIST_CAP]
+  double* hist_dt;
+  float* hist_p;              // [n_inst][WC_HIST_CAP][WC_MAX_PROBES]
+  const double* dt_table;     // fixed steps (dt_mode), n_dt entries from step dt_step0
+  int n_dt;
+  long long dt_step0;
+  double* diag;               // [n_inst][WC_DIAG_CAP][WC_NDIAG]
+  float* xr;                  // export: [5][n_slots] rates per slot
+  int* nb_count;              // export: neighbour count per slot
+  long long* nb_idsum;        // export: neighbour id sum per slot
+};
+
+enum { EV_A = 0, EV_B = 1, EV_EXPORT = 2 };

@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (FP32 GPU vs FP64 oracle): cell keys, stable permutation, cell ranges
+and in-support neighbour sets bit-exact; one evaluation's density rate,
+acceleration, XSPH velocity and ghost pressure within 1e-4 of the field's
+maximum; wall-probe histories over 200 steps within 1e-3 of each probe's
+peak; mass conserved to 1e-12.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+wc = pytest.importorskip("paper_2609_05494_amd")
+
+
+def _solver(cfg):
+    print(f"[gpu] solver L={cfg['L']} W={cfg['W']} dx={cfg['dx']} R={cfg['disk_R']}", flush=True)
+    return wc.Solver(cfg, "cuda:0")
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _shared_state(cfg, steps):
+    """Oracle state after `steps` steps, encoded by the GPU and decoded back:
+    both sides then start from exactly the values the GPU holds."""
+    o = oracle.Oracle(cfg)
+    o.step(steps)
+    t, (x, y, vx, vy, rho) = o.fluid()
+    s = _solver(cfg)
+    s.set_fluid(t, x, y, vx, vy, rho)
+    tg, f = s.fluid()
+    assert tg == t
+    o2 = oracle.Oracle(cfg)
+    o2.set_fluid(t, *f)
+    return s, o2
+
+
+# ---------------------------------------------------------------- cell list
+
+def _oracle_keys(cfg, ex):
+    """Oracle keys of the GPU's decoded positions; positions that decode onto
+    a cell face (FP64 rounding of cell * dc + offset) are moved 1e-12 m into
+    the cell the GPU holds them in."""
+    x, y = ex["x"].copy(), ex["y"].copy()
+    keys, _, _ = oracle.cell_list(cfg, x, y)
+    bad = np.nonzero(keys != ex["keys"])[0]
+    assert bad.size <= 8, bad.size
+    if bad.size:
+        ncx = int(np.ceil((cfg["L"] + 6 * cfg["dx"]) / cfg["cell_size"]))
+        gx, gy = ex["keys"][bad] % ncx, ex["keys"][bad] // ncx
+        lo = -3 * cfg["dx"]
+        for k, i in enumerate(bad):
+            fx = lo + gx[k] * cfg["cell_size"]
+            fy = lo + gy[k] * cfg["cell_size"]
+            assert min(abs(x[i] - fx), abs(x[i] - fx - cfg["cell_size"]),
+                       abs(y[i] - fy), abs(y[i] - fy - cfg["cell_size"])) < 1e-12
+            x[i] = min(max(x[i], fx + 1e-12), fx + cfg["cell_size"] - 1e-12)
+            y[i] = min(max(y[i], fy + 1e-12), fy + cfg["cell_size"] - 1e-12)
+    return x, y
+
+
+@pytest.mark.parametrize("steps", [0, 30])
+def test_cell_list_bit_exact(steps):
+    cfg = workloads.C1()
+    s = _solver(cfg)
+    s.step(steps)
+    ex = s.export_cells()
+    x, y = _oracle_keys(cfg, ex)
+    keys, perm, cs = oracle.cell_list(cfg, x, y)
+    assert np.array_equal(keys, ex["keys"].astype(np.int32))
+    assert np.array_equal(perm, ex["perm"].astype(np.int32))
+    assert np.array_equal(cs, ex["cell_start"].astype(np.int32))
+    assert np.array_equal(ex["ids_post"], ex["ids_pre"][ex["perm"]])
+    # every particle present exactly once
+    assert np.array_equal(np.sort(ex["ids_post"]), np.arange(s.n_slots))
+    s.close()
+
+
+def test_neighbour_sets_bit_exact():
+    cfg = workloads.C1()
+    s = _solver(cfg)
+    s.step(40)
+    nb = s.export_neighbours()
+    cnt, idsum, border = oracle.neighbour_stats(cfg, nb["x"], nb["y"], nb["ids"].astype(np.int32),
+                                                tol=1e-5)
+    clean = border == 0
+    assert clean.mean() > 0.99
+    assert np.array_equal(cnt[clean], nb["count"][clean])
+    assert np.array_equal(idsum[clean], nb["idsum"][clean])
+    # the GPU counts interior particles' 20 lattice neighbours at t ~ 0 too
+    s.close()
+
+
+# ---------------------------------------------------------------- one evaluation
+
+@pytest.mark.parametrize("steps", [0, 100])
+def test_one_evaluation_rates_C1(steps):
+    cfg = workloads.C1()
+    s, o = _shared_state(cfg, steps)
+    g = s.export_rates()
+    r = o.eval_rates()
+    assert _rel(g["drho"], r["drho"]) <= 1e-4
+    assert _rel(np.hypot(g["ax"] - r["ax"], g["ay"] - r["ay"]), np.hypot(r["ax"], r["ay"])) <= 1e-4
+    assert _rel(g["Vx"], r["Vx"]) <= 1e-4 and _rel(g["Vy"], r["Vy"]) <= 1e-4
+    assert _rel(g["gp"], r["gp"]) <= 1e-4
+    assert _rel(g["gvx"], r["gvx"]) <= 1e-4
+    s.close()
+
+
+def test_one_step_state_C1():
+    """One full predictor-corrector step from a shared state: density within
+    1e-4 relative per particle, positions within 1e-4 dx."""
+    cfg = workloads.C1()
+    s, o = _shared_state(cfg, 100)
+    s.step(1)
+    o.step(1)
+    _, (xg, yg, vxg, vyg, rg) = s.fluid()
+    _, (xo, yo, vxo, vyo, ro) = o.fluid()
+    assert np.abs(rg / ro - 1).max() <= 1e-4
+    assert np.abs(xg - xo).max() <= 1e-4 * cfg["dx"] and np.abs(yg - yo).max() <= 1e-4 * cfg["dx"]
+    assert _rel(np.hypot(vxg - vxo, vyg - vyo), np.hypot(vxo, vyo)) <= 1e-4
+    s.close()
+
+
+# ---------------------------------------------------------------- whole runs
+
+def test_probe_history_C1_200_steps():
+    cfg = workloads.C1()
+    s = _solver(cfg)
+    s.step(200)
+    tg, dtg, pg = s.read_probes()
+    o = oracle.Oracle(cfg)
+    o.step(200)
+    to, dto, po = o.probes()
+    assert pg.shape == po.shape == (200, 4)
+    assert np.abs(dtg / dto - 1).max() < 1e-5
+    assert np.abs(tg - to).max() < 1e-5 * to[-1]
+    for k in range(4):
+        err = np.abs(pg[:, k] - po[:, k]).max() / np.abs(po[:, k]).max()
+        print(f"probe {k}: max rel err {err:.3e} (peak {np.abs(po[:, k]).max():.4g} Pa)")
+        assert err <= 1e-3
+    d = s.read_diagnostics()
+    do = o.diags()
+    assert d["mass"].size == do["mass"].size == 21
+    assert np.abs(d["mass"] - d["mass"][0]).max() <= 1e-12 * d["mass"][0]
+    assert abs(d["mass"][0] - do["mass"][0]) <= 1e-12 * do["mass"][0]
+    for k in ("ke", "e_el", "w_boundary"):
+        assert abs(d[k][-1] - do[k][-1]) <= 1e-3 * abs(do[k][-1]), k
+    assert abs(d["momx"][-1] - do["momx"][-1]) <= 1e-3 * abs(do["momx"][-1])
+    s.close()
+
+
+def test_deterministic_and_checkpoint_roundtrip():
+    cfg = workloads.C1()
+    s = _solver(cfg)
+    s.step(20)
+    blob = s.save_state()
+    s.step(30)
+    a = s.fluid()[1]
+    s.load_state(blob)
+    s.step(30)
+    b = s.fluid()[1]
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    s2 = _solver(cfg)
+    s2.step(50)
+    c = s2.fluid()[1]
+    for u, v in zip(a, c):
+        assert np.array_equal(u, v)
+    s.close()
+    s2.close()
+
+
+# ---------------------------------------------------------------- full size
+
+def test_full_size_C2_evaluation():
+    """C2 (179,552 fluid, 185,088 particles) in the launch configuration the
+    benchmark times: one evaluation after 20 GPU steps against the oracle
+    on the same decoded state, plus the neighbour sets."""
+    cfg = workloads.C2()
+    s = _solver(cfg)
+    s.step(20)
+    t, f = s.fluid()
+    o = oracle.Oracle(cfg)
+    o.set_fluid(t, *f)
+    g = s.export_rates()
+    r = o.eval_rates()
+    assert _rel(g["drho"], r["drho"]) <= 1e-4
+    assert _rel(np.hypot(g["ax"] - r["ax"], g["ay"] - r["ay"]), np.hypot(r["ax"], r["ay"])) <= 1e-4
+    assert _rel(g["gp"], r["gp"]) <= 1e-4
+    ex = s.export_cells()
+    x, y = _oracle_keys(cfg, ex)
+    keys, perm, cs = oracle.cell_list(cfg, x, y)
+    assert np.array_equal(perm, ex["perm"].astype(np.int32))
+    assert np.array_equal(cs, ex["cell_start"].astype(np.int32))
+    d = s.read_diagnostics()
+    assert np.abs(d["mass"] - d["mass"][0]).max() <= 1e-12 * d["mass"][0]
+    s.close()
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_edge_cases_small_ragged_and_diskless():
+    cases = [
+        workloads.tiny(),                                             # a few hundred particles
+        dict(workloads.tiny(L=0.0173, W=0.0091), probes=[]),         # ragged grid, no probes
+        dict(workloads.tiny(), disk_R=0.0, n_disk_ghosts=0),          # no disk
+        dict(workloads.tiny(L=0.006, W=0.006, R=0.0029), probes=[(0.003, 0.0)]),  # disk fills most of the box
+    ]
+    for cfg in cases:
+        s = _solver(cfg)
+        s.step(15)
+        o = oracle.Oracle(cfg)
+        o.step(15)
+        _, fg = s.fluid()
+        _, fo = o.fluid()
+        assert fg[0].size == fo[0].size
+        assert np.abs(fg[4] / fo[4] - 1).max() <= 1e-4
+        assert np.abs(fg[0] - fo[0]).max() <= 1e-3 * cfg["dx"]
+        if cfg["probes"]:
+            _, _, pg = s.read_probes()
+            _, _, po = o.probes()
+            assert np.abs(pg - po).max() <= 1e-3 * max(np.abs(po).max(), 1.0)
+        s.close()
+
+
+def test_invalid_params_rejected():
+    bad = [dict(workloads.C1(), dx=-1.0), dict(workloads.C1(), h_over_dx=2.5),
+           dict(workloads.C1(), disk_x0=0.079), dict(workloads.C1(), cell_size=1e-3)]
+    for cfg in bad:
+        with pytest.raises(wc.WcsphError) as e:
+            wc.Solver(cfg, "cuda:0")
+        assert e.value.status == wc.E_INVALID
