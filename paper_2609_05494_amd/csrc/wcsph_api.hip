@@ -122,7 +122,8 @@ void validate(const wcsph_params& p) {
   require(p.rho_lo > 0 && p.rho_hi > p.rho_lo, "density band must satisfy 0 < rho_lo < rho_hi");
   require(p.eps_wall >= 0 && p.eps_wall < 0.5 * p.dx, "eps_wall must lie in [0, dx/2)");
   require(p.ghost_layers >= 1 && p.ghost_layers <= 8, "ghost_layers must lie in [1, 8]");
-  require(p.n_disk_ghosts >= 0 && p.n_disk_ghosts <= 200, "n_disk_ghosts must lie in [0, 200]");
+  require(p.n_disk_ghosts >= 0 && p.n_disk_ghosts <= WC_MAX_RING_BLOCKS * WC_GHOST_BLOCK / 4,
+          "n_disk_ghosts must lie in [0, 256]");
   require(p.ghost_rho_mode == 0 || p.ghost_rho_mode == 1, "ghost_rho_mode must be 0 or 1");
   require(p.init_mode == 0 || p.init_mode == 1, "init_mode must be 0 or 1");
   require(p.disk_R >= 0, "disk_R must be >= 0");
@@ -384,7 +385,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
     id0 += q.nf + q.nw + q.nd;
     gmap0 += q.nw + q.nd;
     cell_off += q.ncell;
-    require((long long)id0 < (1ll << 30) && (long long)cell_off < (1ll << 30), "problem too large");
+    require((long long)id0 < (1ll << 28) && (long long)cell_off < (1ll << 30), "problem too large");
     c->n_fluid += q.nf;
     c->hp.push_back(q);
     c->geo.push_back(std::move(g));
@@ -403,9 +404,10 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
       encode(q, c->geo[i].wx[k], c->geo[i].wy[k], key, ox, oy);
       c->h_wrank[q.gmap0 + k] = c->h_wallcount[key]++;
     }
-    for (int g0 = 0; g0 < q.nw; g0 += WC_GHOST_BLOCK)
-      c->h_gblk.push_back(make_int4(i, g0, std::min(WC_GHOST_BLOCK, q.nw - g0), 0));
-    c->h_gblk.push_back(make_int4(i, q.nw, q.nd, 1));
+    const int gq = WC_GHOST_BLOCK / 4;  // ghosts per block, four lanes each
+    for (int g0 = 0; g0 < q.nw; g0 += gq) c->h_gblk.push_back(make_int4(i, g0, std::min(gq, q.nw - g0), 0));
+    for (int g0 = 0; g0 < q.nd; g0 += gq) c->h_gblk.push_back(make_int4(i, q.nw + g0, std::min(gq, q.nd - g0), 1));
+    if (q.n_probes > 0) c->h_gblk.push_back(make_int4(i, 0, q.n_probes, 2));
   }
   c->n_gblk = (int)c->h_gblk.size();
   // device memory
@@ -438,6 +440,8 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.hist_dt = dalloc_n<double>(c, (size_t)n_inst * WC_HIST_CAP);
   d.hist_p = dalloc_n<float>(c, (size_t)n_inst * WC_HIST_CAP * WC_MAX_PROBES);
   d.diag = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_CAP * WC_NDIAG);
+  d.diag_part = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_BLOCKS * 8);
+  d.wb_part = dalloc_n<double>(c, (size_t)n_inst * WC_MAX_RING_BLOCKS);
   d.xr = dalloc_n<float>(c, (size_t)5 * c->n_slots);
   d.nb_count = dalloc_n<int>(c, c->n_slots);
   d.nb_idsum = dalloc_n<long long>(c, c->n_slots);
@@ -449,6 +453,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   HC(hipMemcpyAsync(wrank, c->h_wrank.data(), (size_t)c->n_ghost * 4, hipMemcpyHostToDevice, c->st));
   HC(hipMemcpyAsync(gblk, c->h_gblk.data(), (size_t)c->n_gblk * sizeof(int4), hipMemcpyHostToDevice, c->st));
   HC(hipMemsetAsync(d.hist_p, 0, (size_t)n_inst * WC_HIST_CAP * WC_MAX_PROBES * 4, c->st));
+  HC(hipMemsetAsync(d.wb_part, 0, (size_t)n_inst * WC_MAX_RING_BLOCKS * 8, c->st));
   c->hist_read.assign(n_inst, 0);
   c->diag_rows.assign(n_inst, 0);
   c->diag_read.assign(n_inst, 0);

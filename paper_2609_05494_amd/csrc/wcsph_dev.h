@@ -18,6 +18,8 @@
 #define WC_NDIAG 15
 #define WC_BLOCK 256
 #define WC_GHOST_BLOCK 256
+#define WC_MAX_RING_BLOCKS 4   // ring ghosts per instance <= 4 * WC_GHOST_BLOCK / 4
+#define WC_DIAG_BLOCKS 64      // diagnostic partial sums per instance
 
 // Per-instance constants (read-only in kernels).
 struct InstParams {
@@ -91,6 +93,8 @@ struct Dev {
   int n_dt;
   long long dt_step0;
   double* diag;               // [n_inst][WC_DIAG_CAP][WC_NDIAG]
+  double* diag_part;          // [n_inst][WC_DIAG_BLOCKS][8] partial sums
+  double* wb_part;            // [n_inst][WC_MAX_RING_BLOCKS] ring force partials
   float* xr;                  // export: [5][n_slots] rates per slot
   int* nb_count;              // export: neighbour count per slot
   long long* nb_idsum;        // export: neighbour id sum per slot

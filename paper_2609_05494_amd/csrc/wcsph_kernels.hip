@@ -147,7 +147,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Max of |v| into the instance accumulator: one atomic per wave when the
-// wave holds a single instance, else one per lane.
+// wave holds a single instance, else one per lane. The stored value only
+// grows during a kernel, so a wave whose maximum does not exceed the value
+// it reads skips the atomic (this keeps thousands of waves from
+// serialising on one address).
+__device__ __forceinline__ void vmax_atomic(unsigned int* a, float w) {
+  if (w > 0.0f && __float_as_uint(w) > __atomic_load_n(a, __ATOMIC_RELAXED)) atomicMax(a, __float_as_uint(w));
+}
 template <bool BATCH>
 __device__ __forceinline__ void vmax_update(Clock* clk, int inst, bool act, float v) {
   const float m = act ? v : 0.0f;
@@ -155,13 +161,13 @@ __device__ __forceinline__ void vmax_update(Clock* clk, int inst, bool act, floa
     const int i0 = __shfl(inst, 0);
     if (__all(inst == i0)) {
       const float w = wave_max(m);
-      if ((threadIdx.x & 63) == 0 && w > 0.0f) atomicMax(&clk[i0].vmax_bits, __float_as_uint(w));
-    } else if (act && m > 0.0f) {
-      atomicMax(&clk[inst].vmax_bits, __float_as_uint(m));
+      if ((threadIdx.x & 63) == 0) vmax_atomic(&clk[i0].vmax_bits, w);
+    } else if (act) {
+      vmax_atomic(&clk[inst].vmax_bits, m);
     }
   } else {
     const float w = wave_max(m);
-    if ((threadIdx.x & 63) == 0 && w > 0.0f) atomicMax(&clk[0].vmax_bits, __float_as_uint(w));
+    if ((threadIdx.x & 63) == 0) vmax_atomic(&clk[0].vmax_bits, w);
   }
 }
 
@@ -183,61 +189,187 @@ struct PairAcc {
   float D, ax, ay, Vx, Vy;
 };
 
-// Sum the pair law of fluid slot s over its 3x3 block of cells
-// (rows bottom to top, cells left to right, sorted order inside a cell).
+// One of the three cell rows around (cx, cy): slots [rs, re) of its (up to)
+// three cells, middle cell [ms, me).
+struct RowRange {
+  uint32_t rs, ms, me, re;
+};
+__device__ __forceinline__ RowRange row_range(const Dev& d, const InstParams& P, int cx, int cy, int dy) {
+  RowRange r = {0u, 0u, 0u, 0u};
+  const int yy = cy + dy;
+  if (yy < 0 || yy >= P.ncy) return r;
+  const int xlo = max(cx - 1, 0), xhi = min(cx + 1, P.ncx - 1);
+  const uint32_t k0 = (uint32_t)(P.cell_off + yy * P.ncx);
+  r.rs = d.start[k0 + xlo];
+  r.ms = d.start[k0 + cx];
+  r.me = d.start[k0 + cx + 1];
+  r.re = d.start[k0 + xhi + 1];
+  return r;
+}
+// cell shift code of slot j inside a row: 0 left, 1 middle, 2 right
+__device__ __forceinline__ uint32_t dx_code(uint32_t j, const RowRange& r) {
+  return j < r.ms ? 0u : (j < r.me ? 1u : 2u);
+}
+
+// Pair law of fluid particle i (state pi, rho_i, P_i = p_i/rho_i^2, c_i) with
+// neighbour j at r_ij = (rx, ry): continuity + delta diffusion, pressure + AV
+// (symmetric form), laminar (Lo-Shao), XSPH. Branch-free: a ghost neighbour
+// (m < 0) contributes nothing to the delta and XSPH terms through m_fl = 0,
+// and the AV switch is min(v_ij . r_ij, 0).
+__device__ __forceinline__ void pair_body(const InstParams& P, const float4& pi, float rhoi, float Pi,
+                                          float ci, float rx, float ry, float r2, const float4& pj,
+                                          const float4& aj, PairAcc& acc) {
+  float W, F;
+  wendland(P, r2, W, F);
+  const float vxij = pi.z - pj.z, vyij = pi.w - pj.w;
+  const float vr = vxij * rx + vyij * ry;
+  const float mj = fabsf(aj.w);
+  const float mfl = fmaxf(aj.w, 0.0f);  // m_j for fluid, 0 for ghosts
+  const float rsum = rhoi + aj.x;       // 2 rho_bar
+  const float den = r2 + P.eta2h2;      // r^2 + eta^2 h^2
+  const float inv = fast_rcp(den * rsum);
+  // Monaghan AV: -alpha c_bar mu / rho_bar = -alpha (c_i + c_j) h vr inv for vr < 0
+  const float piav = -P.alpha * P.h * (ci + aj.z) * fminf(vr, 0.0f) * inv;
+  const float mF = mj * F;
+  // continuity + delta diffusion 2 delta h c0 (m_j / rho_j)(rho_i - rho_j) F (fluid pairs)
+  acc.D += mF * vr + P.two_delta_h_c0 * mfl * fast_rcp(aj.x) * (rhoi - aj.x) * F;
+  const float sp = Pi + aj.y + piav;
+  // laminar (Lo-Shao): 4 nu0 m_j F r^2 / ((rho_i + rho_j)(r^2 + eta^2 h^2)) v_ij
+  const float lam = P.four_nu0 * mF * r2 * inv;
+  acc.ax += lam * vxij - mF * sp * rx;
+  acc.ay += lam * vyij - mF * sp * ry;
+  // XSPH eps (m_j / rho_bar) W (v_j - v_i) over fluid; 1 / rho_bar = 2 den inv
+  const float w = P.eps_xsph * mfl * 2.0f * den * inv * W;
+  acc.Vx -= w * vxij;
+  acc.Vy -= w * vyij;
+}
+
+#define PAIR_BLOCK 128
+#define GLIST_CAP 16
+#define SCAN_UNROLL 4
+
+// Sum the pair law of fluid slot s over its 3x3 block of cells with four
+// lanes (quad lane q). The candidates, rows bottom to top and cells left to
+// right in sorted order, are dealt round-robin to the four lanes; each lane
+// scans its share (SCAN_UNROLL loads in flight), writes the in-support
+// neighbours (slot and cell shift) to a lane-private list in LDS, then sums
+// the pair law over its list while fetching the next neighbour. The quad's
+// partial sums are combined in a fixed order by the caller.
 __device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, const Buf& sb, int s,
-                                          uint32_t K, float4 pi, float4 ai, PairAcc& acc) {
+                                          uint32_t K, float4 pi, float4 ai, int q, uint32_t* my,
+                                          PairAcc& acc) {
   const float rhoi = ai.x, Pi = ai.y, ci = ai.z;
   int cx, cy;
   cell_xy(P, K, cx, cy);
-  for (int dy = -1; dy <= 1; ++dy) {
-    const int yy = cy + dy;
-    if (yy < 0 || yy >= P.ncy) continue;
-    const float shy = (float)dy * P.dc;
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int xx = cx + dx;
-      if (xx < 0 || xx >= P.ncx) continue;
-      const float shx = (float)dx * P.dc;
-      const uint32_t K2 = (uint32_t)(P.cell_off + yy * P.ncx + xx);
-      const uint32_t j0 = d.start[K2], j1 = d.start[K2 + 1];
-      for (uint32_t j = j0; j < j1; ++j) {
-        const float4 pj = sb.pv[j];
-        const float rx = (pi.x - pj.x) - shx;  // r_i - r_j
-        const float ry = (pi.y - pj.y) - shy;
-        const float r2 = rx * rx + ry * ry;
-        if (!(r2 < P.four_h2) || j == (uint32_t)s) continue;
-        const float4 aj = sb.aux[j];
-        float W, F;
-        wendland(P, r2, W, F);
-        const float vxij = pi.z - pj.z, vyij = pi.w - pj.w;
-        const float vr = vxij * rx + vyij * ry;
-        const bool fl = aj.w > 0.0f;
-        const float mj = fabsf(aj.w);
-        const float rsum = rhoi + aj.x;       // 2 rho_bar
-        const float den = r2 + P.eta2h2;      // r^2 + eta^2 h^2
-        const float inv = fast_rcp(den * rsum);
-        // Monaghan AV: -alpha c_bar mu / rho_bar = -alpha (c_i + c_j) h vr inv
-        const float piav = vr < 0.0f ? -P.alpha * (ci + aj.z) * P.h * vr * inv : 0.0f;
-        const float mF = mj * F;
-        acc.D += mF * vr;
-        const float sp = Pi + aj.y + piav;
-        acc.ax -= mF * sp * rx;
-        acc.ay -= mF * sp * ry;
-        // laminar (Lo-Shao): 4 nu0 m_j F r^2 / ((rho_i + rho_j)(r^2 + eta^2 h^2)) v_ij
-        const float lam = P.four_nu0 * mF * r2 * inv;
-        acc.ax += lam * vxij;
-        acc.ay += lam * vyij;
-        if (fl) {
-          // delta diffusion 2 delta h c0 (m_j / rho_j)(rho_i - rho_j) F
-          acc.D += P.two_delta_h_c0 * mj * fast_rcp(aj.x) * (rhoi - aj.x) * F;
-          // XSPH eps (m_j / rho_bar) W (v_j - v_i); 1 / rho_bar = 2 den inv
-          const float w = P.eps_xsph * mj * 2.0f * den * inv * W;
-          acc.Vx -= w * vxij;
-          acc.Vy -= w * vyij;
-        }
+  const RowRange r0 = row_range(d, P, cx, cy, -1), r1 = row_range(d, P, cx, cy, 0),
+                 r2 = row_range(d, P, cx, cy, 1);
+  const uint32_t n0 = r0.re - r0.rs, n01 = n0 + (r1.re - r1.rs), n = n01 + (r2.re - r2.rs);
+  int cnt = 0;
+  auto flush = [&]() {
+    if (cnt == 0) return;
+    uint32_t e = my[0];
+    float4 pj = sb.pv[e >> 4];
+    float4 aj = sb.aux[e >> 4];
+    for (int k = 0; k < cnt; ++k) {
+      const uint32_t ec = e;
+      const float4 pc = pj, ac = aj;
+      if (k + 1 < cnt) {
+        e = my[(k + 1) * PAIR_BLOCK];
+        pj = sb.pv[e >> 4];
+        aj = sb.aux[e >> 4];
+      }
+      const float shx = (float)((int)(ec & 3u) - 1) * P.dc;
+      const float shy = (float)((int)((ec >> 2) & 3u) - 1) * P.dc;
+      const float rx = (pi.x - pc.x) - shx;
+      const float ry = (pi.y - pc.y) - shy;
+      pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pc, ac, acc);
+    }
+    cnt = 0;
+  };
+  for (uint32_t c0 = (uint32_t)q; c0 < n; c0 += 4 * SCAN_UNROLL) {
+    uint32_t jj[SCAN_UNROLL], code[SCAN_UNROLL];
+    float2 pp[SCAN_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SCAN_UNROLL; ++u) {
+      const uint32_t c = min(c0 + 4 * u, n - 1);
+      const uint32_t row = c < n0 ? 0u : (c < n01 ? 1u : 2u);
+      const RowRange& r = row == 0 ? r0 : (row == 1 ? r1 : r2);
+      const uint32_t j = r.rs + c - (row == 0 ? 0u : (row == 1 ? n0 : n01));
+      jj[u] = j;
+      code[u] = (row << 2) | dx_code(j, r);
+      const float4 t = sb.pv[j];
+      pp[u] = make_float2(t.x, t.y);
+    }
+#pragma unroll
+    for (int u = 0; u < SCAN_UNROLL; ++u) {
+      const float rx = (pi.x - pp[u].x) - ((float)(int)(code[u] & 3u) - 1.0f) * P.dc;
+      const float ry = (pi.y - pp[u].y) - ((float)(int)(code[u] >> 2) - 1.0f) * P.dc;
+      if (c0 + 4 * u < n && rx * rx + ry * ry < P.four_h2 && jj[u] != (uint32_t)s) {
+        my[cnt * PAIR_BLOCK] = (jj[u] << 4) | code[u];
+        ++cnt;
       }
     }
+    if (cnt > GLIST_CAP - SCAN_UNROLL) flush();
   }
+  flush();
+}
+
+// Shepard sums over the fluid around an encoded point (cell K, offset o),
+// restricted to one cell row (dy); four lanes cover a point (rows -1, 0, 1
+// and an idle lane) and their sums are added in a fixed order.
+struct Shep {
+  float W, p, rx, ry, vx, vy;
+};
+__device__ __forceinline__ Shep shepard_row(const Dev& d, const InstParams& P, const Buf& sb, uint32_t K,
+                                            float ox, float oy, int q) {
+  Shep S = {0, 0, 0, 0, 0, 0};
+  if (q > 2) return S;
+  int cx, cy;
+  cell_xy(P, K, cx, cy);
+  const RowRange r = row_range(d, P, cx, cy, q - 1);
+  const float shy = (float)(q - 1) * P.dc;
+  for (uint32_t j0 = r.rs; j0 < r.re; j0 += SCAN_UNROLL) {
+    float4 pq[SCAN_UNROLL], aq[SCAN_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SCAN_UNROLL; ++u) {
+      const uint32_t j = min(j0 + u, r.re - 1);
+      pq[u] = sb.pv[j];
+      aq[u] = sb.aux[j];
+    }
+#pragma unroll
+    for (int u = 0; u < SCAN_UNROLL; ++u) {
+      const uint32_t j = j0 + u;
+      const float4 pj = pq[u], aj = aq[u];
+      const float rx = (ox - pj.x) - ((float)dx_code(j, r) - 1.0f) * P.dc;  // r_g - r_j
+      const float ry = (oy - pj.y) - shy;
+      const float r2 = rx * rx + ry * ry;
+      if (!(j < r.re) || !(aj.w > 0.0f) || !(r2 < P.four_h2)) continue;  // fluid in support
+      float W, F;
+      wendland(P, r2, W, F);
+      const float pj_ = aj.y * aj.x * aj.x;  // p = P rho^2
+      S.W += W;
+      S.p += pj_ * W;
+      S.rx += aj.x * rx * W;
+      S.ry += aj.x * ry * W;
+      S.vx += pj.z * W;
+      S.vy += pj.w * W;
+    }
+  }
+  return S;
+}
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  return v;
+}
+__device__ __forceinline__ Shep quad_sum(Shep S) {
+  S.W = quad_sum(S.W);
+  S.p = quad_sum(S.p);
+  S.rx = quad_sum(S.rx);
+  S.ry = quad_sum(S.ry);
+  S.vx = quad_sum(S.vx);
+  S.vy = quad_sum(S.vy);
+  return S;
 }
 
 }  // namespace
@@ -295,34 +427,56 @@ __global__ __launch_bounds__(256) void k_kin(Dev d, Buf pre) {
 }
 
 // Exclusive scan of count -> start over all cells; count is re-armed with the
-// static wall-ghost occupancy for the next sort. One block.
+// static wall-ghost occupancy for the next sort. One block walks the cells in
+// tiles of 4096 (four consecutive cells per thread, coalesced uint4 loads).
 __global__ __launch_bounds__(1024) void k_scan(Dev d) {
   __shared__ uint32_t wsum[16];
   const int n = d.n_cells;
-  const int t = threadIdx.x;
-  const int chunk = (n + 1023) / 1024;
-  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
-  uint32_t s = 0;
-  for (int c = lo; c < hi; ++c) s += d.count[c];
-  // inclusive scan of per-thread sums: wave level then across waves
-  uint32_t incl = s;
-  const int lane = t & 63, wv = t >> 6;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t u = __shfl_up(incl, o);
-    if (lane >= o) incl += u;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  uint32_t carry = 0;
+  for (int base = 0; base < n; base += 4096) {
+    const int i0 = base + 4 * t;
+    uint32_t a[4];
+    if (i0 + 3 < n) {
+      const uint4 v = *reinterpret_cast<const uint4*>(d.count + i0);
+      a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+    } else {
+      for (int k = 0; k < 4; ++k) a[k] = (i0 + k < n) ? d.count[i0 + k] : 0u;
+    }
+    const uint32_t s = a[0] + a[1] + a[2] + a[3];
+    uint32_t incl = s;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t u = __shfl_up(incl, o);
+      if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t woff = 0, tile = 0;
+    for (int w = 0; w < 16; ++w) {
+      const uint32_t x = wsum[w];
+      woff += (w < wv) ? x : 0u;
+      tile += x;
+    }
+    uint32_t run = carry + woff + incl - s;
+    uint32_t o4[4];
+    for (int k = 0; k < 4; ++k) {
+      o4[k] = run;
+      run += a[k];
+    }
+    if (i0 + 3 < n) {
+      *reinterpret_cast<uint4*>(d.start + i0) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+      *reinterpret_cast<uint4*>(d.count + i0) = *reinterpret_cast<const uint4*>(d.wallcount + i0);
+    } else {
+      for (int k = 0; k < 4; ++k)
+        if (i0 + k < n) {
+          d.start[i0 + k] = o4[k];
+          d.count[i0 + k] = d.wallcount[i0 + k];
+        }
+    }
+    carry += tile;
+    __syncthreads();
   }
-  if (lane == 63) wsum[wv] = incl;
-  __syncthreads();
-  uint32_t base = 0;
-  for (int w = 0; w < wv; ++w) base += wsum[w];
-  uint32_t run = base + incl - s;
-  for (int c = lo; c < hi; ++c) {
-    const uint32_t v = d.count[c];
-    d.start[c] = run;
-    run += v;
-    d.count[c] = d.wallcount[c];
-  }
-  if (t == 1023) d.start[n] = base + incl;
+  if (t == 0) d.start[n] = carry;
 }
 
 // Every slot into its bucket: tmp[start[key] + bucket slot] = slot.
@@ -344,8 +498,10 @@ __global__ __launch_bounds__(WC_BLOCK) void k_scatter(Dev d, Buf pre) {
 // Stable rank inside the bucket and gather into sorted order. In eval B the
 // state at time n (pre2, same slot order as pre) is permuted alongside.
 template <int MODE, bool BATCH>
-__global__ __launch_bounds__(WC_BLOCK) void k_permute(Dev d, Buf pre, Buf out, Buf pre2, Buf out2) {
-  const int p = blockIdx.x * WC_BLOCK + threadIdx.x;
+__global__ __launch_bounds__(128) void k_permute(Dev d, Buf pre, Buf out, Buf pre2, Buf out2) {
+  // same slot -> XCD mapping as k_pair, so the sorted buffer is written into
+  // the L2 of the XCD that reads it next
+  const int p = xcd_block(blockIdx.x, gridDim.x) * 128 + threadIdx.x;
   if (p >= d.n_slots) return;
   const uint32_t e = d.tmp[p];
   if (e >= (uint32_t)d.n_slots) {
@@ -388,68 +544,39 @@ __global__ __launch_bounds__(WC_BLOCK) void k_permute(Dev d, Buf pre, Buf out, B
   }
 }
 
-// Shepard sums over the fluid around an encoded point (cell K, offset o).
-struct Shep {
-  float W, p, rx, ry, vx, vy;
-};
-__device__ __forceinline__ Shep shepard(const Dev& d, const InstParams& P, const Buf& sb, uint32_t K,
-                                        float ox, float oy) {
-  Shep S = {0, 0, 0, 0, 0, 0};
-  int cx, cy;
-  cell_xy(P, K, cx, cy);
-  for (int dy = -1; dy <= 1; ++dy) {
-    const int yy = cy + dy;
-    if (yy < 0 || yy >= P.ncy) continue;
-    const float shy = (float)dy * P.dc;
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int xx = cx + dx;
-      if (xx < 0 || xx >= P.ncx) continue;
-      const float shx = (float)dx * P.dc;
-      const uint32_t K2 = (uint32_t)(P.cell_off + yy * P.ncx + xx);
-      const uint32_t j0 = d.start[K2], j1 = d.start[K2 + 1];
-      for (uint32_t j = j0; j < j1; ++j) {
-        const float4 aj = sb.aux[j];
-        if (!(aj.w > 0.0f)) continue;  // fluid only
-        const float4 pj = sb.pv[j];
-        const float rx = (ox - pj.x) - shx;  // r_g - r_j
-        const float ry = (oy - pj.y) - shy;
-        const float r2 = rx * rx + ry * ry;
-        if (!(r2 < P.four_h2)) continue;
-        float W, F;
-        wendland(P, r2, W, F);
-        const float pj_ = aj.y * aj.x * aj.x;  // p = P rho^2
-        S.W += W;
-        S.p += pj_ * W;
-        S.rx += aj.x * rx * W;
-        S.ry += aj.x * ry * W;
-        S.vx += pj.z * W;
-        S.vy += pj.w * W;
-      }
-    }
-  }
-  return S;
-}
-
 // Adami ghost state (walls and ring), probes, ghost v_max and ring work.
-// Block table entry: (instance, first ghost, ghost count, kind); kind 1 is
-// the instance's ring + probe block.
+// Four lanes per ghost or probe, one cell row each. Block table entry:
+// (instance, first item, item count, kind); kind 0 wall ghosts, 1 ring
+// ghosts (work partial (first - nw) / GQ), 2 probes.
+#define GQ (WC_GHOST_BLOCK / 4)
 template <int MODE, bool BATCH>
 __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
   const int4 blk = d.gblk[blockIdx.x];
-  const int inst = blk.x;
+  const int inst = blk.x, kind = blk.w;
   const InstParams& P = d.prm[inst];
   Clock& C = d.clk[inst];
-  const int t = threadIdx.x;
-  const bool is_ghost = t < blk.z;
-  const int g = blk.y + t;
-  const bool disk = blk.w == 1;
-  float vmag = 0.0f;
-  float fx = 0.0f;
-  if (is_ghost) {
+  const int t = threadIdx.x, qd = t >> 2, q = t & 3;
+  const bool act = qd < blk.z;
+  if (kind == 2) {
+    // probes: Shepard average of the fluid pressure at fixed wall points
+    if (MODE == EV_A && act) {
+      const int k = blk.y + qd;
+      const Shep S = quad_sum(shepard_row(d, P, sb, P.probe_cell[k], P.probe_ox[k], P.probe_oy[k], q));
+      if (q == 0) {
+        const long long row = (long long)inst * WC_HIST_CAP + (C.step % WC_HIST_CAP);
+        d.hist_p[row * WC_MAX_PROBES + k] = S.W > 0.0f ? S.p / S.W : 0.0f;
+      }
+    }
+    return;
+  }
+  const bool disk = kind == 1;
+  float vmag = 0.0f, fx = 0.0f;
+  if (act) {
+    const int g = blk.y + qd;
     const uint32_t s = d.gslot[P.gmap0 + g];
     const uint32_t K = sb.cell[s];
     const float4 pg = sb.pv[s];
-    const Shep S = shepard(d, P, sb, K, pg.x, pg.y);
+    const Shep S = quad_sum(shepard_row(d, P, sb, K, pg.x, pg.y, q));
     const float vwx = disk ? (float)C.vd : 0.0f;
     const float awx = disk ? (float)C.ad : 0.0f;
     float p, vgx, vgy;
@@ -471,53 +598,44 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
     const float Pg = p / (rg * rg);
     const float cg = P.c0 * expf(P.c_exp * log1pf((rg - P.rho0) / P.rho0));
     const float m = disk ? P.m_disk : P.m_wall;
-    sb.pv[s] = make_float4(pg.x, pg.y, vgx, vgy);
-    sb.aux[s] = make_float4(rg, Pg, cg, -m);
-    vmag = fast_sqrt(vgx * vgx + vgy * vgy);
+    if (q == 0) {
+      sb.pv[s] = make_float4(pg.x, pg.y, vgx, vgy);
+      sb.aux[s] = make_float4(rg, Pg, cg, -m);
+      vmag = fast_sqrt(vgx * vgx + vgy * vgy);
+    }
     if (MODE == EV_B && disk) {
       // x force of this ring ghost on its fluid neighbours (pressure + AV)
-      int cx, cy;
-      cell_xy(P, K, cx, cy);
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int yy = cy + dy;
-        if (yy < 0 || yy >= P.ncy) continue;
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int xx = cx + dx;
-          if (xx < 0 || xx >= P.ncx) continue;
-          const uint32_t K2 = (uint32_t)(P.cell_off + yy * P.ncx + xx);
-          for (uint32_t j = d.start[K2]; j < d.start[K2 + 1]; ++j) {
-            const float4 aj = sb.aux[j];
-            if (!(aj.w > 0.0f)) continue;
-            const float4 pj = sb.pv[j];
-            const float rx = (pj.x + (float)dx * P.dc) - pg.x;  // r_i - r_g
-            const float ry = (pj.y + (float)dy * P.dc) - pg.y;
-            const float r2 = rx * rx + ry * ry;
-            if (!(r2 < P.four_h2)) continue;
-            float W, F;
-            wendland(P, r2, W, F);
-            const float vr = (pj.z - vgx) * rx + (pj.w - vgy) * ry;
-            const float rsum = aj.x + rg, den = r2 + P.eta2h2;
-            const float inv = fast_rcp(den * rsum);
-            const float piav = vr < 0.0f ? -P.alpha * (aj.z + cg) * P.h * vr * inv : 0.0f;
-            fx -= aj.w * m * (aj.y + Pg + piav) * F * rx;
-          }
+      if (q < 3) {
+        int cx, cy;
+        cell_xy(P, K, cx, cy);
+        const RowRange r = row_range(d, P, cx, cy, q - 1);
+        const float shy = (float)(q - 1) * P.dc;
+        for (uint32_t j = r.rs; j < r.re; ++j) {
+          const float4 aj = sb.aux[j];
+          const float4 pj = sb.pv[j];
+          if (!(aj.w > 0.0f)) continue;
+          const float rx = (pj.x - pg.x) + ((float)dx_code(j, r) - 1.0f) * P.dc;  // r_i - r_g
+          const float ry = (pj.y - pg.y) + shy;
+          const float r2 = rx * rx + ry * ry;
+          if (!(r2 < P.four_h2)) continue;
+          float W, F;
+          wendland(P, r2, W, F);
+          const float vr = (pj.z - vgx) * rx + (pj.w - vgy) * ry;
+          const float rsum = aj.x + rg, den = r2 + P.eta2h2;
+          const float inv = fast_rcp(den * rsum);
+          const float piav = vr < 0.0f ? -P.alpha * (aj.z + cg) * P.h * vr * inv : 0.0f;
+          fx -= aj.w * m * (aj.y + Pg + piav) * F * rx;
         }
       }
+      fx = quad_sum(fx);
+      if (q != 0) fx = 0.0f;
     }
   }
   if (MODE == EV_A) {
     if constexpr (BATCH) {
-      if (is_ghost && vmag > 0.0f) atomicMax(&C.vmax_bits, __float_as_uint(vmag));
+      vmax_atomic(&C.vmax_bits, vmag);
     } else {
-      vmax_update<false>(d.clk, 0, is_ghost, vmag);
-    }
-    // probes: Shepard average of the fluid pressure at fixed wall points
-    if (disk && t >= blk.z && t < blk.z + P.n_probes) {
-      const int k = t - blk.z;
-      const Shep S = shepard(d, P, sb, P.probe_cell[k], P.probe_ox[k], P.probe_oy[k]);
-      const float pk = S.W > 0.0f ? S.p / S.W : 0.0f;
-      const long long row = (long long)inst * WC_HIST_CAP + (C.step % WC_HIST_CAP);
-      d.hist_p[row * WC_MAX_PROBES + k] = pk;
+      vmax_update<false>(d.clk, 0, act, vmag);
     }
   }
   if (MODE == EV_B && disk) {
@@ -529,7 +647,7 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
     if (t == 0) {
       double f = 0.0;
       for (int w = 0; w < WC_GHOST_BLOCK / 64; ++w) f += ws[w];
-      C.w_boundary += C.dt * f * C.vd;
+      d.wb_part[inst * WC_MAX_RING_BLOCKS + (blk.y - P.nw) / GQ] = f;
     }
   }
 }
@@ -537,8 +655,11 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
 // Pair sums + predictor (eval A) / corrector (eval B) for every fluid slot;
 // ghost slots are carried into the output buffer. EV_EXPORT writes the rates.
 template <int MODE, bool BATCH>
-__global__ __launch_bounds__(WC_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
-  const int s = xcd_block(blockIdx.x, gridDim.x) * WC_BLOCK + threadIdx.x;
+__global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
+  __shared__ uint32_t lst[GLIST_CAP * PAIR_BLOCK];
+  // four lanes per slot; blocks map to XCDs in contiguous slot ranges
+  const int q = threadIdx.x & 3;
+  const int s = xcd_block(blockIdx.x, gridDim.x) * (PAIR_BLOCK / 4) + (threadIdx.x >> 2);
   const bool inr = s < d.n_slots;
   const int inst = inr ? inst_at<BATCH>(sb, s) : 0;
   const InstParams& P = d.prm[inst];
@@ -552,7 +673,7 @@ __global__ __launch_bounds__(WC_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Buf 
     ai = sb.aux[s];
   }
   const bool fluid = inr && ai.w > 0.0f;
-  if (MODE == EV_A && inr && !fluid) {
+  if (MODE == EV_A && inr && !fluid && q == 0) {
     out.cell[s] = K;
     out.id[s] = sb.id[s];
     out.pv[s] = pi;
@@ -560,9 +681,16 @@ __global__ __launch_bounds__(WC_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Buf 
     if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
   }
   PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  if (fluid) pair_sums(d, P, sb, s, K, pi, ai, acc);
+  if (fluid) pair_sums(d, P, sb, s, K, pi, ai, q, lst + threadIdx.x, acc);
+  // fixed-order combination of the quad's partial sums: (l0 + l1) + (l2 + l3)
+  acc.D = quad_sum(acc.D);
+  acc.ax = quad_sum(acc.ax);
+  acc.ay = quad_sum(acc.ay);
+  acc.Vx = quad_sum(acc.Vx);
+  acc.Vy = quad_sum(acc.Vy);
+  const bool lead = fluid && q == 0;
   if (MODE == EV_EXPORT) {
-    if (fluid) {
+    if (lead) {
       d.xr[s] = acc.D;
       d.xr[d.n_slots + s] = acc.ax;
       d.xr[2 * d.n_slots + s] = acc.ay + P.gy;
@@ -573,7 +701,7 @@ __global__ __launch_bounds__(WC_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Buf 
   }
   bool clamp_hit = false, enf_hit = false;
   float vnew = 0.0f;
-  if (fluid) {
+  if (lead) {
     const double dt = MODE == EV_A ? step_dt(d, P, C) : C.dt;
     const float hdt = (float)(MODE == EV_A ? 0.5 * dt : dt);
     const double te = C.t + (MODE == EV_A ? 0.5 * dt : dt);
@@ -652,10 +780,16 @@ __global__ __launch_bounds__(WC_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Buf 
   }
   count_hits<BATCH>(clk, inst, clamp_hit, enf_hit);
   if (MODE == EV_B) {
-    vmax_update<BATCH>(clk, inst, fluid, vnew);
-    if (blockIdx.x == 0 && threadIdx.x < d.n_inst) {
-      Clock& Ci = clk[threadIdx.x];
-      Ci.t_next = Ci.t + Ci.dt;
+    vmax_update<BATCH>(clk, inst, lead, vnew);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      for (int i = 0; i < d.n_inst; ++i) {
+        Clock& Ci = clk[i];
+        const InstParams& Pi = d.prm[i];
+        double f = 0.0;
+        for (int k = 0; k * GQ < Pi.nd; ++k) f += d.wb_part[i * WC_MAX_RING_BLOCKS + k];
+        Ci.w_boundary += Ci.dt * f * Ci.vd;
+        Ci.t_next = Ci.t + Ci.dt;
+      }
     }
   }
 }
@@ -681,11 +815,11 @@ __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
   vmax_update<BATCH>(d.clk, inst, fl, v);
 }
 
-// FP64 diagnostics of every instance; one block per instance, fixed order.
-__global__ __launch_bounds__(1024) void k_diag(Dev d, Buf X, int row, int sorted) {
-  const int i = blockIdx.x;
+// FP64 diagnostics: partial sums over fixed chunks of each instance's slots
+// (grid: WC_DIAG_BLOCKS x n_inst), then one fixed-order pass per instance.
+__global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
+  const int i = blockIdx.y, b = blockIdx.x;
   const InstParams& P = d.prm[i];
-  Clock& C = d.clk[i];
   int lo, hi;
   if (sorted) {
     lo = (int)d.start[P.cell_off];
@@ -694,15 +828,14 @@ __global__ __launch_bounds__(1024) void k_diag(Dev d, Buf X, int row, int sorted
     lo = P.id0;
     hi = P.id0 + P.nf + P.nw + P.nd;
   }
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // M, Px, Py, KE, Eel, Epot, ncav, bad
-  const double g = P.gammad, r0 = P.rho0d, B = P.Bd;
+  const int chunk = (hi - lo + WC_DIAG_BLOCKS - 1) / WC_DIAG_BLOCKS;
+  const int a = lo + b * chunk, e = min(hi, a + chunk);
+  const double g = P.gammad, r0 = P.rho0d, B = P.Bd, m = P.m_fluidd;
   const double rc = r0 * pow(1.0 + P.p_cavd / B, 1.0 / g);
-  auto e_tait = [&](double q) {
-    return B * ((pow(q, g - 1.0) - pow(r0, g - 1.0)) / ((g - 1.0) * pow(r0, g)) + 1.0 / q - 1.0 / r0);
-  };
-  const double erc = e_tait(rc);
-  const double m = P.m_fluidd;
-  for (int s = lo + (int)threadIdx.x; s < hi; s += 1024) {
+  const double k1 = B / ((g - 1.0) * pow(r0, g)), r0g1 = pow(r0, g - 1.0);
+  const double erc = B * ((pow(rc, g - 1.0) - r0g1) / ((g - 1.0) * pow(r0, g)) + 1.0 / rc - 1.0 / r0);
+  double M = 0, px = 0, py = 0, ke = 0, eel = 0, epot = 0, ncav = 0, bad = 0;
+  for (int s = a + (int)threadIdx.x; s < e; s += 256) {
     const int local = (int)X.id[s] - P.id0;
     if (local < 0 || local >= P.nf) continue;
     const float4 pv = X.pv[s];
@@ -711,45 +844,58 @@ __global__ __launch_bounds__(1024) void k_diag(Dev d, Buf X, int row, int sorted
     cell_xy(P, X.cell[s], cx, cy);
     const double y = P.y_lo + (double)cy * P.dcd + (double)pv.y;
     const double u = pv.z, w = pv.w;
-    acc[0] += m;
-    acc[1] += m * u;
-    acc[2] += m * w;
-    acc[3] += 0.5 * m * (u * u + w * w);
-    acc[4] += m * (r >= rc ? e_tait(r) : erc + P.p_cavd * (1.0 / rc - 1.0 / r));
-    acc[5] += m * (-(double)P.gy) * y;
-    acc[6] += (B * (pow(r / r0, g) - 1.0) <= P.p_cavd) ? 1.0 : 0.0;
-    if (!(r == r) || !(fabs(u) < 1e30) || !(fabs(w) < 1e30)) acc[7] += 1.0;
+    M += m;
+    px += m * u;
+    py += m * w;
+    ke += 0.5 * m * (u * u + w * w);
+    const double rg1 = pow(r, g - 1.0);
+    // specific elastic energy of the Tait law, cutoff branch below rho_c
+    eel += m * (r >= rc ? k1 * (rg1 - r0g1) + B * (1.0 / r - 1.0 / r0) : erc + P.p_cavd * (1.0 / rc - 1.0 / r));
+    epot += m * (-(double)P.gy) * y;
+    ncav += (B * (rg1 * r / pow(r0, g) - 1.0) <= P.p_cavd) ? 1.0 : 0.0;
+    if (!(r == r) || !(fabs(u) < 1e30) || !(fabs(w) < 1e30)) bad += 1.0;
   }
-  __shared__ double ws[16][8];
+  const double v[8] = {M, px, py, ke, eel, epot, ncav, bad};
+  __shared__ double ws[4][8];
+#pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const double v = wave_sum(acc[k]);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6][k] = v;
+    const double x = wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6][k] = x;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int w = 0; w < 16; ++w)
-      for (int k = 0; k < 8; ++k) tot[k] += ws[w][k];
-    double xd, vd, ad;
-    kinematics(P, C.t_next, xd, vd, ad);
-    double* o = d.diag + ((long long)i * WC_DIAG_CAP + (row % WC_DIAG_CAP)) * WC_NDIAG;
-    o[0] = C.t_next;
-    o[1] = C.step >= 0 ? C.dt : 0.0;
-    o[2] = C.step >= 0 ? C.vmax_used : 0.0;
-    o[3] = tot[0];
-    o[4] = tot[1];
-    o[5] = tot[2];
-    o[6] = tot[3];
-    o[7] = tot[4];
-    o[8] = tot[5];
-    o[9] = 0.5 * P.disk_mass * vd * vd;
-    o[10] = C.w_boundary;
-    o[11] = (double)(C.step + 1);
-    o[12] = (double)C.n_clamp;
-    o[13] = tot[6];
-    o[14] = (double)C.n_enforce;
-    if (tot[7] > 0.0 || !(tot[3] == tot[3])) C.bad |= 1u;
+  if (threadIdx.x < 8) {
+    const int k = threadIdx.x;
+    d.diag_part[((long long)i * WC_DIAG_BLOCKS + b) * 8 + k] = ((ws[0][k] + ws[1][k]) + ws[2][k]) + ws[3][k];
   }
+}
+
+__global__ __launch_bounds__(64) void k_diag_final(Dev d, int row) {
+  const int i = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const InstParams& P = d.prm[i];
+  Clock& C = d.clk[i];
+  double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < WC_DIAG_BLOCKS; ++b)
+    for (int k = 0; k < 8; ++k) tot[k] += d.diag_part[((long long)i * WC_DIAG_BLOCKS + b) * 8 + k];
+  double xd, vd, ad;
+  kinematics(P, C.t_next, xd, vd, ad);
+  double* o = d.diag + ((long long)i * WC_DIAG_CAP + (row % WC_DIAG_CAP)) * WC_NDIAG;
+  o[0] = C.t_next;
+  o[1] = C.step >= 0 ? C.dt : 0.0;
+  o[2] = C.step >= 0 ? C.vmax_used : 0.0;
+  o[3] = tot[0];
+  o[4] = tot[1];
+  o[5] = tot[2];
+  o[6] = tot[3];
+  o[7] = tot[4];
+  o[8] = tot[5];
+  o[9] = 0.5 * P.disk_mass * vd * vd;
+  o[10] = C.w_boundary;
+  o[11] = (double)(C.step + 1);
+  o[12] = (double)C.n_clamp;
+  o[13] = tot[6];
+  o[14] = (double)C.n_enforce;
+  if (tot[7] > 0.0 || !(tot[3] == tot[3])) C.bad |= 1u;
 }
 
 // Test hook: in-support neighbour count and id sum per sorted slot.
@@ -790,6 +936,8 @@ __global__ __launch_bounds__(WC_BLOCK) void k_neigh(Dev d, Buf sb) {
 // Launch wrappers (host side of this translation unit).
 
 #define NB(n) (((n) + WC_BLOCK - 1) / WC_BLOCK)
+#define NP(n) (((n) + PAIR_BLOCK - 1) / PAIR_BLOCK)
+#define NQ(n) (((n) + PAIR_BLOCK / 4 - 1) / (PAIR_BLOCK / 4))
 
 template <bool BATCH>
 static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, const Buf& out,
@@ -800,19 +948,20 @@ static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, co
   else k_kin<EV_EXPORT><<<d.n_inst, 256, 0, st>>>(d, pre);
   k_scan<<<1, 1024, 0, st>>>(d);
   k_scatter<BATCH><<<nb, WC_BLOCK, 0, st>>>(d, pre);
-  if (mode == EV_B) k_permute<EV_B, BATCH><<<nb, WC_BLOCK, 0, st>>>(d, pre, out, pre2, out2);
-  else k_permute<EV_A, BATCH><<<nb, WC_BLOCK, 0, st>>>(d, pre, out, pre2, out2);
+  const int np = NP(d.n_slots);
+  if (mode == EV_B) k_permute<EV_B, BATCH><<<np, 128, 0, st>>>(d, pre, out, pre2, out2);
+  else k_permute<EV_A, BATCH><<<np, 128, 0, st>>>(d, pre, out, pre2, out2);
 }
 
 template <bool BATCH>
 static void enqueue_step_t(const Dev& d, const Bufs& b, int n_gblk, hipStream_t st) {
-  const int nb = NB(d.n_slots);
+  const int np = NP(d.n_slots);
   eval_sort<BATCH>(d, st, EV_A, b.X, b.Y, b.Y, b.Y);
   k_ghost<EV_A, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
-  k_pair<EV_A, BATCH><<<nb, WC_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
+  k_pair<EV_A, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
   eval_sort<BATCH>(d, st, EV_B, b.Z, b.W, b.Y, b.X);
   k_ghost<EV_B, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.W);
-  k_pair<EV_B, BATCH><<<nb, WC_BLOCK, 0, st>>>(d, b.W, b.X, b.X);
+  k_pair<EV_B, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.X, b.X);
 }
 
 void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, hipStream_t st) {
@@ -826,7 +975,8 @@ void wc_enqueue_init(const Dev& d, const Bufs& b, bool batch, hipStream_t st) {
 }
 
 void wc_enqueue_diag(const Dev& d, const Bufs& b, int row, bool sorted, hipStream_t st) {
-  k_diag<<<d.n_inst, 1024, 0, st>>>(d, b.X, row, sorted ? 1 : 0);
+  k_diag_part<<<dim3(WC_DIAG_BLOCKS, d.n_inst), 256, 0, st>>>(d, b.X, sorted ? 1 : 0);
+  k_diag_final<<<d.n_inst, 64, 0, st>>>(d, row);
 }
 
 // Eval-A sort of X into Y without advancing the clock (test hooks).
@@ -840,12 +990,12 @@ void wc_enqueue_export_ghosts(const Dev& d, const Bufs& b, int n_gblk, hipStream
 }
 
 void wc_enqueue_export_pair(const Dev& d, const Bufs& b, hipStream_t st) {
-  k_pair<EV_EXPORT, false><<<NB(d.n_slots), WC_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
+  k_pair<EV_EXPORT, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
 }
 
 void wc_enqueue_pair_a(const Dev& d, const Bufs& b, bool batch, hipStream_t st) {
-  if (batch) k_pair<EV_A, true><<<NB(d.n_slots), WC_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
-  else k_pair<EV_A, false><<<NB(d.n_slots), WC_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
+  if (batch) k_pair<EV_A, true><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
+  else k_pair<EV_A, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
 }
 
 void wc_enqueue_neigh(const Dev& d, const Bufs& b, hipStream_t st) {

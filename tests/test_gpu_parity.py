@@ -23,7 +23,21 @@ def _solver(cfg):
 
 
 def _rel(a, b):
+    """max_i |a_i - b_i| / max_i |b_i|"""
     return np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _relvec(ax, ay, bx, by):
+    """max_i |a_i - b_i| / max_i |b_i| for 2-vectors"""
+    d = np.hypot(np.asarray(ax, np.float64) - bx, np.asarray(ay, np.float64) - by)
+    return d.max() / max(np.hypot(bx, by).max(), 1e-300)
+
+
+def p_quantum(cfg):
+    """Pressure step of one FP32 ulp of rho near rho0: gamma B ulp(rho0) / rho0.
+    Pressures below a few of these are not resolved by an FP32 density."""
+    B = cfg["rho0"] * cfg["c0"] ** 2 / cfg["gamma"]
+    return cfg["gamma"] * B * float(np.spacing(np.float32(cfg["rho0"]))) / cfg["rho0"]
 
 
 def _shared_state(cfg, steps):
@@ -106,7 +120,7 @@ def test_one_evaluation_rates_C1(steps):
     g = s.export_rates()
     r = o.eval_rates()
     assert _rel(g["drho"], r["drho"]) <= 1e-4
-    assert _rel(np.hypot(g["ax"] - r["ax"], g["ay"] - r["ay"]), np.hypot(r["ax"], r["ay"])) <= 1e-4
+    assert _relvec(g["ax"], g["ay"], r["ax"], r["ay"]) <= 1e-4
     assert _rel(g["Vx"], r["Vx"]) <= 1e-4 and _rel(g["Vy"], r["Vy"]) <= 1e-4
     assert _rel(g["gp"], r["gp"]) <= 1e-4
     assert _rel(g["gvx"], r["gvx"]) <= 1e-4
@@ -124,7 +138,7 @@ def test_one_step_state_C1():
     _, (xo, yo, vxo, vyo, ro) = o.fluid()
     assert np.abs(rg / ro - 1).max() <= 1e-4
     assert np.abs(xg - xo).max() <= 1e-4 * cfg["dx"] and np.abs(yg - yo).max() <= 1e-4 * cfg["dx"]
-    assert _rel(np.hypot(vxg - vxo, vyg - vyo), np.hypot(vxo, vyo)) <= 1e-4
+    assert _relvec(vxg, vyg, vxo, vyo) <= 1e-4
     s.close()
 
 
@@ -192,7 +206,7 @@ def test_full_size_C2_evaluation():
     g = s.export_rates()
     r = o.eval_rates()
     assert _rel(g["drho"], r["drho"]) <= 1e-4
-    assert _rel(np.hypot(g["ax"] - r["ax"], g["ay"] - r["ay"]), np.hypot(r["ax"], r["ay"])) <= 1e-4
+    assert _relvec(g["ax"], g["ay"], r["ax"], r["ay"]) <= 1e-4
     assert _rel(g["gp"], r["gp"]) <= 1e-4
     ex = s.export_cells()
     x, y = _oracle_keys(cfg, ex)
@@ -226,7 +240,7 @@ def test_edge_cases_small_ragged_and_diskless():
         if cfg["probes"]:
             _, _, pg = s.read_probes()
             _, _, po = o.probes()
-            assert np.abs(pg - po).max() <= 1e-3 * max(np.abs(po).max(), 1.0)
+            assert np.abs(pg - po).max() <= 1e-3 * np.abs(po).max() + 2 * p_quantum(cfg)
         s.close()
 
 
