@@ -75,6 +75,45 @@ def cpu_baseline(cfg, budget_s: float = 15.0):
                        f"FP64 oracle (C++17, OpenMP), {dt:.1f} s wall")
 
 
+def batched_vs_plain(wc, workloads, steps: int):
+    """The 64-instance coefficient sweep (seeded draws) in one batched
+    context vs the same 64 problems run one after another through the plain
+    solver, both for `steps` steps from t = 0 on the same GPU."""
+    import torch
+    cfgs = workloads.C4()
+    b = wc.Solver(cfgs, "cuda:0")
+    blob = b.save_state()
+    b.step(5)
+    b.synchronize()
+    b.load_state(blob)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.synchronize()
+    tb = time.perf_counter() - t0
+    nf = b.n_fluid_total
+    unstable = any("unstable" in b.read_diagnostics(k) for k in range(b.n_inst))
+    b.close()
+    tp = 0.0
+    for cfg in cfgs:
+        s = wc.Solver(cfg, "cuda:0")
+        s.step(2)
+        s.synchronize()
+        blob = s.save_state()
+        s.load_state(blob)
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.synchronize()
+        tp += time.perf_counter() - t0
+        s.close()
+    return dict(workload="64 instances, L in 200-400 mm x 100 mm, dx 1 mm, alpha in [0.01, 0.5], "
+                         "delta in [0, 0.2], v0 in [600, 900] m/s, seed 2609",
+                n_fluid=int(nf), steps=steps,
+                batched_s=round(tb, 4), plain_sequential_s=round(tp, 4),
+                batched_value=nf * steps / tb, plain_value=nf * steps / tp,
+                speedup=round(tp / tb, 3), unit="fluid particle-steps/s", unstable=unstable)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +121,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--reps", type=int, default=50, help="pair-kernel timing launches")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--batch-steps", type=int, default=1000,
+                    help="steps of the batched-sweep comparison (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -127,6 +168,7 @@ def main():
     nf = s.nf
     s.close()
 
+    batched = batched_vs_plain(wc, workloads, args.batch_steps) if args.batch_steps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(cfg)
     out = {
         "metric": "WCSPH fluid particle-steps/s at 180k particles",
@@ -146,6 +188,7 @@ def main():
                    "n_fluid": nf, "steps": args.steps, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched_sweep": batched,
         "unstable": unstable,
         "probe_peak_pa": float(np.abs(p).max()) if p.size else None,
     }

@@ -426,6 +426,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.n_ghost = c->n_ghost;
   d.count = dalloc_n<uint32_t>(c, c->n_cells);
   d.start = dalloc_n<uint32_t>(c, c->n_cells + 1);
+  d.bsum = dalloc_n<uint32_t>(c, (size_t)c->n_cells / 4096 + 1);
   c->d_wallcount = dalloc_n<uint32_t>(c, c->n_cells);
   d.wallcount = c->d_wallcount;
   d.tmp = dalloc_n<uint32_t>(c, c->n_slots);

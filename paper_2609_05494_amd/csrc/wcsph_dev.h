@@ -80,6 +80,7 @@ struct Dev {
   int n_inst, n_slots, n_cells, n_ghost;
   uint32_t* count;            // per cell: bucket fill for the next sort
   uint32_t* start;            // per cell + 1: exclusive scan of count
+  uint32_t* bsum;             // per scan tile: cell-count total
   const uint32_t* wallcount;  // per cell: static wall ghosts (pre-fill of count)
   uint32_t* tmp;              // per slot: bucket contents (old slots)
   uint32_t* perm;             // per slot: perm[new] = old of the last sort

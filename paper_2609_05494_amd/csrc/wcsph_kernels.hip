@@ -3,7 +3,7 @@
 // One step = two evaluations (predictor-corrector). Each evaluation runs:
 //   k_kin      clock, prescribed disk kinematics, disk-ring placement and
 //              the ring's bucket slots for the next sort
-//   k_scan     exclusive scan of the per-cell counts -> cell ranges
+//   k_scan_*   exclusive scan of the per-cell counts -> cell ranges
 //   k_scatter  every slot into its cell bucket
 //   k_permute  stable rank inside the bucket (by old slot) and gather of the
 //              state into sorted order; per-particle EOS (P = p/rho^2, c)
@@ -426,57 +426,82 @@ __global__ __launch_bounds__(256) void k_kin(Dev d, Buf pre) {
   }
 }
 
-// Exclusive scan of count -> start over all cells; count is re-armed with the
-// static wall-ghost occupancy for the next sort. One block walks the cells in
-// tiles of 4096 (four consecutive cells per thread, coalesced uint4 loads).
-__global__ __launch_bounds__(1024) void k_scan(Dev d) {
-  __shared__ uint32_t wsum[16];
-  const int n = d.n_cells;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  uint32_t carry = 0;
-  for (int base = 0; base < n; base += 4096) {
-    const int i0 = base + 4 * t;
-    uint32_t a[4];
-    if (i0 + 3 < n) {
-      const uint4 v = *reinterpret_cast<const uint4*>(d.count + i0);
-      a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
-    } else {
-      for (int k = 0; k < 4; ++k) a[k] = (i0 + k < n) ? d.count[i0 + k] : 0u;
-    }
-    const uint32_t s = a[0] + a[1] + a[2] + a[3];
-    uint32_t incl = s;
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t u = __shfl_up(incl, o);
-      if (lane >= o) incl += u;
-    }
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    uint32_t woff = 0, tile = 0;
-    for (int w = 0; w < 16; ++w) {
-      const uint32_t x = wsum[w];
-      woff += (w < wv) ? x : 0u;
-      tile += x;
-    }
-    uint32_t run = carry + woff + incl - s;
-    uint32_t o4[4];
-    for (int k = 0; k < 4; ++k) {
-      o4[k] = run;
-      run += a[k];
-    }
-    if (i0 + 3 < n) {
-      *reinterpret_cast<uint4*>(d.start + i0) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
-      *reinterpret_cast<uint4*>(d.count + i0) = *reinterpret_cast<const uint4*>(d.wallcount + i0);
-    } else {
-      for (int k = 0; k < 4; ++k)
-        if (i0 + k < n) {
-          d.start[i0 + k] = o4[k];
-          d.count[i0 + k] = d.wallcount[i0 + k];
-        }
-    }
-    carry += tile;
-    __syncthreads();
+// Exclusive scan of count -> start over all cells in two passes over tiles
+// of SCAN_TILE cells (four consecutive cells per thread, coalesced uint4
+// loads): k_scan_sum writes each tile's total, k_scan_apply adds the totals
+// of the preceding tiles and scans its own tile. count is re-armed with the
+// static wall-ghost occupancy for the next sort.
+#define SCAN_TILE 4096
+__device__ __forceinline__ void load4(const uint32_t* p, int i0, int n, uint32_t a[4]) {
+  if (i0 + 3 < n) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p + i0);
+    a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+  } else {
+    for (int k = 0; k < 4; ++k) a[k] = (i0 + k < n) ? p[i0 + k] : 0u;
   }
-  if (t == 0) d.start[n] = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sum(Dev d) {
+  __shared__ uint32_t wsum[16];
+  const int n = d.n_cells, t = threadIdx.x;
+  uint32_t a[4];
+  load4(d.count, blockIdx.x * SCAN_TILE + 4 * t, n, a);
+  uint32_t s = a[0] + a[1] + a[2] + a[3];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((t & 63) == 0) wsum[t >> 6] = s;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < 16; ++w) tot += wsum[w];
+    d.bsum[blockIdx.x] = tot;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(Dev d) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t base_sh;
+  const int n = d.n_cells, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int b = blockIdx.x;
+  if (t < 64) {
+    uint32_t v = 0;
+    for (int k = t; k < b; k += 64) v += d.bsum[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (t == 0) base_sh = v;
+  }
+  const int i0 = b * SCAN_TILE + 4 * t;
+  uint32_t a[4];
+  load4(d.count, i0, n, a);
+  const uint32_t s = a[0] + a[1] + a[2] + a[3];
+  uint32_t incl = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  uint32_t woff = 0, tile = 0;
+  for (int w = 0; w < 16; ++w) {
+    const uint32_t x = wsum[w];
+    woff += (w < wv) ? x : 0u;
+    tile += x;
+  }
+  uint32_t run = base_sh + woff + incl - s;
+  uint32_t o4[4];
+  for (int k = 0; k < 4; ++k) {
+    o4[k] = run;
+    run += a[k];
+  }
+  if (i0 + 3 < n) {
+    *reinterpret_cast<uint4*>(d.start + i0) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+    *reinterpret_cast<uint4*>(d.count + i0) = *reinterpret_cast<const uint4*>(d.wallcount + i0);
+  } else {
+    for (int k = 0; k < 4; ++k)
+      if (i0 + k < n) {
+        d.start[i0 + k] = o4[k];
+        d.count[i0 + k] = d.wallcount[i0 + k];
+      }
+  }
+  if (b == (int)gridDim.x - 1 && t == 0) d.start[n] = base_sh + tile;
 }
 
 // Every slot into its bucket: tmp[start[key] + bucket slot] = slot.
@@ -946,7 +971,9 @@ static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, co
   if (mode == EV_A) k_kin<EV_A><<<d.n_inst, 256, 0, st>>>(d, pre);
   else if (mode == EV_B) k_kin<EV_B><<<d.n_inst, 256, 0, st>>>(d, pre);
   else k_kin<EV_EXPORT><<<d.n_inst, 256, 0, st>>>(d, pre);
-  k_scan<<<1, 1024, 0, st>>>(d);
+  const int nt = (d.n_cells + SCAN_TILE - 1) / SCAN_TILE;
+  k_scan_sum<<<nt, 1024, 0, st>>>(d);
+  k_scan_apply<<<nt, 1024, 0, st>>>(d);
   k_scatter<BATCH><<<nb, WC_BLOCK, 0, st>>>(d, pre);
   const int np = NP(d.n_slots);
   if (mode == EV_B) k_permute<EV_B, BATCH><<<np, 128, 0, st>>>(d, pre, out, pre2, out2);
