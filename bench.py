@@ -114,6 +114,41 @@ def batched_vs_plain(wc, workloads, steps: int):
                 speedup=round(tp / tb, 3), unit="fluid particle-steps/s", unstable=unstable)
 
 
+def adjoint_vs_fd(wc, workloads, steps: int, ckpt: int):
+    """Gradient of the summed wall-probe impulse w.r.t. (alpha, delta, c0) on
+    the 120x60 mm / dx 0.5 mm channel: one forward + reverse sweep (with
+    checkpoints) vs the plain solver's forward + six runs a central finite
+    difference needs, on the same GPU and fixed time-step table."""
+    cfg = workloads.C5()
+    s = wc.Solver(cfg, "cuda:0")
+    blob = s.save_state()
+    s.step(steps)
+    _, dt, _ = s.read_probes()
+    s.load_state(blob)
+    s.set_dt_table(dt)
+    s.synchronize()
+    t0 = time.perf_counter()
+    J = s.adj_forward(steps, ckpt)
+    g = s.adj_backward(1.0)
+    t_adj = time.perf_counter() - t0
+    # plain runs: forward + 6 perturbed runs of the same length
+    t_plain = 0.0
+    for k in range(7):
+        s.load_state(blob)
+        s.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.synchronize()
+        t_plain += time.perf_counter() - t0
+    nf = s.nf
+    s.close()
+    return dict(workload="120x60 mm channel, dx 0.5 mm, 28,352 fluid, 900 m/s, "
+                         f"{steps} steps, checkpoint every {ckpt}",
+                n_fluid=int(nf), steps=steps, J=J, grad_alpha_delta_c0=[float(x) for x in g],
+                adjoint_s=round(t_adj, 4), forward_plus_6_fd_s=round(t_plain, 4),
+                ratio_fd_over_adjoint=round(t_plain / t_adj, 3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +158,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="steps of the batched-sweep comparison (0 skips it)")
+    ap.add_argument("--adj-steps", type=int, default=500,
+                    help="steps of the adjoint comparison (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -169,6 +206,7 @@ def main():
     s.close()
 
     batched = batched_vs_plain(wc, workloads, args.batch_steps) if args.batch_steps > 0 else None
+    adjoint = adjoint_vs_fd(wc, workloads, args.adj_steps, 50) if args.adj_steps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(cfg)
     out = {
         "metric": "WCSPH fluid particle-steps/s at 180k particles",
@@ -189,6 +227,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched_sweep": batched,
+        "adjoint": adjoint,
         "unstable": unstable,
         "probe_peak_pa": float(np.abs(p).max()) if p.size else None,
     }

@@ -212,6 +212,30 @@ wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, 
  * between two HIP events on the context stream. The state is restored. */
 wcsph_status wcsph_time_pair_kernel(wcsph_ctx* ctx, int reps, float* avg_ms);
 
+/* ---- coefficients and reverse sweep --------------------------------------- */
+
+/* Replace the Monaghan alpha, the delta-diffusion coefficient and the Tait
+ * sound speed c0 of instance `inst` (B = rho0 c0^2 / gamma and every constant
+ * derived from them follow). The particle state is untouched. */
+wcsph_status wcsph_set_coefficients(wcsph_ctx* ctx, int inst, double alpha, double delta, double c0);
+
+/* Reverse-mode gradient of the summed wall-probe pressure impulse
+ *   J = sum_k sum_n p_k^n dt_n   (probes sampled at the state of step n)
+ * with respect to (alpha, delta, c0), for a single-instance context with the
+ * linear ghost density and the rest initial state, at a fixed time-step
+ * table (wcsph_set_dt_table must cover the run, so dt does not depend on c0).
+ * adj_forward advances n_steps from the current state, keeps a device
+ * checkpoint every ckpt_every steps and returns J. adj_backward walks the
+ * segments last to first: it restores a checkpoint, replays the segment
+ * taping each evaluation's sorted state and pre-enforcement state, and runs
+ * the hand-written transpose of the step (enforcement, pair sums, Adami ghost
+ * Shepard sums, probes, Tait EOS) in FP32 with FP64 coefficient
+ * accumulators; grad[3] = dJ * dJ/d(alpha, delta, c0). The state is left at
+ * the end of the forward run. Non-smooth points (AV switch, cavitation
+ * cutoff, density band, enforcement) take the branch of the forward run. */
+wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, double* J);
+wcsph_status wcsph_adj_backward(wcsph_ctx* ctx, double dJ, double* grad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,6 +27,7 @@ SYMBOLS = (
     "wcsph_synchronize", "wcsph_read_probes", "wcsph_read_diagnostics", "wcsph_get_fluid",
     "wcsph_set_fluid", "wcsph_save_state", "wcsph_load_state", "wcsph_export_cells",
     "wcsph_export_rates", "wcsph_export_neighbours", "wcsph_time_pair_kernel",
+    "wcsph_set_coefficients", "wcsph_adj_forward", "wcsph_adj_backward",
 )
 
 
@@ -132,6 +133,9 @@ def lib():
             "wcsph_export_rates": [_V, _F, _F, _F, _F, _F, _F, _F, _F, _F, C.c_int, C.c_int],
             "wcsph_export_neighbours": [_V, _U, _I, _LL, _D, _D, C.c_size_t],
             "wcsph_time_pair_kernel": [_V, C.c_int, _F],
+            "wcsph_set_coefficients": [_V, C.c_int, C.c_double, C.c_double, C.c_double],
+            "wcsph_adj_forward": [_V, C.c_int, C.c_int, _D],
+            "wcsph_adj_backward": [_V, C.c_double, _D],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -313,7 +317,45 @@ class Solver:
                                                   _p(y, C.c_double), n))
         return dict(ids=ids, count=cnt, idsum=sm, x=x, y=y)
 
+    # -- coefficients and reverse sweep ----------------------------------------
+    def set_coefficients(self, alpha: float, delta: float, c0: float, inst: int = 0):
+        self._check(lib().wcsph_set_coefficients(self.handle, inst, float(alpha), float(delta), float(c0)))
+
+    def adj_forward(self, n_steps: int, ckpt_every: int = 50) -> float:
+        J = C.c_double()
+        self._check(lib().wcsph_adj_forward(self.handle, n_steps, ckpt_every, C.byref(J)))
+        return J.value
+
+    def adj_backward(self, dJ: float = 1.0) -> np.ndarray:
+        g = np.zeros(3)
+        self._check(lib().wcsph_adj_backward(self.handle, float(dJ), _p(g, C.c_double)))
+        return g
+
     def time_pair_kernel(self, reps: int = 20) -> float:
         ms = C.c_float()
         self._check(lib().wcsph_time_pair_kernel(self.handle, reps, C.byref(ms)))
         return ms.value
+
+
+def impulse_fn():
+    """torch.autograd.Function computing the summed wall-probe pressure
+    impulse J(alpha, delta, c0) of a solver run from a saved state, with the
+    library's reverse sweep as its backward."""
+    import torch
+
+    class ImpulseFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, alpha, delta, c0, solver, state0, n_steps, ckpt_every):
+            solver.load_state(state0)
+            solver.set_coefficients(float(alpha), float(delta), float(c0))
+            J = solver.adj_forward(n_steps, ckpt_every)
+            ctx.solver = solver
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            g = ctx.solver.adj_backward(float(gJ))
+            t = [torch.tensor(x, dtype=torch.float64) for x in g]
+            return t[0], t[1], t[2], None, None, None, None
+
+    return ImpulseFn

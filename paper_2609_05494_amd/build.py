@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libwcsph.so")
-SOURCES = ["wcsph_kernels.hip", "wcsph_api.hip"]
+SOURCES = ["wcsph_kernels.hip", "wcsph_adjoint.hip", "wcsph_api.hip"]
 ARCH = os.environ.get("WCSPH_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,0 +1,499 @@
+// wcsph_adjoint.hip -- reverse sweep of the WCSPH step (gradient of the
+// summed wall-probe pressure impulse J = sum_k sum_n p_k^n dt_n with respect
+// to alpha, delta and c0 at a fixed time-step table).
+//
+// One step is U* = E_A(U^n + dt/2 f(U^n)), U^{n+1} = E_B(U^n + dt f(U*)),
+// f = rates (pair sums over fluid and Adami ghosts, ghosts from Shepard sums
+// of the fluid), E = density band + wall / disk enforcement. Given the
+// adjoint of U^{n+1} the sweep runs, per step and in reverse:
+//   k_adj_enforce (B)  transpose of E_B; adjoint of U^n (direct part) and of f(U*)
+//   k_adj_gather       rate adjoints into the sorted slot order of U*
+//   k_adj_ghost        ghost-state adjoints (pair terms seen by the fluid)
+//   k_adj_fluid        pull-form transpose of the rates at U* -> adjoint of U*
+//   k_adj_enforce (A), k_adj_gather, k_adj_ghost, k_adj_fluid at U^n with the
+//                      probe terms of step n
+// Adjoints are FP32 per fluid particle (indexed by particle id); the
+// coefficient gradients are reduced per block in FP64 in a fixed order.
+// The sorted states, cell lists and pre-enforcement states of each
+// evaluation come from a taped replay of the checkpoint segment.
+
+#include "wcsph_adjoint.h"
+#include "wcsph_launch.h"
+
+namespace {
+
+__device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ float d_pow(float a, float b) { return powf(a, b); }
+
+__device__ void kin_d(const InstParams& P, double t, double& x, double& v, double& a) {
+  const double v0 = P.kin_v0, tr = P.kin_t_ramp;
+  if (t < tr) {
+    v = v0 * t / tr;
+    a = v0 / tr;
+    x = P.disk_x0 + 0.5 * v0 * t * t / tr;
+    return;
+  }
+  const double tau = t - tr, xr = P.disk_x0 + 0.5 * v0 * tr;
+  if (P.kin_mode == 1) {
+    const double k = P.kin_coef;
+    v = v0 / (1.0 + k * v0 * tau);
+    a = -k * v * v;
+    x = k > 0.0 ? xr + log1p(k * v0 * tau) / k : xr + v0 * tau;
+    return;
+  }
+  const double ad = P.kin_coef;
+  if (ad > 0.0 && tau >= v0 / ad) {
+    v = 0.0;
+    a = 0.0;
+    x = xr + 0.5 * v0 * v0 / ad;
+    return;
+  }
+  v = v0 - ad * tau;
+  a = -ad;
+  x = xr + v0 * tau - 0.5 * ad * tau * tau;
+}
+
+__device__ __forceinline__ PairK<float> pair_k(const InstParams& P) {
+  PairK<float> k;
+  k.h = P.h;
+  k.inv_h = P.inv_h;
+  k.four_h2 = P.four_h2;
+  k.sigma = P.sigma;
+  k.fgrad = P.fgrad;
+  k.eta2h2 = P.eta2h2;
+  k.alpha = P.alpha;
+  k.delta = P.delta;
+  k.two_h_c0 = P.two_h_c0;
+  k.eps = P.eps_xsph;
+  k.four_nu0 = P.four_nu0;
+  return k;
+}
+
+__device__ __forceinline__ void cxy(const InstParams& P, uint32_t K, int& cx, int& cy) {
+  const int local = (int)K - P.cell_off;
+  cy = local / P.ncx;
+  cx = local - cy * P.ncx;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+// Ghost density, P and c as functions of the ghost pressure (linear branch)
+// and their derivatives.
+struct GhostD {
+  float rho, P, c, drho_dp, drho_dc0, dP_dp, dP_dc0, dc_drho, dc_dc0;
+};
+__device__ __forceinline__ GhostD ghost_d(const InstParams& P, float p) {
+  GhostD g;
+  const float c0 = P.c0;
+  g.rho = P.rho0 * (1.0f + p * P.inv_rho0c02);
+  g.drho_dp = 1.0f / (c0 * c0);
+  g.drho_dc0 = -2.0f * p / (c0 * c0 * c0);
+  const float r2 = g.rho * g.rho;
+  g.P = p / r2;
+  g.dP_dp = 1.0f / r2 - 2.0f * p / (r2 * g.rho) * g.drho_dp;
+  g.dP_dc0 = -2.0f * p / (r2 * g.rho) * g.drho_dc0;
+  g.c = c0 * powf(g.rho / P.rho0, P.c_exp);
+  g.dc_drho = P.c_exp * g.c / g.rho;
+  g.dc_dc0 = g.c / c0;
+  return g;
+}
+
+}  // namespace
+
+// Transpose of the update + enforcement of one evaluation for every fluid
+// particle (by id). lam_out: adjoint of the evaluation's output state
+// (x, y, vx, vy, rho); pre: pre-enforcement state taped by the forward
+// kernel; te: time of the enforcement; hdt: dt/2 (eval A) or dt (eval B).
+// Writes lam_base (+= when accumulate) and the rate adjoints
+// lam_f = hdt * (lam_pre_rho -> D, lam_pre_v -> a, lam_pre_r -> V).
+__global__ __launch_bounds__(256) void k_adj_enforce(Dev d, AdjPtrs a, double te, float hdt, int accumulate) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const InstParams& P = d.prm[0];
+  if (i >= P.nf) return;
+  const int n = P.nf;
+  float lx = a.lam_out[i], ly = a.lam_out[n + i], lvx = a.lam_out[2 * n + i], lvy = a.lam_out[3 * n + i],
+        lr = a.lam_out[4 * n + i];
+  const double2 xp = a.pre_pos[i];
+  const float4 vp = a.pre_vel[i];
+  // density band
+  if (vp.z < P.rho_lo || vp.z > P.rho_hi) lr = 0.0f;
+  // walls (applied first in the forward)
+  const double e = P.eps_wall;
+  double xw = xp.x, yw = xp.y;
+  float vxw = vp.x, vyw = vp.y;
+  bool hx = false, hy = false;
+  if (xw < e) { xw = e; vxw = -vxw; hx = true; }
+  if (xw > P.L - e) { xw = P.L - e; vxw = -vxw; hx = true; }
+  if (yw < e) { yw = e; vyw = -vyw; hy = true; }
+  if (yw > P.W - e) { yw = P.W - e; vyw = -vyw; hy = true; }
+  // disk: radial pull-out and reflection of the inward relative velocity
+  if (P.nd > 0) {
+    double xd, vd, ad;
+    kin_d(P, te, xd, vd, ad);
+    const double dx = xw - xd, dy = yw - P.disk_y0;
+    const double d2 = dx * dx + dy * dy;
+    if (d2 < P.R * P.R) {
+      if (d2 > 0.0) {
+        const double dd = sqrt(d2);
+        const double nx = dx / dd, ny = dy / dd;
+        const double s = (P.R + e) / dd;
+        const double ux = (double)vxw - vd, uy = (double)vyw;
+        const double w = ux * nx + uy * ny;
+        // position: r = c + (R + eps) n  ->  d r / d r_w = s (I - n n^T)
+        const double ln = lx * nx + ly * ny;
+        double gx = s * (lx - ln * nx), gy = s * (ly - ln * ny);
+        double gvx = lvx, gvy = lvy;
+        if (w < 0.0) {
+          // v = v_w - 2 w n: d v/d v_w = I - 2 n n^T;
+          // d v/d r_w = -(2/|d|) [n (u^T P) + w P], P = I - n n^T
+          const double lvn = lvx * nx + lvy * ny;
+          gvx = lvx - 2.0 * lvn * nx;
+          gvy = lvy - 2.0 * lvn * ny;
+          const double un = ux * nx + uy * ny;
+          const double pux = ux - un * nx, puy = uy - un * ny;   // P u
+          const double plx = lvx - lvn * nx, ply = lvy - lvn * ny;  // P lam_v
+          gx += -(2.0 / dd) * (pux * lvn + w * plx);
+          gy += -(2.0 / dd) * (puy * lvn + w * ply);
+        }
+        lx = (float)gx;
+        ly = (float)gy;
+        lvx = (float)gvx;
+        lvy = (float)gvy;
+      } else {
+        lx = 0.0f;
+        ly = 0.0f;
+      }
+    }
+  }
+  if (hx) { lx = 0.0f; lvx = -lvx; }
+  if (hy) { ly = 0.0f; lvy = -lvy; }
+  float* lb = a.lam_base;
+  if (accumulate) {
+    lb[i] += lx; lb[n + i] += ly; lb[2 * n + i] += lvx; lb[3 * n + i] += lvy; lb[4 * n + i] += lr;
+  } else {
+    lb[i] = lx; lb[n + i] = ly; lb[2 * n + i] = lvx; lb[3 * n + i] = lvy; lb[4 * n + i] = lr;
+  }
+  // rates: rho' = rho + h D, v' = v + h a, r' = r + h V
+  a.lam_f[i] = hdt * lr;
+  a.lam_f[n + i] = hdt * lvx;
+  a.lam_f[2 * n + i] = hdt * lvy;
+  a.lam_f[3 * n + i] = hdt * lx;
+  a.lam_f[4 * n + i] = hdt * ly;
+}
+
+// Rate adjoints (by id) into the sorted slot order of the taped evaluation;
+// zero for ghost slots.
+__global__ __launch_bounds__(256) void k_adj_gather(Dev d, AdjPtrs a, TapeEval te) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= d.n_slots) return;
+  const InstParams& P = d.prm[0];
+  const int id = (int)te.id[s] - P.id0;
+  const bool fl = id >= 0 && id < P.nf;
+  for (int c = 0; c < 5; ++c) a.lam_s[c * d.n_slots + s] = fl ? a.lam_f[c * P.nf + id] : 0.0f;
+}
+
+// Ghost adjoints. For ghost g: the pair terms phi(i, g) of its fluid
+// neighbours i give dL/d(rho_g, P_g, c_g, v_g); through the linear ghost
+// density these become the adjoint of the ghost pressure (zero when the
+// cavitation cutoff is active) and of c0. The ghost's Shepard sums are
+// stored for the fluid pass. Extra threads compute the probes' Shepard sums.
+__global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te, double t_eval, int n_gb) {
+  __shared__ double shd[4];
+  const InstParams& P = d.prm[0];
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int ng = P.nw + P.nd;
+  double c0bar = 0.0;
+  const PairK<float> k = pair_k(P);
+  if (t < ng) {
+    const uint32_t s = te.gslot[t];
+    const uint32_t K = te.cell[s];
+    const float4 pg = te.pv[s];
+    const float4 ag = te.aux[s];  // rho_g, P_g, c_g, -m
+    const bool disk = t >= P.nw;
+    double xd, vd, ad;
+    kin_d(P, t_eval, xd, vd, ad);
+    const float awx = disk ? (float)ad : 0.0f;
+    const float vwx = disk ? (float)vd : 0.0f;
+    const float mg = -ag.w;
+    int cx, cy;
+    cxy(P, K, cx, cy);
+    float gr = 0, gP = 0, gc = 0, gvx = 0, gvy = 0;
+    float SW = 0, Sp = 0, Srx = 0, Sry = 0, Svx = 0, Svy = 0;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = cy + dy;
+      if (yy < 0 || yy >= P.ncy) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = cx + dx;
+        if (xx < 0 || xx >= P.ncx) continue;
+        const uint32_t K2 = (uint32_t)(P.cell_off + yy * P.ncx + xx);
+        for (uint32_t j = te.start[K2]; j < te.start[K2 + 1]; ++j) {
+          const float4 aj = te.aux[j];
+          if (!(aj.w > 0.0f)) continue;
+          const float4 pj = te.pv[j];
+          // r_i - r_g for the pair phi(i, g)
+          const float rx = (pj.x + (float)dx * P.dc) - pg.x, ry = (pj.y + (float)dy * P.dc) - pg.y;
+          const float r2 = rx * rx + ry * ry;
+          if (!(r2 < P.four_h2)) continue;
+          PairIn<float> in;
+          in.rx = rx; in.ry = ry; in.vx = pj.z - pg.z; in.vy = pj.w - pg.w;
+          in.ra = aj.x; in.rb = ag.x; in.Pa = aj.y; in.Pb = ag.y; in.ca = aj.z; in.cb = ag.z;
+          in.mb = mg; in.fl = 0.0f;
+          PairGrad<float> g;
+          const float* ls = a.lam_s;
+          const int N = d.n_slots;
+          pair_vjp(in, k, ls[j], ls[N + j], ls[2 * N + j], ls[3 * N + j], ls[4 * N + j], g, d_sqrt);
+          gr += g.rb;
+          gP += g.P;
+          gc += g.c;
+          gvx -= g.vx;  // v = v_i - v_g
+          gvy -= g.vy;
+          // Shepard sums of the ghost (r_g - r_j = -(r_i - r_g))
+          const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
+          const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
+          const float pj_ = aj.y * aj.x * aj.x;
+          SW += W;
+          Sp += pj_ * W;
+          Srx += aj.x * (-rx) * W;
+          Sry += aj.x * (-ry) * W;
+          Svx += pj.z * W;
+          Svy += pj.w * W;
+        }
+      }
+    }
+    float pt = 0.0f, pbar = 0.0f, vax = 0.0f, vay = 0.0f;
+    const float ax_ = 0.0f - awx, ay_ = P.gy;  // g - a_w
+    if (SW > 0.0f) {
+      pt = (Sp + ax_ * Srx + ay_ * Sry) / SW;
+      vax = Svx / SW;
+      vay = Svy / SW;
+    }
+    const float p = ag.y * ag.x * ag.x;  // taped ghost pressure
+    const GhostD gd = ghost_d(P, p);
+    const float pb = gr * gd.drho_dp + gP * gd.dP_dp + gc * gd.dc_drho * gd.drho_dp;
+    c0bar += (double)(gr * gd.drho_dc0 + gP * gd.dP_dc0 + gc * (gd.dc_dc0 + gd.dc_drho * gd.drho_dc0));
+    // v_g = 2 v_w - S_v / S_W; p_g = max(p~, p_cav)
+    pbar = (SW > 0.0f && pt >= P.p_cav) ? pb : 0.0f;
+    float* o = a.gadj + (size_t)s * 10;
+    o[0] = pbar;
+    o[1] = SW > 0.0f ? gvx : 0.0f;
+    o[2] = SW > 0.0f ? gvy : 0.0f;
+    o[3] = SW;
+    o[4] = pt;
+    o[5] = vax;
+    o[6] = vay;
+    o[7] = ax_;
+    o[8] = ay_;
+    o[9] = 0.0f;
+    (void)vwx;
+  } else if (t < ng + P.n_probes) {
+    // probe Shepard sums at state n
+    const int kk = t - ng;
+    const uint32_t K = P.probe_cell[kk];
+    int cx, cy;
+    cxy(P, K, cx, cy);
+    float SW = 0, Sp = 0;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = cy + dy;
+      if (yy < 0 || yy >= P.ncy) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = cx + dx;
+        if (xx < 0 || xx >= P.ncx) continue;
+        const uint32_t K2 = (uint32_t)(P.cell_off + yy * P.ncx + xx);
+        for (uint32_t j = te.start[K2]; j < te.start[K2 + 1]; ++j) {
+          const float4 aj = te.aux[j];
+          if (!(aj.w > 0.0f)) continue;
+          const float4 pj = te.pv[j];
+          const float rx = P.probe_ox[kk] - (pj.x + (float)dx * P.dc), ry = P.probe_oy[kk] - (pj.y + (float)dy * P.dc);
+          const float r2 = rx * rx + ry * ry;
+          if (!(r2 < P.four_h2)) continue;
+          const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
+          const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
+          SW += W;
+          Sp += aj.y * aj.x * aj.x * W;
+        }
+      }
+    }
+    a.padj[2 * kk] = SW;
+    a.padj[2 * kk + 1] = SW > 0.0f ? Sp / SW : 0.0f;
+  }
+  const double tot = block_sum(c0bar, shd);
+  if (threadIdx.x == 0) a.theta_part[(size_t)blockIdx.x * 3 + 2] = tot;
+  if (threadIdx.x == 0) {
+    a.theta_part[(size_t)blockIdx.x * 3 + 0] = 0.0;
+    a.theta_part[(size_t)blockIdx.x * 3 + 1] = 0.0;
+  }
+}
+
+// Fluid adjoints (pull form) for every fluid slot j of the taped
+// evaluation: its own rates' dependence on its state, the dependence of its
+// fluid neighbours' rates on its state, the ghost-mediated dependence
+// through the Shepard sums, the XSPH identity and (probe_seed != 0) the
+// probe terms; then the EOS chain. Output by particle id into lam_base
+// (added, or set when accumulate == 0).
+__global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te, float probe_seed,
+                                                    int accumulate, int block0) {
+  __shared__ double shd[4];
+  const InstParams& P = d.prm[0];
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  const int N = d.n_slots;
+  const PairK<float> k = pair_k(P);
+  double th_a = 0.0, th_d = 0.0, th_c = 0.0;
+  if (s < N) {
+    const float4 ai = te.aux[s];
+    const int id = (int)te.id[s] - P.id0;
+    if (ai.w > 0.0f && id >= 0 && id < P.nf) {
+      const float4 pi = te.pv[s];
+      const uint32_t K = te.cell[s];
+      const float* ls = a.lam_s;
+      const float lD = ls[s], lax = ls[N + s], lay = ls[2 * N + s], lVx = ls[3 * N + s], lVy = ls[4 * N + s];
+      const EosD<float> ei = eos_d<float>(ai.x, P.rho0, P.c0, P.gamma, P.p_cav, d_pow);
+      float urx = 0, ury = 0, uvx = lVx, uvy = lVy, ur = 0, uP = 0, uc = 0, uc0 = 0;
+      int cx, cy;
+      cxy(P, K, cx, cy);
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = cy + dy;
+        if (yy < 0 || yy >= P.ncy) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int xx = cx + dx;
+          if (xx < 0 || xx >= P.ncx) continue;
+          const uint32_t K2 = (uint32_t)(P.cell_off + yy * P.ncx + xx);
+          for (uint32_t j = te.start[K2]; j < te.start[K2 + 1]; ++j) {
+            if (j == (uint32_t)s) continue;
+            const float4 pj = te.pv[j];
+            const float rx = (pi.x - pj.x) - (float)dx * P.dc;  // r_s - r_j
+            const float ry = (pi.y - pj.y) - (float)dy * P.dc;
+            const float r2 = rx * rx + ry * ry;
+            if (!(r2 < P.four_h2)) continue;
+            const float4 aj = te.aux[j];
+            const bool jfl = aj.w > 0.0f;
+            // own rates: phi(s, j)
+            PairIn<float> in;
+            in.rx = rx; in.ry = ry; in.vx = pi.z - pj.z; in.vy = pi.w - pj.w;
+            in.ra = ai.x; in.rb = aj.x; in.Pa = ai.y; in.Pb = aj.y; in.ca = ai.z; in.cb = aj.z;
+            in.mb = fabsf(aj.w); in.fl = jfl ? 1.0f : 0.0f;
+            PairGrad<float> g;
+            pair_vjp(in, k, lD, lax, lay, lVx, lVy, g, d_sqrt);
+            urx += g.rx; ury += g.ry; uvx += g.vx; uvy += g.vy; ur += g.ra; uP += g.P; uc += g.c;
+            th_a += (double)g.alpha;
+            th_d += (double)g.delta;
+            th_c += (double)g.c0x;
+            if (jfl) {
+              // the neighbour's rates: phi(j, s), r = r_j - r_s
+              PairIn<float> jn;
+              jn.rx = -rx; jn.ry = -ry; jn.vx = pj.z - pi.z; jn.vy = pj.w - pi.w;
+              jn.ra = aj.x; jn.rb = ai.x; jn.Pa = aj.y; jn.Pb = ai.y; jn.ca = aj.z; jn.cb = ai.z;
+              jn.mb = ai.w; jn.fl = 1.0f;
+              PairGrad<float> h;
+              pair_vjp(jn, k, ls[j], ls[N + j], ls[2 * N + j], ls[3 * N + j], ls[4 * N + j], h, d_sqrt);
+              urx -= h.rx; ury -= h.ry; uvx -= h.vx; uvy -= h.vy; ur += h.rb; uP += h.P; uc += h.c;
+            } else {
+              // ghost j: this particle enters the ghost's Shepard sums
+              const float* gq = a.gadj + (size_t)j * 10;
+              const float SW = gq[3];
+              if (SW > 0.0f) {
+                const float pbar = gq[0], vbx = gq[1], vby = gq[2], pt = gq[4], vax = gq[5], vay = gq[6];
+                const float gx = gq[7], gy = gq[8];
+                const float ddx = -rx, ddy = -ry;  // d = r_g - r_s
+                const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
+                const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
+                const float F = -P.fgrad * s2 * sq;
+                const float ad_ = gx * ddx + gy * ddy;
+                const float iw = 1.0f / SW;
+                ur += pbar * (ei.dp + ad_) * W * iw;
+                const float cf = -(ei.p + ai.x * ad_ - pt) * F * iw;
+                const float vv = vbx * (pi.z - vax) + vby * (pi.w - vay);
+                urx += pbar * (cf * ddx - ai.x * W * iw * gx) + vv * F * ddx * iw;
+                ury += pbar * (cf * ddy - ai.x * W * iw * gy) + vv * F * ddy * iw;
+                uvx -= vbx * W * iw;
+                uvy -= vby * W * iw;
+                uc0 += pbar * ei.dpdc0 * W * iw;
+              }
+            }
+          }
+        }
+      }
+      if (probe_seed != 0.0f) {
+        for (int kk = 0; kk < P.n_probes; ++kk) {
+          const float SW = a.padj[2 * kk];
+          if (!(SW > 0.0f)) continue;
+          int px, py;
+          cxy(P, P.probe_cell[kk], px, py);
+          if (abs(px - cx) > 1 || abs(py - cy) > 1) continue;
+          const float ddx = (P.probe_ox[kk] + (float)(px - cx) * P.dc) - pi.x;  // d = r_k - r_s
+          const float ddy = (P.probe_oy[kk] + (float)(py - cy) * P.dc) - pi.y;
+          const float r2 = ddx * ddx + ddy * ddy;
+          if (!(r2 < P.four_h2)) continue;
+          const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
+          const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
+          const float F = -P.fgrad * s2 * sq;
+          const float iw = probe_seed / SW;
+          ur += ei.dp * W * iw;
+          urx += -(ei.p - a.padj[2 * kk + 1]) * F * ddx * iw;
+          ury += -(ei.p - a.padj[2 * kk + 1]) * F * ddy * iw;
+          uc0 += ei.dpdc0 * W * iw;
+        }
+      }
+      // EOS chain: P(rho; c0), c(rho; c0)
+      ur += uP * ei.dPdr + uc * ei.dcdr;
+      uc0 += uP * ei.dPdc0 + uc * ei.dcdc0;
+      th_c += (double)uc0;
+      const int n = P.nf;
+      float* lb = a.lam_base;
+      if (accumulate) {
+        lb[id] += urx; lb[n + id] += ury; lb[2 * n + id] += uvx; lb[3 * n + id] += uvy; lb[4 * n + id] += ur;
+      } else {
+        lb[id] = urx; lb[n + id] = ury; lb[2 * n + id] = uvx; lb[3 * n + id] = uvy; lb[4 * n + id] = ur;
+      }
+    }
+  }
+  const double ta = block_sum(th_a, shd), td = block_sum(th_d, shd), tc = block_sum(th_c, shd);
+  if (threadIdx.x == 0) {
+    double* o = a.theta_part + (size_t)(block0 + blockIdx.x) * 3;
+    o[0] = ta;
+    o[1] = td;
+    o[2] = tc;
+  }
+}
+
+// theta += sum of the per-block partials in block order (FP64).
+__global__ void k_adj_theta(AdjPtrs a, int nblk) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double t0 = 0, t1 = 0, t2 = 0;
+  for (int b = 0; b < nblk; ++b) {
+    t0 += a.theta_part[3 * b];
+    t1 += a.theta_part[3 * b + 1];
+    t2 += a.theta_part[3 * b + 2];
+  }
+  a.theta[0] += t0;
+  a.theta[1] += t1;
+  a.theta[2] += t2;
+}
+
+// ---------------------------------------------------------------------------
+// Backward pass of one evaluation's rates (ghost adjoints, fluid adjoints,
+// coefficient partials). lam_f (by id) -> lam_base (by id).
+void wc_enqueue_adj_rates(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_eval, float probe_seed,
+                          bool accumulate, hipStream_t st) {
+  const InstParams* P = nullptr;
+  (void)P;
+  const int ns = (d.n_slots + 255) / 256;
+  k_adj_gather<<<ns, 256, 0, st>>>(d, a, te);
+  const int ngb = (a.n_ghost_probe + 255) / 256;
+  k_adj_ghost<<<ngb, 256, 0, st>>>(d, a, te, t_eval, ngb);
+  k_adj_fluid<<<ns, 256, 0, st>>>(d, a, te, probe_seed, accumulate ? 1 : 0, ngb);
+  k_adj_theta<<<1, 64, 0, st>>>(a, ngb + ns);
+}
+
+void wc_enqueue_adj_enforce(const Dev& d, const AdjPtrs& a, int nf, double te, float hdt, bool accumulate,
+                            hipStream_t st) {
+  k_adj_enforce<<<(nf + 255) / 256, 256, 0, st>>>(d, a, te, hdt, accumulate ? 1 : 0);
+}

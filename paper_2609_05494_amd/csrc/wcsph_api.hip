@@ -75,6 +75,23 @@ struct wcsph_ctx {
   double* d_dt = nullptr;
   size_t d_dt_cap = 0;
   bool dead = false;
+  // reverse sweep
+  struct Adj {
+    bool fwd_done = false;
+    int n_steps = 0, ckpt = 0, n_seg = 0;
+    long long step0 = 0;
+    std::vector<double> t, dt;         // time and step of every forward step
+    std::vector<char*> ckpt_dev;       // state at each segment start, then the end state
+    size_t ckpt_bytes = 0;
+    int tape_steps = 0;                // taped steps allocated
+    std::vector<TapeEval> tA, tB;
+    std::vector<double2*> pA, pB;
+    std::vector<float4*> vA, vB;
+    AdjPtrs a{};
+    float *L0 = nullptr, *L1 = nullptr, *Ls = nullptr;
+    int nblk = 0;
+    double J = 0.0;
+  } adj;
 };
 
 namespace {
@@ -203,6 +220,8 @@ InstParams derive(const wcsph_params& p) {
   q.gy = (float)p.gravity_y;
   q.two_delta_h_c0 = (float)(2.0 * p.delta * h * p.c0);
   q.four_nu0 = (float)(4.0 * p.mu_dyn / p.rho0);
+  q.delta = (float)p.delta;
+  q.two_h_c0 = (float)(2.0 * h * p.c0);
   q.m_fluid = (float)(p.rho0 * p.dx * p.dx);
   q.m_wall = (float)(p.rho0 * p.dx * p.dx);
   q.m_disk = p.n_disk_ghosts > 0 ? (float)(p.rho0 * p.dx * 2.0 * M_PI * p.disk_R / p.n_disk_ghosts) : 0.0f;
@@ -551,6 +570,81 @@ std::vector<T> d2h(wcsph_ctx* c, const T* p, size_t n) {
   std::vector<T> v(n);
   if (n) HC(hipMemcpy(v.data(), p, n * sizeof(T), hipMemcpyDeviceToHost));
   return v;
+}
+
+// Device-side checkpoint of the whole evolving state (X buffer with its
+// sort bookkeeping, clocks, bucket counts, ghost slots).
+size_t ckpt_size(const wcsph_ctx* c) {
+  return (size_t)c->n_slots * 44 + (size_t)c->n_inst * sizeof(Clock) + (size_t)c->n_cells * 4 +
+         (size_t)c->n_ghost * 4 + 256;
+}
+void ckpt_copy(wcsph_ctx* c, char* blob, bool save) {
+  const size_t N = c->n_slots;
+  size_t off = 0;
+  auto mv = [&](void* dev, size_t bytes) {
+    if (save) HC(hipMemcpyAsync(blob + off, dev, bytes, hipMemcpyDeviceToDevice, c->st));
+    else HC(hipMemcpyAsync(dev, blob + off, bytes, hipMemcpyDeviceToDevice, c->st));
+    off += (bytes + 15) & ~size_t(15);
+  };
+  mv(c->b.X.cell, N * 4);
+  mv(c->b.X.id, N * 4);
+  mv(c->b.X.pv, N * 16);
+  mv(c->b.X.aux, N * 16);
+  mv(c->b.X.bslot, N * 4);
+  mv(c->d_clk, c->n_inst * sizeof(Clock));
+  mv(c->d.count, (size_t)c->n_cells * 4);
+  mv(c->d.gslot, (size_t)c->n_ghost * 4);
+}
+
+void alloc_tape(wcsph_ctx* c, int steps) {
+  auto& A = c->adj;
+  if (A.tape_steps >= steps) return;
+  const size_t N = c->n_slots, nf = c->hp[0].nf;
+  for (int k = A.tape_steps; k < steps; ++k) {
+    for (int e = 0; e < 2; ++e) {
+      TapeEval t;
+      t.cell = dalloc_n<uint32_t>(c, N);
+      t.id = dalloc_n<uint32_t>(c, N);
+      t.pv = dalloc_n<float4>(c, N);
+      t.aux = dalloc_n<float4>(c, N);
+      t.start = dalloc_n<uint32_t>(c, (size_t)c->n_cells + 1);
+      t.gslot = dalloc_n<uint32_t>(c, (size_t)c->n_ghost);
+      (e == 0 ? A.tA : A.tB).push_back(t);
+      (e == 0 ? A.pA : A.pB).push_back(dalloc_n<double2>(c, nf));
+      (e == 0 ? A.vA : A.vB).push_back(dalloc_n<float4>(c, nf));
+    }
+  }
+  A.tape_steps = steps;
+}
+
+void tape_copy(wcsph_ctx* c, const Buf& b, const TapeEval& t) {
+  const size_t N = c->n_slots;
+  HC(hipMemcpyAsync(t.cell, b.cell, N * 4, hipMemcpyDeviceToDevice, c->st));
+  HC(hipMemcpyAsync(t.id, b.id, N * 4, hipMemcpyDeviceToDevice, c->st));
+  HC(hipMemcpyAsync(t.pv, b.pv, N * 16, hipMemcpyDeviceToDevice, c->st));
+  HC(hipMemcpyAsync(t.aux, b.aux, N * 16, hipMemcpyDeviceToDevice, c->st));
+  HC(hipMemcpyAsync(t.start, c->d.start, ((size_t)c->n_cells + 1) * 4, hipMemcpyDeviceToDevice, c->st));
+  HC(hipMemcpyAsync(t.gslot, c->d.gslot, (size_t)c->n_ghost * 4, hipMemcpyDeviceToDevice, c->st));
+}
+
+// Re-run local steps [0, n) of a segment from its checkpoint with plain
+// launches, taping each evaluation's sorted state and pre-enforcement state.
+void replay_taped(wcsph_ctx* c, int n) {
+  auto& A = c->adj;
+  for (int k = 0; k < n; ++k) {
+    Dev dA = c->d;
+    dA.tape_pos = A.pA[k];
+    dA.tape_vel = A.vA[k];
+    wc_enqueue_eval(dA, c->b, c->n_gblk, EV_A, c->st);
+    HC(hipGetLastError());
+    tape_copy(c, c->b.Y, A.tA[k]);
+    Dev dB = c->d;
+    dB.tape_pos = A.pB[k];
+    dB.tape_vel = A.vB[k];
+    wc_enqueue_eval(dB, c->b, c->n_gblk, EV_B, c->st);
+    HC(hipGetLastError());
+    tape_copy(c, c->b.W, A.tB[k]);
+  }
 }
 
 }  // namespace
@@ -998,6 +1092,148 @@ wcsph_status wcsph_time_pair_kernel(wcsph_ctx* ctx, int reps, float* avg_ms) {
   hipEventDestroy(e1);
   *avg_ms = ms / reps;
   guard.restore();
+  API_END(ctx)
+}
+
+wcsph_status wcsph_set_coefficients(wcsph_ctx* ctx, int inst, double alpha, double delta, double c0) {
+  API_BEGIN(ctx)
+  require(inst >= 0 && inst < ctx->n_inst, "instance out of range");
+  require(alpha >= 0 && delta >= 0 && c0 > 0 && std::isfinite(alpha + delta + c0), "invalid coefficients");
+  wcsph_params p = ctx->pin[inst];
+  p.alpha = alpha;
+  p.delta = delta;
+  p.c0 = c0;
+  InstParams q = derive(p);
+  InstParams& o = ctx->hp[inst];
+  // keep layout and geometry, take the re-derived scheme constants
+  q.ncx = o.ncx; q.ncy = o.ncy; q.cell_off = o.cell_off; q.ncell = o.ncell;
+  q.id0 = o.id0; q.nf = o.nf; q.nw = o.nw; q.nd = o.nd; q.gmap0 = o.gmap0;
+  q.n_probes = o.n_probes;
+  for (int k = 0; k < WC_MAX_PROBES; ++k) {
+    q.probe_cell[k] = o.probe_cell[k];
+    q.probe_ox[k] = o.probe_ox[k];
+    q.probe_oy[k] = o.probe_oy[k];
+  }
+  q.kin_mode = o.kin_mode; q.kin_v0 = o.kin_v0; q.kin_t_ramp = o.kin_t_ramp; q.kin_coef = o.kin_coef;
+  o = q;
+  ctx->pin[inst] = p;
+  sync(ctx);
+  HC(hipMemcpy(ctx->d_prm + inst, &o, sizeof(InstParams), hipMemcpyHostToDevice));
+  API_END(ctx)
+}
+
+wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, double* J) {
+  API_BEGIN(ctx)
+  require(!ctx->batch && ctx->n_inst == 1, "the reverse sweep needs a single-instance context");
+  require(ctx->pin[0].ghost_rho_mode == 0, "the reverse sweep supports the linear ghost density only");
+  require(ctx->pin[0].init_mode == 0, "the reverse sweep needs the rest initial state");
+  require(n_steps >= 1 && ckpt_every >= 1, "n_steps and ckpt_every must be >= 1");
+  const long long k0 = ctx->steps - ctx->d.dt_step0;
+  require(ctx->d.n_dt > 0 && k0 >= 0 && k0 + n_steps <= ctx->d.n_dt,
+          "a fixed dt table covering the run is required (wcsph_set_dt_table)");
+  auto& A = ctx->adj;
+  A.fwd_done = false;
+  A.n_steps = n_steps;
+  A.ckpt = ckpt_every;
+  A.n_seg = (n_steps + ckpt_every - 1) / ckpt_every;
+  A.step0 = ctx->steps;
+  std::vector<double> tab(ctx->d.n_dt);
+  sync(ctx);
+  HC(hipMemcpy(tab.data(), ctx->d_dt, tab.size() * 8, hipMemcpyDeviceToHost));
+  Clock ck;
+  HC(hipMemcpy(&ck, ctx->d_clk, sizeof ck, hipMemcpyDeviceToHost));
+  A.t.assign(n_steps, 0.0);
+  A.dt.assign(n_steps, 0.0);
+  double t = ck.t_next;
+  for (int k = 0; k < n_steps; ++k) {
+    A.t[k] = t;
+    A.dt[k] = tab[k0 + k];
+    t = t + A.dt[k];
+  }
+  A.ckpt_bytes = ckpt_size(ctx);
+  while ((int)A.ckpt_dev.size() < A.n_seg + 1) A.ckpt_dev.push_back(static_cast<char*>(dalloc(ctx, A.ckpt_bytes)));
+  ctx->hist_read[0] = ctx->steps;
+  for (int g = 0; g < A.n_seg; ++g) {
+    ckpt_copy(ctx, A.ckpt_dev[g], true);
+    const int n = std::min(ckpt_every, n_steps - g * ckpt_every);
+    for (int k = 0; k < n; ++k) HC(hipGraphLaunch(ctx->gexec, ctx->st));
+    ctx->steps += n;
+  }
+  ckpt_copy(ctx, A.ckpt_dev[A.n_seg], true);
+  // J = sum_n sum_k p_k^n dt_n (probe rows of this run)
+  sync(ctx);
+  const int np = ctx->hp[0].n_probes;
+  std::vector<float> pr((size_t)n_steps * WC_MAX_PROBES);
+  double Jv = 0.0;
+  for (int k = 0; k < n_steps; ++k) {
+    const size_t row = (size_t)((A.step0 + k) % WC_HIST_CAP);
+    float v[WC_MAX_PROBES];
+    HC(hipMemcpy(v, ctx->d.hist_p + row * WC_MAX_PROBES, sizeof v, hipMemcpyDeviceToHost));
+    for (int j = 0; j < np; ++j) Jv += (double)v[j] * A.dt[k];
+  }
+  ctx->hist_read[0] = ctx->steps;
+  A.J = Jv;
+  A.fwd_done = true;
+  if (J) *J = Jv;
+  API_END(ctx)
+}
+
+wcsph_status wcsph_adj_backward(wcsph_ctx* ctx, double dJ, double* grad) {
+  API_BEGIN(ctx)
+  auto& A = ctx->adj;
+  if (!A.fwd_done) throw WcError{WCSPH_E_STATE, "wcsph_adj_forward must run first"};
+  require(grad != nullptr, "grad[3] required");
+  const InstParams& q = ctx->hp[0];
+  const int nf = q.nf;
+  alloc_tape(ctx, A.ckpt);
+  if (!A.L0) {
+    A.L0 = dalloc_n<float>(ctx, (size_t)5 * nf);
+    A.L1 = dalloc_n<float>(ctx, (size_t)5 * nf);
+    A.Ls = dalloc_n<float>(ctx, (size_t)5 * nf);
+    A.a.lam_f = dalloc_n<float>(ctx, (size_t)5 * nf);
+    A.a.lam_s = dalloc_n<float>(ctx, (size_t)5 * ctx->n_slots);
+    A.a.gadj = dalloc_n<float>(ctx, (size_t)10 * ctx->n_slots);
+    A.a.padj = dalloc_n<float>(ctx, 2 * WC_MAX_PROBES);
+    A.a.n_ghost_probe = q.nw + q.nd + q.n_probes;
+    A.nblk = (A.a.n_ghost_probe + 255) / 256 + (ctx->n_slots + 255) / 256;
+    A.a.theta_part = dalloc_n<double>(ctx, (size_t)3 * A.nblk);
+    A.a.theta = dalloc_n<double>(ctx, 3);
+  }
+  HC(hipMemsetAsync(A.L1, 0, (size_t)5 * nf * 4, ctx->st));
+  HC(hipMemsetAsync(A.a.theta, 0, 3 * 8, ctx->st));
+  const long long steps_after = ctx->steps;
+  for (int g = A.n_seg - 1; g >= 0; --g) {
+    const int n = std::min(A.ckpt, A.n_steps - g * A.ckpt);
+    ckpt_copy(ctx, A.ckpt_dev[g], false);
+    replay_taped(ctx, n);
+    for (int k = n - 1; k >= 0; --k) {
+      const int st = g * A.ckpt + k;
+      const double t = A.t[st], dt = A.dt[st];
+      AdjPtrs a = A.a;
+      // corrector: U^{n+1} = E_B(U^n + dt f(U*))
+      a.lam_out = A.L1;
+      a.lam_base = A.L0;
+      a.pre_pos = A.pB[k];
+      a.pre_vel = A.vB[k];
+      wc_enqueue_adj_enforce(ctx->d, a, nf, t + dt, (float)dt, false, ctx->st);
+      a.lam_base = A.Ls;
+      wc_enqueue_adj_rates(ctx->d, a, A.tB[k], t + 0.5 * dt, 0.0f, false, ctx->st);
+      // predictor: U* = E_A(U^n + dt/2 f(U^n)); probes of step n
+      a.lam_out = A.Ls;
+      a.lam_base = A.L0;
+      a.pre_pos = A.pA[k];
+      a.pre_vel = A.vA[k];
+      wc_enqueue_adj_enforce(ctx->d, a, nf, t + 0.5 * dt, (float)(0.5 * dt), true, ctx->st);
+      wc_enqueue_adj_rates(ctx->d, a, A.tA[k], t, (float)(dJ * dt), true, ctx->st);
+      HC(hipGetLastError());
+      std::swap(A.L0, A.L1);
+    }
+  }
+  // back to the state at the end of the forward run
+  ckpt_copy(ctx, A.ckpt_dev[A.n_seg], false);
+  ctx->steps = steps_after;
+  sync(ctx);
+  HC(hipMemcpy(grad, A.a.theta, 3 * 8, hipMemcpyDeviceToHost));
   API_END(ctx)
 }
 

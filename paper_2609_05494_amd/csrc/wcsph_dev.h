@@ -33,7 +33,7 @@ struct InstParams {
   // pair arithmetic (FP32)
   float h, inv_h, four_h2, sigma, fgrad, eta2h2;
   float rho0, c0, B, p_cav, alpha, eps_xsph, gy;
-  float two_delta_h_c0, four_nu0;
+  float two_delta_h_c0, four_nu0, delta, two_h_c0;
   float m_fluid, m_wall, m_disk;
   float rho_lo, rho_hi, inv_rho0c02, c_exp, gamma, inv_gamma;
   int ghost_rho_mode;
@@ -99,6 +99,34 @@ struct Dev {
   float* xr;                  // export: [5][n_slots] rates per slot
   int* nb_count;              // export: neighbour count per slot
   long long* nb_idsum;        // export: neighbour id sum per slot
+  double2* tape_pos;          // reverse sweep: pre-enforcement position per fluid id (or NULL)
+  float4* tape_vel;           // reverse sweep: pre-enforcement (vx, vy, rho, 0) per fluid id
+};
+
+// One taped evaluation for the reverse sweep: the sorted state (with ghost
+// states), its cell ranges and ghost slots.
+struct TapeEval {
+  uint32_t* cell;
+  uint32_t* id;
+  float4* pv;
+  float4* aux;
+  uint32_t* start;
+  uint32_t* gslot;
+};
+
+// Reverse-sweep work arrays (adjoints by fluid id unless stated).
+struct AdjPtrs {
+  float* lam_out;      // [5][nf] adjoint of the evaluation's output state (x, y, vx, vy, rho)
+  float* lam_base;     // [5][nf] adjoint of the base / evaluated state
+  float* lam_f;        // [5][nf] rate adjoints (D, ax, ay, Vx, Vy)
+  float* lam_s;        // [5][n_slots] rate adjoints in sorted slot order
+  float* gadj;         // [n_slots][10] ghost adjoint and Shepard data
+  float* padj;         // [16][2] probe Shepard sums
+  double2* pre_pos;    // taped pre-enforcement state of the evaluation
+  float4* pre_vel;
+  double* theta_part;  // per-block partial coefficient gradients [blocks][3]
+  double* theta;       // dJ/d(alpha, delta, c0), FP64
+  int n_ghost_probe;
 };
 
 enum { EV_A = 0, EV_B = 1, EV_EXPORT = 2 };

@@ -756,6 +756,11 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     // enforcement in FP64: hard walls, then radial pull-out from the disk
     double x = P.x_lo + (double)cx * P.dcd + (double)ox;
     double y = P.y_lo + (double)cy * P.dcd + (double)oy;
+    if (d.tape_pos != nullptr) {  // pre-enforcement state for the reverse sweep
+      const int fid = (int)sb.id[s] - P.id0;
+      d.tape_pos[fid] = make_double2(x, y);
+      d.tape_vel[fid] = make_float4(vx, vy, rb + hdt * acc.D, 0.0f);
+    }
     bool moved = false;
     const double e = P.eps_wall;
     if (x < e) { x = e; vx = -vx; moved = true; }
@@ -1027,4 +1032,16 @@ void wc_enqueue_pair_a(const Dev& d, const Bufs& b, bool batch, hipStream_t st) 
 
 void wc_enqueue_neigh(const Dev& d, const Bufs& b, hipStream_t st) {
   k_neigh<<<NB(d.n_slots), WC_BLOCK, 0, st>>>(d, b.Y);
+}
+
+void wc_enqueue_eval(const Dev& d, const Bufs& b, int n_gblk, int mode, hipStream_t st) {
+  if (mode == EV_A) {
+    eval_sort<false>(d, st, EV_A, b.X, b.Y, b.Y, b.Y);
+    k_ghost<EV_A, false><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
+    k_pair<EV_A, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
+  } else {
+    eval_sort<false>(d, st, EV_B, b.Z, b.W, b.Y, b.X);
+    k_ghost<EV_B, false><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.W);
+    k_pair<EV_B, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.X, b.X);
+  }
 }

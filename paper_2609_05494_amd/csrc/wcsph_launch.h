@@ -19,3 +19,12 @@ void wc_enqueue_export_ghosts(const Dev& d, const Bufs& b, int n_gblk, hipStream
 void wc_enqueue_export_pair(const Dev& d, const Bufs& b, hipStream_t st);
 void wc_enqueue_pair_a(const Dev& d, const Bufs& b, bool batch, hipStream_t st);
 void wc_enqueue_neigh(const Dev& d, const Bufs& b, hipStream_t st);
+
+// One evaluation (A: sort of X into Y, ghosts, pair sums + predictor into Z;
+// B: sort of Z into W with state n into X, ghosts, pair sums + corrector)
+// with plain launches; single instance.
+void wc_enqueue_eval(const Dev& d, const Bufs& b, int n_gblk, int mode, hipStream_t st);
+void wc_enqueue_adj_rates(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_eval, float probe_seed,
+                          bool accumulate, hipStream_t st);
+void wc_enqueue_adj_enforce(const Dev& d, const AdjPtrs& a, int nf, double te, float hdt, bool accumulate,
+                            hipStream_t st);
