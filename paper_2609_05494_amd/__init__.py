@@ -10,8 +10,10 @@ present; there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -173,7 +175,23 @@ class _TorchMemory:
             return None
 
     def _do_free(self, ptr, stream, user):
-        self.torch.cuda.caching_allocator_delete(ptr)
+        cuda = getattr(self.torch, "cuda", None)
+        if cuda is not None and getattr(cuda, "caching_allocator_delete", None) is not None:
+            cuda.caching_allocator_delete(ptr)
+        # else: interpreter shutdown, the process releases the memory
+
+
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Destroy open contexts while PyTorch is still alive."""
+    for s in list(_live):
+        try:
+            s.close()
+        except Exception:
+            pass
 
 
 class Solver:
@@ -207,6 +225,7 @@ class Solver:
             self.sizes.append((nf.value, ng.value, nc.value))
         self.nf, self.ng, self.ncells = self.sizes[0]
         self.n_probes = [len(c.get("probes", [])) for c in self.cfgs]
+        _live.add(self)
 
     def _check(self, st):
         if st != OK:

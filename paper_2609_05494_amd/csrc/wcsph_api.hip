@@ -139,7 +139,7 @@ void validate(const wcsph_params& p) {
   require(p.rho_lo > 0 && p.rho_hi > p.rho_lo, "density band must satisfy 0 < rho_lo < rho_hi");
   require(p.eps_wall >= 0 && p.eps_wall < 0.5 * p.dx, "eps_wall must lie in [0, dx/2)");
   require(p.ghost_layers >= 1 && p.ghost_layers <= 8, "ghost_layers must lie in [1, 8]");
-  require(p.n_disk_ghosts >= 0 && p.n_disk_ghosts <= WC_MAX_RING_BLOCKS * WC_GHOST_BLOCK / 4,
+  require(p.n_disk_ghosts >= 0 && p.n_disk_ghosts <= WC_MAX_RING,
           "n_disk_ghosts must lie in [0, 256]");
   require(p.ghost_rho_mode == 0 || p.ghost_rho_mode == 1, "ghost_rho_mode must be 0 or 1");
   require(p.init_mode == 0 || p.init_mode == 1, "init_mode must be 0 or 1");
@@ -423,10 +423,10 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
       encode(q, c->geo[i].wx[k], c->geo[i].wy[k], key, ox, oy);
       c->h_wrank[q.gmap0 + k] = c->h_wallcount[key]++;
     }
-    const int gq = WC_GHOST_BLOCK / 4;  // ghosts per block, four lanes each
+    const int gq = WC_GHOST_BLOCK / WC_GHOST_LANES;  // ghosts or probes per block
     for (int g0 = 0; g0 < q.nw; g0 += gq) c->h_gblk.push_back(make_int4(i, g0, std::min(gq, q.nw - g0), 0));
     for (int g0 = 0; g0 < q.nd; g0 += gq) c->h_gblk.push_back(make_int4(i, q.nw + g0, std::min(gq, q.nd - g0), 1));
-    if (q.n_probes > 0) c->h_gblk.push_back(make_int4(i, 0, q.n_probes, 2));
+    for (int k0 = 0; k0 < q.n_probes; k0 += gq) c->h_gblk.push_back(make_int4(i, k0, std::min(gq, q.n_probes - k0), 2));
   }
   c->n_gblk = (int)c->h_gblk.size();
   // device memory
@@ -461,7 +461,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.hist_p = dalloc_n<float>(c, (size_t)n_inst * WC_HIST_CAP * WC_MAX_PROBES);
   d.diag = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_CAP * WC_NDIAG);
   d.diag_part = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_BLOCKS * 8);
-  d.wb_part = dalloc_n<double>(c, (size_t)n_inst * WC_MAX_RING_BLOCKS);
+  d.wb_part = dalloc_n<double>(c, (size_t)n_inst * WC_MAX_RING);
   d.xr = dalloc_n<float>(c, (size_t)5 * c->n_slots);
   d.nb_count = dalloc_n<int>(c, c->n_slots);
   d.nb_idsum = dalloc_n<long long>(c, c->n_slots);
@@ -473,7 +473,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   HC(hipMemcpyAsync(wrank, c->h_wrank.data(), (size_t)c->n_ghost * 4, hipMemcpyHostToDevice, c->st));
   HC(hipMemcpyAsync(gblk, c->h_gblk.data(), (size_t)c->n_gblk * sizeof(int4), hipMemcpyHostToDevice, c->st));
   HC(hipMemsetAsync(d.hist_p, 0, (size_t)n_inst * WC_HIST_CAP * WC_MAX_PROBES * 4, c->st));
-  HC(hipMemsetAsync(d.wb_part, 0, (size_t)n_inst * WC_MAX_RING_BLOCKS * 8, c->st));
+  HC(hipMemsetAsync(d.wb_part, 0, (size_t)n_inst * WC_MAX_RING * 8, c->st));
   c->hist_read.assign(n_inst, 0);
   c->diag_rows.assign(n_inst, 0);
   c->diag_read.assign(n_inst, 0);
@@ -730,6 +730,11 @@ wcsph_status wcsph_set_disk_kinematics(wcsph_ctx* ctx, int inst, int mode, const
   ctx->pin[inst].kin_t_ramp = coeffs[1];
   ctx->pin[inst].kin_coef = coeffs[2];
   HC(hipMemcpyAsync(ctx->d_prm + inst, &q, sizeof(InstParams), hipMemcpyHostToDevice, ctx->st));
+  // the ring of the newest state was placed with the old law: place it again
+  // (and recount the buckets of the next sort)
+  HC(hipMemcpyAsync(ctx->d.count, ctx->d_wallcount, (size_t)ctx->n_cells * 4, hipMemcpyDeviceToDevice, ctx->st));
+  wc_enqueue_init(ctx->d, ctx->b, ctx->batch, ctx->st);
+  HC(hipGetLastError());
   sync(ctx);
   API_END(ctx)
 }

@@ -18,7 +18,8 @@
 #define WC_NDIAG 15
 #define WC_BLOCK 256
 #define WC_GHOST_BLOCK 256
-#define WC_MAX_RING_BLOCKS 4   // ring ghosts per instance <= 4 * WC_GHOST_BLOCK / 4
+#define WC_GHOST_LANES 16      // lanes per ghost or probe in the ghost kernel
+#define WC_MAX_RING 256        // disk-ring ghosts per instance
 #define WC_DIAG_BLOCKS 64      // diagnostic partial sums per instance
 
 // Per-instance constants (read-only in kernels).
@@ -86,7 +87,7 @@ struct Dev {
   uint32_t* perm;             // per slot: perm[new] = old of the last sort
   uint32_t* gslot;            // per ghost: current slot
   const uint32_t* wrank;      // per ghost: static bucket rank of a wall ghost
-  const int4* gblk;           // ghost-kernel block table: (inst, first ghost, count, kind)
+  const int4* gblk;           // ghost-kernel block table: (inst, first item, count, kind)
   double* hist_t;             // [n_inst][WC_HIST_CAP]
   double* hist_dt;
   float* hist_p;              // [n_inst][WC_HIST_CAP][WC_MAX_PROBES]
@@ -95,7 +96,7 @@ struct Dev {
   long long dt_step0;
   double* diag;               // [n_inst][WC_DIAG_CAP][WC_NDIAG]
   double* diag_part;          // [n_inst][WC_DIAG_BLOCKS][8] partial sums
-  double* wb_part;            // [n_inst][WC_MAX_RING_BLOCKS] ring force partials
+  double* wb_part;            // [n_inst][WC_MAX_RING] x force of each ring ghost on the fluid
   float* xr;                  // export: [5][n_slots] rates per slot
   int* nb_count;              // export: neighbour count per slot
   long long* nb_idsum;        // export: neighbour id sum per slot

@@ -1,9 +1,9 @@
 // wcsph_kernels.hip -- HIP kernels of the planar WCSPH step for gfx950.
 //
 // One step = two evaluations (predictor-corrector). Each evaluation runs:
-//   k_kin      clock, prescribed disk kinematics, disk-ring placement and
-//              the ring's bucket slots for the next sort
-//   k_scan_*   exclusive scan of the per-cell counts -> cell ranges
+//   k_scan_*   exclusive scan of the per-cell counts -> cell ranges; the
+//              first block advances the clock and evaluates the prescribed
+//              disk kinematics
 //   k_scatter  every slot into its cell bucket
 //   k_permute  stable rank inside the bucket (by old slot) and gather of the
 //              state into sorted order; per-particle EOS (P = p/rho^2, c)
@@ -11,7 +11,8 @@
 //              v_max of the ghosts (eval A), work of the ring (eval B)
 //   k_pair     pair sums over the 3x3 cells (continuity + delta, pressure +
 //              AV + laminar, XSPH) fused with the predictor / corrector,
-//              density band, enforcement, new cell key and bucket slot
+//              density band, enforcement, new cell key and bucket slot;
+//              the disk ring is placed at the next evaluation's time
 // Pair arithmetic is FP32 on cell-relative offsets; time, kinematics,
 // enforcement geometry and diagnostics are FP64.
 
@@ -314,123 +315,155 @@ __device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, con
   flush();
 }
 
-// Shepard sums over the fluid around an encoded point (cell K, offset o),
-// restricted to one cell row (dy); four lanes cover a point (rows -1, 0, 1
-// and an idle lane) and their sums are added in a fixed order.
-struct Shep {
-  float W, p, rx, ry, vx, vy;
-};
-__device__ __forceinline__ Shep shepard_row(const Dev& d, const InstParams& P, const Buf& sb, uint32_t K,
-                                            float ox, float oy, int q) {
-  Shep S = {0, 0, 0, 0, 0, 0};
-  if (q > 2) return S;
+// Visit the candidates of the 3x3 block of cells around cell K (rows bottom
+// to top, cells left to right, sorted order inside a cell), dealt
+// round-robin to a group of G lanes (lane l takes c = l, l + G, ...) with
+// SCAN_UNROLL loads in flight. fn gets the candidate's pv and aux and its
+// cell-shift code (row << 2) | column.
+template <int G, class Fn>
+__device__ __forceinline__ void for_candidates(const Dev& d, const InstParams& P, const Buf& sb, uint32_t K,
+                                               int lane, Fn&& fn) {
   int cx, cy;
   cell_xy(P, K, cx, cy);
-  const RowRange r = row_range(d, P, cx, cy, q - 1);
-  const float shy = (float)(q - 1) * P.dc;
-  for (uint32_t j0 = r.rs; j0 < r.re; j0 += SCAN_UNROLL) {
+  const RowRange r0 = row_range(d, P, cx, cy, -1), r1 = row_range(d, P, cx, cy, 0),
+                 r2 = row_range(d, P, cx, cy, 1);
+  const uint32_t n0 = r0.re - r0.rs, n01 = n0 + (r1.re - r1.rs), n = n01 + (r2.re - r2.rs);
+  for (uint32_t c0 = (uint32_t)lane; c0 < n; c0 += G * SCAN_UNROLL) {
+    uint32_t code[SCAN_UNROLL];
     float4 pq[SCAN_UNROLL], aq[SCAN_UNROLL];
 #pragma unroll
     for (int u = 0; u < SCAN_UNROLL; ++u) {
-      const uint32_t j = min(j0 + u, r.re - 1);
+      const uint32_t c = min(c0 + G * u, n - 1);
+      const uint32_t row = c < n0 ? 0u : (c < n01 ? 1u : 2u);
+      const RowRange& r = row == 0 ? r0 : (row == 1 ? r1 : r2);
+      const uint32_t j = r.rs + c - (row == 0 ? 0u : (row == 1 ? n0 : n01));
+      code[u] = (row << 2) | dx_code(j, r);
       pq[u] = sb.pv[j];
       aq[u] = sb.aux[j];
     }
 #pragma unroll
-    for (int u = 0; u < SCAN_UNROLL; ++u) {
-      const uint32_t j = j0 + u;
-      const float4 pj = pq[u], aj = aq[u];
-      const float rx = (ox - pj.x) - ((float)dx_code(j, r) - 1.0f) * P.dc;  // r_g - r_j
-      const float ry = (oy - pj.y) - shy;
-      const float r2 = rx * rx + ry * ry;
-      if (!(j < r.re) || !(aj.w > 0.0f) || !(r2 < P.four_h2)) continue;  // fluid in support
-      float W, F;
-      wendland(P, r2, W, F);
-      const float pj_ = aj.y * aj.x * aj.x;  // p = P rho^2
-      S.W += W;
-      S.p += pj_ * W;
-      S.rx += aj.x * rx * W;
-      S.ry += aj.x * ry * W;
-      S.vx += pj.z * W;
-      S.vy += pj.w * W;
-    }
+    for (int u = 0; u < SCAN_UNROLL; ++u)
+      if (c0 + G * u < n) fn(pq[u], aq[u], code[u]);
   }
-  return S;
 }
-__device__ __forceinline__ float quad_sum(float v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
+// r_a - r_j for a point at offset (ox, oy) of the centre cell and a candidate
+// with shift code `code`
+__device__ __forceinline__ void rel_pos(const InstParams& P, float ox, float oy, const float4& pj, uint32_t code,
+                                        float& rx, float& ry) {
+  rx = (ox - pj.x) - ((float)(int)(code & 3u) - 1.0f) * P.dc;
+  ry = (oy - pj.y) - ((float)(int)(code >> 2) - 1.0f) * P.dc;
+}
+
+// Sum over a group of G consecutive lanes (xor butterfly: fixed order, the
+// same bits on every lane of the group).
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
   return v;
 }
-__device__ __forceinline__ Shep quad_sum(Shep S) {
-  S.W = quad_sum(S.W);
-  S.p = quad_sum(S.p);
-  S.rx = quad_sum(S.rx);
-  S.ry = quad_sum(S.ry);
-  S.vx = quad_sum(S.vx);
-  S.vy = quad_sum(S.vy);
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ float quad_sum(float v) { return group_sum<4>(v); }
+
+// Shepard sums over the fluid in support of an encoded point (cell K,
+// offset o), one group of G lanes per point.
+struct Shep {
+  float W, p, rx, ry, vx, vy;
+};
+template <int G>
+__device__ __forceinline__ Shep shepard(const Dev& d, const InstParams& P, const Buf& sb, uint32_t K, float ox,
+                                        float oy, int lane) {
+  Shep S = {0, 0, 0, 0, 0, 0};
+  for_candidates<G>(d, P, sb, K, lane, [&](const float4& pj, const float4& aj, uint32_t code) __attribute__((always_inline)) {
+    float rx, ry;  // r_g - r_j
+    rel_pos(P, ox, oy, pj, code, rx, ry);
+    const float r2 = rx * rx + ry * ry;
+    if (!(aj.w > 0.0f) || !(r2 < P.four_h2)) return;  // fluid in support only
+    float W, F;
+    wendland(P, r2, W, F);
+    const float pj_ = aj.y * aj.x * aj.x;  // p = P rho^2
+    S.W += W;
+    S.p += pj_ * W;
+    S.rx += aj.x * rx * W;
+    S.ry += aj.x * ry * W;
+    S.vx += pj.z * W;
+    S.vy += pj.w * W;
+  });
+  S.W = group_sum<G>(S.W);
+  S.p = group_sum<G>(S.p);
+  S.rx = group_sum<G>(S.rx);
+  S.ry = group_sum<G>(S.ry);
+  S.vx = group_sum<G>(S.vx);
+  S.vy = group_sum<G>(S.vy);
   return S;
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Clock, kinematics and disk-ring placement; one block per instance.
+// Clock of one instance at the start of an evaluation (one thread):
+//   EV_A     commit the previous step (t = t_next, step + 1), evaluate at t
+//   EV_B     dt of the step from v_max (or the fixed table), start the next
+//            v_max, record (t, dt); evaluate at t + dt/2
+//   EV_EXPORT evaluate the newest state at t_next without advancing
+// The disk kinematics at the evaluation time feed the ghost kernel.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_kin(Dev d, Buf pre) {
-  const int i = blockIdx.x;
+__device__ void clock_commit(const Dev& d, int i) {
   const InstParams& P = d.prm[i];
   Clock& C = d.clk[i];
-  __shared__ double sh[3];
-  if (threadIdx.x == 0) {
-    double te;
-    if (MODE == EV_A) {
-      C.t = C.t_next;
-      C.step += 1;
-      te = C.t;
-    } else if (MODE == EV_B) {
-      const double dt = step_dt(d, P, C);
-      C.dt = dt;
-      C.vmax_used = (double)__uint_as_float(C.vmax_bits);
-      C.vmax_bits = 0u;
-      const long long row = (long long)i * WC_HIST_CAP + (C.step % WC_HIST_CAP);
-      d.hist_t[row] = C.t;
-      d.hist_dt[row] = dt;
-      te = C.t + 0.5 * dt;
-    } else {
-      te = C.t_next;
-    }
-    double x, v, a;
-    kinematics(P, te, x, v, a);
-    C.t_eval = te;
-    C.xd = x;
-    C.vd = v;
-    C.ad = a;
-    sh[0] = x;
+  double te;
+  if (MODE == EV_A) {
+    C.t = C.t_next;
+    C.step += 1;
+    te = C.t;
+  } else if (MODE == EV_B) {
+    const double dt = step_dt(d, P, C);
+    C.dt = dt;
+    C.vmax_used = (double)__uint_as_float(C.vmax_bits);
+    C.vmax_bits = 0u;
+    const long long row = (long long)i * WC_HIST_CAP + (C.step % WC_HIST_CAP);
+    d.hist_t[row] = C.t;
+    d.hist_dt[row] = dt;
+    te = C.t + 0.5 * dt;
+  } else {
+    te = C.t_next;
   }
-  __syncthreads();
-  const double xc = sh[0];
-  for (int k = threadIdx.x; k < P.nd; k += blockDim.x) {
-    double sn, cs;
-    sincos(2.0 * M_PI * (double)k / (double)P.nd, &sn, &cs);
-    const double x = xc + P.R * cs, y = P.disk_y0 + P.R * sn;
-    int cx, cy;
-    float ox, oy;
-    encode_axis(x, P.x_lo, P.dcd, P.dc, P.ncx, cx, ox);
-    encode_axis(y, P.y_lo, P.dcd, P.dc, P.ncy, cy, oy);
-    const uint32_t key = (uint32_t)(P.cell_off + cy * P.ncx + cx);
-    const uint32_t s = d.gslot[P.gmap0 + P.nw + k];
-    pre.cell[s] = key;
-    pre.pv[s] = make_float4(ox, oy, 0.0f, 0.0f);
-    pre.bslot[s] = atomicAdd(&d.count[key], 1u);
-  }
+  double x, v, a;
+  kinematics(P, te, x, v, a);
+  C.t_eval = te;
+  C.xd = x;
+  C.vd = v;
+  C.ad = a;
+}
+
+// Disk-ring ghost k at time te: r_k = c(te) + R (cos 2 pi k / nd, sin 2 pi k / nd),
+// encoded, with its bucket slot for the next sort.
+__device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, int k, double te, const Buf& out,
+                                           int s) {
+  double xc, v, a;
+  kinematics(P, te, xc, v, a);
+  double sn, cs;
+  sincos(2.0 * M_PI * (double)k / (double)P.nd, &sn, &cs);
+  const double x = xc + P.R * cs, y = P.disk_y0 + P.R * sn;
+  int cx, cy;
+  float ox, oy;
+  encode_axis(x, P.x_lo, P.dcd, P.dc, P.ncx, cx, ox);
+  encode_axis(y, P.y_lo, P.dcd, P.dc, P.ncy, cy, oy);
+  const uint32_t key = (uint32_t)(P.cell_off + cy * P.ncx + cx);
+  out.cell[s] = key;
+  out.pv[s] = make_float4(ox, oy, 0.0f, 0.0f);
+  out.bslot[s] = atomicAdd(&d.count[key], 1u);
 }
 
 // Exclusive scan of count -> start over all cells in two passes over tiles
 // of SCAN_TILE cells (four consecutive cells per thread, coalesced uint4
-// loads): k_scan_sum writes each tile's total, k_scan_apply adds the totals
-// of the preceding tiles and scans its own tile. count is re-armed with the
-// static wall-ghost occupancy for the next sort.
+// loads): k_scan_sum writes each tile's total (and its first block advances
+// the clocks), k_scan_apply adds the totals of the preceding tiles and scans
+// its own tile. count is re-armed with the static wall-ghost occupancy for
+// the next sort.
 #define SCAN_TILE 4096
 __device__ __forceinline__ void load4(const uint32_t* p, int i0, int n, uint32_t a[4]) {
   if (i0 + 3 < n) {
@@ -441,8 +474,11 @@ __device__ __forceinline__ void load4(const uint32_t* p, int i0, int n, uint32_t
   }
 }
 
+template <int MODE>
 __global__ __launch_bounds__(1024) void k_scan_sum(Dev d) {
   __shared__ uint32_t wsum[16];
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < d.n_inst; i += blockDim.x) clock_commit<MODE>(d, i);
   const int n = d.n_cells, t = threadIdx.x;
   uint32_t a[4];
   load4(d.count, blockIdx.x * SCAN_TILE + 4 * t, n, a);
@@ -570,24 +606,24 @@ __global__ __launch_bounds__(128) void k_permute(Dev d, Buf pre, Buf out, Buf pr
 }
 
 // Adami ghost state (walls and ring), probes, ghost v_max and ring work.
-// Four lanes per ghost or probe, one cell row each. Block table entry:
-// (instance, first item, item count, kind); kind 0 wall ghosts, 1 ring
-// ghosts (work partial (first - nw) / GQ), 2 probes.
-#define GQ (WC_GHOST_BLOCK / 4)
+// WC_GHOST_LANES lanes per ghost or probe share its 3x3 candidates. Block
+// table entry: (instance, first item, item count, kind); kind 0 wall ghosts,
+// 1 ring ghosts, 2 probes.
+#define GL WC_GHOST_LANES
 template <int MODE, bool BATCH>
 __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
   const int4 blk = d.gblk[blockIdx.x];
   const int inst = blk.x, kind = blk.w;
   const InstParams& P = d.prm[inst];
   Clock& C = d.clk[inst];
-  const int t = threadIdx.x, qd = t >> 2, q = t & 3;
-  const bool act = qd < blk.z;
+  const int t = threadIdx.x, item = t / GL, lane = t % GL;
+  const bool act = item < blk.z;
   if (kind == 2) {
     // probes: Shepard average of the fluid pressure at fixed wall points
     if (MODE == EV_A && act) {
-      const int k = blk.y + qd;
-      const Shep S = quad_sum(shepard_row(d, P, sb, P.probe_cell[k], P.probe_ox[k], P.probe_oy[k], q));
-      if (q == 0) {
+      const int k = blk.y + item;
+      const Shep S = shepard<GL>(d, P, sb, P.probe_cell[k], P.probe_ox[k], P.probe_oy[k], lane);
+      if (lane == 0) {
         const long long row = (long long)inst * WC_HIST_CAP + (C.step % WC_HIST_CAP);
         d.hist_p[row * WC_MAX_PROBES + k] = S.W > 0.0f ? S.p / S.W : 0.0f;
       }
@@ -595,13 +631,13 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
     return;
   }
   const bool disk = kind == 1;
-  float vmag = 0.0f, fx = 0.0f;
+  float vmag = 0.0f;
   if (act) {
-    const int g = blk.y + qd;
+    const int g = blk.y + item;
     const uint32_t s = d.gslot[P.gmap0 + g];
     const uint32_t K = sb.cell[s];
     const float4 pg = sb.pv[s];
-    const Shep S = quad_sum(shepard_row(d, P, sb, K, pg.x, pg.y, q));
+    const Shep S = shepard<GL>(d, P, sb, K, pg.x, pg.y, lane);
     const float vwx = disk ? (float)C.vd : 0.0f;
     const float awx = disk ? (float)C.ad : 0.0f;
     float p, vgx, vgy;
@@ -623,59 +659,41 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
     const float Pg = p / (rg * rg);
     const float cg = P.c0 * expf(P.c_exp * log1pf((rg - P.rho0) / P.rho0));
     const float m = disk ? P.m_disk : P.m_wall;
-    if (q == 0) {
+    if (lane == 0) {
       sb.pv[s] = make_float4(pg.x, pg.y, vgx, vgy);
       sb.aux[s] = make_float4(rg, Pg, cg, -m);
       vmag = fast_sqrt(vgx * vgx + vgy * vgy);
     }
     if (MODE == EV_B && disk) {
       // x force of this ring ghost on its fluid neighbours (pressure + AV)
-      if (q < 3) {
-        int cx, cy;
-        cell_xy(P, K, cx, cy);
-        const RowRange r = row_range(d, P, cx, cy, q - 1);
-        const float shy = (float)(q - 1) * P.dc;
-        for (uint32_t j = r.rs; j < r.re; ++j) {
-          const float4 aj = sb.aux[j];
-          const float4 pj = sb.pv[j];
-          if (!(aj.w > 0.0f)) continue;
-          const float rx = (pj.x - pg.x) + ((float)dx_code(j, r) - 1.0f) * P.dc;  // r_i - r_g
-          const float ry = (pj.y - pg.y) + shy;
-          const float r2 = rx * rx + ry * ry;
-          if (!(r2 < P.four_h2)) continue;
-          float W, F;
-          wendland(P, r2, W, F);
-          const float vr = (pj.z - vgx) * rx + (pj.w - vgy) * ry;
-          const float rsum = aj.x + rg, den = r2 + P.eta2h2;
-          const float inv = fast_rcp(den * rsum);
-          const float piav = vr < 0.0f ? -P.alpha * (aj.z + cg) * P.h * vr * inv : 0.0f;
-          fx -= aj.w * m * (aj.y + Pg + piav) * F * rx;
-        }
-      }
-      fx = quad_sum(fx);
-      if (q != 0) fx = 0.0f;
+      float fx = 0.0f;
+      for_candidates<GL>(d, P, sb, K, lane, [&](const float4& pj, const float4& aj, uint32_t code) __attribute__((always_inline)) {
+        if (!(aj.w > 0.0f)) return;
+        float rx, ry;
+        rel_pos(P, pg.x, pg.y, pj, code, rx, ry);
+        rx = -rx;  // r_i - r_g
+        ry = -ry;
+        const float r2 = rx * rx + ry * ry;
+        if (!(r2 < P.four_h2)) return;
+        float W, F;
+        wendland(P, r2, W, F);
+        const float vr = (pj.z - vgx) * rx + (pj.w - vgy) * ry;
+        const float rsum = aj.x + rg, den = r2 + P.eta2h2;
+        const float inv = fast_rcp(den * rsum);
+        const float piav = vr < 0.0f ? -P.alpha * (aj.z + cg) * P.h * vr * inv : 0.0f;
+        fx -= aj.w * m * (aj.y + Pg + piav) * F * rx;
+      });
+      const double f = group_sum<GL>((double)fx);
+      if (lane == 0) d.wb_part[inst * WC_MAX_RING + (g - P.nw)] = f;
     }
   }
   if (MODE == EV_A) {
-    if constexpr (BATCH) {
-      vmax_atomic(&C.vmax_bits, vmag);
-    } else {
-      vmax_update<false>(d.clk, 0, act, vmag);
-    }
-  }
-  if (MODE == EV_B && disk) {
-    // fixed-order block reduction of the ring force, FP64
-    __shared__ double ws[WC_GHOST_BLOCK / 64];
-    const double v = wave_sum((double)fx);
-    if ((t & 63) == 0) ws[t >> 6] = v;
-    __syncthreads();
-    if (t == 0) {
-      double f = 0.0;
-      for (int w = 0; w < WC_GHOST_BLOCK / 64; ++w) f += ws[w];
-      d.wb_part[inst * WC_MAX_RING_BLOCKS + (blk.y - P.nw) / GQ] = f;
-    }
+    // the items of a block belong to one instance
+    const float w = wave_max(vmag);
+    if ((t & 63) == 0) vmax_atomic(&C.vmax_bits, w);
   }
 }
+#undef GL
 
 // Pair sums + predictor (eval A) / corrector (eval B) for every fluid slot;
 // ghost slots are carried into the output buffer. EV_EXPORT writes the rates.
@@ -698,12 +716,23 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     ai = sb.aux[s];
   }
   const bool fluid = inr && ai.w > 0.0f;
-  if (MODE == EV_A && inr && !fluid && q == 0) {
-    out.cell[s] = K;
-    out.id[s] = sb.id[s];
-    out.pv[s] = pi;
-    out.aux[s] = make_float4(ai.x, 0.0f, 0.0f, 0.0f);
-    if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
+  if (MODE != EV_EXPORT && inr && !fluid && q == 0) {
+    // ghosts: wall ghosts are carried, the disk ring is placed at the time of
+    // the next evaluation (t + dt/2 after eval A, t + dt after eval B)
+    const uint32_t id = sb.id[s];
+    const int ring = (int)id - P.id0 - P.nf - P.nw;
+    if (MODE == EV_A) {
+      out.id[s] = id;
+      out.aux[s] = make_float4(ai.x, 0.0f, 0.0f, 0.0f);
+      if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
+    }
+    if (ring >= 0) {
+      const double te = MODE == EV_A ? C.t + 0.5 * step_dt(d, P, C) : C.t + C.dt;
+      place_ring(d, P, ring, te, out, s);
+    } else if (MODE == EV_A) {
+      out.cell[s] = K;
+      out.pv[s] = pi;
+    }
   }
   PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   if (fluid) pair_sums(d, P, sb, s, K, pi, ai, q, lst + threadIdx.x, acc);
@@ -811,20 +840,27 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
   count_hits<BATCH>(clk, inst, clamp_hit, enf_hit);
   if (MODE == EV_B) {
     vmax_update<BATCH>(clk, inst, lead, vnew);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      for (int i = 0; i < d.n_inst; ++i) {
-        Clock& Ci = clk[i];
+    // work of the ring on the fluid over the step (fixed-order sum of the
+    // per-ghost forces at t + dt/2) and the time of the new state; the first
+    // wave of block i serves instance i
+    for (int i = blockIdx.x; i < d.n_inst; i += gridDim.x) {
+      if (threadIdx.x < 64) {
         const InstParams& Pi = d.prm[i];
         double f = 0.0;
-        for (int k = 0; k * GQ < Pi.nd; ++k) f += d.wb_part[i * WC_MAX_RING_BLOCKS + k];
-        Ci.w_boundary += Ci.dt * f * Ci.vd;
-        Ci.t_next = Ci.t + Ci.dt;
+        for (int k = (int)threadIdx.x; k < Pi.nd; k += 64) f += d.wb_part[i * WC_MAX_RING + k];
+        f = wave_sum(f);
+        if (threadIdx.x == 0) {
+          Clock& Ci = clk[i];
+          Ci.w_boundary += Ci.dt * f * Ci.vd;
+          Ci.t_next = Ci.t + Ci.dt;
+        }
       }
     }
   }
 }
 
-// First bucket slots and v_max of a freshly loaded state (slots in any order).
+// First bucket slots and v_max of a freshly loaded state (slots in any
+// order); the disk ring is placed at the time of the state.
 template <bool BATCH>
 __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
   const int s = blockIdx.x * WC_BLOCK + threadIdx.x;
@@ -840,6 +876,8 @@ __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
       X.bslot[s] = atomicAdd(&d.count[X.cell[s]], 1u);
       const float4 pv = X.pv[s];
       v = fast_sqrt(pv.z * pv.z + pv.w * pv.w);
+    } else if (local >= P.nf + P.nw) {
+      place_ring(d, P, local - P.nf - P.nw, d.clk[inst].t_next, X, s);
     }
   }
   vmax_update<BATCH>(d.clk, inst, fl, v);
@@ -973,11 +1011,10 @@ template <bool BATCH>
 static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, const Buf& out,
                       const Buf& pre2, const Buf& out2) {
   const int nb = NB(d.n_slots);
-  if (mode == EV_A) k_kin<EV_A><<<d.n_inst, 256, 0, st>>>(d, pre);
-  else if (mode == EV_B) k_kin<EV_B><<<d.n_inst, 256, 0, st>>>(d, pre);
-  else k_kin<EV_EXPORT><<<d.n_inst, 256, 0, st>>>(d, pre);
   const int nt = (d.n_cells + SCAN_TILE - 1) / SCAN_TILE;
-  k_scan_sum<<<nt, 1024, 0, st>>>(d);
+  if (mode == EV_A) k_scan_sum<EV_A><<<nt, 1024, 0, st>>>(d);
+  else if (mode == EV_B) k_scan_sum<EV_B><<<nt, 1024, 0, st>>>(d);
+  else k_scan_sum<EV_EXPORT><<<nt, 1024, 0, st>>>(d);
   k_scan_apply<<<nt, 1024, 0, st>>>(d);
   k_scatter<BATCH><<<nb, WC_BLOCK, 0, st>>>(d, pre);
   const int np = NP(d.n_slots);

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import workloads
+from tests import shared_state
 
 pytestmark = pytest.mark.gpu
 
@@ -41,73 +42,65 @@ def p_quantum(cfg):
 
 
 def _shared_state(cfg, steps):
-    """Oracle state after `steps` steps, encoded by the GPU and decoded back:
-    both sides then start from exactly the values the GPU holds."""
-    o = oracle.Oracle(cfg)
-    o.step(steps)
-    t, (x, y, vx, vy, rho) = o.fluid()
-    s = _solver(cfg)
-    s.set_fluid(t, x, y, vx, vy, rho)
-    tg, f = s.fluid()
-    assert tg == t
-    o2 = oracle.Oracle(cfg)
-    o2.set_fluid(t, *f)
-    return s, o2
+    """Oracle state after `steps` steps rounded to the FP32 representation
+    (in the test) and loaded into both sides."""
+    print(f"[gpu] shared state after {steps} oracle steps", flush=True)
+    s, o = shared_state.shared(cfg, steps, wc, oracle)
+    t, f = s.fluid()
+    to, fo = o.fluid()
+    assert t == to
+    for a, b in zip(f, fo):  # the GPU holds exactly the rounded values
+        assert np.abs(a - b).max() <= 1e-12 * max(1.0, np.abs(b).max())
+    return s, o
 
 
 # ---------------------------------------------------------------- cell list
 
-def _oracle_keys(cfg, ex):
-    """Oracle keys of the GPU's decoded positions; positions that decode onto
-    a cell face (FP64 rounding of cell * dc + offset) are moved 1e-12 m into
-    the cell the GPU holds them in."""
-    x, y = ex["x"].copy(), ex["y"].copy()
-    keys, _, _ = oracle.cell_list(cfg, x, y)
-    bad = np.nonzero(keys != ex["keys"])[0]
-    assert bad.size <= 8, bad.size
-    if bad.size:
-        ncx = int(np.ceil((cfg["L"] + 6 * cfg["dx"]) / cfg["cell_size"]))
-        gx, gy = ex["keys"][bad] % ncx, ex["keys"][bad] // ncx
-        lo = -3 * cfg["dx"]
-        for k, i in enumerate(bad):
-            fx = lo + gx[k] * cfg["cell_size"]
-            fy = lo + gy[k] * cfg["cell_size"]
-            assert min(abs(x[i] - fx), abs(x[i] - fx - cfg["cell_size"]),
-                       abs(y[i] - fy), abs(y[i] - fy - cfg["cell_size"])) < 1e-12
-            x[i] = min(max(x[i], fx + 1e-12), fx + cfg["cell_size"] - 1e-12)
-            y[i] = min(max(y[i], fy + 1e-12), fy + cfg["cell_size"] - 1e-12)
-    return x, y
+def _all_positions(o, f):
+    """Fluid positions (rounded state) followed by the oracle's own ghost
+    positions, in particle-id order (the storage order after a load)."""
+    gx, gy, _ = o.ghosts()
+    return np.concatenate([f[0], gx]), np.concatenate([f[1], gy])
+
+
+def _sort_inputs(cfg, steps):
+    s, o = _shared_state(cfg, steps)
+    o.eval_rates()  # places the disk ring at the state's time
+    _, f = o.fluid()
+    x, y = _all_positions(o, f)
+    return s, o, x, y
 
 
 @pytest.mark.parametrize("steps", [0, 30])
 def test_cell_list_bit_exact(steps):
+    """Keys, stable permutation and cell ranges of one cell-list build from
+    the same state (the oracle's state after `steps` steps, rounded)."""
     cfg = workloads.C1()
-    s = _solver(cfg)
-    s.step(steps)
+    s, o, x, y = _sort_inputs(cfg, steps)
     ex = s.export_cells()
-    x, y = _oracle_keys(cfg, ex)
+    assert np.array_equal(ex["ids_pre"], np.arange(s.n_slots))  # load order = id order
     keys, perm, cs = oracle.cell_list(cfg, x, y)
     assert np.array_equal(keys, ex["keys"].astype(np.int32))
     assert np.array_equal(perm, ex["perm"].astype(np.int32))
     assert np.array_equal(cs, ex["cell_start"].astype(np.int32))
     assert np.array_equal(ex["ids_post"], ex["ids_pre"][ex["perm"]])
-    # every particle present exactly once
     assert np.array_equal(np.sort(ex["ids_post"]), np.arange(s.n_slots))
     s.close()
 
 
 def test_neighbour_sets_bit_exact():
+    """In-support neighbour count and neighbour-id sum of every particle from
+    the same state; pairs within 1e-5 of the support radius (W ~ 0) may fall
+    either side in FP32 and are excluded."""
     cfg = workloads.C1()
-    s = _solver(cfg)
-    s.step(40)
+    s, o, x, y = _sort_inputs(cfg, 40)
     nb = s.export_neighbours()
-    cnt, idsum, border = oracle.neighbour_stats(cfg, nb["x"], nb["y"], nb["ids"].astype(np.int32),
-                                                tol=1e-5)
-    clean = border == 0
+    cnt, idsum, border = oracle.neighbour_stats(cfg, x, y, np.arange(x.size, dtype=np.int32), tol=1e-5)
+    ids = nb["ids"].astype(np.int64)
+    clean = border[ids] == 0
     assert clean.mean() > 0.99
-    assert np.array_equal(cnt[clean], nb["count"][clean])
-    assert np.array_equal(idsum[clean], nb["idsum"][clean])
-    # the GPU counts interior particles' 20 lattice neighbours at t ~ 0 too
+    assert np.array_equal(cnt[ids][clean], nb["count"][clean])
+    assert np.array_equal(idsum[ids][clean], nb["idsum"][clean])
     s.close()
 
 
@@ -195,24 +188,23 @@ def test_deterministic_and_checkpoint_roundtrip():
 
 def test_full_size_C2_evaluation():
     """C2 (179,552 fluid, 185,088 particles) in the launch configuration the
-    benchmark times: one evaluation after 20 GPU steps against the oracle
-    on the same decoded state, plus the neighbour sets."""
+    benchmark times: one evaluation from a shared state after 20 oracle
+    steps, the cell list, and 20 GPU steps' mass."""
     cfg = workloads.C2()
-    s = _solver(cfg)
-    s.step(20)
-    t, f = s.fluid()
-    o = oracle.Oracle(cfg)
-    o.set_fluid(t, *f)
+    s, o = _shared_state(cfg, 20)
     g = s.export_rates()
     r = o.eval_rates()
     assert _rel(g["drho"], r["drho"]) <= 1e-4
     assert _relvec(g["ax"], g["ay"], r["ax"], r["ay"]) <= 1e-4
     assert _rel(g["gp"], r["gp"]) <= 1e-4
     ex = s.export_cells()
-    x, y = _oracle_keys(cfg, ex)
+    o.eval_rates()
+    _, f = o.fluid()
+    x, y = _all_positions(o, f)
     keys, perm, cs = oracle.cell_list(cfg, x, y)
     assert np.array_equal(perm, ex["perm"].astype(np.int32))
     assert np.array_equal(cs, ex["cell_start"].astype(np.int32))
+    s.step(20)
     d = s.read_diagnostics()
     assert np.abs(d["mass"] - d["mass"][0]).max() <= 1e-12 * d["mass"][0]
     s.close()
