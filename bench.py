@@ -7,9 +7,13 @@ recorded every step, 2,000 predictor-corrector steps from t = 0.
 value = fluid particle-steps per second over the timed steps, with the
 state already resident in HBM. The roofline block prices the pair-sum
 kernel (the dominant kernel) with its algorithmic flops against the FP32
-vector peak, timed with HIP events on the library's stream. cpu_baseline
-times the FP64 oracle on the host cores on a bounded sample of the same
-workload (its first steps).
+vector peak, timed with HIP events on the library's stream; its traffic
+is the HBM bytes per launch from the committed hardware-counter summary
+(null once the kernel source differs from the one measured).
+step_roofline prices the whole step with its algorithmic HBM bytes per
+fluid particle-step against the HBM peak. cpu_baseline times the FP64
+oracle on the host cores on a bounded sample of the same workload (its
+first steps).
 
 python bench.py [--gpus 1] [--steps 2000] [--warmup 50]
 """
@@ -26,11 +30,39 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic work of one pair-kernel launch (roofline)
+# algorithmic work of one pair-kernel launch: per fluid particle, every
+# candidate of its 3x3 cells costs the distance test and every in-support
+# neighbour the pair law
 FLOP_PER_CANDIDATE = 7     # r_ij from cell-relative offsets, |r|^2, compare
 FLOP_PER_PAIR = 60         # kernel, continuity + delta, pressure + AV, laminar, XSPH
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (published)
-PEAK_HBM_GBS = 8000.0
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E peak (published)
+# algorithmic HBM bytes of one fluid particle-step (two evaluations): the
+# state read and written by each evaluation plus the cell-list rebuild
+# (keys, counting sort, permuted state), neighbour data counted once
+ALG_BYTES_PER_PARTICLE_STEP = 292
+KERNELS_SRC = os.path.join(ROOT, "paper_2609_05494_amd", "csrc", "wcsph_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_traffic.json")
+
+
+def kernels_sha256() -> str:
+    import hashlib
+    with open(KERNELS_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def pair_traffic():
+    """HBM bytes per pair-kernel launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or
+    None when the kernel source has changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernels_sha256") != kernels_sha256():
+        return None
+    return float(t["bytes_per_launch"])
 
 
 def pair_flops(s) -> float:
@@ -160,15 +192,26 @@ def main():
                     help="steps of the batched-sweep comparison (0 skips it)")
     ap.add_argument("--adj-steps", type=int, default=500,
                     help="steps of the adjoint comparison (0 skips it)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference kernel "
+                         "of known traffic for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; "
+              "run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
     import workloads
     import paper_2609_05494_amd as wc
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cfg = workloads.C2()
     s = wc.Solver(cfg, "cuda:0")
@@ -198,10 +241,14 @@ def main():
     pair_ms = s.time_pair_kernel(args.reps)
     achieved = flops / (pair_ms * 1e-3) / 1e12
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
+                frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=pair_traffic(),
                 kernel="k_pair<EV_A>", kernel_ms=round(pair_ms, 5),
                 flop_per_launch=flops, mean_candidates=round(mean_cand, 2),
                 mean_pairs=round(mean_pair, 2))
+    step_gbs = ALG_BYTES_PER_PARTICLE_STEP * value / 1e9
+    step_roof = dict(bound="hbm", alg_bytes_per_particle_step=ALG_BYTES_PER_PARTICLE_STEP,
+                     achieved=round(step_gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                     frac=round(step_gbs / PEAK_HBM_GBS, 4))
     nf = s.nf
     s.close()
 
@@ -225,6 +272,7 @@ def main():
                                "disk R 6 mm at 900 m/s, 4 wall probes, predictor-corrector",
                    "n_fluid": nf, "steps": args.steps, "parallelism": "single GPU"},
         "roofline": roof,
+        "step_roofline": step_roof,
         "cpu_baseline": cpu,
         "batched_sweep": batched,
         "adjoint": adjoint,

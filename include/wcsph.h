@@ -41,7 +41,8 @@ typedef enum {
   WCSPH_E_OOM = 2,      /* an allocation failed; the context is still destroyable */
   WCSPH_E_HIP = 3,      /* a HIP runtime call failed */
   WCSPH_E_STATE = 4,    /* call not valid in the current state (NULL / destroyed ctx) */
-  WCSPH_E_UNSTABLE = 5, /* a diagnostic found a non-finite value or an escaped particle */
+  WCSPH_E_UNSTABLE = 5, /* a diagnostic found a non-finite value or an escaped particle,
+                           or a cell held more particles than a cell bucket takes (64) */
   WCSPH_E_RANGE = 6     /* a size argument is too small for the data */
 } wcsph_status;
 
@@ -170,7 +171,9 @@ wcsph_status wcsph_synchronize(wcsph_ctx* ctx);
 wcsph_status wcsph_read_probes(wcsph_ctx* ctx, int inst, double* t, double* dt, float* p,
                                int max_rows, int* rows_out);
 /* Diagnostic records of instance `inst` since the last read (ring of 4096).
- * Returns E_UNSTABLE if a record found a non-finite value. */
+ * Returns E_UNSTABLE (records still written) if a record found a non-finite
+ * value or the cell list broke down (a cell with more than 64 particles);
+ * wcsph_last_error names which. */
 wcsph_status wcsph_read_diagnostics(wcsph_ctx* ctx, int inst, wcsph_diag* out, int max, int* n_out);
 
 /* Fluid state of instance `inst` in particle-id order (id = j nx + i of the
@@ -209,7 +212,9 @@ wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, 
                                      double* x, double* y, size_t cap_slots);
 /* Measurement hook: average duration (ms) of the pair-sum kernel of the
  * first evaluation, re-launched `reps` times on the current sorted state
- * between two HIP events on the context stream. The state is restored. */
+ * between HIP events on the context stream (each launch preceded by a
+ * re-arm copy of the cell counts, whose time is measured alone and
+ * subtracted). The state is restored. */
 wcsph_status wcsph_time_pair_kernel(wcsph_ctx* ctx, int reps, float* avg_ms);
 
 /* ---- coefficients and reverse sweep --------------------------------------- */

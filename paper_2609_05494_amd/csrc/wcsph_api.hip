@@ -284,11 +284,18 @@ void alloc_buf(wcsph_ctx* c, Buf& b) {
   b.id = dalloc_n<uint32_t>(c, n);
   b.pv = dalloc_n<float4>(c, n);
   b.aux = dalloc_n<float4>(c, n);
-  b.bslot = dalloc_n<uint32_t>(c, n);
   b.inst = c->batch ? dalloc_n<uint16_t>(c, n) : nullptr;
 }
 
 void sync(wcsph_ctx* c) { HC(hipStreamSynchronize(c->st)); }
+
+// Refill the buckets of the next sort from the state in X (after the state,
+// the clocks or the disk law changed from the host).
+void rearm(wcsph_ctx* c) {
+  HC(hipMemcpyAsync(c->d.count, c->d_wallcount, (size_t)c->n_cells * 4, hipMemcpyDeviceToDevice, c->st));
+  wc_enqueue_init(c->d, c->b, c->batch, c->st);
+  HC(hipGetLastError());
+}
 
 // Write the set-up (or a given fluid state for instance 0) into X in id
 // order, re-arm the sort counters and reset the clocks.
@@ -429,6 +436,8 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
     for (int k0 = 0; k0 < q.n_probes; k0 += gq) c->h_gblk.push_back(make_int4(i, k0, std::min(gq, q.n_probes - k0), 2));
   }
   c->n_gblk = (int)c->h_gblk.size();
+  for (uint32_t w : c->h_wallcount)
+    require(w <= WC_BUCKET / 2, "too many wall ghosts in one cell (ghost_layers too large for h/dx)");
   // device memory
   alloc_buf(c, c->b.X);
   alloc_buf(c, c->b.Y);
@@ -445,10 +454,14 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.n_ghost = c->n_ghost;
   d.count = dalloc_n<uint32_t>(c, c->n_cells);
   d.start = dalloc_n<uint32_t>(c, c->n_cells + 1);
-  d.bsum = dalloc_n<uint32_t>(c, (size_t)c->n_cells / 4096 + 1);
   c->d_wallcount = dalloc_n<uint32_t>(c, c->n_cells);
   d.wallcount = c->d_wallcount;
-  d.tmp = dalloc_n<uint32_t>(c, c->n_slots);
+  d.bucket_a = dalloc_n<uint32_t>(c, (size_t)c->n_cells * WC_BUCKET);
+  d.bucket_b = dalloc_n<uint32_t>(c, (size_t)c->n_cells * WC_BUCKET);
+  const size_t n_tiles = ((size_t)c->n_cells + WC_SORT_TILE - 1) / WC_SORT_TILE;
+  d.tile_flag = dalloc_n<unsigned long long>(c, n_tiles);
+  d.sort_epoch = dalloc_n<uint32_t>(c, 2);
+  d.sort_done = d.sort_epoch + 1;
   d.perm = dalloc_n<uint32_t>(c, c->n_slots);
   d.gslot = dalloc_n<uint32_t>(c, c->n_ghost);
   c->d_gslot_save = dalloc_n<uint32_t>(c, c->n_ghost);
@@ -474,6 +487,11 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   HC(hipMemcpyAsync(gblk, c->h_gblk.data(), (size_t)c->n_gblk * sizeof(int4), hipMemcpyHostToDevice, c->st));
   HC(hipMemsetAsync(d.hist_p, 0, (size_t)n_inst * WC_HIST_CAP * WC_MAX_PROBES * 4, c->st));
   HC(hipMemsetAsync(d.wb_part, 0, (size_t)n_inst * WC_MAX_RING * 8, c->st));
+  // look-back flags carry epoch 0, the first sort runs with epoch 1
+  HC(hipMemsetAsync(d.tile_flag, 0, n_tiles * 8, c->st));
+  const uint32_t epoch0[2] = {1u, 0u};
+  HC(hipMemcpyAsync(d.sort_epoch, epoch0, sizeof epoch0, hipMemcpyHostToDevice, c->st));
+  sync(c);
   c->hist_read.assign(n_inst, 0);
   c->diag_rows.assign(n_inst, 0);
   c->diag_read.assign(n_inst, 0);
@@ -550,12 +568,10 @@ struct HookGuard {
   }
   void restore() {
     HC(hipMemcpyAsync(c->d.gslot, c->d_gslot_save, (size_t)c->n_ghost * 4, hipMemcpyDeviceToDevice, c->st));
-    HC(hipMemcpyAsync(c->d.count, c->d_wallcount, (size_t)c->n_cells * 4, hipMemcpyDeviceToDevice, c->st));
     std::vector<Clock> k = clk;
     for (auto& q : k) q.vmax_bits = 0u;
     HC(hipMemcpyAsync(c->d_clk, k.data(), k.size() * sizeof(Clock), hipMemcpyHostToDevice, c->st));
-    wc_enqueue_init(c->d, c->b, c->batch, c->st);
-    HC(hipGetLastError());
+    rearm(c);
     sync(c);
     // the fluid |v| max is recomputed; keep the larger of it and the saved value
     std::vector<Clock> now(c->n_inst);
@@ -572,11 +588,10 @@ std::vector<T> d2h(wcsph_ctx* c, const T* p, size_t n) {
   return v;
 }
 
-// Device-side checkpoint of the whole evolving state (X buffer with its
-// sort bookkeeping, clocks, bucket counts, ghost slots).
+// Device-side checkpoint of the whole evolving state (X buffer, clocks,
+// ghost slots); the buckets of the next sort are refilled on restore.
 size_t ckpt_size(const wcsph_ctx* c) {
-  return (size_t)c->n_slots * 44 + (size_t)c->n_inst * sizeof(Clock) + (size_t)c->n_cells * 4 +
-         (size_t)c->n_ghost * 4 + 256;
+  return (size_t)c->n_slots * 40 + (size_t)c->n_inst * sizeof(Clock) + (size_t)c->n_ghost * 4 + 256;
 }
 void ckpt_copy(wcsph_ctx* c, char* blob, bool save) {
   const size_t N = c->n_slots;
@@ -590,10 +605,9 @@ void ckpt_copy(wcsph_ctx* c, char* blob, bool save) {
   mv(c->b.X.id, N * 4);
   mv(c->b.X.pv, N * 16);
   mv(c->b.X.aux, N * 16);
-  mv(c->b.X.bslot, N * 4);
   mv(c->d_clk, c->n_inst * sizeof(Clock));
-  mv(c->d.count, (size_t)c->n_cells * 4);
   mv(c->d.gslot, (size_t)c->n_ghost * 4);
+  if (!save) rearm(c);
 }
 
 void alloc_tape(wcsph_ctx* c, int steps) {
@@ -731,10 +745,7 @@ wcsph_status wcsph_set_disk_kinematics(wcsph_ctx* ctx, int inst, int mode, const
   ctx->pin[inst].kin_coef = coeffs[2];
   HC(hipMemcpyAsync(ctx->d_prm + inst, &q, sizeof(InstParams), hipMemcpyHostToDevice, ctx->st));
   // the ring of the newest state was placed with the old law: place it again
-  // (and recount the buckets of the next sort)
-  HC(hipMemcpyAsync(ctx->d.count, ctx->d_wallcount, (size_t)ctx->n_cells * 4, hipMemcpyDeviceToDevice, ctx->st));
-  wc_enqueue_init(ctx->d, ctx->b, ctx->batch, ctx->st);
-  HC(hipGetLastError());
+  rearm(ctx);
   sync(ctx);
   API_END(ctx)
 }
@@ -834,10 +845,20 @@ wcsph_status wcsph_read_diagnostics(wcsph_ctx* ctx, int inst, wcsph_diag* out, i
   }
   rd += rows;
   *n_out = (int)rows;
-  Clock k;
+  // flags: 1 non-finite state (this instance); on instance 0 for the whole
+  // context: 4 corrupted permutation, 8 a cell holds more than WC_BUCKET
+  // particles, 16 the sort's look-back scan gave up waiting
+  Clock k, k0;
   HC(hipMemcpy(&k, ctx->d_clk + inst, sizeof k, hipMemcpyDeviceToHost));
-  if (k.bad) {
-    ctx->err = "non-finite value or corrupted cell list detected (flags " + std::to_string(k.bad) + ")";
+  HC(hipMemcpy(&k0, ctx->d_clk, sizeof k0, hipMemcpyDeviceToHost));
+  const unsigned bad = k.bad | (k0.bad & ~1u);
+  if (bad) {
+    std::string m;
+    if (bad & 1u) m += " non-finite or escaped particle;";
+    if (bad & 4u) m += " corrupted cell-list permutation;";
+    if (bad & 8u) m += " more than " + std::to_string(WC_BUCKET) + " particles in one cell;";
+    if (bad & 16u) m += " cell-list scan timed out;";
+    ctx->err = "state invalid (flags " + std::to_string(bad) + "):" + m;
     return WCSPH_E_UNSTABLE;
   }
   API_END(ctx)
@@ -903,8 +924,8 @@ struct BlobHeader {
 wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* need) {
   API_BEGIN(ctx)
   const size_t N = ctx->n_slots;
-  const size_t sz = sizeof(BlobHeader) + ctx->n_inst * sizeof(Clock) + N * (4 + 4 + 16 + 16 + 4 + 2) +
-                    (size_t)ctx->n_ghost * 4 + (size_t)ctx->n_cells * 4;
+  const size_t sz = sizeof(BlobHeader) + ctx->n_inst * sizeof(Clock) + N * (4 + 4 + 16 + 16 + 2) +
+                    (size_t)ctx->n_ghost * 4;
   if (need) *need = sz;
   if (!buf) return WCSPH_OK;
   if (cap < sz) throw WcError{WCSPH_E_RANGE, "buffer too small for the state"};
@@ -912,7 +933,7 @@ wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* nee
   char* o = static_cast<char*>(buf);
   BlobHeader h;
   std::memset(&h, 0, sizeof h);
-  std::memcpy(h.magic, "WCSPHST1", 8);
+  std::memcpy(h.magic, "WCSPHST2", 8);
   h.n_inst = ctx->n_inst;
   h.n_slots = N;
   h.n_cells = ctx->n_cells;
@@ -930,14 +951,12 @@ wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* nee
   put(ctx->b.X.id, N * 4);
   put(ctx->b.X.pv, N * 16);
   put(ctx->b.X.aux, N * 16);
-  put(ctx->b.X.bslot, N * 4);
   if (ctx->batch) put(ctx->b.X.inst, N * 2);
   else {
     std::memset(o, 0, N * 2);
     o += N * 2;
   }
   put(ctx->d.gslot, (size_t)ctx->n_ghost * 4);
-  put(ctx->d.count, (size_t)ctx->n_cells * 4);
   API_END(ctx)
 }
 
@@ -946,13 +965,13 @@ wcsph_status wcsph_load_state(wcsph_ctx* ctx, const void* buf, size_t n) {
   require(buf != nullptr && n >= sizeof(BlobHeader), "buffer too small");
   BlobHeader h;
   std::memcpy(&h, buf, sizeof h);
-  require(std::memcmp(h.magic, "WCSPHST1", 8) == 0, "not a state blob");
+  require(std::memcmp(h.magic, "WCSPHST2", 8) == 0, "not a state blob");
   require(h.n_inst == ctx->n_inst && h.n_slots == ctx->n_slots && h.n_cells == ctx->n_cells &&
               h.n_ghost == ctx->n_ghost && h.batch == (long long)ctx->batch,
           "state blob does not match this context");
   const size_t N = ctx->n_slots;
-  const size_t sz = sizeof(BlobHeader) + ctx->n_inst * sizeof(Clock) + N * (4 + 4 + 16 + 16 + 4 + 2) +
-                    (size_t)ctx->n_ghost * 4 + (size_t)ctx->n_cells * 4;
+  const size_t sz = sizeof(BlobHeader) + ctx->n_inst * sizeof(Clock) + N * (4 + 4 + 16 + 16 + 2) +
+                    (size_t)ctx->n_ghost * 4;
   require(n >= sz, "state blob truncated");
   sync(ctx);
   const char* o = static_cast<const char*>(buf) + sizeof h;
@@ -965,11 +984,11 @@ wcsph_status wcsph_load_state(wcsph_ctx* ctx, const void* buf, size_t n) {
   get(ctx->b.X.id, N * 4);
   get(ctx->b.X.pv, N * 16);
   get(ctx->b.X.aux, N * 16);
-  get(ctx->b.X.bslot, N * 4);
   if (ctx->batch) get(ctx->b.X.inst, N * 2);
   else o += N * 2;
   get(ctx->d.gslot, (size_t)ctx->n_ghost * 4);
-  get(ctx->d.count, (size_t)ctx->n_cells * 4);
+  rearm(ctx);
+  sync(ctx);
   ctx->steps = h.steps;
   for (int i = 0; i < ctx->n_inst; ++i) {
     ctx->hist_read[i] = ctx->steps;
@@ -1084,18 +1103,33 @@ wcsph_status wcsph_time_pair_kernel(wcsph_ctx* ctx, int reps, float* avg_ms) {
   wc_enqueue_export_sort(ctx->d, ctx->b, ctx->batch, ctx->st);
   if (!ctx->batch) wc_enqueue_export_ghosts(ctx->d, ctx->b, ctx->n_gblk, ctx->st);
   HC(hipGetLastError());
-  hipEvent_t e0, e1;
+  // each launch fills the buckets of the next sort, so the counts are
+  // re-armed before every launch; the re-arm copies are timed on their own
+  // and taken off
+  hipEvent_t e0, e1, e2;
   HC(hipEventCreate(&e0));
   HC(hipEventCreate(&e1));
+  HC(hipEventCreate(&e2));
+  const size_t cbytes = (size_t)ctx->n_cells * 4;
   HC(hipEventRecord(e0, ctx->st));
-  for (int r = 0; r < reps; ++r) wc_enqueue_pair_a(ctx->d, ctx->b, ctx->batch, ctx->st);
+  for (int r = 0; r < reps; ++r) {
+    HC(hipMemcpyAsync(ctx->d.count, ctx->d_wallcount, cbytes, hipMemcpyDeviceToDevice, ctx->st));
+    wc_enqueue_pair_a(ctx->d, ctx->b, ctx->batch, ctx->st);
+  }
   HC(hipEventRecord(e1, ctx->st));
-  HC(hipEventSynchronize(e1));
-  float ms = 0;
-  HC(hipEventElapsedTime(&ms, e0, e1));
+  for (int r = 0; r < reps; ++r)
+    HC(hipMemcpyAsync(ctx->d.count, ctx->d_wallcount, cbytes, hipMemcpyDeviceToDevice, ctx->st));
+  HC(hipEventRecord(e2, ctx->st));
+  HC(hipGetLastError());
+  HC(hipEventSynchronize(e2));
+  float t_all = 0, t_copy = 0;
+  HC(hipEventElapsedTime(&t_all, e0, e1));
+  HC(hipEventElapsedTime(&t_copy, e1, e2));
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  *avg_ms = ms / reps;
+  hipEventDestroy(e2);
+  const double total = (double)t_all - (double)t_copy;
+  *avg_ms = (float)(total / reps);
   guard.restore();
   API_END(ctx)
 }

@@ -21,6 +21,8 @@
 #define WC_GHOST_LANES 16      // lanes per ghost or probe in the ghost kernel
 #define WC_MAX_RING 256        // disk-ring ghosts per instance
 #define WC_DIAG_BLOCKS 64      // diagnostic partial sums per instance
+#define WC_BUCKET 64           // capacity of one cell bucket (particles per cell)
+#define WC_SORT_TILE 64        // cells per block of the sort kernel
 
 // Per-instance constants (read-only in kernels).
 struct InstParams {
@@ -70,7 +72,6 @@ struct Buf {
   uint32_t* id;     // global particle id
   float4* pv;       // (ox, oy, vx, vy): offset inside the cell, velocity
   float4* aux;      // (rho, P = p / rho^2, c, m) ; m < 0 marks a ghost
-  uint32_t* bslot;  // slot inside the cell bucket for the next sort
   uint16_t* inst;   // instance (batched contexts only)
 };
 
@@ -81,9 +82,14 @@ struct Dev {
   int n_inst, n_slots, n_cells, n_ghost;
   uint32_t* count;            // per cell: bucket fill for the next sort
   uint32_t* start;            // per cell + 1: exclusive scan of count
-  uint32_t* bsum;             // per scan tile: cell-count total
   const uint32_t* wallcount;  // per cell: static wall ghosts (pre-fill of count)
-  uint32_t* tmp;              // per slot: bucket contents (old slots)
+  // cell buckets [n_cells][WC_BUCKET] of slots, filled for the next sort:
+  // bucket_a by eval B (and at load) for eval A, bucket_b by eval A for eval B
+  uint32_t* bucket_a;
+  uint32_t* bucket_b;
+  unsigned long long* tile_flag;  // per sort tile: (epoch, status, prefix) of the look-back scan
+  uint32_t* sort_epoch;       // increases by one per sort launch
+  uint32_t* sort_done;        // blocks of the running sort that have finished
   uint32_t* perm;             // per slot: perm[new] = old of the last sort
   uint32_t* gslot;            // per ghost: current slot
   const uint32_t* wrank;      // per ghost: static bucket rank of a wall ghost

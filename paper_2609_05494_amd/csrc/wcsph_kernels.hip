@@ -1,18 +1,18 @@
 // wcsph_kernels.hip -- HIP kernels of the planar WCSPH step for gfx950.
 //
 // One step = two evaluations (predictor-corrector). Each evaluation runs:
-//   k_scan_*   exclusive scan of the per-cell counts -> cell ranges; the
-//              first block advances the clock and evaluates the prescribed
-//              disk kinematics
-//   k_scatter  every slot into its cell bucket
-//   k_permute  stable rank inside the bucket (by old slot) and gather of the
-//              state into sorted order; per-particle EOS (P = p/rho^2, c)
+//   k_sort     the cell list: stable counting sort of the slots by cell key
+//              from the cell buckets (look-back scan of the counts -> cell
+//              ranges, buckets ordered by old slot, gather into sorted
+//              order, per-particle EOS P = p/rho^2 and c); its first block
+//              advances the clock and the prescribed disk kinematics
 //   k_ghost    Adami-Shepard ghost state on walls and ring, probes (eval A),
 //              v_max of the ghosts (eval A), work of the ring (eval B)
 //   k_pair     pair sums over the 3x3 cells (continuity + delta, pressure +
 //              AV + laminar, XSPH) fused with the predictor / corrector,
-//              density band, enforcement, new cell key and bucket slot;
-//              the disk ring is placed at the next evaluation's time
+//              density band, enforcement, new cell key; every slot goes
+//              into the bucket of its cell for the next sort, the disk ring
+//              placed at the next evaluation's time
 // Pair arithmetic is FP32 on cell-relative offsets; time, kinematics,
 // enforcement geometry and diagnostics are FP64.
 
@@ -315,6 +315,10 @@ __device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, con
   flush();
 }
 
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __shfl_xor(v, 1);
+  return v + __shfl_xor(v, 2);
+}
 // Visit the candidates of the 3x3 block of cells around cell K (rows bottom
 // to top, cells left to right, sorted order inside a cell), dealt
 // round-robin to a group of G lanes (lane l takes c = l, l + G, ...) with
@@ -366,7 +370,6 @@ __device__ __forceinline__ double group_sum(double v) {
   for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
   return v;
 }
-__device__ __forceinline__ float quad_sum(float v) { return group_sum<4>(v); }
 
 // Shepard sums over the fluid in support of an encoded point (cell K,
 // offset o), one group of G lanes per point.
@@ -439,10 +442,23 @@ __device__ void clock_commit(const Dev& d, int i) {
   C.ad = a;
 }
 
+// Slot s into the bucket of cell K for the next sort (bucket slot from the
+// cell's fill counter); an overfull cell is flagged and the slot dropped.
+__device__ __forceinline__ void bucket_put(const Dev& d, uint32_t* bucket, uint32_t K, uint32_t s) {
+  const uint32_t b = atomicAdd(&d.count[K], 1u);
+  if (b < WC_BUCKET) bucket[(size_t)K * WC_BUCKET + b] = s;
+  else atomicOr(&d.clk[0].bad, 8u);
+}
+// Wall ghost g (static position) into its fixed place at the front of its bucket.
+__device__ __forceinline__ void bucket_put_wall(const Dev& d, const InstParams& P, uint32_t* bucket, uint32_t K,
+                                                int g, uint32_t s) {
+  bucket[(size_t)K * WC_BUCKET + d.wrank[P.gmap0 + g]] = s;
+}
+
 // Disk-ring ghost k at time te: r_k = c(te) + R (cos 2 pi k / nd, sin 2 pi k / nd),
-// encoded, with its bucket slot for the next sort.
+// encoded, and put into its bucket for the next sort.
 __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, int k, double te, const Buf& out,
-                                           int s) {
+                                           int s, uint32_t* bucket) {
   double xc, v, a;
   kinematics(P, te, xc, v, a);
   double sn, cs;
@@ -455,153 +471,161 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
   const uint32_t key = (uint32_t)(P.cell_off + cy * P.ncx + cx);
   out.cell[s] = key;
   out.pv[s] = make_float4(ox, oy, 0.0f, 0.0f);
-  out.bslot[s] = atomicAdd(&d.count[key], 1u);
+  bucket_put(d, bucket, key, (uint32_t)s);
 }
 
-// Exclusive scan of count -> start over all cells in two passes over tiles
-// of SCAN_TILE cells (four consecutive cells per thread, coalesced uint4
-// loads): k_scan_sum writes each tile's total (and its first block advances
-// the clocks), k_scan_apply adds the totals of the preceding tiles and scans
-// its own tile. count is re-armed with the static wall-ghost occupancy for
-// the next sort.
-#define SCAN_TILE 4096
-__device__ __forceinline__ void load4(const uint32_t* p, int i0, int n, uint32_t a[4]) {
-  if (i0 + 3 < n) {
-    const uint4 v = *reinterpret_cast<const uint4*>(p + i0);
-    a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
-  } else {
-    for (int k = 0; k < 4; ++k) a[k] = (i0 + k < n) ? p[i0 + k] : 0u;
-  }
+// ---------------------------------------------------------------------------
+// The cell-list build of one evaluation in one launch: a stable counting
+// sort of the slots by cell key. The previous evaluation left every slot in
+// the bucket of its new cell (bucket order arbitrary, from atomics). Block b
+// owns cells [b T, (b+1) T) (T = WC_SORT_TILE):
+//   1. its cells' counts -> local offsets and the tile total; the exclusive
+//      prefix over the preceding tiles by decoupled look-back on per-tile
+//      flags (epoch-tagged, so no clearing between launches) -> start[]
+//   2. each bucket ordered by old slot (rank = number of smaller entries:
+//      the sort is stable with respect to the current order)
+//   3. gather of the state into sorted order, per-particle EOS, ghost slots,
+//      perm[new] = old; in eval B the state at time n (pre2) alongside
+// The first block also advances the clocks, and the block that finishes last
+// bumps the epoch for the next launch.
+#define SORT_BLOCK 256
+#define SORT_SPIN_LIMIT (1 << 20)
+__device__ __forceinline__ unsigned long long tile_word(uint32_t epoch, uint32_t status, uint32_t v) {
+  return ((unsigned long long)epoch << 34) | ((unsigned long long)status << 32) | (unsigned long long)v;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(1024) void k_scan_sum(Dev d) {
-  __shared__ uint32_t wsum[16];
-  if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < d.n_inst; i += blockDim.x) clock_commit<MODE>(d, i);
-  const int n = d.n_cells, t = threadIdx.x;
-  uint32_t a[4];
-  load4(d.count, blockIdx.x * SCAN_TILE + 4 * t, n, a);
-  uint32_t s = a[0] + a[1] + a[2] + a[3];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if ((t & 63) == 0) wsum[t >> 6] = s;
-  __syncthreads();
-  if (t == 0) {
-    uint32_t tot = 0;
-    for (int w = 0; w < 16; ++w) tot += wsum[w];
-    d.bsum[blockIdx.x] = tot;
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_scan_apply(Dev d) {
-  __shared__ uint32_t wsum[16];
-  __shared__ uint32_t base_sh;
-  const int n = d.n_cells, t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int b = blockIdx.x;
-  if (t < 64) {
-    uint32_t v = 0;
-    for (int k = t; k < b; k += 64) v += d.bsum[k];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (t == 0) base_sh = v;
-  }
-  const int i0 = b * SCAN_TILE + 4 * t;
-  uint32_t a[4];
-  load4(d.count, i0, n, a);
-  const uint32_t s = a[0] + a[1] + a[2] + a[3];
-  uint32_t incl = s;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t u = __shfl_up(incl, o);
-    if (lane >= o) incl += u;
-  }
-  if (lane == 63) wsum[wv] = incl;
-  __syncthreads();
-  uint32_t woff = 0, tile = 0;
-  for (int w = 0; w < 16; ++w) {
-    const uint32_t x = wsum[w];
-    woff += (w < wv) ? x : 0u;
-    tile += x;
-  }
-  uint32_t run = base_sh + woff + incl - s;
-  uint32_t o4[4];
-  for (int k = 0; k < 4; ++k) {
-    o4[k] = run;
-    run += a[k];
-  }
-  if (i0 + 3 < n) {
-    *reinterpret_cast<uint4*>(d.start + i0) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
-    *reinterpret_cast<uint4*>(d.count + i0) = *reinterpret_cast<const uint4*>(d.wallcount + i0);
-  } else {
-    for (int k = 0; k < 4; ++k)
-      if (i0 + k < n) {
-        d.start[i0 + k] = o4[k];
-        d.count[i0 + k] = d.wallcount[i0 + k];
-      }
-  }
-  if (b == (int)gridDim.x - 1 && t == 0) d.start[n] = base_sh + tile;
-}
-
-// Every slot into its bucket: tmp[start[key] + bucket slot] = slot.
-template <bool BATCH>
-__global__ __launch_bounds__(WC_BLOCK) void k_scatter(Dev d, Buf pre) {
-  const int s = blockIdx.x * WC_BLOCK + threadIdx.x;
-  if (s >= d.n_slots) return;
-  const InstParams& P = d.prm[inst_at<BATCH>(pre, s)];
-  const uint32_t K = pre.cell[s];
-  const int local = (int)pre.id[s] - P.id0;
-  uint32_t b;
-  if (local >= P.nf && local < P.nf + P.nw) b = d.wrank[P.gmap0 + local - P.nf];
-  else b = pre.bslot[s];
-  const uint32_t dst = d.start[K] + b;
-  if (dst < d.start[K + 1] && dst < (uint32_t)d.n_slots) d.tmp[dst] = (uint32_t)s;
-  else atomicOr(&d.clk[0].bad, 2u);
-}
-
-// Stable rank inside the bucket and gather into sorted order. In eval B the
-// state at time n (pre2, same slot order as pre) is permuted alongside.
 template <int MODE, bool BATCH>
-__global__ __launch_bounds__(128) void k_permute(Dev d, Buf pre, Buf out, Buf pre2, Buf out2) {
-  // same slot -> XCD mapping as k_pair, so the sorted buffer is written into
-  // the L2 of the XCD that reads it next
-  const int p = xcd_block(blockIdx.x, gridDim.x) * 128 + threadIdx.x;
-  if (p >= d.n_slots) return;
-  const uint32_t e = d.tmp[p];
-  if (e >= (uint32_t)d.n_slots) {
-    atomicOr(&d.clk[0].bad, 4u);
-    return;
+__global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out, Buf pre2, Buf out2) {
+  constexpr int T = WC_SORT_TILE;
+  __shared__ uint32_t s_off[T + 1];  // exclusive offsets of the tile's cells, total at [T]
+  __shared__ uint32_t s_cnt[T];
+  __shared__ uint32_t s_base;        // sorted slots before this tile
+  __shared__ uint32_t s_raw[T * WC_BUCKET];
+  __shared__ uint32_t s_srt[T * WC_BUCKET];
+  const int t = threadIdx.x, tile = blockIdx.x;
+  const uint32_t* bucket = MODE == EV_B ? d.bucket_b : d.bucket_a;
+  const uint32_t epoch = *d.sort_epoch;
+  if (tile == 0)
+    for (int i = t; i < d.n_inst; i += SORT_BLOCK) clock_commit<MODE>(d, i);
+
+  if (t < 64) {  // wave 0: counts, tile scan, look-back
+    const int K = tile * T + t;
+    uint32_t c = 0;
+    if (K < d.n_cells) {
+      c = d.count[K];
+      if (c > WC_BUCKET) c = WC_BUCKET;  // overflow was flagged by the producer
+      d.count[K] = d.wallcount[K];      // re-arm for the next sort
+    }
+    uint32_t incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t u = __shfl_up(incl, o);
+      if (t >= o) incl += u;
+    }
+    const uint32_t total = __shfl(incl, 63);
+    s_off[t] = incl - c;
+    s_cnt[t] = c;
+    if (t == 63) s_off[T] = total;
+    if (t == 0)
+      __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, tile == 0 ? 2u : 1u, total), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0;
+    if (tile > 0) {
+      // lane l inspects tile k - l; stop at the nearest tile holding its
+      // inclusive prefix, adding the aggregates of the tiles in between
+      int k = tile - 1;
+      for (;;) {
+        const int kk = k - t;
+        unsigned long long f = tile_word(epoch, 2u, 0u);
+        if (kk >= 0) {
+          int spin = 0;
+          do {
+            f = __hip_atomic_load(&d.tile_flag[kk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } while ((uint32_t)(f >> 34) != epoch && ++spin < SORT_SPIN_LIMIT);
+          if ((uint32_t)(f >> 34) != epoch) {  // never published: give up, flag the sort
+            atomicOr(&d.clk[0].bad, 16u);
+            f = tile_word(epoch, 2u, 0u);
+          }
+        }
+        const unsigned long long has_prefix = __ballot(((uint32_t)(f >> 32) & 3u) == 2u);
+        const int stop = has_prefix ? __ffsll((long long)has_prefix) - 1 : 63;
+        uint32_t v = t <= stop ? (uint32_t)f : 0u;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        excl += v;
+        if (has_prefix) break;
+        k -= 64;
+      }
+      if (t == 0)
+        __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, 2u, excl + total), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (t == 0) s_base = excl;
+    if (K < d.n_cells) d.start[K] = excl + (incl - c);
+    if (K == d.n_cells - 1) d.start[d.n_cells] = excl + incl;
   }
-  const uint32_t K = pre.cell[e];
-  const uint32_t lo = d.start[K], hi = min(d.start[K + 1], (uint32_t)d.n_slots);
-  uint32_t rank = 0;
-  for (uint32_t t = lo; t < hi; ++t) rank += d.tmp[t] < e ? 1u : 0u;
-  const uint32_t dst = lo + rank;
-  const int inst = inst_at<BATCH>(pre, e);
-  const InstParams& P = d.prm[inst];
-  const uint32_t id = pre.id[e];
-  const float4 pv = pre.pv[e];
-  const float rho = pre.aux[e].x;
-  const int local = (int)id - P.id0;
-  float4 a;
-  if (local < P.nf) {
-    float Pq, c;
-    fluid_eos(P, rho, Pq, c);
-    a = make_float4(rho, Pq, c, P.m_fluid);
-  } else {
-    const int g = local - P.nf;
-    a = make_float4(rho, 0.0f, 0.0f, g < P.nw ? -P.m_wall : -P.m_disk);
-    d.gslot[P.gmap0 + g] = dst;
+  __syncthreads();
+
+  // bucket contents into LDS, then each bucket ordered by old slot
+  const uint32_t base = s_base, total = s_off[T];
+  {
+    const int c = t >> 2, sub = t & 3;
+    const int K = tile * T + c;
+    const uint32_t n = s_cnt[c], o = s_off[c];
+    for (uint32_t i = sub; i < n; i += 4) s_raw[o + i] = bucket[(size_t)K * WC_BUCKET + i];
+    __syncthreads();
+    for (uint32_t i = sub; i < n; i += 4) {
+      const uint32_t e = s_raw[o + i];
+      uint32_t r = 0;
+      for (uint32_t k = 0; k < n; ++k) r += s_raw[o + k] < e ? 1u : 0u;
+      s_srt[o + r] = e;
+    }
   }
-  out.cell[dst] = K;
-  out.id[dst] = id;
-  out.pv[dst] = pv;
-  out.aux[dst] = a;
-  if constexpr (BATCH) out.inst[dst] = (uint16_t)inst;
-  d.perm[dst] = e;
-  if (MODE == EV_B) {
-    out2.cell[dst] = pre2.cell[e];
-    out2.id[dst] = pre2.id[e];
-    out2.pv[dst] = pre2.pv[e];
-    out2.aux[dst] = pre2.aux[e];
-    if constexpr (BATCH) out2.inst[dst] = (uint16_t)inst;
+  __syncthreads();
+
+  // gather into sorted order
+  for (uint32_t p = t; p < total; p += SORT_BLOCK) {
+    const uint32_t e = s_srt[p], dst = base + p;
+    if (e >= (uint32_t)d.n_slots || dst >= (uint32_t)d.n_slots) {
+      atomicOr(&d.clk[0].bad, 4u);
+      continue;
+    }
+    const int inst = inst_at<BATCH>(pre, e);
+    const InstParams& P = d.prm[inst];
+    const uint32_t id = pre.id[e];
+    const float4 pv = pre.pv[e];
+    const float rho = pre.aux[e].x;
+    const int local = (int)id - P.id0;
+    float4 a;
+    if (local < P.nf) {
+      float Pq, c;
+      fluid_eos(P, rho, Pq, c);
+      a = make_float4(rho, Pq, c, P.m_fluid);
+    } else {
+      const int g = local - P.nf;
+      a = make_float4(rho, 0.0f, 0.0f, g < P.nw ? -P.m_wall : -P.m_disk);
+      d.gslot[P.gmap0 + g] = dst;
+    }
+    out.cell[dst] = pre.cell[e];
+    out.id[dst] = id;
+    out.pv[dst] = pv;
+    out.aux[dst] = a;
+    if constexpr (BATCH) out.inst[dst] = (uint16_t)inst;
+    d.perm[dst] = e;
+    if (MODE == EV_B) {
+      out2.cell[dst] = pre2.cell[e];
+      out2.id[dst] = pre2.id[e];
+      out2.pv[dst] = pre2.pv[e];
+      out2.aux[dst] = pre2.aux[e];
+      if constexpr (BATCH) out2.inst[dst] = (uint16_t)inst;
+    }
+  }
+
+  // the last block to finish moves the epoch on (every block has read it)
+  if (t == 0) {
+    const uint32_t done = atomicAdd(d.sort_done, 1u);
+    if (done == gridDim.x - 1) {
+      atomicExch(d.sort_done, 0u);
+      atomicAdd(d.sort_epoch, 1u);
+    }
   }
 }
 
@@ -726,12 +750,16 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       out.aux[s] = make_float4(ai.x, 0.0f, 0.0f, 0.0f);
       if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
     }
+    uint32_t* bucket = MODE == EV_A ? d.bucket_b : d.bucket_a;
     if (ring >= 0) {
       const double te = MODE == EV_A ? C.t + 0.5 * step_dt(d, P, C) : C.t + C.dt;
-      place_ring(d, P, ring, te, out, s);
-    } else if (MODE == EV_A) {
-      out.cell[s] = K;
-      out.pv[s] = pi;
+      place_ring(d, P, ring, te, out, s, bucket);
+    } else {
+      if (MODE == EV_A) {
+        out.cell[s] = K;
+        out.pv[s] = pi;
+      }
+      bucket_put_wall(d, P, bucket, K, (int)id - P.id0 - P.nf, (uint32_t)s);
     }
   }
   PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
@@ -833,7 +861,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       out.id[s] = sb.id[s];
       if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
     }
-    out.bslot[s] = atomicAdd(&d.count[Kn], 1u);
+    bucket_put(d, MODE == EV_A ? d.bucket_b : d.bucket_a, Kn, (uint32_t)s);
     vnew = fast_sqrt(vx * vx + vy * vy);
     if (!(rn == rn) || !(vnew <= 3.0e38f)) atomicOr(&clk[inst].bad, 1u);
   }
@@ -859,8 +887,8 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
   }
 }
 
-// First bucket slots and v_max of a freshly loaded state (slots in any
-// order); the disk ring is placed at the time of the state.
+// Buckets and v_max of a freshly loaded state (slots in any order); the
+// disk ring is placed at the time of the state.
 template <bool BATCH>
 __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
   const int s = blockIdx.x * WC_BLOCK + threadIdx.x;
@@ -873,11 +901,13 @@ __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
     const int local = (int)X.id[s] - P.id0;
     fl = local < P.nf;
     if (fl) {
-      X.bslot[s] = atomicAdd(&d.count[X.cell[s]], 1u);
+      bucket_put(d, d.bucket_a, X.cell[s], (uint32_t)s);
       const float4 pv = X.pv[s];
       v = fast_sqrt(pv.z * pv.z + pv.w * pv.w);
     } else if (local >= P.nf + P.nw) {
-      place_ring(d, P, local - P.nf - P.nw, d.clk[inst].t_next, X, s);
+      place_ring(d, P, local - P.nf - P.nw, d.clk[inst].t_next, X, s, d.bucket_a);
+    } else {
+      bucket_put_wall(d, P, d.bucket_a, X.cell[s], local - P.nf, (uint32_t)s);
     }
   }
   vmax_update<BATCH>(d.clk, inst, fl, v);
@@ -1004,27 +1034,19 @@ __global__ __launch_bounds__(WC_BLOCK) void k_neigh(Dev d, Buf sb) {
 // Launch wrappers (host side of this translation unit).
 
 #define NB(n) (((n) + WC_BLOCK - 1) / WC_BLOCK)
-#define NP(n) (((n) + PAIR_BLOCK - 1) / PAIR_BLOCK)
 #define NQ(n) (((n) + PAIR_BLOCK / 4 - 1) / (PAIR_BLOCK / 4))
 
 template <bool BATCH>
 static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, const Buf& out,
                       const Buf& pre2, const Buf& out2) {
-  const int nb = NB(d.n_slots);
-  const int nt = (d.n_cells + SCAN_TILE - 1) / SCAN_TILE;
-  if (mode == EV_A) k_scan_sum<EV_A><<<nt, 1024, 0, st>>>(d);
-  else if (mode == EV_B) k_scan_sum<EV_B><<<nt, 1024, 0, st>>>(d);
-  else k_scan_sum<EV_EXPORT><<<nt, 1024, 0, st>>>(d);
-  k_scan_apply<<<nt, 1024, 0, st>>>(d);
-  k_scatter<BATCH><<<nb, WC_BLOCK, 0, st>>>(d, pre);
-  const int np = NP(d.n_slots);
-  if (mode == EV_B) k_permute<EV_B, BATCH><<<np, 128, 0, st>>>(d, pre, out, pre2, out2);
-  else k_permute<EV_A, BATCH><<<np, 128, 0, st>>>(d, pre, out, pre2, out2);
+  const int nt = (d.n_cells + WC_SORT_TILE - 1) / WC_SORT_TILE;
+  if (mode == EV_A) k_sort<EV_A, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out, pre2, out2);
+  else if (mode == EV_B) k_sort<EV_B, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out, pre2, out2);
+  else k_sort<EV_EXPORT, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out, pre2, out2);
 }
 
 template <bool BATCH>
 static void enqueue_step_t(const Dev& d, const Bufs& b, int n_gblk, hipStream_t st) {
-  const int np = NP(d.n_slots);
   eval_sort<BATCH>(d, st, EV_A, b.X, b.Y, b.Y, b.Y);
   k_ghost<EV_A, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
   k_pair<EV_A, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
