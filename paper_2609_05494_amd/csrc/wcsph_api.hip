@@ -68,8 +68,11 @@ struct wcsph_ctx {
   uint32_t* d_gslot_save = nullptr;
   std::vector<uint32_t> h_wallcount, h_wrank;
   std::vector<int4> h_gblk;
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;       // one step
   hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph_k = nullptr;     // steps_k steps and a diagnostic record
+  hipGraphExec_t gexec_k = nullptr;
+  int steps_k = 0;
   long long steps = 0;
   std::vector<long long> hist_read, diag_rows, diag_read;
   double* d_dt = nullptr;
@@ -199,6 +202,7 @@ InstParams derive(const wcsph_params& p) {
   const double h = p.h_over_dx * p.dx;
   q.dc = cell_edge(p);
   q.dcd = (double)q.dc;
+  q.inv_dcd = 1.0 / q.dcd;
   q.x_lo = -p.ghost_layers * p.dx;
   q.y_lo = -p.ghost_layers * p.dx;
   q.ncx = (int)std::ceil((p.L + 2.0 * p.ghost_layers * p.dx) / q.dcd);
@@ -365,28 +369,42 @@ void upload_state(wcsph_ctx* c, double t0, const double* fx, const double* fy, c
     c->diag_rows[i] = 0;
     c->diag_read[i] = 0;
   }
-  wc_enqueue_diag(c->d, c->b, 0, false, c->st);
+  wc_enqueue_diag(c->d, c->b, false, c->st);
   HC(hipGetLastError());
   for (int i = 0; i < c->n_inst; ++i) c->diag_rows[i] = 1;
   sync(c);
 }
 
+void drop_graphs(wcsph_ctx* c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->gexec_k) hipGraphExecDestroy(c->gexec_k);
+  if (c->graph_k) hipGraphDestroy(c->graph_k);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->gexec_k = nullptr;
+  c->graph_k = nullptr;
+}
+
+// Capture the step graphs: one step, and diag_every steps followed by the
+// diagnostic record (launched when the step count is a multiple of
+// diag_every), so that consecutive steps run without host round trips.
 void capture(wcsph_ctx* c) {
-  if (c->gexec) {
-    HC(hipGraphExecDestroy(c->gexec));
-    c->gexec = nullptr;
-  }
-  if (c->graph) {
-    HC(hipGraphDestroy(c->graph));
-    c->graph = nullptr;
-  }
+  drop_graphs(c);
+  hipGraph_t g = nullptr;
   HC(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
   wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, c->st);
-  hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(c->st, &g);
-  HC(e);
+  HC(hipStreamEndCapture(c->st, &g));
   c->graph = g;
   HC(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  c->steps_k = c->diag_every > 0 ? c->diag_every : 10;
+  g = nullptr;
+  HC(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < c->steps_k; ++k) wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, c->st);
+  if (c->diag_every > 0) wc_enqueue_diag(c->d, c->b, true, c->st);
+  HC(hipStreamEndCapture(c->st, &g));
+  c->graph_k = g;
+  HC(hipGraphInstantiate(&c->gexec_k, c->graph_k, nullptr, nullptr, 0));
 }
 
 void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
@@ -460,8 +478,18 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.bucket_b = dalloc_n<uint32_t>(c, (size_t)c->n_cells * WC_BUCKET);
   const size_t n_tiles = ((size_t)c->n_cells + WC_SORT_TILE - 1) / WC_SORT_TILE;
   d.tile_flag = dalloc_n<unsigned long long>(c, n_tiles);
-  d.sort_epoch = dalloc_n<uint32_t>(c, 2);
+  d.sort_epoch = dalloc_n<uint32_t>(c, 4);
   d.sort_done = d.sort_epoch + 1;
+  // (cos, sin) of the ring angles 2 pi k / nd, per instance
+  std::vector<double2> ring((size_t)n_inst * WC_MAX_RING, make_double2(0.0, 0.0));
+  for (int i = 0; i < n_inst; ++i)
+    for (int k = 0; k < c->hp[i].nd; ++k) {
+      const double th = 2.0 * M_PI * (double)k / (double)c->hp[i].nd;
+      ring[(size_t)i * WC_MAX_RING + k] = make_double2(std::cos(th), std::sin(th));
+    }
+  double2* ring_cs = dalloc_n<double2>(c, ring.size());
+  d.ring_cs = ring_cs;
+  HC(hipMemcpyAsync(ring_cs, ring.data(), ring.size() * sizeof(double2), hipMemcpyHostToDevice, c->st));
   d.perm = dalloc_n<uint32_t>(c, c->n_slots);
   d.gslot = dalloc_n<uint32_t>(c, c->n_ghost);
   c->d_gslot_save = dalloc_n<uint32_t>(c, c->n_ghost);
@@ -489,7 +517,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   HC(hipMemsetAsync(d.wb_part, 0, (size_t)n_inst * WC_MAX_RING * 8, c->st));
   // look-back flags carry epoch 0, the first sort runs with epoch 1
   HC(hipMemsetAsync(d.tile_flag, 0, n_tiles * 8, c->st));
-  const uint32_t epoch0[2] = {1u, 0u};
+  const uint32_t epoch0[4] = {1u, 0u, 0u, 0u};
   HC(hipMemcpyAsync(d.sort_epoch, epoch0, sizeof epoch0, hipMemcpyHostToDevice, c->st));
   sync(c);
   c->hist_read.assign(n_inst, 0);
@@ -501,10 +529,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
 
 void release(wcsph_ctx* c) {
   if (c->st) hipStreamSynchronize(c->st);
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->graph) hipGraphDestroy(c->graph);
-  c->gexec = nullptr;
-  c->graph = nullptr;
+  drop_graphs(c);
   for (void* p : c->blocks) {
     if (c->custom_alloc) c->al.free(p, (void*)c->st, c->al.user);
     else hipFree(p);
@@ -770,11 +795,22 @@ wcsph_status wcsph_set_dt_table(wcsph_ctx* ctx, const double* dt, int n) {
 wcsph_status wcsph_step(wcsph_ctx* ctx, int n_steps) {
   API_BEGIN(ctx)
   require(n_steps >= 0, "n_steps must be >= 0");
-  for (int k = 0; k < n_steps; ++k) {
+  const int de = ctx->diag_every, K = ctx->steps_k;
+  int n = n_steps;
+  while (n > 0) {
+    if (n >= K && (de <= 0 || ctx->steps % de == 0)) {
+      HC(hipGraphLaunch(ctx->gexec_k, ctx->st));
+      ctx->steps += K;
+      n -= K;
+      if (de > 0)
+        for (int i = 0; i < ctx->n_inst; ++i) ctx->diag_rows[i]++;
+      continue;
+    }
     HC(hipGraphLaunch(ctx->gexec, ctx->st));
     ctx->steps++;
-    if (ctx->diag_every > 0 && ctx->steps % ctx->diag_every == 0) {
-      wc_enqueue_diag(ctx->d, ctx->b, (int)(ctx->diag_rows[0] % WC_DIAG_CAP), true, ctx->st);
+    --n;
+    if (de > 0 && ctx->steps % de == 0) {
+      wc_enqueue_diag(ctx->d, ctx->b, true, ctx->st);
       HC(hipGetLastError());
       for (int i = 0; i < ctx->n_inst; ++i) ctx->diag_rows[i]++;
     }
@@ -990,8 +1026,11 @@ wcsph_status wcsph_load_state(wcsph_ctx* ctx, const void* buf, size_t n) {
   rearm(ctx);
   sync(ctx);
   ctx->steps = h.steps;
+  std::vector<Clock> clk(ctx->n_inst);
+  HC(hipMemcpy(clk.data(), ctx->d_clk, clk.size() * sizeof(Clock), hipMemcpyDeviceToHost));
   for (int i = 0; i < ctx->n_inst; ++i) {
     ctx->hist_read[i] = ctx->steps;
+    ctx->diag_rows[i] = clk[i].diag_row;
     ctx->diag_read[i] = ctx->diag_rows[i];
   }
   API_END(ctx)

@@ -27,7 +27,7 @@
 // Per-instance constants (read-only in kernels).
 struct InstParams {
   // grid: cell key = cell_off + cy * ncx + cx; origin (x_lo, y_lo); edge dc
-  double x_lo, y_lo, dcd;
+  double x_lo, y_lo, dcd, inv_dcd;
   float dc;
   int ncx, ncy, cell_off, ncell;
   // ids: [id0, id0+nf) fluid, then nw wall ghosts, then nd disk ghosts;
@@ -58,9 +58,11 @@ struct Clock {
   double dt;       // dt of the current step
   double t_eval;   // time of the current evaluation
   double xd, vd, ad;  // disk centre x, velocity, acceleration at t_eval
+  double xd_next, vd_next;  // disk centre x and velocity at t + dt (from the second evaluation on)
   double w_boundary;  // integrated work of the disk ghosts on the fluid
   double vmax_used;   // v_max that set dt
   long long step;     // index of the current step (-1 before the first)
+  long long diag_row; // diagnostic records written so far
   unsigned long long n_clamp, n_enforce;
   unsigned int vmax_bits;  // running max of |v| (float bits) for the next dt
   unsigned int bad;        // non-finite / escaped-particle flag
@@ -91,6 +93,7 @@ struct Dev {
   uint32_t* sort_epoch;       // increases by one per sort launch
   uint32_t* sort_done;        // blocks of the running sort that have finished
   uint32_t* perm;             // per slot: perm[new] = old of the last sort
+  const double2* ring_cs;     // [n_inst][WC_MAX_RING] (cos, sin) of the ring angles
   uint32_t* gslot;            // per ghost: current slot
   const uint32_t* wrank;      // per ghost: static bucket rank of a wall ghost
   const int4* gblk;           // ghost-kernel block table: (inst, first item, count, kind)

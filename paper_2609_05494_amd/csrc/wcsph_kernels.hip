@@ -93,13 +93,22 @@ __device__ __forceinline__ void cell_xy(const InstParams& P, uint32_t K, int& cx
   cx = local - cy * P.ncx;
 }
 
-// Encode an FP64 position into (cell, FP32 offset inside the cell).
-__device__ __forceinline__ void encode_axis(double x, double lo, double dcd, float dc, int n, int& c,
-                                            float& o) {
+// Encode an FP64 position into (cell, FP32 offset inside the cell): the
+// cell from u / dc (by the inverse edge, then corrected so that the offset
+// lies in [0, dc)), clamped to the grid.
+__device__ __forceinline__ void encode_axis(double x, double lo, double dcd, double inv_dcd, float dc, int n,
+                                            int& c, float& o) {
   const double u = x - lo;
-  c = (int)floor(u / dcd);
-  if (c < 0) c = 0;
-  if (c > n - 1) c = n - 1;
+  double cf = floor(u * inv_dcd);
+  double r = u - cf * dcd;
+  if (r < 0.0) {
+    cf -= 1.0;
+    r += dcd;
+  } else if (r >= dcd) {
+    cf += 1.0;
+    r -= dcd;
+  }
+  c = (int)fmin(fmax(cf, 0.0), (double)(n - 1));
   o = (float)(u - (double)c * dcd);
   if (o >= dc && c < n - 1) {
     o -= dc;
@@ -129,13 +138,19 @@ __device__ __forceinline__ void renorm(float& o, int& c, float dc) {
   }
 }
 
-__device__ __forceinline__ double step_dt(const Dev& d, const InstParams& P, const Clock& C) {
+// dt of the current step: the fixed table where it covers the step, else the
+// CFL gate of eq. cfl from v_max (float bits vb).
+__device__ __forceinline__ double step_dt_bits(const Dev& d, const InstParams& P, const Clock& C,
+                                               unsigned int vb) {
   if (d.n_dt > 0) {
     const long long k = C.step - d.dt_step0;
     if (k >= 0 && k < d.n_dt) return d.dt_table[k];
   }
-  const float vm = __uint_as_float(C.vmax_bits);
+  const float vm = __uint_as_float(vb);
   return P.cfl * P.hd / (P.c0d + (double)vm);
+}
+__device__ __forceinline__ double step_dt(const Dev& d, const InstParams& P, const Clock& C) {
+  return step_dt_bits(d, P, C, C.vmax_bits);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -319,6 +334,7 @@ __device__ __forceinline__ float quad_sum(float v) {
   v += __shfl_xor(v, 1);
   return v + __shfl_xor(v, 2);
 }
+
 // Visit the candidates of the 3x3 block of cells around cell K (rows bottom
 // to top, cells left to right, sorted order inside a cell), dealt
 // round-robin to a group of G lanes (lane l takes c = l, l + G, ...) with
@@ -431,6 +447,10 @@ __device__ void clock_commit(const Dev& d, int i) {
     d.hist_t[row] = C.t;
     d.hist_dt[row] = dt;
     te = C.t + 0.5 * dt;
+    double xn, vn, an;
+    kinematics(P, C.t + dt, xn, vn, an);
+    C.xd_next = xn;
+    C.vd_next = vn;
   } else {
     te = C.t_next;
   }
@@ -455,19 +475,17 @@ __device__ __forceinline__ void bucket_put_wall(const Dev& d, const InstParams& 
   bucket[(size_t)K * WC_BUCKET + d.wrank[P.gmap0 + g]] = s;
 }
 
-// Disk-ring ghost k at time te: r_k = c(te) + R (cos 2 pi k / nd, sin 2 pi k / nd),
-// encoded, and put into its bucket for the next sort.
-__device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, int k, double te, const Buf& out,
-                                           int s, uint32_t* bucket) {
-  double xc, v, a;
-  kinematics(P, te, xc, v, a);
-  double sn, cs;
-  sincos(2.0 * M_PI * (double)k / (double)P.nd, &sn, &cs);
-  const double x = xc + P.R * cs, y = P.disk_y0 + P.R * sn;
+// Disk-ring ghost k of instance inst for a disk centre at x = xc:
+// r_k = (xc, y0) + R (cos 2 pi k / nd, sin 2 pi k / nd), encoded, and put
+// into its bucket for the next sort.
+__device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, int inst, int k, double xc,
+                                           const Buf& out, int s, uint32_t* bucket) {
+  const double2 cs = d.ring_cs[inst * WC_MAX_RING + k];
+  const double x = xc + P.R * cs.x, y = P.disk_y0 + P.R * cs.y;
   int cx, cy;
   float ox, oy;
-  encode_axis(x, P.x_lo, P.dcd, P.dc, P.ncx, cx, ox);
-  encode_axis(y, P.y_lo, P.dcd, P.dc, P.ncy, cy, oy);
+  encode_axis(x, P.x_lo, P.dcd, P.inv_dcd, P.dc, P.ncx, cx, ox);
+  encode_axis(y, P.y_lo, P.dcd, P.inv_dcd, P.dc, P.ncy, cy, oy);
   const uint32_t key = (uint32_t)(P.cell_off + cy * P.ncx + cx);
   out.cell[s] = key;
   out.pv[s] = make_float4(ox, oy, 0.0f, 0.0f);
@@ -752,8 +770,12 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     }
     uint32_t* bucket = MODE == EV_A ? d.bucket_b : d.bucket_a;
     if (ring >= 0) {
-      const double te = MODE == EV_A ? C.t + 0.5 * step_dt(d, P, C) : C.t + C.dt;
-      place_ring(d, P, ring, te, out, s, bucket);
+      double xc = C.xd_next;
+      if (MODE == EV_A) {  // disk at t + dt/2
+        double vc, ac;
+        kinematics(P, C.t + 0.5 * step_dt(d, P, C), xc, vc, ac);
+      }
+      place_ring(d, P, inst, ring, xc, out, s, bucket);
     } else {
       if (MODE == EV_A) {
         out.cell[s] = K;
@@ -786,7 +808,6 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
   if (lead) {
     const double dt = MODE == EV_A ? step_dt(d, P, C) : C.dt;
     const float hdt = (float)(MODE == EV_A ? 0.5 * dt : dt);
-    const double te = C.t + (MODE == EV_A ? 0.5 * dt : dt);
     uint32_t Kb;
     float4 pb;
     float rb;
@@ -825,8 +846,12 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     if (y < e) { y = e; vy = -vy; moved = true; }
     if (y > P.W - e) { y = P.W - e; vy = -vy; moved = true; }
     if (P.nd > 0) {
-      double xd, vd, ad;
-      kinematics(P, te, xd, vd, ad);
+      // disk at the time of the new state (t + dt/2 or t + dt)
+      double xd = C.xd_next, vd = C.vd_next;
+      if (MODE == EV_A) {
+        double ad;
+        kinematics(P, C.t + 0.5 * dt, xd, vd, ad);
+      }
       const double rx = x - xd, ry = y - P.disk_y0;
       const double d2 = rx * rx + ry * ry;
       if (d2 < P.R * P.R) {
@@ -848,8 +873,8 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     }
     enf_hit = moved;
     if (moved) {
-      encode_axis(x, P.x_lo, P.dcd, P.dc, P.ncx, cx, ox);
-      encode_axis(y, P.y_lo, P.dcd, P.dc, P.ncy, cy, oy);
+      encode_axis(x, P.x_lo, P.dcd, P.inv_dcd, P.dc, P.ncx, cx, ox);
+      encode_axis(y, P.y_lo, P.dcd, P.inv_dcd, P.dc, P.ncy, cy, oy);
     }
     cx = min(max(cx, 0), P.ncx - 1);
     cy = min(max(cy, 0), P.ncy - 1);
@@ -905,7 +930,9 @@ __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
       const float4 pv = X.pv[s];
       v = fast_sqrt(pv.z * pv.z + pv.w * pv.w);
     } else if (local >= P.nf + P.nw) {
-      place_ring(d, P, local - P.nf - P.nw, d.clk[inst].t_next, X, s, d.bucket_a);
+      double xc, vc, ac;
+      kinematics(P, d.clk[inst].t_next, xc, vc, ac);
+      place_ring(d, P, inst, local - P.nf - P.nw, xc, X, s, d.bucket_a);
     } else {
       bucket_put_wall(d, P, d.bucket_a, X.cell[s], local - P.nf, (uint32_t)s);
     }
@@ -967,11 +994,12 @@ __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_diag_final(Dev d, int row) {
+__global__ __launch_bounds__(64) void k_diag_final(Dev d) {
   const int i = blockIdx.x;
   if (threadIdx.x != 0) return;
   const InstParams& P = d.prm[i];
   Clock& C = d.clk[i];
+  const long long row = C.diag_row++;
   double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = 0; b < WC_DIAG_BLOCKS; ++b)
     for (int k = 0; k < 8; ++k) tot[k] += d.diag_part[((long long)i * WC_DIAG_BLOCKS + b) * 8 + k];
@@ -1065,9 +1093,9 @@ void wc_enqueue_init(const Dev& d, const Bufs& b, bool batch, hipStream_t st) {
   else k_init<false><<<NB(d.n_slots), WC_BLOCK, 0, st>>>(d, b.X);
 }
 
-void wc_enqueue_diag(const Dev& d, const Bufs& b, int row, bool sorted, hipStream_t st) {
+void wc_enqueue_diag(const Dev& d, const Bufs& b, bool sorted, hipStream_t st) {
   k_diag_part<<<dim3(WC_DIAG_BLOCKS, d.n_inst), 256, 0, st>>>(d, b.X, sorted ? 1 : 0);
-  k_diag_final<<<d.n_inst, 64, 0, st>>>(d, row);
+  k_diag_final<<<d.n_inst, 64, 0, st>>>(d);
 }
 
 // Eval-A sort of X into Y without advancing the clock (test hooks).

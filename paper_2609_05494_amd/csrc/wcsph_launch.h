@@ -13,7 +13,7 @@ struct Bufs {
 
 void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, hipStream_t st);
 void wc_enqueue_init(const Dev& d, const Bufs& b, bool batch, hipStream_t st);
-void wc_enqueue_diag(const Dev& d, const Bufs& b, int row, bool sorted, hipStream_t st);
+void wc_enqueue_diag(const Dev& d, const Bufs& b, bool sorted, hipStream_t st);
 void wc_enqueue_export_sort(const Dev& d, const Bufs& b, bool batch, hipStream_t st);
 void wc_enqueue_export_ghosts(const Dev& d, const Bufs& b, int n_gblk, hipStream_t st);
 void wc_enqueue_export_pair(const Dev& d, const Bufs& b, hipStream_t st);
