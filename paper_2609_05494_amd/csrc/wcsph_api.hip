@@ -479,7 +479,6 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   const size_t n_tiles = ((size_t)c->n_cells + WC_SORT_TILE - 1) / WC_SORT_TILE;
   d.tile_flag = dalloc_n<unsigned long long>(c, n_tiles);
   d.sort_epoch = dalloc_n<uint32_t>(c, 4);
-  d.sort_done = d.sort_epoch + 1;
   // (cos, sin) of the ring angles 2 pi k / nd, per instance
   std::vector<double2> ring((size_t)n_inst * WC_MAX_RING, make_double2(0.0, 0.0));
   for (int i = 0; i < n_inst; ++i)
@@ -492,6 +491,8 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   HC(hipMemcpyAsync(ring_cs, ring.data(), ring.size() * sizeof(double2), hipMemcpyHostToDevice, c->st));
   d.perm = dalloc_n<uint32_t>(c, c->n_slots);
   d.gslot = dalloc_n<uint32_t>(c, c->n_ghost);
+  d.gcell = dalloc_n<uint32_t>(c, c->n_ghost);
+  d.gpos = dalloc_n<float2>(c, c->n_ghost);
   c->d_gslot_save = dalloc_n<uint32_t>(c, c->n_ghost);
   uint32_t* wrank = dalloc_n<uint32_t>(c, c->n_ghost);
   d.wrank = wrank;

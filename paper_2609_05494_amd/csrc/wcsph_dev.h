@@ -90,11 +90,12 @@ struct Dev {
   uint32_t* bucket_a;
   uint32_t* bucket_b;
   unsigned long long* tile_flag;  // per sort tile: (epoch, status, prefix) of the look-back scan
-  uint32_t* sort_epoch;       // increases by one per sort launch
-  uint32_t* sort_done;        // blocks of the running sort that have finished
+  uint32_t* sort_epoch;       // moved on after every sort launch
   uint32_t* perm;             // per slot: perm[new] = old of the last sort
   const double2* ring_cs;     // [n_inst][WC_MAX_RING] (cos, sin) of the ring angles
   uint32_t* gslot;            // per ghost: current slot
+  uint32_t* gcell;            // per ghost: cell key in the current sorted order
+  float2* gpos;               // per ghost: offset inside that cell
   const uint32_t* wrank;      // per ghost: static bucket rank of a wall ghost
   const int4* gblk;           // ghost-kernel block table: (inst, first item, count, kind)
   double* hist_t;             // [n_inst][WC_HIST_CAP]

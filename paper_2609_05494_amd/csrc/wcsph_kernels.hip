@@ -261,8 +261,13 @@ __device__ __forceinline__ void pair_body(const InstParams& P, const float4& pi,
 }
 
 #define PAIR_BLOCK 128
+#ifndef GLIST_CAP
 #define GLIST_CAP 16
+#endif
 #define SCAN_UNROLL 4
+#ifndef PAIR_UNROLL
+#define PAIR_UNROLL 4
+#endif
 
 // Sum the pair law of fluid slot s over its 3x3 block of cells with four
 // lanes (quad lane q). The candidates, rows bottom to top and cells left to
@@ -302,11 +307,11 @@ __device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, con
     }
     cnt = 0;
   };
-  for (uint32_t c0 = (uint32_t)q; c0 < n; c0 += 4 * SCAN_UNROLL) {
-    uint32_t jj[SCAN_UNROLL], code[SCAN_UNROLL];
-    float2 pp[SCAN_UNROLL];
+  for (uint32_t c0 = (uint32_t)q; c0 < n; c0 += 4 * PAIR_UNROLL) {
+    uint32_t jj[PAIR_UNROLL], code[PAIR_UNROLL];
+    float2 pp[PAIR_UNROLL];
 #pragma unroll
-    for (int u = 0; u < SCAN_UNROLL; ++u) {
+    for (int u = 0; u < PAIR_UNROLL; ++u) {
       const uint32_t c = min(c0 + 4 * u, n - 1);
       const uint32_t row = c < n0 ? 0u : (c < n01 ? 1u : 2u);
       const RowRange& r = row == 0 ? r0 : (row == 1 ? r1 : r2);
@@ -317,7 +322,7 @@ __device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, con
       pp[u] = make_float2(t.x, t.y);
     }
 #pragma unroll
-    for (int u = 0; u < SCAN_UNROLL; ++u) {
+    for (int u = 0; u < PAIR_UNROLL; ++u) {
       const float rx = (pi.x - pp[u].x) - ((float)(int)(code[u] & 3u) - 1.0f) * P.dc;
       const float ry = (pi.y - pp[u].y) - ((float)(int)(code[u] >> 2) - 1.0f) * P.dc;
       if (c0 + 4 * u < n && rx * rx + ry * ry < P.four_h2 && jj[u] != (uint32_t)s) {
@@ -325,7 +330,7 @@ __device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, con
         ++cnt;
       }
     }
-    if (cnt > GLIST_CAP - SCAN_UNROLL) flush();
+    if (cnt > GLIST_CAP - PAIR_UNROLL) flush();
   }
   flush();
 }
@@ -469,6 +474,39 @@ __device__ __forceinline__ void bucket_put(const Dev& d, uint32_t* bucket, uint3
   if (b < WC_BUCKET) bucket[(size_t)K * WC_BUCKET + b] = s;
   else atomicOr(&d.clk[0].bad, 8u);
 }
+// bucket_put for the lanes with `act` set, one atomic per run: consecutive
+// active lanes (slots in sorted order, mostly keeping their cell) with the
+// same key share one fill-counter update and take consecutive bucket slots.
+__device__ __forceinline__ void bucket_put_wave(const Dev& d, uint32_t* bucket, bool act, uint32_t K,
+                                                uint32_t s) {
+  const int lane = (int)(threadIdx.x & 63);
+  const unsigned long long A = __ballot(act);
+  if (A == 0ull) return;
+  // previous active lane (below this one) and its key
+  const unsigned long long below = A & ((1ull << lane) - 1ull);
+  const int prev = below ? 63 - __clzll((long long)below) : -1;
+  const uint32_t kprev = __shfl(K, prev < 0 ? lane : prev);
+  const bool head = act && (prev < 0 || kprev != K);
+  const unsigned long long H = __ballot(head);
+  // this lane's run head and the next head above it
+  const unsigned long long upto = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+  const unsigned long long hb = H & upto;
+  const int h = hb ? 63 - __clzll((long long)hb) : 0;
+  const unsigned long long above = H & ~upto;
+  const int nh = above ? __ffsll((long long)above) - 1 : 64;
+  const unsigned long long from_h = ~((1ull << h) - 1ull);
+  const unsigned long long to_nh = nh == 64 ? ~0ull : ((1ull << nh) - 1ull);
+  const uint32_t len = (uint32_t)__popcll(A & from_h & to_nh);
+  const uint32_t rank = (uint32_t)__popcll(A & from_h & ((1ull << lane) - 1ull));
+  uint32_t b0 = 0;
+  if (head) b0 = atomicAdd(&d.count[K], len);
+  b0 = __shfl(b0, h);
+  if (!act) return;
+  const uint32_t b = b0 + rank;
+  if (b < WC_BUCKET) bucket[(size_t)K * WC_BUCKET + b] = s;
+  else atomicOr(&d.clk[0].bad, 8u);
+}
+
 // Wall ghost g (static position) into its fixed place at the front of its bucket.
 __device__ __forceinline__ void bucket_put_wall(const Dev& d, const InstParams& P, uint32_t* bucket, uint32_t K,
                                                 int g, uint32_t s) {
@@ -503,17 +541,72 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
 //   2. each bucket ordered by old slot (rank = number of smaller entries:
 //      the sort is stable with respect to the current order)
 //   3. gather of the state into sorted order, per-particle EOS, ghost slots,
-//      perm[new] = old; in eval B the state at time n (pre2) alongside
-// The first block also advances the clocks, and the block that finishes last
-// bumps the epoch for the next launch.
+//      perm[new] = old
+// The first block also advances the clocks. The epoch is moved on by the
+// kernel that follows every sort (the ghost kernel, or k_init after a test
+// hook), so each sort launch sees an epoch of its own.
 #define SORT_BLOCK 256
+#define SORT_SPEC 3  // bucket entries per thread loaded with the counts
 #define SORT_SPIN_LIMIT (1 << 20)
 __device__ __forceinline__ unsigned long long tile_word(uint32_t epoch, uint32_t status, uint32_t v) {
   return ((unsigned long long)epoch << 34) | ((unsigned long long)status << 32) | (unsigned long long)v;
 }
 
+// One particle moved by the sort: its state at the old slot e with the
+// per-particle EOS (fluid) or ghost mass.
+struct Gathered {
+  uint32_t cell, id;
+  float4 pv, aux;
+  int inst, ghost;  // ghost: -1 for fluid, else the ghost index g of its instance
+};
+template <bool BATCH>
+__device__ __forceinline__ Gathered sort_gather(const Dev& d, const Buf& pre, uint32_t e) {
+  Gathered v;
+  if (e >= (uint32_t)d.n_slots) {  // corrupted bucket: flagged, nothing moved
+    v.inst = -1;
+    return v;
+  }
+  v.inst = inst_at<BATCH>(pre, e);
+  const InstParams& P = d.prm[v.inst];
+  v.cell = pre.cell[e];
+  v.id = pre.id[e];
+  v.pv = pre.pv[e];
+  const float rho = pre.aux[e].x;
+  const int local = (int)v.id - P.id0;
+  if (local < P.nf) {
+    float Pq, c;
+    fluid_eos(P, rho, Pq, c);
+    v.aux = make_float4(rho, Pq, c, P.m_fluid);
+    v.ghost = -1;
+  } else {
+    v.ghost = local - P.nf;
+    v.aux = make_float4(rho, 0.0f, 0.0f, v.ghost < P.nw ? -P.m_wall : -P.m_disk);
+  }
+  return v;
+}
+template <bool BATCH>
+__device__ __forceinline__ void sort_store(const Dev& d, const Buf& out, uint32_t e, uint32_t dst,
+                                           const Gathered& v) {
+  if (v.inst < 0 || dst >= (uint32_t)d.n_slots) {
+    atomicOr(&d.clk[0].bad, 4u);
+    return;
+  }
+  if (v.ghost >= 0) {
+    const int gi = d.prm[v.inst].gmap0 + v.ghost;
+    d.gslot[gi] = dst;
+    d.gcell[gi] = v.cell;
+    d.gpos[gi] = make_float2(v.pv.x, v.pv.y);
+  }
+  out.cell[dst] = v.cell;
+  out.id[dst] = v.id;
+  out.pv[dst] = v.pv;
+  out.aux[dst] = v.aux;
+  if constexpr (BATCH) out.inst[dst] = (uint16_t)v.inst;
+  d.perm[dst] = e;
+}
+
 template <int MODE, bool BATCH>
-__global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out, Buf pre2, Buf out2) {
+__global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
   constexpr int T = WC_SORT_TILE;
   __shared__ uint32_t s_off[T + 1];  // exclusive offsets of the tile's cells, total at [T]
   __shared__ uint32_t s_cnt[T];
@@ -526,14 +619,26 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out, Bu
   if (tile == 0)
     for (int i = t; i < d.n_inst; i += SORT_BLOCK) clock_commit<MODE>(d, i);
 
-  if (t < 64) {  // wave 0: counts, tile scan, look-back
+  // Four threads per cell load the cell's count and, before it is known,
+  // the first SORT_SPEC entries of its bucket (stale entries past the count
+  // are ignored).
+  const int sc = t >> 2, ssub = t & 3;
+  const int sK = tile * T + sc;
+  uint32_t scnt = 0, sre[SORT_SPEC];
+  if (sK < d.n_cells) {
+    scnt = min(d.count[sK], (uint32_t)WC_BUCKET);  // overflow was flagged by the producer
+#pragma unroll
+    for (int u = 0; u < SORT_SPEC; ++u) sre[u] = bucket[(size_t)sK * WC_BUCKET + ssub + 4 * u];
+  }
+  if (ssub == 0) s_cnt[sc] = scnt;
+  __syncthreads();
+  // wave 0: the tile's local offsets; its aggregate is published at once so
+  // that later tiles can look past it
+  uint32_t w0_incl = 0, w0_c = 0, w0_total = 0;
+  if (t < 64) {
     const int K = tile * T + t;
-    uint32_t c = 0;
-    if (K < d.n_cells) {
-      c = d.count[K];
-      if (c > WC_BUCKET) c = WC_BUCKET;  // overflow was flagged by the producer
-      d.count[K] = d.wallcount[K];      // re-arm for the next sort
-    }
+    const uint32_t c = s_cnt[t];
+    if (K < d.n_cells) d.count[K] = d.wallcount[K];  // re-arm for the next sort
     uint32_t incl = c;
     for (int o = 1; o < 64; o <<= 1) {
       const uint32_t u = __shfl_up(incl, o);
@@ -541,54 +646,26 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out, Bu
     }
     const uint32_t total = __shfl(incl, 63);
     s_off[t] = incl - c;
-    s_cnt[t] = c;
     if (t == 63) s_off[T] = total;
     if (t == 0)
       __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, tile == 0 ? 2u : 1u, total), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t excl = 0;
-    if (tile > 0) {
-      // lane l inspects tile k - l; stop at the nearest tile holding its
-      // inclusive prefix, adding the aggregates of the tiles in between
-      int k = tile - 1;
-      for (;;) {
-        const int kk = k - t;
-        unsigned long long f = tile_word(epoch, 2u, 0u);
-        if (kk >= 0) {
-          int spin = 0;
-          do {
-            f = __hip_atomic_load(&d.tile_flag[kk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          } while ((uint32_t)(f >> 34) != epoch && ++spin < SORT_SPIN_LIMIT);
-          if ((uint32_t)(f >> 34) != epoch) {  // never published: give up, flag the sort
-            atomicOr(&d.clk[0].bad, 16u);
-            f = tile_word(epoch, 2u, 0u);
-          }
-        }
-        const unsigned long long has_prefix = __ballot(((uint32_t)(f >> 32) & 3u) == 2u);
-        const int stop = has_prefix ? __ffsll((long long)has_prefix) - 1 : 63;
-        uint32_t v = t <= stop ? (uint32_t)f : 0u;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        excl += v;
-        if (has_prefix) break;
-        k -= 64;
-      }
-      if (t == 0)
-        __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, 2u, excl + total), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (t == 0) s_base = excl;
-    if (K < d.n_cells) d.start[K] = excl + (incl - c);
-    if (K == d.n_cells - 1) d.start[d.n_cells] = excl + incl;
+    w0_incl = incl;
+    w0_c = c;
+    w0_total = total;
   }
   __syncthreads();
 
   // bucket contents into LDS, then each bucket ordered by old slot
-  const uint32_t base = s_base, total = s_off[T];
+  const uint32_t total = s_off[T];
   {
-    const int c = t >> 2, sub = t & 3;
-    const int K = tile * T + c;
-    const uint32_t n = s_cnt[c], o = s_off[c];
-    for (uint32_t i = sub; i < n; i += 4) s_raw[o + i] = bucket[(size_t)K * WC_BUCKET + i];
+    const int c = sc, sub = ssub;
+    const int K = sK;
+    const uint32_t n = scnt, o = s_off[c];
+#pragma unroll
+    for (int u = 0; u < SORT_SPEC; ++u)
+      if ((uint32_t)(sub + 4 * u) < n) s_raw[o + sub + 4 * u] = sre[u];
+    for (uint32_t i = sub + 4 * SORT_SPEC; i < n; i += 4) s_raw[o + i] = bucket[(size_t)K * WC_BUCKET + i];
     __syncthreads();
     for (uint32_t i = sub; i < n; i += 4) {
       const uint32_t e = s_raw[o + i];
@@ -599,52 +676,80 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out, Bu
   }
   __syncthreads();
 
-  // gather into sorted order
-  for (uint32_t p = t; p < total; p += SORT_BLOCK) {
-    const uint32_t e = s_srt[p], dst = base + p;
-    if (e >= (uint32_t)d.n_slots || dst >= (uint32_t)d.n_slots) {
-      atomicOr(&d.clk[0].bad, 4u);
-      continue;
+  // The first SORT_ROUNDS entries of each thread are loaded (and their EOS
+  // evaluated) before the tile's place in the sorted order is known; wave 0
+  // resolves that place meanwhile.
+  constexpr int R = 2;
+  Gathered gv[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const uint32_t p = t + k * SORT_BLOCK;
+    if (p < total) gv[k] = sort_gather<BATCH>(d, pre, s_srt[p]);
+  }
+  if (t < 64) {
+    uint32_t excl = 0;
+    if (tile > 0) {
+      // Look back over windows of 4 x 64 tiles: lane l inspects tiles
+      // k - l - 64 j (j = 0..3), nearest first. Stop at the nearest tile
+      // holding its inclusive prefix, adding the aggregates of the tiles in
+      // between.
+      int k = tile - 1;
+      for (;;) {
+        unsigned long long f[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int kk = k - t - 64 * j;
+          f[j] = kk >= 0 ? __hip_atomic_load(&d.tile_flag[kk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                         : tile_word(epoch, 2u, 0u);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int kk = k - t - 64 * j;
+          int spin = 0;
+          while ((uint32_t)(f[j] >> 34) != epoch && ++spin < SORT_SPIN_LIMIT)
+            f[j] = __hip_atomic_load(&d.tile_flag[kk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if ((uint32_t)(f[j] >> 34) != epoch) {  // never published: give up, flag the sort
+            atomicOr(&d.clk[0].bad, 16u);
+            f[j] = tile_word(epoch, 2u, 0u);
+          }
+        }
+        bool found = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (found) break;
+          const unsigned long long has_prefix = __ballot(((uint32_t)(f[j] >> 32) & 3u) == 2u);
+          const int stop = has_prefix ? __ffsll((long long)has_prefix) - 1 : 63;
+          uint32_t v = t <= stop ? (uint32_t)f[j] : 0u;
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+          excl += v;
+          found = has_prefix != 0;
+        }
+        if (found) break;
+        k -= 256;
+      }
+      if (t == 0)
+        __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, 2u, excl + w0_total), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
-    const int inst = inst_at<BATCH>(pre, e);
-    const InstParams& P = d.prm[inst];
-    const uint32_t id = pre.id[e];
-    const float4 pv = pre.pv[e];
-    const float rho = pre.aux[e].x;
-    const int local = (int)id - P.id0;
-    float4 a;
-    if (local < P.nf) {
-      float Pq, c;
-      fluid_eos(P, rho, Pq, c);
-      a = make_float4(rho, Pq, c, P.m_fluid);
-    } else {
-      const int g = local - P.nf;
-      a = make_float4(rho, 0.0f, 0.0f, g < P.nw ? -P.m_wall : -P.m_disk);
-      d.gslot[P.gmap0 + g] = dst;
-    }
-    out.cell[dst] = pre.cell[e];
-    out.id[dst] = id;
-    out.pv[dst] = pv;
-    out.aux[dst] = a;
-    if constexpr (BATCH) out.inst[dst] = (uint16_t)inst;
-    d.perm[dst] = e;
-    if (MODE == EV_B) {
-      out2.cell[dst] = pre2.cell[e];
-      out2.id[dst] = pre2.id[e];
-      out2.pv[dst] = pre2.pv[e];
-      out2.aux[dst] = pre2.aux[e];
-      if constexpr (BATCH) out2.inst[dst] = (uint16_t)inst;
-    }
+    if (t == 0) s_base = excl;
+    const int K = tile * T + t;
+    if (K < d.n_cells) d.start[K] = excl + (w0_incl - w0_c);
+    if (K == d.n_cells - 1) d.start[d.n_cells] = excl + w0_incl;
+  }
+  __syncthreads();
+
+  // stores into sorted order
+  const uint32_t base = s_base;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const uint32_t p = t + k * SORT_BLOCK;
+    if (p < total) sort_store<BATCH>(d, out, s_srt[p], base + p, gv[k]);
+  }
+  for (uint32_t p = t + R * SORT_BLOCK; p < total; p += SORT_BLOCK) {
+    const uint32_t e = s_srt[p];
+    sort_store<BATCH>(d, out, e, base + p, sort_gather<BATCH>(d, pre, e));
   }
 
-  // the last block to finish moves the epoch on (every block has read it)
-  if (t == 0) {
-    const uint32_t done = atomicAdd(d.sort_done, 1u);
-    if (done == gridDim.x - 1) {
-      atomicExch(d.sort_done, 0u);
-      atomicAdd(d.sort_epoch, 1u);
-    }
-  }
 }
 
 // Adami ghost state (walls and ring), probes, ghost v_max and ring work.
@@ -654,6 +759,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out, Bu
 #define GL WC_GHOST_LANES
 template <int MODE, bool BATCH>
 __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(d.sort_epoch, 1u);  // for the next sort
   const int4 blk = d.gblk[blockIdx.x];
   const int inst = blk.x, kind = blk.w;
   const InstParams& P = d.prm[inst];
@@ -677,8 +783,8 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
   if (act) {
     const int g = blk.y + item;
     const uint32_t s = d.gslot[P.gmap0 + g];
-    const uint32_t K = sb.cell[s];
-    const float4 pg = sb.pv[s];
+    const uint32_t K = d.gcell[P.gmap0 + g];
+    const float2 pg = d.gpos[P.gmap0 + g];
     const Shep S = shepard<GL>(d, P, sb, K, pg.x, pg.y, lane);
     const float vwx = disk ? (float)C.vd : 0.0f;
     const float awx = disk ? (float)C.ad : 0.0f;
@@ -758,16 +864,16 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     ai = sb.aux[s];
   }
   const bool fluid = inr && ai.w > 0.0f;
+  // eval B: slot of this particle's state n, fetched ahead of the pair sums
+  const uint32_t eb = (MODE == EV_B && fluid && q == 0) ? d.perm[s] : 0u;
   if (MODE != EV_EXPORT && inr && !fluid && q == 0) {
     // ghosts: wall ghosts are carried, the disk ring is placed at the time of
     // the next evaluation (t + dt/2 after eval A, t + dt after eval B)
     const uint32_t id = sb.id[s];
     const int ring = (int)id - P.id0 - P.nf - P.nw;
-    if (MODE == EV_A) {
-      out.id[s] = id;
-      out.aux[s] = make_float4(ai.x, 0.0f, 0.0f, 0.0f);
-      if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
-    }
+    out.id[s] = id;
+    out.aux[s] = make_float4(ai.x, 0.0f, 0.0f, 0.0f);
+    if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
     uint32_t* bucket = MODE == EV_A ? d.bucket_b : d.bucket_a;
     if (ring >= 0) {
       double xc = C.xd_next;
@@ -777,10 +883,8 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       }
       place_ring(d, P, inst, ring, xc, out, s, bucket);
     } else {
-      if (MODE == EV_A) {
-        out.cell[s] = K;
-        out.pv[s] = pi;
-      }
+      out.cell[s] = K;
+      out.pv[s] = pi;
       bucket_put_wall(d, P, bucket, K, (int)id - P.id0 - P.nf, (uint32_t)s);
     }
   }
@@ -805,6 +909,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
   }
   bool clamp_hit = false, enf_hit = false;
   float vnew = 0.0f;
+  uint32_t newkey = 0u;
   if (lead) {
     const double dt = MODE == EV_A ? step_dt(d, P, C) : C.dt;
     const float hdt = (float)(MODE == EV_A ? 0.5 * dt : dt);
@@ -816,9 +921,11 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       pb = pi;
       rb = ai.x;
     } else {
-      Kb = base.cell[s];
-      pb = base.pv[s];
-      rb = base.aux[s].x;
+      // state n of this particle: the sort of this evaluation took it from
+      // slot perm[s] of the step's first sorted state
+      Kb = base.cell[eb];
+      pb = base.pv[eb];
+      rb = base.aux[eb].x;
     }
     float rn = rb + hdt * acc.D;
     if (rn < P.rho_lo) { rn = P.rho_lo; clamp_hit = true; }
@@ -882,14 +989,13 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     out.cell[s] = Kn;
     out.pv[s] = make_float4(ox, oy, vx, vy);
     out.aux[s] = make_float4(rn, 0.0f, 0.0f, 0.0f);
-    if (MODE == EV_A) {
-      out.id[s] = sb.id[s];
-      if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
-    }
-    bucket_put(d, MODE == EV_A ? d.bucket_b : d.bucket_a, Kn, (uint32_t)s);
+    out.id[s] = sb.id[s];
+    if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
+    newkey = Kn;
     vnew = fast_sqrt(vx * vx + vy * vy);
     if (!(rn == rn) || !(vnew <= 3.0e38f)) atomicOr(&clk[inst].bad, 1u);
   }
+  bucket_put_wave(d, MODE == EV_A ? d.bucket_b : d.bucket_a, lead, newkey, (uint32_t)s);
   count_hits<BATCH>(clk, inst, clamp_hit, enf_hit);
   if (MODE == EV_B) {
     vmax_update<BATCH>(clk, inst, lead, vnew);
@@ -917,6 +1023,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
 template <bool BATCH>
 __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
   const int s = blockIdx.x * WC_BLOCK + threadIdx.x;
+  if (s == 0) atomicAdd(d.sort_epoch, 1u);  // for the next sort
   const bool inr = s < d.n_slots;
   const int inst = inr ? inst_at<BATCH>(X, s) : 0;
   const InstParams& P = d.prm[inst];
@@ -1065,22 +1172,21 @@ __global__ __launch_bounds__(WC_BLOCK) void k_neigh(Dev d, Buf sb) {
 #define NQ(n) (((n) + PAIR_BLOCK / 4 - 1) / (PAIR_BLOCK / 4))
 
 template <bool BATCH>
-static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, const Buf& out,
-                      const Buf& pre2, const Buf& out2) {
+static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, const Buf& out) {
   const int nt = (d.n_cells + WC_SORT_TILE - 1) / WC_SORT_TILE;
-  if (mode == EV_A) k_sort<EV_A, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out, pre2, out2);
-  else if (mode == EV_B) k_sort<EV_B, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out, pre2, out2);
-  else k_sort<EV_EXPORT, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out, pre2, out2);
+  if (mode == EV_A) k_sort<EV_A, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+  else if (mode == EV_B) k_sort<EV_B, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+  else k_sort<EV_EXPORT, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
 }
 
 template <bool BATCH>
 static void enqueue_step_t(const Dev& d, const Bufs& b, int n_gblk, hipStream_t st) {
-  eval_sort<BATCH>(d, st, EV_A, b.X, b.Y, b.Y, b.Y);
+  eval_sort<BATCH>(d, st, EV_A, b.X, b.Y);
   k_ghost<EV_A, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
   k_pair<EV_A, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
-  eval_sort<BATCH>(d, st, EV_B, b.Z, b.W, b.Y, b.X);
+  eval_sort<BATCH>(d, st, EV_B, b.Z, b.W);
   k_ghost<EV_B, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.W);
-  k_pair<EV_B, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.X, b.X);
+  k_pair<EV_B, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.Y, b.X);
 }
 
 void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, hipStream_t st) {
@@ -1100,8 +1206,8 @@ void wc_enqueue_diag(const Dev& d, const Bufs& b, bool sorted, hipStream_t st) {
 
 // Eval-A sort of X into Y without advancing the clock (test hooks).
 void wc_enqueue_export_sort(const Dev& d, const Bufs& b, bool batch, hipStream_t st) {
-  if (batch) eval_sort<true>(d, st, EV_EXPORT, b.X, b.Y, b.Y, b.Y);
-  else eval_sort<false>(d, st, EV_EXPORT, b.X, b.Y, b.Y, b.Y);
+  if (batch) eval_sort<true>(d, st, EV_EXPORT, b.X, b.Y);
+  else eval_sort<false>(d, st, EV_EXPORT, b.X, b.Y);
 }
 
 void wc_enqueue_export_ghosts(const Dev& d, const Bufs& b, int n_gblk, hipStream_t st) {
@@ -1123,12 +1229,12 @@ void wc_enqueue_neigh(const Dev& d, const Bufs& b, hipStream_t st) {
 
 void wc_enqueue_eval(const Dev& d, const Bufs& b, int n_gblk, int mode, hipStream_t st) {
   if (mode == EV_A) {
-    eval_sort<false>(d, st, EV_A, b.X, b.Y, b.Y, b.Y);
+    eval_sort<false>(d, st, EV_A, b.X, b.Y);
     k_ghost<EV_A, false><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
     k_pair<EV_A, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
   } else {
-    eval_sort<false>(d, st, EV_B, b.Z, b.W, b.Y, b.X);
+    eval_sort<false>(d, st, EV_B, b.Z, b.W);
     k_ghost<EV_B, false><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.W);
-    k_pair<EV_B, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.X, b.X);
+    k_pair<EV_B, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.Y, b.X);
   }
 }
