@@ -20,7 +20,7 @@
 #define WC_GHOST_BLOCK 256
 #define WC_GHOST_LANES 16      // lanes per ghost or probe in the ghost kernel
 #define WC_MAX_RING 256        // disk-ring ghosts per instance
-#define WC_DIAG_BLOCKS 64      // diagnostic partial sums per instance
+#define WC_DIAG_BLOCKS 256     // diagnostic partial sums per instance
 #define WC_BUCKET 64           // capacity of one cell bucket (particles per cell)
 #define WC_SORT_TILE 64        // cells per block of the sort kernel
 

@@ -260,6 +260,101 @@ __device__ __forceinline__ void pair_body(const InstParams& P, const float4& pi,
   acc.Vy -= w * vyij;
 }
 
+#ifdef PAIR_POOLED
+#define PAIR_BLOCK 128
+#define SCAN_UNROLL 4
+#ifndef PAIR_SCAN_UNROLL
+#define PAIR_SCAN_UNROLL 2
+#endif
+#ifndef QCAP
+#define QCAP 48                       // entries of a quad's neighbour list
+#endif
+#define NQB (PAIR_BLOCK / 4)          // quads per block
+#define QSTR (NQB + 1)                // LDS stride between list entries
+
+// Exchange inside a quad of lanes (DPP quad permutations).
+__device__ __forceinline__ int quad_xor1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int quad_xor2(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); }
+__device__ __forceinline__ float quad_xor1(float v) { return __int_as_float(quad_xor1(__float_as_int(v))); }
+__device__ __forceinline__ float quad_xor2(float v) { return __int_as_float(quad_xor2(__float_as_int(v))); }
+// Fixed-order quad sum: (l0 + l1) + (l2 + l3), the same bits on all four lanes.
+__device__ __forceinline__ float quad_sum(float v) {
+  v += quad_xor1(v);
+  return v + quad_xor2(v);
+}
+
+// Sum the pair law of fluid slot s over its 3x3 block of cells with the
+// four lanes of a quad (lane q). The cell rows are walked bottom to top;
+// inside a row the quad takes PAIR_SCAN_UNROLL groups of four consecutive
+// slots per pass (lane q the q-th of each group). In-support neighbours go
+// to the quad's list in LDS (slot << 4 | row << 2 | column of the cell) in
+// scan order; whenever the list may overflow, and at the end, the quad sums
+// the pair law over the list with lane q taking entries q, q + 4, ...
+// Lane partial sums are combined in a fixed order by the caller.
+__device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, const Buf& sb, int s,
+                                          uint32_t K, float4 pi, float4 ai, int q, uint32_t* lq,
+                                          PairAcc& acc) {
+  constexpr int U = PAIR_SCAN_UNROLL;
+  const float rhoi = ai.x, Pi = ai.y, ci = ai.z;
+  int cx, cy;
+  cell_xy(P, K, cx, cy);
+  // offsets of particle i seen from the cell with shift code 0 (left / below)
+  const float oxl = pi.x + P.dc, oyb = pi.y + P.dc;
+  int cnt = 0;  // entries in the quad's list (the same on its four lanes)
+  auto flush = [&]() __attribute__((always_inline)) {
+    for (int k = q; k < cnt; k += 4) {
+      const uint32_t e = lq[__umul24((uint32_t)k, QSTR)];
+      const float4 pj = sb.pv[e >> 4], aj = sb.aux[e >> 4];
+      const float rx = fmaf(-P.dc, (float)(e & 3u), oxl - pj.x);
+      const float ry = fmaf(-P.dc, (float)((e >> 2) & 3u), oyb - pj.y);
+      pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc);
+    }
+    cnt = 0;
+  };
+  const float oxr = pi.x - P.dc;
+  for (int dy = -1; dy <= 1; ++dy) {
+    const RowRange r = row_range(d, P, cx, cy, dy);
+    const float oy = pi.y - (float)dy * P.dc;
+    const uint32_t rc = (uint32_t)(dy + 1) << 2;
+    for (uint32_t jb = r.rs; jb < r.re; jb += 4u * U) {
+      uint32_t jj[U];
+      float2 pp[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        jj[u] = jb + 4u * u + (uint32_t)q;
+        const float4 t = sb.pv[min(jj[u], r.re - 1)];
+        pp[u] = make_float2(t.x, t.y);
+      }
+      bool hit[U];
+      uint32_t ent[U];
+      int h = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t j = jj[u];
+        const bool l = j < r.ms, m = j < r.me;
+        const float ox = l ? oxl : (m ? pi.x : oxr);
+        const float hx = ox - pp[u].x, hy = oy - pp[u].y;
+        hit[u] = j < r.re && hx * hx + hy * hy < P.four_h2 && j != (uint32_t)s;
+        ent[u] = (j << 4) | rc | (l ? 0u : (m ? 1u : 2u));
+        h += hit[u] ? 1 : 0;
+      }
+      // place of this lane's hits in the quad list: exclusive prefix over the quad
+      const int h1 = quad_xor1(h), h2 = h + h1, h2o = quad_xor2(h2);
+      uint32_t at = __umul24((uint32_t)(cnt + ((q & 1) ? h1 : 0) + ((q & 2) ? h2o : 0)), QSTR);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (hit[u]) {
+          lq[at] = ent[u];
+          at += QSTR;
+        }
+      cnt += h2 + h2o;
+      if (cnt > QCAP - 4 * U) flush();
+    }
+  }
+  flush();
+}
+
+#else
 #define PAIR_BLOCK 128
 #ifndef GLIST_CAP
 #define GLIST_CAP 16
@@ -282,6 +377,56 @@ __device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, con
   const float rhoi = ai.x, Pi = ai.y, ci = ai.z;
   int cx, cy;
   cell_xy(P, K, cx, cy);
+#ifdef PAIR_ROWSCAN
+  int cnt = 0;
+  auto flush = [&]() {
+    if (cnt == 0) return;
+    uint32_t e = my[0];
+    float4 pj = sb.pv[e >> 4];
+    float4 aj = sb.aux[e >> 4];
+    for (int k = 0; k < cnt; ++k) {
+      const uint32_t ec = e;
+      const float4 pc = pj, ac = aj;
+      if (k + 1 < cnt) {
+        e = my[(k + 1) * PAIR_BLOCK];
+        pj = sb.pv[e >> 4];
+        aj = sb.aux[e >> 4];
+      }
+      const float shx = (float)((int)(ec & 3u) - 1) * P.dc;
+      const float shy = (float)((int)((ec >> 2) & 3u) - 1) * P.dc;
+      const float rx = (pi.x - pc.x) - shx;
+      const float ry = (pi.y - pc.y) - shy;
+      pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pc, ac, acc);
+    }
+    cnt = 0;
+  };
+  const float oxl = pi.x + P.dc, oxr = pi.x - P.dc;
+  for (int dy = -1; dy <= 1; ++dy) {
+    const RowRange r = row_range(d, P, cx, cy, dy);
+    const float oy = pi.y - (float)dy * P.dc;
+    const uint32_t rc = (uint32_t)(dy + 1) << 2;
+    for (uint32_t jb = r.rs + (uint32_t)q; jb < r.re; jb += 4 * PAIR_UNROLL) {
+      float2 pp[PAIR_UNROLL];
+#pragma unroll
+      for (int u = 0; u < PAIR_UNROLL; ++u) {
+        const float4 t = sb.pv[min(jb + 4 * u, r.re - 1)];
+        pp[u] = make_float2(t.x, t.y);
+      }
+#pragma unroll
+      for (int u = 0; u < PAIR_UNROLL; ++u) {
+        const uint32_t j = jb + 4 * u;
+        const bool l = j < r.ms, m = j < r.me;
+        const float rx = (l ? oxl : (m ? pi.x : oxr)) - pp[u].x;
+        const float ry = oy - pp[u].y;
+        if (j < r.re && rx * rx + ry * ry < P.four_h2 && j != (uint32_t)s) {
+          my[cnt * PAIR_BLOCK] = (j << 4) | rc | (l ? 0u : (m ? 1u : 2u));
+          ++cnt;
+        }
+      }
+      if (cnt > GLIST_CAP - PAIR_UNROLL) flush();
+    }
+  }
+#else
   const RowRange r0 = row_range(d, P, cx, cy, -1), r1 = row_range(d, P, cx, cy, 0),
                  r2 = row_range(d, P, cx, cy, 1);
   const uint32_t n0 = r0.re - r0.rs, n01 = n0 + (r1.re - r1.rs), n = n01 + (r2.re - r2.rs);
@@ -332,6 +477,7 @@ __device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, con
     }
     if (cnt > GLIST_CAP - PAIR_UNROLL) flush();
   }
+#endif
   flush();
 }
 
@@ -339,6 +485,8 @@ __device__ __forceinline__ float quad_sum(float v) {
   v += __shfl_xor(v, 1);
   return v + __shfl_xor(v, 2);
 }
+
+#endif
 
 // Visit the candidates of the 3x3 block of cells around cell K (rows bottom
 // to top, cells left to right, sorted order inside a cell), dealt
@@ -846,8 +994,16 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
 // Pair sums + predictor (eval A) / corrector (eval B) for every fluid slot;
 // ghost slots are carried into the output buffer. EV_EXPORT writes the rates.
 template <int MODE, bool BATCH>
+#ifdef PAIR_MINW
+__global__ __launch_bounds__(PAIR_BLOCK, PAIR_MINW) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
+#else
 __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
+#endif
+#ifdef PAIR_POOLED
+  __shared__ uint32_t lst[QCAP * QSTR];
+#else
   __shared__ uint32_t lst[GLIST_CAP * PAIR_BLOCK];
+#endif
   // four lanes per slot; blocks map to XCDs in contiguous slot ranges
   const int q = threadIdx.x & 3;
   const int s = xcd_block(blockIdx.x, gridDim.x) * (PAIR_BLOCK / 4) + (threadIdx.x >> 2);
@@ -889,7 +1045,11 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     }
   }
   PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#ifdef PAIR_POOLED
+  if (fluid) pair_sums(d, P, sb, s, K, pi, ai, q, lst + (threadIdx.x >> 2), acc);
+#else
   if (fluid) pair_sums(d, P, sb, s, K, pi, ai, q, lst + threadIdx.x, acc);
+#endif
   // fixed-order combination of the quad's partial sums: (l0 + l1) + (l2 + l3)
   acc.D = quad_sum(acc.D);
   acc.ax = quad_sum(acc.ax);
@@ -1047,6 +1207,21 @@ __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
   vmax_update<BATCH>(d.clk, inst, fl, v);
 }
 
+// r^(gamma - 1) in FP64: repeated products for an integer gamma (the Tait
+// gamma = 7 gives r^6), pow otherwise.
+__device__ __forceinline__ double pow_gm1(double r, double g) {
+  const double e = g - 1.0;
+  if (e == floor(e) && e >= 0.0 && e <= 16.0) {
+    double p = 1.0, b = r;
+    for (int k = (int)e; k > 0; k >>= 1) {
+      if (k & 1) p *= b;
+      b *= b;
+    }
+    return p;
+  }
+  return pow(r, e);
+}
+
 // FP64 diagnostics: partial sums over fixed chunks of each instance's slots
 // (grid: WC_DIAG_BLOCKS x n_inst), then one fixed-order pass per instance.
 __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
@@ -1066,6 +1241,7 @@ __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
   const double rc = r0 * pow(1.0 + P.p_cavd / B, 1.0 / g);
   const double k1 = B / ((g - 1.0) * pow(r0, g)), r0g1 = pow(r0, g - 1.0);
   const double erc = B * ((pow(rc, g - 1.0) - r0g1) / ((g - 1.0) * pow(r0, g)) + 1.0 / rc - 1.0 / r0);
+  const double inv_r0g = 1.0 / pow(r0, g);
   double M = 0, px = 0, py = 0, ke = 0, eel = 0, epot = 0, ncav = 0, bad = 0;
   for (int s = a + (int)threadIdx.x; s < e; s += 256) {
     const int local = (int)X.id[s] - P.id0;
@@ -1080,11 +1256,11 @@ __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
     px += m * u;
     py += m * w;
     ke += 0.5 * m * (u * u + w * w);
-    const double rg1 = pow(r, g - 1.0);
+    const double rg1 = pow_gm1(r, g);
     // specific elastic energy of the Tait law, cutoff branch below rho_c
     eel += m * (r >= rc ? k1 * (rg1 - r0g1) + B * (1.0 / r - 1.0 / r0) : erc + P.p_cavd * (1.0 / rc - 1.0 / r));
     epot += m * (-(double)P.gy) * y;
-    ncav += (B * (rg1 * r / pow(r0, g) - 1.0) <= P.p_cavd) ? 1.0 : 0.0;
+    ncav += (B * (rg1 * r * inv_r0g - 1.0) <= P.p_cavd) ? 1.0 : 0.0;
     if (!(r == r) || !(fabs(u) < 1e30) || !(fabs(w) < 1e30)) bad += 1.0;
   }
   const double v[8] = {M, px, py, ke, eel, epot, ncav, bad};
@@ -1103,13 +1279,20 @@ __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
 
 __global__ __launch_bounds__(64) void k_diag_final(Dev d) {
   const int i = blockIdx.x;
+  // fixed-order sum of the block partials: lane l adds blocks l, l + 64, ...
+  // in order, then a butterfly over the wave
+  double tot[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    double v = 0.0;
+    for (int b = (int)threadIdx.x; b < WC_DIAG_BLOCKS; b += 64)
+      v += d.diag_part[((long long)i * WC_DIAG_BLOCKS + b) * 8 + k];
+    tot[k] = wave_sum(v);
+  }
   if (threadIdx.x != 0) return;
   const InstParams& P = d.prm[i];
   Clock& C = d.clk[i];
   const long long row = C.diag_row++;
-  double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int b = 0; b < WC_DIAG_BLOCKS; ++b)
-    for (int k = 0; k < 8; ++k) tot[k] += d.diag_part[((long long)i * WC_DIAG_BLOCKS + b) * 8 + k];
   double xd, vd, ad;
   kinematics(P, C.t_next, xd, vd, ad);
   double* o = d.diag + ((long long)i * WC_DIAG_CAP + (row % WC_DIAG_CAP)) * WC_NDIAG;
