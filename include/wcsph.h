@@ -211,10 +211,9 @@ wcsph_status wcsph_export_rates(wcsph_ctx* ctx, float* drho, float* ax, float* a
 wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, long long* idsum,
                                      double* x, double* y, size_t cap_slots);
 /* Measurement hook: average duration (ms) of the pair-sum kernel of the
- * first evaluation, re-launched `reps` times on the current sorted state
- * between HIP events on the context stream (each launch preceded by a
- * re-arm copy of the cell counts, whose time is measured alone and
- * subtracted). The state is restored. */
+ * first evaluation, re-launched `reps` (1..1000) times back to back on the
+ * current sorted state between two HIP events on the context stream. The
+ * state is restored. */
 wcsph_status wcsph_time_pair_kernel(wcsph_ctx* ctx, int reps, float* avg_ms);
 
 /* ---- coefficients and reverse sweep --------------------------------------- */

