@@ -201,19 +201,66 @@ __global__ __launch_bounds__(256) void k_adj_gather(Dev d, AdjPtrs a, TapeEval t
   for (int c = 0; c < 5; ++c) a.lam_s[c * d.n_slots + s] = fl ? a.lam_f[c * P.nf + id] : 0.0f;
 }
 
+// The 3x3 block of cells around (cx, cy) in a taped cell list as three row
+// ranges; candidate c (rows bottom to top, cells left to right) maps to
+// slot j and cell shift (dx, dy).
+struct TRow {
+  uint32_t rs, ms, me, re;
+};
+__device__ __forceinline__ TRow trow(const TapeEval& te, const InstParams& P, int cx, int cy, int dy) {
+  TRow r = {0u, 0u, 0u, 0u};
+  const int yy = cy + dy;
+  if (yy < 0 || yy >= P.ncy) return r;
+  const int xlo = max(cx - 1, 0), xhi = min(cx + 1, P.ncx - 1);
+  const uint32_t k0 = (uint32_t)(P.cell_off + yy * P.ncx);
+  r.rs = te.start[k0 + xlo];
+  r.ms = te.start[k0 + cx];
+  r.me = te.start[k0 + cx + 1];
+  r.re = te.start[k0 + xhi + 1];
+  return r;
+}
+// candidate counts below rows 1 and 2, and in all three rows
+struct TCount {
+  uint32_t n0, n01, n;
+};
+__device__ __forceinline__ TCount tcount(const TRow& r0, const TRow& r1, const TRow& r2) {
+  TCount k;
+  k.n0 = r0.re - r0.rs;
+  k.n01 = k.n0 + (r1.re - r1.rs);
+  k.n = k.n01 + (r2.re - r2.rs);
+  return k;
+}
+// (three separate row variables: kept in registers, not indexed memory)
+__device__ __forceinline__ void tcand(const TRow& r0, const TRow& r1, const TRow& r2, const TCount& k, uint32_t c,
+                                      uint32_t& j, int& dx, int& dy) {
+  const bool a0 = c < k.n0, a1 = c < k.n01;
+  const TRow& r = a0 ? r0 : (a1 ? r1 : r2);
+  j = r.rs + c - (a0 ? 0u : (a1 ? k.n0 : k.n01));
+  dy = a0 ? -1 : (a1 ? 0 : 1);
+  dx = j < r.ms ? -1 : (j < r.me ? 0 : 1);
+}
+template <int G>
+__device__ __forceinline__ float gsum(float v) {
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
 // Ghost adjoints. For ghost g: the pair terms phi(i, g) of its fluid
 // neighbours i give dL/d(rho_g, P_g, c_g, v_g); through the linear ghost
 // density these become the adjoint of the ghost pressure (zero when the
 // cavitation cutoff is active) and of c0. The ghost's Shepard sums are
 // stored for the fluid pass. Extra threads compute the probes' Shepard sums.
+#define AG_L 16  // lanes per ghost or probe
 __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te, double t_eval, int n_gb) {
   __shared__ double shd[4];
   const InstParams& P = d.prm[0];
-  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int item = (int)((blockIdx.x * 256 + threadIdx.x) / AG_L);
+  const int lane = (int)(threadIdx.x % AG_L);
   const int ng = P.nw + P.nd;
   double c0bar = 0.0;
   const PairK<float> k = pair_k(P);
-  if (t < ng) {
+  if (item < ng) {
+    const int t = item;
     const uint32_t s = te.gslot[t];
     const uint32_t K = te.cell[s];
     const float4 pg = te.pv[s];
@@ -222,114 +269,121 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
     double xd, vd, ad;
     kin_d(P, t_eval, xd, vd, ad);
     const float awx = disk ? (float)ad : 0.0f;
-    const float vwx = disk ? (float)vd : 0.0f;
     const float mg = -ag.w;
     int cx, cy;
     cxy(P, K, cx, cy);
+    const TRow r0 = trow(te, P, cx, cy, -1), r1 = trow(te, P, cx, cy, 0), r2 = trow(te, P, cx, cy, 1);
+    const TCount blk = tcount(r0, r1, r2);
     float gr = 0, gP = 0, gc = 0, gvx = 0, gvy = 0;
     float SW = 0, Sp = 0, Srx = 0, Sry = 0, Svx = 0, Svy = 0;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int yy = cy + dy;
-      if (yy < 0 || yy >= P.ncy) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int xx = cx + dx;
-        if (xx < 0 || xx >= P.ncx) continue;
-        const uint32_t K2 = (uint32_t)(P.cell_off + yy * P.ncx + xx);
-        for (uint32_t j = te.start[K2]; j < te.start[K2 + 1]; ++j) {
-          const float4 aj = te.aux[j];
-          if (!(aj.w > 0.0f)) continue;
-          const float4 pj = te.pv[j];
-          // r_i - r_g for the pair phi(i, g)
-          const float rx = (pj.x + (float)dx * P.dc) - pg.x, ry = (pj.y + (float)dy * P.dc) - pg.y;
-          const float r2 = rx * rx + ry * ry;
-          if (!(r2 < P.four_h2)) continue;
-          PairIn<float> in;
-          in.rx = rx; in.ry = ry; in.vx = pj.z - pg.z; in.vy = pj.w - pg.w;
-          in.ra = aj.x; in.rb = ag.x; in.Pa = aj.y; in.Pb = ag.y; in.ca = aj.z; in.cb = ag.z;
-          in.mb = mg; in.fl = 0.0f;
-          PairGrad<float> g;
-          const float* ls = a.lam_s;
-          const int N = d.n_slots;
-          pair_vjp(in, k, ls[j], ls[N + j], ls[2 * N + j], ls[3 * N + j], ls[4 * N + j], g, d_sqrt);
-          gr += g.rb;
-          gP += g.P;
-          gc += g.c;
-          gvx -= g.vx;  // v = v_i - v_g
-          gvy -= g.vy;
-          // Shepard sums of the ghost (r_g - r_j = -(r_i - r_g))
-          const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
-          const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
-          const float pj_ = aj.y * aj.x * aj.x;
-          SW += W;
-          Sp += pj_ * W;
-          Srx += aj.x * (-rx) * W;
-          Sry += aj.x * (-ry) * W;
-          Svx += pj.z * W;
-          Svy += pj.w * W;
-        }
+    const float* ls = a.lam_s;
+    const int N = d.n_slots;
+    for (uint32_t c = (uint32_t)lane; c < blk.n; c += AG_L) {
+      uint32_t j;
+      int dx, dy;
+      tcand(r0, r1, r2, blk, c, j, dx, dy);
+      const float4 aj = te.aux[j];
+      if (!(aj.w > 0.0f)) continue;
+      const float4 pj = te.pv[j];
+      // r_i - r_g for the pair phi(i, g)
+      const float rx = (pj.x + (float)dx * P.dc) - pg.x, ry = (pj.y + (float)dy * P.dc) - pg.y;
+      const float r2 = rx * rx + ry * ry;
+      if (!(r2 < P.four_h2)) continue;
+      PairIn<float> in;
+      in.rx = rx; in.ry = ry; in.vx = pj.z - pg.z; in.vy = pj.w - pg.w;
+      in.ra = aj.x; in.rb = ag.x; in.Pa = aj.y; in.Pb = ag.y; in.ca = aj.z; in.cb = ag.z;
+      in.mb = mg; in.fl = 0.0f;
+      PairGrad<float> g;
+      pair_vjp(in, k, ls[j], ls[N + j], ls[2 * N + j], ls[3 * N + j], ls[4 * N + j], g, d_sqrt);
+      gr += g.rb;
+      gP += g.P;
+      gc += g.c;
+      gvx -= g.vx;  // v = v_i - v_g
+      gvy -= g.vy;
+      // Shepard sums of the ghost (r_g - r_j = -(r_i - r_g))
+      const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
+      const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
+      const float pj_ = aj.y * aj.x * aj.x;
+      SW += W;
+      Sp += pj_ * W;
+      Srx += aj.x * (-rx) * W;
+      Sry += aj.x * (-ry) * W;
+      Svx += pj.z * W;
+      Svy += pj.w * W;
+    }
+    gr = gsum<AG_L>(gr);
+    gP = gsum<AG_L>(gP);
+    gc = gsum<AG_L>(gc);
+    gvx = gsum<AG_L>(gvx);
+    gvy = gsum<AG_L>(gvy);
+    SW = gsum<AG_L>(SW);
+    Sp = gsum<AG_L>(Sp);
+    Srx = gsum<AG_L>(Srx);
+    Sry = gsum<AG_L>(Sry);
+    Svx = gsum<AG_L>(Svx);
+    Svy = gsum<AG_L>(Svy);
+    if (lane == 0) {
+      float pt = 0.0f, pbar = 0.0f, vax = 0.0f, vay = 0.0f;
+      const float ax_ = 0.0f - awx, ay_ = P.gy;  // g - a_w
+      if (SW > 0.0f) {
+        pt = (Sp + ax_ * Srx + ay_ * Sry) / SW;
+        vax = Svx / SW;
+        vay = Svy / SW;
       }
+      const float p = ag.y * ag.x * ag.x;  // taped ghost pressure
+      const GhostD gd = ghost_d(P, p);
+      const float pb = gr * gd.drho_dp + gP * gd.dP_dp + gc * gd.dc_drho * gd.drho_dp;
+      c0bar += (double)(gr * gd.drho_dc0 + gP * gd.dP_dc0 + gc * (gd.dc_dc0 + gd.dc_drho * gd.drho_dc0));
+      // v_g = 2 v_w - S_v / S_W; p_g = max(p~, p_cav)
+      pbar = (SW > 0.0f && pt >= P.p_cav) ? pb : 0.0f;
+      float* o = a.gadj + (size_t)s * 10;
+      o[0] = pbar;
+      o[1] = SW > 0.0f ? gvx : 0.0f;
+      o[2] = SW > 0.0f ? gvy : 0.0f;
+      o[3] = SW;
+      o[4] = pt;
+      o[5] = vax;
+      o[6] = vay;
+      o[7] = ax_;
+      o[8] = ay_;
+      o[9] = 0.0f;
     }
-    float pt = 0.0f, pbar = 0.0f, vax = 0.0f, vay = 0.0f;
-    const float ax_ = 0.0f - awx, ay_ = P.gy;  // g - a_w
-    if (SW > 0.0f) {
-      pt = (Sp + ax_ * Srx + ay_ * Sry) / SW;
-      vax = Svx / SW;
-      vay = Svy / SW;
-    }
-    const float p = ag.y * ag.x * ag.x;  // taped ghost pressure
-    const GhostD gd = ghost_d(P, p);
-    const float pb = gr * gd.drho_dp + gP * gd.dP_dp + gc * gd.dc_drho * gd.drho_dp;
-    c0bar += (double)(gr * gd.drho_dc0 + gP * gd.dP_dc0 + gc * (gd.dc_dc0 + gd.dc_drho * gd.drho_dc0));
-    // v_g = 2 v_w - S_v / S_W; p_g = max(p~, p_cav)
-    pbar = (SW > 0.0f && pt >= P.p_cav) ? pb : 0.0f;
-    float* o = a.gadj + (size_t)s * 10;
-    o[0] = pbar;
-    o[1] = SW > 0.0f ? gvx : 0.0f;
-    o[2] = SW > 0.0f ? gvy : 0.0f;
-    o[3] = SW;
-    o[4] = pt;
-    o[5] = vax;
-    o[6] = vay;
-    o[7] = ax_;
-    o[8] = ay_;
-    o[9] = 0.0f;
-    (void)vwx;
-  } else if (t < ng + P.n_probes) {
+  } else if (item < ng + P.n_probes) {
     // probe Shepard sums at state n
-    const int kk = t - ng;
+    const int kk = item - ng;
     const uint32_t K = P.probe_cell[kk];
     int cx, cy;
     cxy(P, K, cx, cy);
+    const TRow r0 = trow(te, P, cx, cy, -1), r1 = trow(te, P, cx, cy, 0), r2 = trow(te, P, cx, cy, 1);
+    const TCount blk = tcount(r0, r1, r2);
     float SW = 0, Sp = 0;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int yy = cy + dy;
-      if (yy < 0 || yy >= P.ncy) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int xx = cx + dx;
-        if (xx < 0 || xx >= P.ncx) continue;
-        const uint32_t K2 = (uint32_t)(P.cell_off + yy * P.ncx + xx);
-        for (uint32_t j = te.start[K2]; j < te.start[K2 + 1]; ++j) {
-          const float4 aj = te.aux[j];
-          if (!(aj.w > 0.0f)) continue;
-          const float4 pj = te.pv[j];
-          const float rx = P.probe_ox[kk] - (pj.x + (float)dx * P.dc), ry = P.probe_oy[kk] - (pj.y + (float)dy * P.dc);
-          const float r2 = rx * rx + ry * ry;
-          if (!(r2 < P.four_h2)) continue;
-          const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
-          const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
-          SW += W;
-          Sp += aj.y * aj.x * aj.x * W;
-        }
-      }
+    for (uint32_t c = (uint32_t)lane; c < blk.n; c += AG_L) {
+      uint32_t j;
+      int dx, dy;
+      tcand(r0, r1, r2, blk, c, j, dx, dy);
+      const float4 aj = te.aux[j];
+      if (!(aj.w > 0.0f)) continue;
+      const float4 pj = te.pv[j];
+      const float rx = P.probe_ox[kk] - (pj.x + (float)dx * P.dc), ry = P.probe_oy[kk] - (pj.y + (float)dy * P.dc);
+      const float r2 = rx * rx + ry * ry;
+      if (!(r2 < P.four_h2)) continue;
+      const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
+      const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
+      SW += W;
+      Sp += aj.y * aj.x * aj.x * W;
     }
-    a.padj[2 * kk] = SW;
-    a.padj[2 * kk + 1] = SW > 0.0f ? Sp / SW : 0.0f;
+    SW = gsum<AG_L>(SW);
+    Sp = gsum<AG_L>(Sp);
+    if (lane == 0) {
+      a.padj[2 * kk] = SW;
+      a.padj[2 * kk + 1] = SW > 0.0f ? Sp / SW : 0.0f;
+    }
   }
   const double tot = block_sum(c0bar, shd);
-  if (threadIdx.x == 0) a.theta_part[(size_t)blockIdx.x * 3 + 2] = tot;
   if (threadIdx.x == 0) {
     a.theta_part[(size_t)blockIdx.x * 3 + 0] = 0.0;
     a.theta_part[(size_t)blockIdx.x * 3 + 1] = 0.0;
+    a.theta_part[(size_t)blockIdx.x * 3 + 2] = tot;
   }
 }
 
@@ -341,9 +395,11 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
 // (added, or set when accumulate == 0).
 __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te, float probe_seed,
                                                     int accumulate, int block0) {
+  // four lanes per slot (quad lane g) share its 3x3 candidates
   __shared__ double shd[4];
   const InstParams& P = d.prm[0];
-  const int s = blockIdx.x * 256 + threadIdx.x;
+  const int s = (int)((blockIdx.x * 256 + threadIdx.x) >> 2);
+  const int g = (int)(threadIdx.x & 3);
   const int N = d.n_slots;
   const PairK<float> k = pair_k(P);
   double th_a = 0.0, th_d = 0.0, th_c = 0.0;
@@ -356,72 +412,70 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
       const float* ls = a.lam_s;
       const float lD = ls[s], lax = ls[N + s], lay = ls[2 * N + s], lVx = ls[3 * N + s], lVy = ls[4 * N + s];
       const EosD<float> ei = eos_d<float>(ai.x, P.rho0, P.c0, P.gamma, P.p_cav, d_pow);
-      float urx = 0, ury = 0, uvx = lVx, uvy = lVy, ur = 0, uP = 0, uc = 0, uc0 = 0;
+      // the XSPH identity term V = v + ... enters once (lane 0)
+      float urx = 0, ury = 0, uvx = g == 0 ? lVx : 0.0f, uvy = g == 0 ? lVy : 0.0f, ur = 0, uP = 0, uc = 0,
+            uc0 = 0;
       int cx, cy;
       cxy(P, K, cx, cy);
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int yy = cy + dy;
-        if (yy < 0 || yy >= P.ncy) continue;
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int xx = cx + dx;
-          if (xx < 0 || xx >= P.ncx) continue;
-          const uint32_t K2 = (uint32_t)(P.cell_off + yy * P.ncx + xx);
-          for (uint32_t j = te.start[K2]; j < te.start[K2 + 1]; ++j) {
-            if (j == (uint32_t)s) continue;
-            const float4 pj = te.pv[j];
-            const float rx = (pi.x - pj.x) - (float)dx * P.dc;  // r_s - r_j
-            const float ry = (pi.y - pj.y) - (float)dy * P.dc;
-            const float r2 = rx * rx + ry * ry;
-            if (!(r2 < P.four_h2)) continue;
-            const float4 aj = te.aux[j];
-            const bool jfl = aj.w > 0.0f;
-            // own rates: phi(s, j)
-            PairIn<float> in;
-            in.rx = rx; in.ry = ry; in.vx = pi.z - pj.z; in.vy = pi.w - pj.w;
-            in.ra = ai.x; in.rb = aj.x; in.Pa = ai.y; in.Pb = aj.y; in.ca = ai.z; in.cb = aj.z;
-            in.mb = fabsf(aj.w); in.fl = jfl ? 1.0f : 0.0f;
-            PairGrad<float> g;
-            pair_vjp(in, k, lD, lax, lay, lVx, lVy, g, d_sqrt);
-            urx += g.rx; ury += g.ry; uvx += g.vx; uvy += g.vy; ur += g.ra; uP += g.P; uc += g.c;
-            th_a += (double)g.alpha;
-            th_d += (double)g.delta;
-            th_c += (double)g.c0x;
-            if (jfl) {
-              // the neighbour's rates: phi(j, s), r = r_j - r_s
-              PairIn<float> jn;
-              jn.rx = -rx; jn.ry = -ry; jn.vx = pj.z - pi.z; jn.vy = pj.w - pi.w;
-              jn.ra = aj.x; jn.rb = ai.x; jn.Pa = aj.y; jn.Pb = ai.y; jn.ca = aj.z; jn.cb = ai.z;
-              jn.mb = ai.w; jn.fl = 1.0f;
-              PairGrad<float> h;
-              pair_vjp(jn, k, ls[j], ls[N + j], ls[2 * N + j], ls[3 * N + j], ls[4 * N + j], h, d_sqrt);
-              urx -= h.rx; ury -= h.ry; uvx -= h.vx; uvy -= h.vy; ur += h.rb; uP += h.P; uc += h.c;
-            } else {
-              // ghost j: this particle enters the ghost's Shepard sums
-              const float* gq = a.gadj + (size_t)j * 10;
-              const float SW = gq[3];
-              if (SW > 0.0f) {
-                const float pbar = gq[0], vbx = gq[1], vby = gq[2], pt = gq[4], vax = gq[5], vay = gq[6];
-                const float gx = gq[7], gy = gq[8];
-                const float ddx = -rx, ddy = -ry;  // d = r_g - r_s
-                const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
-                const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
-                const float F = -P.fgrad * s2 * sq;
-                const float ad_ = gx * ddx + gy * ddy;
-                const float iw = 1.0f / SW;
-                ur += pbar * (ei.dp + ad_) * W * iw;
-                const float cf = -(ei.p + ai.x * ad_ - pt) * F * iw;
-                const float vv = vbx * (pi.z - vax) + vby * (pi.w - vay);
-                urx += pbar * (cf * ddx - ai.x * W * iw * gx) + vv * F * ddx * iw;
-                ury += pbar * (cf * ddy - ai.x * W * iw * gy) + vv * F * ddy * iw;
-                uvx -= vbx * W * iw;
-                uvy -= vby * W * iw;
-                uc0 += pbar * ei.dpdc0 * W * iw;
-              }
-            }
+      const TRow r0 = trow(te, P, cx, cy, -1), r1 = trow(te, P, cx, cy, 0), r2 = trow(te, P, cx, cy, 1);
+    const TCount blk = tcount(r0, r1, r2);
+      for (uint32_t c = (uint32_t)g; c < blk.n; c += 4) {
+        uint32_t j;
+        int dx, dy;
+        tcand(r0, r1, r2, blk, c, j, dx, dy);
+        if (j == (uint32_t)s) continue;
+        const float4 pj = te.pv[j];
+        const float rx = (pi.x - pj.x) - (float)dx * P.dc;  // r_s - r_j
+        const float ry = (pi.y - pj.y) - (float)dy * P.dc;
+        const float r2 = rx * rx + ry * ry;
+        if (!(r2 < P.four_h2)) continue;
+        const float4 aj = te.aux[j];
+        const bool jfl = aj.w > 0.0f;
+        // own rates: phi(s, j)
+        PairIn<float> in;
+        in.rx = rx; in.ry = ry; in.vx = pi.z - pj.z; in.vy = pi.w - pj.w;
+        in.ra = ai.x; in.rb = aj.x; in.Pa = ai.y; in.Pb = aj.y; in.ca = ai.z; in.cb = aj.z;
+        in.mb = fabsf(aj.w); in.fl = jfl ? 1.0f : 0.0f;
+        PairGrad<float> gg;
+        pair_vjp(in, k, lD, lax, lay, lVx, lVy, gg, d_sqrt);
+        urx += gg.rx; ury += gg.ry; uvx += gg.vx; uvy += gg.vy; ur += gg.ra; uP += gg.P; uc += gg.c;
+        th_a += (double)gg.alpha;
+        th_d += (double)gg.delta;
+        th_c += (double)gg.c0x;
+        if (jfl) {
+          // the neighbour's rates: phi(j, s), r = r_j - r_s
+          PairIn<float> jn;
+          jn.rx = -rx; jn.ry = -ry; jn.vx = pj.z - pi.z; jn.vy = pj.w - pi.w;
+          jn.ra = aj.x; jn.rb = ai.x; jn.Pa = aj.y; jn.Pb = ai.y; jn.ca = aj.z; jn.cb = ai.z;
+          jn.mb = ai.w; jn.fl = 1.0f;
+          PairGrad<float> h;
+          pair_vjp(jn, k, ls[j], ls[N + j], ls[2 * N + j], ls[3 * N + j], ls[4 * N + j], h, d_sqrt);
+          urx -= h.rx; ury -= h.ry; uvx -= h.vx; uvy -= h.vy; ur += h.rb; uP += h.P; uc += h.c;
+        } else {
+          // ghost j: this particle enters the ghost's Shepard sums
+          const float* gq = a.gadj + (size_t)j * 10;
+          const float SW = gq[3];
+          if (SW > 0.0f) {
+            const float pbar = gq[0], vbx = gq[1], vby = gq[2], pt = gq[4], vax = gq[5], vay = gq[6];
+            const float gx = gq[7], gy = gq[8];
+            const float ddx = -rx, ddy = -ry;  // d = r_g - r_s
+            const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
+            const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
+            const float F = -P.fgrad * s2 * sq;
+            const float ad_ = gx * ddx + gy * ddy;
+            const float iw = 1.0f / SW;
+            ur += pbar * (ei.dp + ad_) * W * iw;
+            const float cf = -(ei.p + ai.x * ad_ - pt) * F * iw;
+            const float vv = vbx * (pi.z - vax) + vby * (pi.w - vay);
+            urx += pbar * (cf * ddx - ai.x * W * iw * gx) + vv * F * ddx * iw;
+            ury += pbar * (cf * ddy - ai.x * W * iw * gy) + vv * F * ddy * iw;
+            uvx -= vbx * W * iw;
+            uvy -= vby * W * iw;
+            uc0 += pbar * ei.dpdc0 * W * iw;
           }
         }
       }
-      if (probe_seed != 0.0f) {
+      if (probe_seed != 0.0f && g == 0) {
         for (int kk = 0; kk < P.n_probes; ++kk) {
           const float SW = a.padj[2 * kk];
           if (!(SW > 0.0f)) continue;
@@ -442,16 +496,27 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
           uc0 += ei.dpdc0 * W * iw;
         }
       }
-      // EOS chain: P(rho; c0), c(rho; c0)
-      ur += uP * ei.dPdr + uc * ei.dcdr;
-      uc0 += uP * ei.dPdc0 + uc * ei.dcdc0;
-      th_c += (double)uc0;
-      const int n = P.nf;
-      float* lb = a.lam_base;
-      if (accumulate) {
-        lb[id] += urx; lb[n + id] += ury; lb[2 * n + id] += uvx; lb[3 * n + id] += uvy; lb[4 * n + id] += ur;
-      } else {
-        lb[id] = urx; lb[n + id] = ury; lb[2 * n + id] = uvx; lb[3 * n + id] = uvy; lb[4 * n + id] = ur;
+      // fixed-order quad sums
+      urx = gsum<4>(urx);
+      ury = gsum<4>(ury);
+      uvx = gsum<4>(uvx);
+      uvy = gsum<4>(uvy);
+      ur = gsum<4>(ur);
+      uP = gsum<4>(uP);
+      uc = gsum<4>(uc);
+      uc0 = gsum<4>(uc0);
+      if (g == 0) {
+        // EOS chain: P(rho; c0), c(rho; c0)
+        ur += uP * ei.dPdr + uc * ei.dcdr;
+        uc0 += uP * ei.dPdc0 + uc * ei.dcdc0;
+        th_c += (double)uc0;
+        const int n = P.nf;
+        float* lb = a.lam_base;
+        if (accumulate) {
+          lb[id] += urx; lb[n + id] += ury; lb[2 * n + id] += uvx; lb[3 * n + id] += uvy; lb[4 * n + id] += ur;
+        } else {
+          lb[id] = urx; lb[n + id] = ury; lb[2 * n + id] = uvx; lb[3 * n + id] = uvy; lb[4 * n + id] = ur;
+        }
       }
     }
   }
@@ -464,33 +529,45 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
   }
 }
 
-// theta += sum of the per-block partials in block order (FP64).
+// theta += sum of the per-block partials (FP64, fixed order: lane l adds
+// blocks l, l + 64, ... in order, then a butterfly over the wave).
 __global__ void k_adj_theta(AdjPtrs a, int nblk) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double t0 = 0, t1 = 0, t2 = 0;
-  for (int b = 0; b < nblk; ++b) {
-    t0 += a.theta_part[3 * b];
-    t1 += a.theta_part[3 * b + 1];
-    t2 += a.theta_part[3 * b + 2];
+  if (blockIdx.x != 0) return;
+  double t[3];
+  for (int k = 0; k < 3; ++k) {
+    double v = 0.0;
+    for (int b = (int)threadIdx.x; b < nblk; b += 64) v += a.theta_part[3 * b + k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    t[k] = v;
   }
-  a.theta[0] += t0;
-  a.theta[1] += t1;
-  a.theta[2] += t2;
+  if (threadIdx.x == 0) {
+    a.theta[0] += t[0];
+    a.theta[1] += t[1];
+    a.theta[2] += t[2];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Backward pass of one evaluation's rates (ghost adjoints, fluid adjoints,
 // coefficient partials). lam_f (by id) -> lam_base (by id).
+static int adj_ghost_blocks(int n_ghost_probe) { return (n_ghost_probe * AG_L + 255) / 256; }
+static int adj_fluid_blocks(int n_slots) { return (n_slots * 4 + 255) / 256; }
+
+int wc_adj_partial_blocks(int n_ghost_probe, int n_slots) {
+  return adj_ghost_blocks(n_ghost_probe) + adj_fluid_blocks(n_slots);
+}
+
 void wc_enqueue_adj_rates(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_eval, float probe_seed,
                           bool accumulate, hipStream_t st) {
   const InstParams* P = nullptr;
   (void)P;
   const int ns = (d.n_slots + 255) / 256;
   k_adj_gather<<<ns, 256, 0, st>>>(d, a, te);
-  const int ngb = (a.n_ghost_probe + 255) / 256;
+  const int ngb = adj_ghost_blocks(a.n_ghost_probe);
   k_adj_ghost<<<ngb, 256, 0, st>>>(d, a, te, t_eval, ngb);
-  k_adj_fluid<<<ns, 256, 0, st>>>(d, a, te, probe_seed, accumulate ? 1 : 0, ngb);
-  k_adj_theta<<<1, 64, 0, st>>>(a, ngb + ns);
+  const int nfb = adj_fluid_blocks(d.n_slots);
+  k_adj_fluid<<<nfb, 256, 0, st>>>(d, a, te, probe_seed, accumulate ? 1 : 0, ngb);
+  k_adj_theta<<<1, 64, 0, st>>>(a, ngb + nfb);
 }
 
 void wc_enqueue_adj_enforce(const Dev& d, const AdjPtrs& a, int nf, double te, float hdt, bool accumulate,

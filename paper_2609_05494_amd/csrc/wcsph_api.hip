@@ -657,33 +657,42 @@ void alloc_tape(wcsph_ctx* c, int steps) {
   A.tape_steps = steps;
 }
 
-void tape_copy(wcsph_ctx* c, const Buf& b, const TapeEval& t) {
-  const size_t N = c->n_slots;
-  HC(hipMemcpyAsync(t.cell, b.cell, N * 4, hipMemcpyDeviceToDevice, c->st));
-  HC(hipMemcpyAsync(t.id, b.id, N * 4, hipMemcpyDeviceToDevice, c->st));
-  HC(hipMemcpyAsync(t.pv, b.pv, N * 16, hipMemcpyDeviceToDevice, c->st));
-  HC(hipMemcpyAsync(t.aux, b.aux, N * 16, hipMemcpyDeviceToDevice, c->st));
-  HC(hipMemcpyAsync(t.start, c->d.start, ((size_t)c->n_cells + 1) * 4, hipMemcpyDeviceToDevice, c->st));
-  HC(hipMemcpyAsync(t.gslot, c->d.gslot, (size_t)c->n_ghost * 4, hipMemcpyDeviceToDevice, c->st));
+// A sorted-state buffer that lives in the tape (the batched instance tags of
+// the working buffer are kept).
+Buf tape_buf(const Buf& work, const TapeEval& t) {
+  Buf b = work;
+  b.cell = t.cell;
+  b.id = t.id;
+  b.pv = t.pv;
+  b.aux = t.aux;
+  return b;
 }
 
 // Re-run local steps [0, n) of a segment from its checkpoint with plain
-// launches, taping each evaluation's sorted state and pre-enforcement state.
+// launches. Each evaluation sorts straight into its tape entry (sorted
+// state, cell ranges, ghost slots); the enforcement kernels tape the
+// pre-enforcement state. The corrector's pair kernel reads the predictor's
+// sorted state from the tape as well.
 void replay_taped(wcsph_ctx* c, int n) {
   auto& A = c->adj;
   for (int k = 0; k < n; ++k) {
+    Bufs bt = c->b;
+    bt.Y = tape_buf(c->b.Y, A.tA[k]);
+    bt.W = tape_buf(c->b.W, A.tB[k]);
     Dev dA = c->d;
+    dA.start = A.tA[k].start;
+    dA.gslot = A.tA[k].gslot;
     dA.tape_pos = A.pA[k];
     dA.tape_vel = A.vA[k];
-    wc_enqueue_eval(dA, c->b, c->n_gblk, EV_A, c->st);
+    wc_enqueue_eval(dA, bt, c->n_gblk, EV_A, c->st);
     HC(hipGetLastError());
-    tape_copy(c, c->b.Y, A.tA[k]);
     Dev dB = c->d;
+    dB.start = A.tB[k].start;
+    dB.gslot = A.tB[k].gslot;
     dB.tape_pos = A.pB[k];
     dB.tape_vel = A.vB[k];
-    wc_enqueue_eval(dB, c->b, c->n_gblk, EV_B, c->st);
+    wc_enqueue_eval(dB, bt, c->n_gblk, EV_B, c->st);
     HC(hipGetLastError());
-    tape_copy(c, c->b.W, A.tB[k]);
   }
 }
 
@@ -1263,7 +1272,7 @@ wcsph_status wcsph_adj_backward(wcsph_ctx* ctx, double dJ, double* grad) {
     A.a.gadj = dalloc_n<float>(ctx, (size_t)10 * ctx->n_slots);
     A.a.padj = dalloc_n<float>(ctx, 2 * WC_MAX_PROBES);
     A.a.n_ghost_probe = q.nw + q.nd + q.n_probes;
-    A.nblk = (A.a.n_ghost_probe + 255) / 256 + (ctx->n_slots + 255) / 256;
+    A.nblk = wc_adj_partial_blocks(A.a.n_ghost_probe, ctx->n_slots);
     A.a.theta_part = dalloc_n<double>(ctx, (size_t)3 * A.nblk);
     A.a.theta = dalloc_n<double>(ctx, 3);
   }

@@ -24,6 +24,8 @@ void wc_enqueue_neigh(const Dev& d, const Bufs& b, hipStream_t st);
 // B: sort of Z into W with state n into X, ghosts, pair sums + corrector)
 // with plain launches; single instance.
 void wc_enqueue_eval(const Dev& d, const Bufs& b, int n_gblk, int mode, hipStream_t st);
+// number of per-block theta partials one adjoint rate evaluation writes
+int wc_adj_partial_blocks(int n_ghost_probe, int n_slots);
 void wc_enqueue_adj_rates(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_eval, float probe_seed,
                           bool accumulate, hipStream_t st);
 void wc_enqueue_adj_enforce(const Dev& d, const AdjPtrs& a, int nf, double te, float hdt, bool accumulate,

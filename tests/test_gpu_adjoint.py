@@ -74,7 +74,7 @@ def test_autograd_function_matches_reverse_sweep():
     s.set_coefficients(cfg["alpha"], cfg["delta"], cfg["c0"])
     J2 = s.adj_forward(n, 5)
     g2 = s.adj_backward(1.0)
-    assert float(J) == J2
+    assert float(J.detach()) == J2
     assert np.array_equal(np.array([t.grad.item() for t in th]), g2)
     s.close()
 
