@@ -79,7 +79,8 @@ __device__ __forceinline__ void fluid_eos(const InstParams& P, float rho, float&
 
 // Wendland C2 (2D): W = sigma (1-q/2)^4 (2q+1); grad_i W = F r_ij,
 // F = -fgrad (1-q/2)^3.
-__device__ __forceinline__ void wendland(const InstParams& P, float r2, float& W, float& F) {
+template <class PP>
+__device__ __forceinline__ void wendland(const PP& P, float r2, float& W, float& F) {
   const float q = fast_sqrt(r2) * P.inv_h;
   const float s = 1.0f - 0.5f * q;
   const float s2 = s * s;
@@ -232,7 +233,8 @@ __device__ __forceinline__ uint32_t dx_code(uint32_t j, const RowRange& r) {
 // (symmetric form), laminar (Lo-Shao), XSPH. Branch-free: a ghost neighbour
 // (m < 0) contributes nothing to the delta and XSPH terms through m_fl = 0,
 // and the AV switch is min(v_ij . r_ij, 0).
-__device__ __forceinline__ void pair_body(const InstParams& P, const float4& pi, float rhoi, float Pi,
+template <class PP>
+__device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float rhoi, float Pi,
                                           float ci, float rx, float ry, float r2, const float4& pj,
                                           const float4& aj, PairAcc& acc) {
   float W, F;
@@ -260,233 +262,272 @@ __device__ __forceinline__ void pair_body(const InstParams& P, const float4& pi,
   acc.Vy -= w * vyij;
 }
 
-#ifdef PAIR_POOLED
-#define PAIR_BLOCK 128
+#define PAIR_BLOCK 256                 // four waves
+#define PAIR_SLOTS (PAIR_BLOCK / 4)    // slots per block (four lanes each)
 #define SCAN_UNROLL 4
-#ifndef PAIR_SCAN_UNROLL
-#define PAIR_SCAN_UNROLL 2
-#endif
-#ifndef QCAP
-#define QCAP 48                       // entries of a quad's neighbour list
-#endif
-#define NQB (PAIR_BLOCK / 4)          // quads per block
-#define QSTR (NQB + 1)                // LDS stride between list entries
-
-// Exchange inside a quad of lanes (DPP quad permutations).
-__device__ __forceinline__ int quad_xor1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
-__device__ __forceinline__ int quad_xor2(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); }
-__device__ __forceinline__ float quad_xor1(float v) { return __int_as_float(quad_xor1(__float_as_int(v))); }
-__device__ __forceinline__ float quad_xor2(float v) { return __int_as_float(quad_xor2(__float_as_int(v))); }
-// Fixed-order quad sum: (l0 + l1) + (l2 + l3), the same bits on all four lanes.
-__device__ __forceinline__ float quad_sum(float v) {
-  v += quad_xor1(v);
-  return v + quad_xor2(v);
-}
-
-// Sum the pair law of fluid slot s over its 3x3 block of cells with the
-// four lanes of a quad (lane q). The cell rows are walked bottom to top;
-// inside a row the quad takes PAIR_SCAN_UNROLL groups of four consecutive
-// slots per pass (lane q the q-th of each group). In-support neighbours go
-// to the quad's list in LDS (slot << 4 | row << 2 | column of the cell) in
-// scan order; whenever the list may overflow, and at the end, the quad sums
-// the pair law over the list with lane q taking entries q, q + 4, ...
-// Lane partial sums are combined in a fixed order by the caller.
-__device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, const Buf& sb, int s,
-                                          uint32_t K, float4 pi, float4 ai, int q, uint32_t* lq,
-                                          PairAcc& acc) {
-  constexpr int U = PAIR_SCAN_UNROLL;
-  const float rhoi = ai.x, Pi = ai.y, ci = ai.z;
-  int cx, cy;
-  cell_xy(P, K, cx, cy);
-  // offsets of particle i seen from the cell with shift code 0 (left / below)
-  const float oxl = pi.x + P.dc, oyb = pi.y + P.dc;
-  int cnt = 0;  // entries in the quad's list (the same on its four lanes)
-  auto flush = [&]() __attribute__((always_inline)) {
-    for (int k = q; k < cnt; k += 4) {
-      const uint32_t e = lq[__umul24((uint32_t)k, QSTR)];
-      const float4 pj = sb.pv[e >> 4], aj = sb.aux[e >> 4];
-      const float rx = fmaf(-P.dc, (float)(e & 3u), oxl - pj.x);
-      const float ry = fmaf(-P.dc, (float)((e >> 2) & 3u), oyb - pj.y);
-      pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc);
-    }
-    cnt = 0;
-  };
-  const float oxr = pi.x - P.dc;
-  for (int dy = -1; dy <= 1; ++dy) {
-    const RowRange r = row_range(d, P, cx, cy, dy);
-    const float oy = pi.y - (float)dy * P.dc;
-    const uint32_t rc = (uint32_t)(dy + 1) << 2;
-    for (uint32_t jb = r.rs; jb < r.re; jb += 4u * U) {
-      uint32_t jj[U];
-      float2 pp[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        jj[u] = jb + 4u * u + (uint32_t)q;
-        const float4 t = sb.pv[min(jj[u], r.re - 1)];
-        pp[u] = make_float2(t.x, t.y);
-      }
-      bool hit[U];
-      uint32_t ent[U];
-      int h = 0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t j = jj[u];
-        const bool l = j < r.ms, m = j < r.me;
-        const float ox = l ? oxl : (m ? pi.x : oxr);
-        const float hx = ox - pp[u].x, hy = oy - pp[u].y;
-        hit[u] = j < r.re && hx * hx + hy * hy < P.four_h2 && j != (uint32_t)s;
-        ent[u] = (j << 4) | rc | (l ? 0u : (m ? 1u : 2u));
-        h += hit[u] ? 1 : 0;
-      }
-      // place of this lane's hits in the quad list: exclusive prefix over the quad
-      const int h1 = quad_xor1(h), h2 = h + h1, h2o = quad_xor2(h2);
-      uint32_t at = __umul24((uint32_t)(cnt + ((q & 1) ? h1 : 0) + ((q & 2) ? h2o : 0)), QSTR);
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (hit[u]) {
-          lq[at] = ent[u];
-          at += QSTR;
-        }
-      cnt += h2 + h2o;
-      if (cnt > QCAP - 4 * U) flush();
-    }
-  }
-  flush();
-}
-
-#else
-#define PAIR_BLOCK 128
-#ifndef GLIST_CAP
-#define GLIST_CAP 16
-#endif
-#define SCAN_UNROLL 4
-#ifndef PAIR_UNROLL
-#define PAIR_UNROLL 4
-#endif
-
-// Sum the pair law of fluid slot s over its 3x3 block of cells with four
-// lanes (quad lane q). The candidates, rows bottom to top and cells left to
-// right in sorted order, are dealt round-robin to the four lanes; each lane
-// scans its share (SCAN_UNROLL loads in flight), writes the in-support
-// neighbours (slot and cell shift) to a lane-private list in LDS, then sums
-// the pair law over its list while fetching the next neighbour. The quad's
-// partial sums are combined in a fixed order by the caller.
-__device__ __forceinline__ void pair_sums(const Dev& d, const InstParams& P, const Buf& sb, int s,
-                                          uint32_t K, float4 pi, float4 ai, int q, uint32_t* my,
-                                          PairAcc& acc) {
-  const float rhoi = ai.x, Pi = ai.y, ci = ai.z;
-  int cx, cy;
-  cell_xy(P, K, cx, cy);
-#ifdef PAIR_ROWSCAN
-  int cnt = 0;
-  auto flush = [&]() {
-    if (cnt == 0) return;
-    uint32_t e = my[0];
-    float4 pj = sb.pv[e >> 4];
-    float4 aj = sb.aux[e >> 4];
-    for (int k = 0; k < cnt; ++k) {
-      const uint32_t ec = e;
-      const float4 pc = pj, ac = aj;
-      if (k + 1 < cnt) {
-        e = my[(k + 1) * PAIR_BLOCK];
-        pj = sb.pv[e >> 4];
-        aj = sb.aux[e >> 4];
-      }
-      const float shx = (float)((int)(ec & 3u) - 1) * P.dc;
-      const float shy = (float)((int)((ec >> 2) & 3u) - 1) * P.dc;
-      const float rx = (pi.x - pc.x) - shx;
-      const float ry = (pi.y - pc.y) - shy;
-      pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pc, ac, acc);
-    }
-    cnt = 0;
-  };
-  const float oxl = pi.x + P.dc, oxr = pi.x - P.dc;
-  for (int dy = -1; dy <= 1; ++dy) {
-    const RowRange r = row_range(d, P, cx, cy, dy);
-    const float oy = pi.y - (float)dy * P.dc;
-    const uint32_t rc = (uint32_t)(dy + 1) << 2;
-    for (uint32_t jb = r.rs + (uint32_t)q; jb < r.re; jb += 4 * PAIR_UNROLL) {
-      float2 pp[PAIR_UNROLL];
-#pragma unroll
-      for (int u = 0; u < PAIR_UNROLL; ++u) {
-        const float4 t = sb.pv[min(jb + 4 * u, r.re - 1)];
-        pp[u] = make_float2(t.x, t.y);
-      }
-#pragma unroll
-      for (int u = 0; u < PAIR_UNROLL; ++u) {
-        const uint32_t j = jb + 4 * u;
-        const bool l = j < r.ms, m = j < r.me;
-        const float rx = (l ? oxl : (m ? pi.x : oxr)) - pp[u].x;
-        const float ry = oy - pp[u].y;
-        if (j < r.re && rx * rx + ry * ry < P.four_h2 && j != (uint32_t)s) {
-          my[cnt * PAIR_BLOCK] = (j << 4) | rc | (l ? 0u : (m ? 1u : 2u));
-          ++cnt;
-        }
-      }
-      if (cnt > GLIST_CAP - PAIR_UNROLL) flush();
-    }
-  }
-#else
-  const RowRange r0 = row_range(d, P, cx, cy, -1), r1 = row_range(d, P, cx, cy, 0),
-                 r2 = row_range(d, P, cx, cy, 1);
-  const uint32_t n0 = r0.re - r0.rs, n01 = n0 + (r1.re - r1.rs), n = n01 + (r2.re - r2.rs);
-  int cnt = 0;
-  auto flush = [&]() {
-    if (cnt == 0) return;
-    uint32_t e = my[0];
-    float4 pj = sb.pv[e >> 4];
-    float4 aj = sb.aux[e >> 4];
-    for (int k = 0; k < cnt; ++k) {
-      const uint32_t ec = e;
-      const float4 pc = pj, ac = aj;
-      if (k + 1 < cnt) {
-        e = my[(k + 1) * PAIR_BLOCK];
-        pj = sb.pv[e >> 4];
-        aj = sb.aux[e >> 4];
-      }
-      const float shx = (float)((int)(ec & 3u) - 1) * P.dc;
-      const float shy = (float)((int)((ec >> 2) & 3u) - 1) * P.dc;
-      const float rx = (pi.x - pc.x) - shx;
-      const float ry = (pi.y - pc.y) - shy;
-      pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pc, ac, acc);
-    }
-    cnt = 0;
-  };
-  for (uint32_t c0 = (uint32_t)q; c0 < n; c0 += 4 * PAIR_UNROLL) {
-    uint32_t jj[PAIR_UNROLL], code[PAIR_UNROLL];
-    float2 pp[PAIR_UNROLL];
-#pragma unroll
-    for (int u = 0; u < PAIR_UNROLL; ++u) {
-      const uint32_t c = min(c0 + 4 * u, n - 1);
-      const uint32_t row = c < n0 ? 0u : (c < n01 ? 1u : 2u);
-      const RowRange& r = row == 0 ? r0 : (row == 1 ? r1 : r2);
-      const uint32_t j = r.rs + c - (row == 0 ? 0u : (row == 1 ? n0 : n01));
-      jj[u] = j;
-      code[u] = (row << 2) | dx_code(j, r);
-      const float4 t = sb.pv[j];
-      pp[u] = make_float2(t.x, t.y);
-    }
-#pragma unroll
-    for (int u = 0; u < PAIR_UNROLL; ++u) {
-      const float rx = (pi.x - pp[u].x) - ((float)(int)(code[u] & 3u) - 1.0f) * P.dc;
-      const float ry = (pi.y - pp[u].y) - ((float)(int)(code[u] >> 2) - 1.0f) * P.dc;
-      if (c0 + 4 * u < n && rx * rx + ry * ry < P.four_h2 && jj[u] != (uint32_t)s) {
-        my[cnt * PAIR_BLOCK] = (jj[u] << 4) | code[u];
-        ++cnt;
-      }
-    }
-    if (cnt > GLIST_CAP - PAIR_UNROLL) flush();
-  }
-#endif
-  flush();
-}
 
 __device__ __forceinline__ float quad_sum(float v) {
   v += __shfl_xor(v, 1);
   return v + __shfl_xor(v, 2);
 }
 
+// The parameters of the candidate test and the pair law, held in registers
+// (the list stores below would otherwise force them to be reloaded).
+struct PairC {
+  float dc, four_h2, inv_h, sigma, fgrad, alpha, h, eta2h2, two_delta_h_c0, four_nu0, eps_xsph;
+};
+__device__ __forceinline__ PairC pair_c(const InstParams& P) {
+  PairC c;
+  c.dc = P.dc;
+  c.four_h2 = P.four_h2;
+  c.inv_h = P.inv_h;
+  c.sigma = P.sigma;
+  c.fgrad = P.fgrad;
+  c.alpha = P.alpha;
+  c.h = P.h;
+  c.eta2h2 = P.eta2h2;
+  c.two_delta_h_c0 = P.two_delta_h_c0;
+  c.four_nu0 = P.four_nu0;
+  c.eps_xsph = P.eps_xsph;
+  return c;
+}
+
+#ifndef UCAP
+#define UCAP 192  // union candidates staged per pass (one wave)
 #endif
+#ifndef LCAP
+#define LCAP 16   // entries of a lane's hit list
+#endif
+#ifndef PU
+#define PU 4      // candidates per lane per scan step
+#endif
+#define QSTRIDE (PAIR_BLOCK / 4)  // bytes between entries of a quad's list
+#define QCAP (4 * LCAP)            // entries of a quad's list
+
+// Exchange inside a quad of lanes (DPP quad permutations).
+__device__ __forceinline__ int quad_xor1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int quad_xor2(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); }
+
+// Order the wave's LDS accesses: stores before this point are seen by every
+// lane's loads after it (accesses of one wave are performed in order; the
+// fences keep the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pair sums of the fluid slots of one wave (16 consecutive slots, four lanes
+// each; every lane of the wave calls this). Fluid slots of one instance and
+// one cell row form a group; the union of their 3x3 blocks is one slot
+// range per row, which the wave stages in LDS in passes of UCAP entries:
+// offset x, offset y seen from the group's row, cell column, slot. Each
+// lane then walks its own particle's candidates (rows bottom to top, cells
+// left to right in sorted order, dealt round-robin to the quad's lanes)
+// through LDS, keeps the in-support ones in a lane-private list and sums
+// the pair law over the list. A lane's candidate order and every operand
+// of a pair depend on the particle and its neighbours only, not on the
+// other slots of the wave.
+template <bool BATCH>
+__device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int s, int inst, uint32_t K,
+                                               bool fluid, float4 pi, float4 ai, int q, float4* U,
+                                               uint8_t* my, PairAcc& acc) {
+  const InstParams& IP = d.prm[inst];
+  const PairC P = pair_c(IP);
+  const float rhoi = ai.x, Pi = ai.y, ci = ai.z;
+  const uint32_t lane = threadIdx.x & 63u;
+  int cx = 0, cy = 0;
+  if (fluid) cell_xy(IP, K, cx, cy);
+  uint64_t pending = __ballot(fluid);
+  while (pending) {
+    const int L = __builtin_ctzll(pending);
+    const int ginst = __builtin_amdgcn_readlane(inst, L);
+    const int gcy = __builtin_amdgcn_readlane(cy, L);
+    const bool mem = fluid && inst == ginst && cy == gcy;
+    const uint64_t mb = __ballot(mem);
+    pending &= ~mb;
+    const int cxa = __builtin_amdgcn_readlane(cx, L);
+    const int cxb = __builtin_amdgcn_readlane(cx, 63 - __builtin_clzll(mb));
+    const InstParams& G = d.prm[ginst];
+    const int gncx = G.ncx, gncy = G.ncy, goff = G.cell_off;
+    const float gdc = G.dc;
+    // union rows: first slot, first cell key; union index bases ub1, ub2
+    uint32_t urs[3] = {0u, 0u, 0u}, un[3] = {0u, 0u, 0u};
+    int k0[3] = {0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int yy = gcy + r - 1;
+      if (yy >= 0 && yy < gncy) {
+        k0[r] = goff + yy * gncx;
+        urs[r] = d.start[k0[r] + max(cxa - 1, 0)];
+        un[r] = d.start[k0[r] + min(cxb + 1, gncx - 1) + 1] - urs[r];
+      }
+    }
+    const uint32_t ub1 = un[0], ub2 = un[0] + un[1], n = ub2 + un[2];
+    // own rows: candidate c of row r has union index c + adj[r]
+    uint32_t p1 = 0u, p2 = 0u, no = 0u, adj0 = 0u, adj1 = 0u, adj2 = 0u;
+    if (mem) {
+      uint32_t ors[3] = {0u, 0u, 0u}, on[3] = {0u, 0u, 0u};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        if (un[r] != 0u) {
+          ors[r] = d.start[k0[r] + max(cx - 1, 0)];
+          on[r] = d.start[k0[r] + min(cx + 1, gncx - 1) + 1] - ors[r];
+        }
+      }
+      p1 = on[0];
+      p2 = on[0] + on[1];
+      no = p2 + on[2];
+      adj0 = ors[0] - urs[0];
+      adj1 = ub1 + (ors[1] - urs[1]) - p1;
+      adj2 = ub2 + (ors[2] - urs[2]) - p2;
+    }
+#ifdef PAIR_QPOOL
+    const float cxi = (float)(cx - cxa);
+    uint8_t* lq = my - threadIdx.x + (threadIdx.x >> 2);  // entry p of the quad at lq[p * QSTRIDE]
+    uint32_t cb = 0u;  // the quad's next step: candidates cb + 4k + q
+    int cnt = 0;       // entries of the quad's list (the same on its four lanes)
+    auto flush = [&]() __attribute__((always_inline)) {
+      if (q < cnt) {
+        float4 E = U[lq[q * QSTRIDE]];
+        uint32_t j = __float_as_uint(E.w);
+        float4 pj = sb.pv[j], aj = sb.aux[j];
+        for (int k = q; k < cnt; k += 4) {
+          const float4 Ec = E, pc = pj, ac = aj;
+          if (k + 4 < cnt) {
+            E = U[lq[(k + 4) * QSTRIDE]];
+            j = __float_as_uint(E.w);
+            pj = sb.pv[j];
+            aj = sb.aux[j];
+          }
+          const float rx = (pi.x - Ec.x) - (Ec.z - cxi) * P.dc;
+          const float ry = pi.y - Ec.y;
+          pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pc, ac, acc);
+        }
+      }
+      cnt = 0;
+    };
+    for (uint32_t u0 = 0; u0 < n; u0 += UCAP) {
+      const uint32_t m = min(n - u0, (uint32_t)UCAP);
+      wave_sync();  // the previous pass is no longer read
+      for (uint32_t t = lane; t < m; t += 64) {
+        const uint32_t u = u0 + t;
+        const bool a0 = u < ub1, a1 = u < ub2;
+        const uint32_t j = a0 ? urs[0] + u : (a1 ? urs[1] + (u - ub1) : urs[2] + (u - ub2));
+        const int kr = a0 ? k0[0] : (a1 ? k0[1] : k0[2]);
+        const float sy = a0 ? -gdc : (a1 ? 0.0f : gdc);
+        const float4 pj = sb.pv[j];
+        const int cxj = (int)sb.cell[j] - kr;
+        U[t] = make_float4(pj.x, pj.y + sy, (float)(cxj - cxa), __uint_as_float(j));
+      }
+      wave_sync();
+      if (mem) {
+        const uint32_t lim = u0 + m;
+        while (cb < no) {
+          uint32_t ix[PU];
+          bool hit[PU];
+          int h = 0, beyond = 0;
+#pragma unroll
+          for (int k = 0; k < PU; ++k) {
+            const uint32_t cc = cb + 4u * k + (uint32_t)q;
+            const uint32_t u = cc + (cc < p1 ? adj0 : (cc < p2 ? adj1 : adj2));
+            // candidates before this pass were done in an earlier one
+            const bool v = (cc < no) & (u - u0 < m);
+            beyond |= ((cc < no) & (u >= lim)) ? 1 : 0;
+            ix[k] = v ? u - u0 : 0u;
+            const float4 E = U[ix[k]];
+            const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
+            const float ry = pi.y - E.y;
+            hit[k] = v & (rx * rx + ry * ry < P.four_h2) & (__float_as_uint(E.w) != (uint32_t)s);
+            h += hit[k] ? 1 : 0;
+          }
+          // this lane's place in the quad list: hits of the lower lanes first
+          const int h1 = quad_xor1(h), s2 = h + h1, s2o = quad_xor2(s2);
+          int at = cnt + ((q & 1) ? h1 : 0) + ((q & 2) ? s2o : 0);
+#pragma unroll
+          for (int k = 0; k < PU; ++k)
+            if (hit[k]) {
+              lq[at * QSTRIDE] = (uint8_t)ix[k];
+              ++at;
+            }
+          cnt += s2 + s2o;
+          beyond |= quad_xor1(beyond);
+          beyond |= quad_xor2(beyond);
+          if (cnt > QCAP - 4 * PU) flush();
+          if (beyond) break;
+          cb += 4u * PU;
+        }
+        flush();
+      }
+#else
+    const float cxi = (float)(cx - cxa);
+    uint32_t c = (uint32_t)q;  // this lane's next own candidate
+    int cnt = 0;
+    auto flush = [&]() __attribute__((always_inline)) {
+      if (cnt == 0) return;
+      float4 E = U[my[0]];
+      uint32_t j = __float_as_uint(E.w);
+      float4 pj = sb.pv[j], aj = sb.aux[j];
+      for (int k = 0; k < cnt; ++k) {
+        const float4 Ec = E, pc = pj, ac = aj;
+        if (k + 1 < cnt) {
+          E = U[my[(k + 1) * PAIR_BLOCK]];
+          j = __float_as_uint(E.w);
+          pj = sb.pv[j];
+          aj = sb.aux[j];
+        }
+        const float rx = (pi.x - Ec.x) - (Ec.z - cxi) * P.dc;
+        const float ry = pi.y - Ec.y;
+        pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pc, ac, acc);
+      }
+      cnt = 0;
+    };
+    for (uint32_t u0 = 0; u0 < n; u0 += UCAP) {
+      const uint32_t m = min(n - u0, (uint32_t)UCAP);
+      wave_sync();  // the previous pass is no longer read
+      for (uint32_t t = lane; t < m; t += 64) {
+        const uint32_t u = u0 + t;
+        const bool a0 = u < ub1, a1 = u < ub2;
+        const uint32_t j = a0 ? urs[0] + u : (a1 ? urs[1] + (u - ub1) : urs[2] + (u - ub2));
+        const int kr = a0 ? k0[0] : (a1 ? k0[1] : k0[2]);
+        const float sy = a0 ? -gdc : (a1 ? 0.0f : gdc);
+        const float4 pj = sb.pv[j];
+        const int cxj = (int)sb.cell[j] - kr;
+        U[t] = make_float4(pj.x, pj.y + sy, (float)(cxj - cxa), __uint_as_float(j));
+      }
+      wave_sync();
+      if (mem) {
+        while (c < no) {
+          uint32_t ix[PU];
+          bool v[PU];
+          int nv = 0;
+#pragma unroll
+          for (int k = 0; k < PU; ++k) {
+            const uint32_t cc = c + 4u * k;
+            const uint32_t u = cc + (cc < p1 ? adj0 : (cc < p2 ? adj1 : adj2));
+            v[k] = (cc < no) & (u - u0 < m);  // inside this pass (unsigned: both bounds)
+            ix[k] = v[k] ? u - u0 : 0u;
+            nv += v[k] ? 1 : 0;
+          }
+#pragma unroll
+          for (int k = 0; k < PU; ++k) {
+            const float4 E = U[ix[k]];
+            const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
+            const float ry = pi.y - E.y;
+            const bool hit = v[k] & (rx * rx + ry * ry < P.four_h2) & (__float_as_uint(E.w) != (uint32_t)s);
+            my[cnt * PAIR_BLOCK] = (uint8_t)ix[k];
+            cnt += hit ? 1 : 0;
+          }
+          c += 4u * (uint32_t)nv;
+          if (cnt > LCAP - PU) flush();
+          if (nv < PU) break;
+        }
+        flush();
+      }
+#endif
+    }
+  }
+}
 
 // Visit the candidates of the 3x3 block of cells around cell K (rows bottom
 // to top, cells left to right, sorted order inside a cell), dealt
@@ -999,20 +1040,54 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
 
 // Pair sums + predictor (eval A) / corrector (eval B) for every fluid slot;
 // ghost slots are carried into the output buffer. EV_EXPORT writes the rates.
+// A block serves PAIR_SLOTS consecutive slots: first every wave sums the pair
+// law with four lanes per slot, then the first wave finishes the slots with
+// one lane each (time integration, enforcement, bucket entries), so the
+// per-slot FP64 work runs on full waves.
 template <int MODE, bool BATCH>
 #ifdef PAIR_MINW
 __global__ __launch_bounds__(PAIR_BLOCK, PAIR_MINW) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
 #else
 __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
 #endif
-#ifdef PAIR_POOLED
-  __shared__ uint32_t lst[QCAP * QSTR];
-#else
-  __shared__ uint32_t lst[GLIST_CAP * PAIR_BLOCK];
-#endif
-  // four lanes per slot; blocks map to XCDs in contiguous slot ranges
-  const int q = threadIdx.x & 3;
-  const int s = xcd_block(blockIdx.x, gridDim.x) * (PAIR_BLOCK / 4) + (threadIdx.x >> 2);
+  __shared__ float4 uni[PAIR_BLOCK / 64][UCAP];
+  __shared__ uint8_t lst[LCAP * PAIR_BLOCK];
+  __shared__ float sacc[5][PAIR_SLOTS];
+  // blocks map to XCDs in contiguous slot ranges
+  const int s0 = xcd_block(blockIdx.x, gridDim.x) * PAIR_SLOTS;
+  {
+    const int q = threadIdx.x & 3;
+    const int s = s0 + (int)(threadIdx.x >> 2);
+    const bool inr = s < d.n_slots;
+    const int inst = inr ? inst_at<BATCH>(sb, s) : 0;
+    uint32_t K = 0;
+    float4 pi = make_float4(0, 0, 0, 0), ai = make_float4(0, 0, 0, 0);
+    if (inr) {
+      K = sb.cell[s];
+      pi = sb.pv[s];
+      ai = sb.aux[s];
+    }
+    const bool fluid = inr && ai.w > 0.0f;
+    PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    pair_sums_wave<BATCH>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6], lst + threadIdx.x, acc);
+    // fixed-order combination of the quad's partial sums: (l0 + l1) + (l2 + l3)
+    acc.D = quad_sum(acc.D);
+    acc.ax = quad_sum(acc.ax);
+    acc.ay = quad_sum(acc.ay);
+    acc.Vx = quad_sum(acc.Vx);
+    acc.Vy = quad_sum(acc.Vy);
+    if (q == 0) {
+      const int k = (int)(threadIdx.x >> 2);
+      sacc[0][k] = acc.D;
+      sacc[1][k] = acc.ax;
+      sacc[2][k] = acc.ay;
+      sacc[3][k] = acc.Vx;
+      sacc[4][k] = acc.Vy;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x >= PAIR_SLOTS) return;
+  const int s = s0 + (int)threadIdx.x;
   const bool inr = s < d.n_slots;
   const int inst = inr ? inst_at<BATCH>(sb, s) : 0;
   const InstParams& P = d.prm[inst];
@@ -1026,9 +1101,9 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     ai = sb.aux[s];
   }
   const bool fluid = inr && ai.w > 0.0f;
-  // eval B: slot of this particle's state n, fetched ahead of the pair sums
-  const uint32_t eb = (MODE == EV_B && fluid && q == 0) ? d.perm[s] : 0u;
-  if (MODE != EV_EXPORT && inr && !fluid && q == 0) {
+  // eval B: slot of this particle's state n
+  const uint32_t eb = (MODE == EV_B && fluid) ? d.perm[s] : 0u;
+  if (MODE != EV_EXPORT && inr && !fluid) {
     // ghosts: wall ghosts are carried, the disk ring is placed at the time of
     // the next evaluation (t + dt/2 after eval A, t + dt after eval B)
     const uint32_t id = sb.id[s];
@@ -1050,19 +1125,13 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       bucket_put_wall(d, P, bucket, K, (int)id - P.id0 - P.nf, (uint32_t)s);
     }
   }
-  PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-#ifdef PAIR_POOLED
-  if (fluid) pair_sums(d, P, sb, s, K, pi, ai, q, lst + (threadIdx.x >> 2), acc);
-#else
-  if (fluid) pair_sums(d, P, sb, s, K, pi, ai, q, lst + threadIdx.x, acc);
-#endif
-  // fixed-order combination of the quad's partial sums: (l0 + l1) + (l2 + l3)
-  acc.D = quad_sum(acc.D);
-  acc.ax = quad_sum(acc.ax);
-  acc.ay = quad_sum(acc.ay);
-  acc.Vx = quad_sum(acc.Vx);
-  acc.Vy = quad_sum(acc.Vy);
-  const bool lead = fluid && q == 0;
+  PairAcc acc;
+  acc.D = sacc[0][threadIdx.x];
+  acc.ax = sacc[1][threadIdx.x];
+  acc.ay = sacc[2][threadIdx.x];
+  acc.Vx = sacc[3][threadIdx.x];
+  acc.Vy = sacc[4][threadIdx.x];
+  const bool lead = fluid;
   if (MODE == EV_EXPORT) {
     if (lead) {
       d.xr[s] = acc.D;
@@ -1358,7 +1427,7 @@ __global__ __launch_bounds__(WC_BLOCK) void k_neigh(Dev d, Buf sb) {
 // Launch wrappers (host side of this translation unit).
 
 #define NB(n) (((n) + WC_BLOCK - 1) / WC_BLOCK)
-#define NQ(n) (((n) + PAIR_BLOCK / 4 - 1) / (PAIR_BLOCK / 4))
+#define NQ(n) (((n) + PAIR_SLOTS - 1) / PAIR_SLOTS)
 
 template <bool BATCH>
 static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, const Buf& out) {
