@@ -262,13 +262,18 @@ __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float r
   acc.Vy -= w * vyij;
 }
 
-#define PAIR_BLOCK 256                 // four waves
-#define PAIR_SLOTS (PAIR_BLOCK / 4)    // slots per block (four lanes each)
+#ifndef PAIR_G
+#define PAIR_G 4                        // lanes per slot in the pair sums
+#endif
+#define PAIR_SLOTS 64                   // slots per block
+#define PAIR_BLOCK (PAIR_SLOTS * PAIR_G)
 #define SCAN_UNROLL 4
 
-__device__ __forceinline__ float quad_sum(float v) {
-  v += __shfl_xor(v, 1);
-  return v + __shfl_xor(v, 2);
+// Fixed-order sum over the PAIR_G lanes of a slot (xor butterfly: the same
+// bits on every lane of the group).
+__device__ __forceinline__ float slot_sum(float v) {
+  for (int o = 1; o < PAIR_G; o <<= 1) v += __shfl_xor(v, o);
+  return v;
 }
 
 // The parameters of the candidate test and the pair law, held in registers
@@ -301,12 +306,6 @@ __device__ __forceinline__ PairC pair_c(const InstParams& P) {
 #ifndef PU
 #define PU 4      // candidates per lane per scan step
 #endif
-#define QSTRIDE (PAIR_BLOCK / 4)  // bytes between entries of a quad's list
-#define QCAP (4 * LCAP)            // entries of a quad's list
-
-// Exchange inside a quad of lanes (DPP quad permutations).
-__device__ __forceinline__ int quad_xor1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
-__device__ __forceinline__ int quad_xor2(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); }
 
 // Order the wave's LDS accesses: stores before this point are seen by every
 // lane's loads after it (accesses of one wave are performed in order; the
@@ -317,13 +316,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Pair sums of the fluid slots of one wave (16 consecutive slots, four lanes
-// each; every lane of the wave calls this). Fluid slots of one instance and
-// one cell row form a group; the union of their 3x3 blocks is one slot
-// range per row, which the wave stages in LDS in passes of UCAP entries:
+// Pair sums of the fluid slots of one wave (64 / PAIR_G consecutive slots,
+// PAIR_G lanes each; every lane of the wave calls this). Fluid slots of one
+// instance and one cell row form a group; the union of their 3x3 blocks is
+// one slot range per row, which the wave stages in LDS in passes of UCAP entries:
 // offset x, offset y seen from the group's row, cell column, slot. Each
 // lane then walks its own particle's candidates (rows bottom to top, cells
-// left to right in sorted order, dealt round-robin to the quad's lanes)
+// left to right in sorted order, dealt round-robin to the slot's lanes)
 // through LDS, keeps the in-support ones in a lane-private list and sums
 // the pair law over the list. A lane's candidate order and every operand
 // of a pair depend on the particle and its neighbours only, not on the
@@ -382,103 +381,33 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
       adj1 = ub1 + (ors[1] - urs[1]) - p1;
       adj2 = ub2 + (ors[2] - urs[2]) - p2;
     }
-#ifdef PAIR_QPOOL
-    const float cxi = (float)(cx - cxa);
-    uint8_t* lq = my - threadIdx.x + (threadIdx.x >> 2);  // entry p of the quad at lq[p * QSTRIDE]
-    uint32_t cb = 0u;  // the quad's next step: candidates cb + 4k + q
-    int cnt = 0;       // entries of the quad's list (the same on its four lanes)
-    auto flush = [&]() __attribute__((always_inline)) {
-      if (q < cnt) {
-        float4 E = U[lq[q * QSTRIDE]];
-        uint32_t j = __float_as_uint(E.w);
-        float4 pj = sb.pv[j], aj = sb.aux[j];
-        for (int k = q; k < cnt; k += 4) {
-          const float4 Ec = E, pc = pj, ac = aj;
-          if (k + 4 < cnt) {
-            E = U[lq[(k + 4) * QSTRIDE]];
-            j = __float_as_uint(E.w);
-            pj = sb.pv[j];
-            aj = sb.aux[j];
-          }
-          const float rx = (pi.x - Ec.x) - (Ec.z - cxi) * P.dc;
-          const float ry = pi.y - Ec.y;
-          pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pc, ac, acc);
-        }
-      }
-      cnt = 0;
-    };
-    for (uint32_t u0 = 0; u0 < n; u0 += UCAP) {
-      const uint32_t m = min(n - u0, (uint32_t)UCAP);
-      wave_sync();  // the previous pass is no longer read
-      for (uint32_t t = lane; t < m; t += 64) {
-        const uint32_t u = u0 + t;
-        const bool a0 = u < ub1, a1 = u < ub2;
-        const uint32_t j = a0 ? urs[0] + u : (a1 ? urs[1] + (u - ub1) : urs[2] + (u - ub2));
-        const int kr = a0 ? k0[0] : (a1 ? k0[1] : k0[2]);
-        const float sy = a0 ? -gdc : (a1 ? 0.0f : gdc);
-        const float4 pj = sb.pv[j];
-        const int cxj = (int)sb.cell[j] - kr;
-        U[t] = make_float4(pj.x, pj.y + sy, (float)(cxj - cxa), __uint_as_float(j));
-      }
-      wave_sync();
-      if (mem) {
-        const uint32_t lim = u0 + m;
-        while (cb < no) {
-          uint32_t ix[PU];
-          bool hit[PU];
-          int h = 0, beyond = 0;
-#pragma unroll
-          for (int k = 0; k < PU; ++k) {
-            const uint32_t cc = cb + 4u * k + (uint32_t)q;
-            const uint32_t u = cc + (cc < p1 ? adj0 : (cc < p2 ? adj1 : adj2));
-            // candidates before this pass were done in an earlier one
-            const bool v = (cc < no) & (u - u0 < m);
-            beyond |= ((cc < no) & (u >= lim)) ? 1 : 0;
-            ix[k] = v ? u - u0 : 0u;
-            const float4 E = U[ix[k]];
-            const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
-            const float ry = pi.y - E.y;
-            hit[k] = v & (rx * rx + ry * ry < P.four_h2) & (__float_as_uint(E.w) != (uint32_t)s);
-            h += hit[k] ? 1 : 0;
-          }
-          // this lane's place in the quad list: hits of the lower lanes first
-          const int h1 = quad_xor1(h), s2 = h + h1, s2o = quad_xor2(s2);
-          int at = cnt + ((q & 1) ? h1 : 0) + ((q & 2) ? s2o : 0);
-#pragma unroll
-          for (int k = 0; k < PU; ++k)
-            if (hit[k]) {
-              lq[at * QSTRIDE] = (uint8_t)ix[k];
-              ++at;
-            }
-          cnt += s2 + s2o;
-          beyond |= quad_xor1(beyond);
-          beyond |= quad_xor2(beyond);
-          if (cnt > QCAP - 4 * PU) flush();
-          if (beyond) break;
-          cb += 4u * PU;
-        }
-        flush();
-      }
-#else
     const float cxi = (float)(cx - cxa);
     uint32_t c = (uint32_t)q;  // this lane's next own candidate
     int cnt = 0;
+    // sum the pair law over the list, two entries in flight (buffers a, b)
+    auto fetch = [&](int k, float4& E, float4& pj, float4& aj) __attribute__((always_inline)) {
+      E = U[my[min(k, cnt - 1) * PAIR_BLOCK]];
+      const uint32_t j = __float_as_uint(E.w);
+      pj = sb.pv[j];
+      aj = sb.aux[j];
+    };
+    auto body = [&](const float4& E, const float4& pj, const float4& aj) __attribute__((always_inline)) {
+      const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
+      const float ry = pi.y - E.y;
+      pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc);
+    };
     auto flush = [&]() __attribute__((always_inline)) {
-      if (cnt == 0) return;
-      float4 E = U[my[0]];
-      uint32_t j = __float_as_uint(E.w);
-      float4 pj = sb.pv[j], aj = sb.aux[j];
-      for (int k = 0; k < cnt; ++k) {
-        const float4 Ec = E, pc = pj, ac = aj;
-        if (k + 1 < cnt) {
-          E = U[my[(k + 1) * PAIR_BLOCK]];
-          j = __float_as_uint(E.w);
-          pj = sb.pv[j];
-          aj = sb.aux[j];
+      if (cnt > 0) {
+        float4 Ea, pa, aa, Eb, pb, ab;
+        fetch(0, Ea, pa, aa);
+        for (int k = 0;; k += 2) {
+          fetch(k + 1, Eb, pb, ab);
+          body(Ea, pa, aa);
+          if (k + 1 >= cnt) break;
+          fetch(k + 2, Ea, pa, aa);
+          body(Eb, pb, ab);
+          if (k + 2 >= cnt) break;
         }
-        const float rx = (pi.x - Ec.x) - (Ec.z - cxi) * P.dc;
-        const float ry = pi.y - Ec.y;
-        pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pc, ac, acc);
       }
       cnt = 0;
     };
@@ -503,7 +432,7 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
           int nv = 0;
 #pragma unroll
           for (int k = 0; k < PU; ++k) {
-            const uint32_t cc = c + 4u * k;
+            const uint32_t cc = c + (uint32_t)(PAIR_G * k);
             const uint32_t u = cc + (cc < p1 ? adj0 : (cc < p2 ? adj1 : adj2));
             v[k] = (cc < no) & (u - u0 < m);  // inside this pass (unsigned: both bounds)
             ix[k] = v[k] ? u - u0 : 0u;
@@ -518,13 +447,12 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
             my[cnt * PAIR_BLOCK] = (uint8_t)ix[k];
             cnt += hit ? 1 : 0;
           }
-          c += 4u * (uint32_t)nv;
+          c += (uint32_t)(PAIR_G * nv);
           if (cnt > LCAP - PU) flush();
           if (nv < PU) break;
         }
         flush();
       }
-#endif
     }
   }
 }
@@ -1056,8 +984,8 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
   // blocks map to XCDs in contiguous slot ranges
   const int s0 = xcd_block(blockIdx.x, gridDim.x) * PAIR_SLOTS;
   {
-    const int q = threadIdx.x & 3;
-    const int s = s0 + (int)(threadIdx.x >> 2);
+    const int q = (int)(threadIdx.x % PAIR_G);
+    const int s = s0 + (int)(threadIdx.x / PAIR_G);
     const bool inr = s < d.n_slots;
     const int inst = inr ? inst_at<BATCH>(sb, s) : 0;
     uint32_t K = 0;
@@ -1070,14 +998,14 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     const bool fluid = inr && ai.w > 0.0f;
     PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     pair_sums_wave<BATCH>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6], lst + threadIdx.x, acc);
-    // fixed-order combination of the quad's partial sums: (l0 + l1) + (l2 + l3)
-    acc.D = quad_sum(acc.D);
-    acc.ax = quad_sum(acc.ax);
-    acc.ay = quad_sum(acc.ay);
-    acc.Vx = quad_sum(acc.Vx);
-    acc.Vy = quad_sum(acc.Vy);
+    // fixed-order combination of the slot's lane partial sums
+    acc.D = slot_sum(acc.D);
+    acc.ax = slot_sum(acc.ax);
+    acc.ay = slot_sum(acc.ay);
+    acc.Vx = slot_sum(acc.Vx);
+    acc.Vy = slot_sum(acc.Vy);
     if (q == 0) {
-      const int k = (int)(threadIdx.x >> 2);
+      const int k = (int)(threadIdx.x / PAIR_G);
       sacc[0][k] = acc.D;
       sacc[1][k] = acc.ax;
       sacc[2][k] = acc.ay;
