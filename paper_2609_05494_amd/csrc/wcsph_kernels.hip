@@ -306,6 +306,9 @@ __device__ __forceinline__ PairC pair_c(const InstParams& P) {
 #ifndef PU
 #define PU 4      // candidates per lane per scan step
 #endif
+#ifndef PAIR_ONEPASS
+#define PAIR_ONEPASS 1  // separate scan loop for a union that fits one pass
+#endif
 
 // Order the wave's LDS accesses: stores before this point are seen by every
 // lane's loads after it (accesses of one wave are performed in order; the
@@ -426,31 +429,49 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
       }
       wave_sync();
       if (mem) {
-        while (c < no) {
-          uint32_t ix[PU];
-          bool v[PU];
-          int nv = 0;
+        // ONE: the whole union is in this pass, so every own candidate is in it
+        auto scan = [&](auto one) __attribute__((always_inline)) {
+          constexpr bool ONE = decltype(one)::value;
+          while (c < no) {
+            uint32_t ix[PU];
+            bool v[PU];
+            int nv = 0;
 #pragma unroll
-          for (int k = 0; k < PU; ++k) {
-            const uint32_t cc = c + (uint32_t)(PAIR_G * k);
-            const uint32_t u = cc + (cc < p1 ? adj0 : (cc < p2 ? adj1 : adj2));
-            v[k] = (cc < no) & (u - u0 < m);  // inside this pass (unsigned: both bounds)
-            ix[k] = v[k] ? u - u0 : 0u;
-            nv += v[k] ? 1 : 0;
-          }
+            for (int k = 0; k < PU; ++k) {
+              const uint32_t cc = c + (uint32_t)(PAIR_G * k);
+              const uint32_t u = cc + (cc < p1 ? adj0 : (cc < p2 ? adj1 : adj2));
+              if constexpr (ONE) {
+                v[k] = cc < no;
+                ix[k] = v[k] ? u : 0u;
+              } else {
+                v[k] = (cc < no) & (u - u0 < m);  // inside this pass (unsigned: both bounds)
+                ix[k] = v[k] ? u - u0 : 0u;
+                nv += v[k] ? 1 : 0;
+              }
+            }
 #pragma unroll
-          for (int k = 0; k < PU; ++k) {
-            const float4 E = U[ix[k]];
-            const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
-            const float ry = pi.y - E.y;
-            const bool hit = v[k] & (rx * rx + ry * ry < P.four_h2) & (__float_as_uint(E.w) != (uint32_t)s);
-            my[cnt * PAIR_BLOCK] = (uint8_t)ix[k];
-            cnt += hit ? 1 : 0;
+            for (int k = 0; k < PU; ++k) {
+              const float4 E = U[ix[k]];
+              const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
+              const float ry = pi.y - E.y;
+              const bool hit = v[k] & (rx * rx + ry * ry < P.four_h2) & (__float_as_uint(E.w) != (uint32_t)s);
+              my[cnt * PAIR_BLOCK] = (uint8_t)ix[k];
+              cnt += hit ? 1 : 0;
+            }
+            if (cnt > LCAP - PU) flush();
+            if constexpr (ONE) {
+              c += (uint32_t)(PAIR_G * PU);
+            } else {
+              c += (uint32_t)(PAIR_G * nv);
+              if (nv < PU) break;
+            }
           }
-          c += (uint32_t)(PAIR_G * nv);
-          if (cnt > LCAP - PU) flush();
-          if (nv < PU) break;
-        }
+        };
+#if PAIR_ONEPASS
+        if (n <= UCAP) scan(std::true_type());
+        else
+#endif
+          scan(std::false_type());
         flush();
       }
     }
@@ -657,53 +678,72 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
 // The cell-list build of one evaluation in one launch: a stable counting
 // sort of the slots by cell key. The previous evaluation left every slot in
 // the bucket of its new cell (bucket order arbitrary, from atomics). Block b
-// owns cells [b T, (b+1) T) (T = WC_SORT_TILE):
-//   1. its cells' counts -> local offsets and the tile total; the exclusive
-//      prefix over the preceding tiles by decoupled look-back on per-tile
-//      flags (epoch-tagged, so no clearing between launches) -> start[]
-//   2. each bucket ordered by old slot (rank = number of smaller entries:
-//      the sort is stable with respect to the current order)
-//   3. gather of the state into sorted order, per-particle EOS, ghost slots,
-//      perm[new] = old
-// The first block also advances the clocks. The epoch is moved on by the
-// kernel that follows every sort (the ghost kernel, or k_init after a test
-// hook), so each sort launch sees an epoch of its own.
-#define SORT_BLOCK 256
-#define SORT_SPEC 3  // bucket entries per thread loaded with the counts
+// owns cells [b T, (b+1) T) (T = WC_SORT_TILE). Its first wave turns the
+// cells' counts into local offsets and the tile total, publishes the total
+// at once, and resolves the exclusive prefix over the preceding tiles by
+// decoupled look-back on per-tile flags (epoch-tagged, so no clearing
+// between launches) -> start[]. Meanwhile the other waves, four lanes per
+// cell, copy each bucket into LDS, fetch the state of their entries, and
+// rank each entry by old slot within its bucket (rank = number of smaller
+// entries: the sort is stable with respect to the current order). After one
+// block barrier every entry is stored at its sorted place with the
+// per-particle EOS; ghost slots and perm[new] = old are recorded. The first
+// block also advances the clocks. The epoch is moved on by the kernel that
+// follows every sort (the ghost kernel, or k_init after a test hook), so
+// each sort launch sees an epoch of its own.
+#define SORT_CELL_WAVES (WC_SORT_TILE / 16)     // four lanes per cell
+#define SORT_BLOCK (64 * (1 + SORT_CELL_WAVES))  // plus the offsets wave
+#define SORT_SPEC 3  // bucket entries per lane fetched with the counts
 #define SORT_SPIN_LIMIT (1 << 20)
 __device__ __forceinline__ unsigned long long tile_word(uint32_t epoch, uint32_t status, uint32_t v) {
   return ((unsigned long long)epoch << 34) | ((unsigned long long)status << 32) | (unsigned long long)v;
 }
 
-// One particle moved by the sort: its state at the old slot e with the
-// per-particle EOS (fluid) or ghost mass.
+// State of one particle at its old slot e, as loaded (before the EOS).
+struct Loaded {
+  uint32_t cell, id;
+  float4 pv;
+  float rho;
+  int inst;  // -1: corrupted bucket entry
+};
+// One particle moved by the sort: its state with the per-particle EOS
+// (fluid) or ghost mass.
 struct Gathered {
   uint32_t cell, id;
   float4 pv, aux;
   int inst, ghost;  // ghost: -1 for fluid, else the ghost index g of its instance
 };
+// (branch-free: an entry outside the slot range reads slot 0 and is marked)
 template <bool BATCH>
-__device__ __forceinline__ Gathered sort_gather(const Dev& d, const Buf& pre, uint32_t e) {
+__device__ __forceinline__ Loaded sort_load(const Dev& d, const Buf& pre, uint32_t e) {
+  Loaded v;
+  const bool ok = e < (uint32_t)d.n_slots;  // else a corrupted bucket: flagged when stored
+  const uint32_t x = ok ? e : 0u;
+  v.inst = inst_at<BATCH>(pre, (int)x);
+  v.cell = pre.cell[x];
+  v.id = pre.id[x];
+  v.pv = pre.pv[x];
+  v.rho = pre.aux[x].x;
+  if (!ok) v.inst = -1;
+  return v;
+}
+__device__ __forceinline__ Gathered sort_finish(const Dev& d, const Loaded& l) {
   Gathered v;
-  if (e >= (uint32_t)d.n_slots) {  // corrupted bucket: flagged, nothing moved
-    v.inst = -1;
-    return v;
-  }
-  v.inst = inst_at<BATCH>(pre, e);
-  const InstParams& P = d.prm[v.inst];
-  v.cell = pre.cell[e];
-  v.id = pre.id[e];
-  v.pv = pre.pv[e];
-  const float rho = pre.aux[e].x;
-  const int local = (int)v.id - P.id0;
+  v.inst = l.inst;
+  if (l.inst < 0) return v;
+  const InstParams& P = d.prm[l.inst];
+  v.cell = l.cell;
+  v.id = l.id;
+  v.pv = l.pv;
+  const int local = (int)l.id - P.id0;
   if (local < P.nf) {
     float Pq, c;
-    fluid_eos(P, rho, Pq, c);
-    v.aux = make_float4(rho, Pq, c, P.m_fluid);
+    fluid_eos(P, l.rho, Pq, c);
+    v.aux = make_float4(l.rho, Pq, c, P.m_fluid);
     v.ghost = -1;
   } else {
     v.ghost = local - P.nf;
-    v.aux = make_float4(rho, 0.0f, 0.0f, v.ghost < P.nw ? -P.m_wall : -P.m_disk);
+    v.aux = make_float4(l.rho, 0.0f, 0.0f, v.ghost < P.nw ? -P.m_wall : -P.m_disk);
   }
   return v;
 }
@@ -732,84 +772,32 @@ template <int MODE, bool BATCH>
 __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
   constexpr int T = WC_SORT_TILE;
   __shared__ uint32_t s_off[T + 1];  // exclusive offsets of the tile's cells, total at [T]
-  __shared__ uint32_t s_cnt[T];
   __shared__ uint32_t s_base;        // sorted slots before this tile
   __shared__ uint32_t s_raw[T * WC_BUCKET];
-  __shared__ uint32_t s_srt[T * WC_BUCKET];
   const int t = threadIdx.x, tile = blockIdx.x;
   const uint32_t* bucket = MODE == EV_B ? d.bucket_b : d.bucket_a;
-  const uint32_t epoch = *d.sort_epoch;
-  if (tile == 0)
-    for (int i = t; i < d.n_inst; i += SORT_BLOCK) clock_commit<MODE>(d, i);
-
-  // Four threads per cell load the cell's count and, before it is known,
-  // the first SORT_SPEC entries of its bucket (stale entries past the count
-  // are ignored).
-  const int sc = t >> 2, ssub = t & 3;
-  const int sK = tile * T + sc;
-  uint32_t scnt = 0, sre[SORT_SPEC];
-  if (sK < d.n_cells) {
-    scnt = min(d.count[sK], (uint32_t)WC_BUCKET);  // overflow was flagged by the producer
-#pragma unroll
-    for (int u = 0; u < SORT_SPEC; ++u) sre[u] = bucket[(size_t)sK * WC_BUCKET + ssub + 4 * u];
-  }
-  if (ssub == 0) s_cnt[sc] = scnt;
-  __syncthreads();
-  // wave 0: the tile's local offsets; its aggregate is published at once so
-  // that later tiles can look past it
-  uint32_t w0_incl = 0, w0_c = 0, w0_total = 0;
+  // cell lanes: lane sub of cell c owns the entries sub + 4 u of its bucket
+  const int ct = t - 64, c = ct >> 2, sub = ct & 3;
+  uint32_t n = 0u, e[SORT_SPEC], r[SORT_SPEC];
+  Loaded lv[SORT_SPEC];
+  Gathered gv[SORT_SPEC];
   if (t < 64) {
+    // the tile's local offsets; the aggregate is published at once so that
+    // later tiles can look past it
+    const uint32_t epoch = *d.sort_epoch;
     const int K = tile * T + t;
-    const uint32_t c = s_cnt[t];
-    if (K < d.n_cells) d.count[K] = d.wallcount[K];  // re-arm for the next sort
-    uint32_t incl = c;
+    const uint32_t cnt = K < d.n_cells ? min(d.count[K], (uint32_t)WC_BUCKET) : 0u;  // overflow was flagged
+    uint32_t incl = cnt;
     for (int o = 1; o < 64; o <<= 1) {
       const uint32_t u = __shfl_up(incl, o);
       if (t >= o) incl += u;
     }
     const uint32_t total = __shfl(incl, 63);
-    s_off[t] = incl - c;
+    s_off[t] = incl - cnt;
     if (t == 63) s_off[T] = total;
     if (t == 0)
       __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, tile == 0 ? 2u : 1u, total), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
-    w0_incl = incl;
-    w0_c = c;
-    w0_total = total;
-  }
-  __syncthreads();
-
-  // bucket contents into LDS, then each bucket ordered by old slot
-  const uint32_t total = s_off[T];
-  {
-    const int c = sc, sub = ssub;
-    const int K = sK;
-    const uint32_t n = scnt, o = s_off[c];
-#pragma unroll
-    for (int u = 0; u < SORT_SPEC; ++u)
-      if ((uint32_t)(sub + 4 * u) < n) s_raw[o + sub + 4 * u] = sre[u];
-    for (uint32_t i = sub + 4 * SORT_SPEC; i < n; i += 4) s_raw[o + i] = bucket[(size_t)K * WC_BUCKET + i];
-    __syncthreads();
-    for (uint32_t i = sub; i < n; i += 4) {
-      const uint32_t e = s_raw[o + i];
-      uint32_t r = 0;
-      for (uint32_t k = 0; k < n; ++k) r += s_raw[o + k] < e ? 1u : 0u;
-      s_srt[o + r] = e;
-    }
-  }
-  __syncthreads();
-
-  // The first SORT_ROUNDS entries of each thread are loaded (and their EOS
-  // evaluated) before the tile's place in the sorted order is known; wave 0
-  // resolves that place meanwhile.
-  constexpr int R = 2;
-  Gathered gv[R];
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const uint32_t p = t + k * SORT_BLOCK;
-    if (p < total) gv[k] = sort_gather<BATCH>(d, pre, s_srt[p]);
-  }
-  if (t < 64) {
     uint32_t excl = 0;
     if (tile > 0) {
       // Look back over windows of 4 x 64 tiles: lane l inspects tiles
@@ -851,28 +839,69 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
         k -= 256;
       }
       if (t == 0)
-        __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, 2u, excl + w0_total), __ATOMIC_RELAXED,
+        __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, 2u, excl + total), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     if (t == 0) s_base = excl;
-    const int K = tile * T + t;
-    if (K < d.n_cells) d.start[K] = excl + (w0_incl - w0_c);
-    if (K == d.n_cells - 1) d.start[d.n_cells] = excl + w0_incl;
-  }
-  __syncthreads();
-
-  // stores into sorted order
-  const uint32_t base = s_base;
+    if (K < d.n_cells) d.start[K] = excl + (incl - cnt);
+    if (K == d.n_cells - 1) d.start[d.n_cells] = excl + incl;
+  } else {
+    if (tile == 0)
+      for (int i = ct; i < d.n_inst; i += SORT_BLOCK - 64) clock_commit<MODE>(d, i);
+    const int K = tile * T + c;
+    if (K < d.n_cells) {
+      n = min(d.count[K], (uint32_t)WC_BUCKET);
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const uint32_t p = t + k * SORT_BLOCK;
-    if (p < total) sort_store<BATCH>(d, out, s_srt[p], base + p, gv[k]);
+      for (int u = 0; u < SORT_SPEC; ++u) e[u] = bucket[(size_t)K * WC_BUCKET + sub + 4 * u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < SORT_SPEC; ++u) e[u] = 0u;
+    }
+    uint32_t* raw = s_raw + c * WC_BUCKET;
+#pragma unroll
+    for (int u = 0; u < SORT_SPEC; ++u)
+      if ((uint32_t)(sub + 4 * u) < n) raw[sub + 4 * u] = e[u];
+    // the state of the lane's entries is in flight during the ranking and
+    // the look-back (issued without branches; entries past the count load
+    // slot 0 and are not used)
+#pragma unroll
+    for (int u = 0; u < SORT_SPEC; ++u) lv[u] = sort_load<BATCH>(d, pre, (uint32_t)(sub + 4 * u) < n ? e[u] : 0u);
+    for (uint32_t i = sub + 4 * SORT_SPEC; i < n; i += 4) raw[i] = bucket[(size_t)K * WC_BUCKET + i];
+    wave_sync();  // the buckets of this wave's cells are in LDS
+    // rank of each entry in its bucket; the first 16 places without branches
+#pragma unroll
+    for (int u = 0; u < SORT_SPEC; ++u) r[u] = 0u;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t x = raw[k];
+#pragma unroll
+      for (int u = 0; u < SORT_SPEC; ++u) r[u] += ((uint32_t)k < n) & (x < e[u]) ? 1u : 0u;
+    }
+    for (uint32_t k = 16; k < n; ++k) {
+      const uint32_t x = raw[k];
+#pragma unroll
+      for (int u = 0; u < SORT_SPEC; ++u) r[u] += x < e[u] ? 1u : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < SORT_SPEC; ++u) gv[u] = sort_finish(d, lv[u]);  // EOS while the look-back runs
   }
-  for (uint32_t p = t + R * SORT_BLOCK; p < total; p += SORT_BLOCK) {
-    const uint32_t e = s_srt[p];
-    sort_store<BATCH>(d, out, e, base + p, sort_gather<BATCH>(d, pre, e));
+  __syncthreads();  // offsets and the tile's base
+  if (t < 64) {
+    const int K = tile * T + t;
+    if (K < d.n_cells) d.count[K] = d.wallcount[K];  // re-arm for the next sort (every count was read)
+    return;
   }
-
+  const uint32_t base = s_base + s_off[c];
+#pragma unroll
+  for (int u = 0; u < SORT_SPEC; ++u)
+    if ((uint32_t)(sub + 4 * u) < n) sort_store<BATCH>(d, out, e[u], base + r[u], gv[u]);
+  const uint32_t* raw = s_raw + c * WC_BUCKET;
+  for (uint32_t i = sub + 4 * SORT_SPEC; i < n; i += 4) {
+    const uint32_t ei = raw[i];
+    uint32_t ri = 0u;
+    for (uint32_t k = 0; k < n; ++k) ri += raw[k] < ei ? 1u : 0u;
+    sort_store<BATCH>(d, out, ei, base + ri, sort_finish(d, sort_load<BATCH>(d, pre, ei)));
+  }
 }
 
 // Adami ghost state (walls and ring), probes, ghost v_max and ring work.
@@ -980,7 +1009,12 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
 #endif
   __shared__ float4 uni[PAIR_BLOCK / 64][UCAP];
   __shared__ uint8_t lst[LCAP * PAIR_BLOCK];
+  // hand-over of each slot from the first phase to the second
   __shared__ float sacc[5][PAIR_SLOTS];
+  __shared__ float4 h_pv[PAIR_SLOTS];
+  __shared__ uint32_t h_K[PAIR_SLOTS], h_id[PAIR_SLOTS], h_eb[PAIR_SLOTS];
+  __shared__ float h_rho[PAIR_SLOTS], h_m[PAIR_SLOTS];
+  __shared__ int h_inst[PAIR_SLOTS];
   // blocks map to XCDs in contiguous slot ranges
   const int s0 = xcd_block(blockIdx.x, gridDim.x) * PAIR_SLOTS;
   {
@@ -996,6 +1030,13 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       ai = sb.aux[s];
     }
     const bool fluid = inr && ai.w > 0.0f;
+    // fetched now, used after the pair sums: the particle id and (eval B)
+    // the slot of its state n in the step's first sorted state
+    uint32_t id = 0u, eb = 0u;
+    if (q == 0 && inr) {
+      id = sb.id[s];
+      if (MODE == EV_B && fluid) eb = d.perm[s];
+    }
     PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     pair_sums_wave<BATCH>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6], lst + threadIdx.x, acc);
     // fixed-order combination of the slot's lane partial sums
@@ -1011,33 +1052,36 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       sacc[2][k] = acc.ay;
       sacc[3][k] = acc.Vx;
       sacc[4][k] = acc.Vy;
+      h_pv[k] = pi;
+      h_K[k] = K;
+      h_rho[k] = ai.x;
+      h_m[k] = inr ? ai.w : 0.0f;
+      h_inst[k] = inst;
+      h_id[k] = id;
+      h_eb[k] = eb;
     }
   }
   __syncthreads();
   if (threadIdx.x >= PAIR_SLOTS) return;
   const int s = s0 + (int)threadIdx.x;
   const bool inr = s < d.n_slots;
-  const int inst = inr ? inst_at<BATCH>(sb, s) : 0;
+  const int inst = h_inst[threadIdx.x];
   const InstParams& P = d.prm[inst];
   Clock* clk = d.clk;
   const Clock& C = clk[inst];
-  uint32_t K = 0;
-  float4 pi = make_float4(0, 0, 0, 0), ai = make_float4(0, 0, 0, 0);
-  if (inr) {
-    K = sb.cell[s];
-    pi = sb.pv[s];
-    ai = sb.aux[s];
-  }
-  const bool fluid = inr && ai.w > 0.0f;
-  // eval B: slot of this particle's state n
-  const uint32_t eb = (MODE == EV_B && fluid) ? d.perm[s] : 0u;
+  const uint32_t K = h_K[threadIdx.x];
+  const float4 pi = h_pv[threadIdx.x];
+  const float rho_i = h_rho[threadIdx.x];
+  const uint32_t id_i = h_id[threadIdx.x];
+  const bool fluid = inr && h_m[threadIdx.x] > 0.0f;
+  const uint32_t eb = h_eb[threadIdx.x];
   if (MODE != EV_EXPORT && inr && !fluid) {
     // ghosts: wall ghosts are carried, the disk ring is placed at the time of
     // the next evaluation (t + dt/2 after eval A, t + dt after eval B)
-    const uint32_t id = sb.id[s];
+    const uint32_t id = id_i;
     const int ring = (int)id - P.id0 - P.nf - P.nw;
     out.id[s] = id;
-    out.aux[s] = make_float4(ai.x, 0.0f, 0.0f, 0.0f);
+    out.aux[s] = make_float4(rho_i, 0.0f, 0.0f, 0.0f);
     if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
     uint32_t* bucket = MODE == EV_A ? d.bucket_b : d.bucket_a;
     if (ring >= 0) {
@@ -1082,7 +1126,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     if (MODE == EV_A) {
       Kb = K;
       pb = pi;
-      rb = ai.x;
+      rb = rho_i;
     } else {
       // state n of this particle: the sort of this evaluation took it from
       // slot perm[s] of the step's first sorted state
@@ -1105,7 +1149,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     double x = P.x_lo + (double)cx * P.dcd + (double)ox;
     double y = P.y_lo + (double)cy * P.dcd + (double)oy;
     if (d.tape_pos != nullptr) {  // pre-enforcement state for the reverse sweep
-      const int fid = (int)sb.id[s] - P.id0;
+      const int fid = (int)id_i - P.id0;
       d.tape_pos[fid] = make_double2(x, y);
       d.tape_vel[fid] = make_float4(vx, vy, rb + hdt * acc.D, 0.0f);
     }
@@ -1152,7 +1196,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     out.cell[s] = Kn;
     out.pv[s] = make_float4(ox, oy, vx, vy);
     out.aux[s] = make_float4(rn, 0.0f, 0.0f, 0.0f);
-    out.id[s] = sb.id[s];
+    out.id[s] = id_i;
     if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
     newkey = Kn;
     vnew = fast_sqrt(vx * vx + vy * vy);
