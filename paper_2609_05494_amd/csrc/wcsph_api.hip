@@ -504,6 +504,8 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.diag = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_CAP * WC_NDIAG);
   d.diag_part = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_BLOCKS * 8);
   d.wb_part = dalloc_n<double>(c, (size_t)n_inst * WC_MAX_RING);
+  d.n_vpart = wc_pair_blocks(c->n_slots);
+  d.vmax_part = dalloc_n<float>(c, (size_t)d.n_vpart);
   d.xr = dalloc_n<float>(c, (size_t)5 * c->n_slots);
   d.nb_count = dalloc_n<int>(c, c->n_slots);
   d.nb_idsum = dalloc_n<long long>(c, c->n_slots);
@@ -516,6 +518,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   HC(hipMemcpyAsync(gblk, c->h_gblk.data(), (size_t)c->n_gblk * sizeof(int4), hipMemcpyHostToDevice, c->st));
   HC(hipMemsetAsync(d.hist_p, 0, (size_t)n_inst * WC_HIST_CAP * WC_MAX_PROBES * 4, c->st));
   HC(hipMemsetAsync(d.wb_part, 0, (size_t)n_inst * WC_MAX_RING * 8, c->st));
+  HC(hipMemsetAsync(d.vmax_part, 0, (size_t)d.n_vpart * 4, c->st));
   // look-back flags carry epoch 0, the first sort runs with epoch 1
   HC(hipMemsetAsync(d.tile_flag, 0, n_tiles * 8, c->st));
   const uint32_t epoch0[4] = {1u, 0u, 0u, 0u};

@@ -107,6 +107,9 @@ struct Dev {
   double* diag;               // [n_inst][WC_DIAG_CAP][WC_NDIAG]
   double* diag_part;          // [n_inst][WC_DIAG_BLOCKS][8] partial sums
   double* wb_part;            // [n_inst][WC_MAX_RING] x force of each ring ghost on the fluid
+  float* vmax_part;           // single instance: per corrector pair block, max |v| of its new fluid
+                              // state (folded into the clock by the next first-evaluation sort)
+  int n_vpart;                // entries of vmax_part (pair blocks)
   float* xr;                  // export: [5][n_slots] rates per slot
   int* nb_count;              // export: neighbour count per slot
   long long* nb_idsum;        // export: neighbour id sum per slot

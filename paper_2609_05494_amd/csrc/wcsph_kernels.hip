@@ -695,6 +695,7 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
 #define SORT_BLOCK (64 * (1 + SORT_CELL_WAVES))  // plus the offsets wave
 #define SORT_SPEC 3  // bucket entries per lane fetched with the counts
 #define SORT_SPIN_LIMIT (1 << 20)
+#define SORT_FOLD 8  // per-block v_max entries per lane folded by a tile
 __device__ __forceinline__ unsigned long long tile_word(uint32_t epoch, uint32_t status, uint32_t v) {
   return ((unsigned long long)epoch << 34) | ((unsigned long long)status << 32) | (unsigned long long)v;
 }
@@ -848,6 +849,19 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
   } else {
     if (tile == 0)
       for (int i = ct; i < d.n_inst; i += SORT_BLOCK - 64) clock_commit<MODE>(d, i);
+    // single instance: the first cell wave of tile k folds entries
+    // [64 F k, 64 F (k + 1)) of the previous corrector's per-block fluid
+    // maxima (F = SORT_FOLD per lane, loads in flight during the sort) into
+    // the clock with one atomic at the end
+    const bool fold = MODE == EV_A && !BATCH && ct < 64 && tile * 64 * SORT_FOLD < d.n_vpart;
+    float vp = 0.0f;
+    if (fold) {
+#pragma unroll
+      for (int k = 0; k < SORT_FOLD; ++k) {
+        const int i = (tile * SORT_FOLD + k) * 64 + ct;
+        vp = fmaxf(vp, i < d.n_vpart ? d.vmax_part[i] : 0.0f);
+      }
+    }
     const int K = tile * T + c;
     if (K < d.n_cells) {
       n = min(d.count[K], (uint32_t)WC_BUCKET);
@@ -884,6 +898,10 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     }
 #pragma unroll
     for (int u = 0; u < SORT_SPEC; ++u) gv[u] = sort_finish(d, lv[u]);  // EOS while the look-back runs
+    if (fold) {
+      const float w = wave_max(vp);
+      if (ct == 0 && w > 0.0f) atomicMax(&d.clk[0].vmax_bits, __float_as_uint(w));
+    }
   }
   __syncthreads();  // offsets and the tile's base
   if (t < 64) {
@@ -1205,7 +1223,14 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
   bucket_put_wave(d, MODE == EV_A ? d.bucket_b : d.bucket_a, lead, newkey, (uint32_t)s);
   count_hits<BATCH>(clk, inst, clamp_hit, enf_hit);
   if (MODE == EV_B) {
-    vmax_update<BATCH>(clk, inst, lead, vnew);
+    if constexpr (BATCH) {
+      vmax_update<BATCH>(clk, inst, lead, vnew);
+    } else {
+      // this block's max |v|, folded into the clock by the next first sort
+      // (no atomics on one address from every wave)
+      const float w = wave_max(lead ? vnew : 0.0f);
+      if (threadIdx.x == 0) d.vmax_part[blockIdx.x] = w;
+    }
     // work of the ring on the fluid over the step (fixed-order sum of the
     // per-ghost forces at t + dt/2) and the time of the new state; the first
     // wave of block i serves instance i
@@ -1252,6 +1277,7 @@ __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
     }
   }
   vmax_update<BATCH>(d.clk, inst, fl, v);
+  if (!BATCH && s < d.n_vpart) d.vmax_part[s] = 0.0f;  // the loaded state's max is in the clock
 }
 
 // r^(gamma - 1) in FP64: repeated products for an integer gamma (the Tait
@@ -1400,6 +1426,7 @@ __global__ __launch_bounds__(WC_BLOCK) void k_neigh(Dev d, Buf sb) {
 
 #define NB(n) (((n) + WC_BLOCK - 1) / WC_BLOCK)
 #define NQ(n) (((n) + PAIR_SLOTS - 1) / PAIR_SLOTS)
+int wc_pair_blocks(int n_slots) { return NQ(n_slots); }
 
 template <bool BATCH>
 static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, const Buf& out) {

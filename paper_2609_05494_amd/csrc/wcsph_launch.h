@@ -24,6 +24,8 @@ void wc_enqueue_neigh(const Dev& d, const Bufs& b, hipStream_t st);
 // B: sort of Z into W with state n into X, ghosts, pair sums + corrector)
 // with plain launches; single instance.
 void wc_enqueue_eval(const Dev& d, const Bufs& b, int n_gblk, int mode, hipStream_t st);
+// blocks of one pair-kernel launch over n_slots slots
+int wc_pair_blocks(int n_slots);
 // number of per-block theta partials one adjoint rate evaluation writes
 int wc_adj_partial_blocks(int n_ghost_probe, int n_slots);
 void wc_enqueue_adj_rates(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_eval, float probe_seed,
