@@ -68,13 +68,23 @@ __device__ void kinematics(const InstParams& P, double t, double& x, double& v, 
 }
 
 // Tait pressure with the cavitation cutoff, P = p / rho^2 and the sound speed
-// c0 (rho/rho0)^((gamma-1)/2); written through log1p/expm1 so that p stays
-// accurate near rho0 in FP32.
+// c0 (rho/rho0)^((gamma-1)/2), with x = rho/rho0 - 1 so that p stays accurate
+// near rho0 in FP32. For gamma = 7, (1 + x)^7 - 1 is x times its binomial
+// polynomial and the sound speed exponent is 3; otherwise log1p/expm1.
 __device__ __forceinline__ void fluid_eos(const InstParams& P, float rho, float& Pq, float& c) {
-  const float l = log1pf((rho - P.rho0) / P.rho0);
-  const float p = fmaxf(P.B * expm1f(P.gamma * l), P.p_cav);
+  const float x = (rho - P.rho0) / P.rho0;
+  float p;
+  if (P.gamma == 7.0f) {
+    const float y = 1.0f + x;
+    p = P.B * (x * (7.0f + x * (21.0f + x * (35.0f + x * (35.0f + x * (21.0f + x * (7.0f + x)))))));
+    c = P.c0 * (y * y * y);
+  } else {
+    const float l = log1pf(x);
+    p = P.B * expm1f(P.gamma * l);
+    c = P.c0 * expf(P.c_exp * l);
+  }
+  p = fmaxf(p, P.p_cav);
   Pq = p / (rho * rho);
-  c = P.c0 * expf(P.c_exp * l);
 }
 
 // Wendland C2 (2D): W = sigma (1-q/2)^4 (2q+1); grad_i W = F r_ij,
@@ -696,6 +706,9 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
 #define SORT_SPEC 3  // bucket entries per lane fetched with the counts
 #define SORT_SPIN_LIMIT (1 << 20)
 #define SORT_FOLD 8  // per-block v_max entries per lane folded by a tile
+#ifndef SORT_LB
+#define SORT_LB 4    // look-back window: SORT_LB x 64 tiles
+#endif
 __device__ __forceinline__ unsigned long long tile_word(uint32_t epoch, uint32_t status, uint32_t v) {
   return ((unsigned long long)epoch << 34) | ((unsigned long long)status << 32) | (unsigned long long)v;
 }
@@ -801,21 +814,21 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
                          __HIP_MEMORY_SCOPE_AGENT);
     uint32_t excl = 0;
     if (tile > 0) {
-      // Look back over windows of 4 x 64 tiles: lane l inspects tiles
-      // k - l - 64 j (j = 0..3), nearest first. Stop at the nearest tile
+      // Look back over windows of SORT_LB x 64 tiles: lane l inspects tiles
+      // k - l - 64 j (j < SORT_LB), nearest first. Stop at the nearest tile
       // holding its inclusive prefix, adding the aggregates of the tiles in
       // between.
       int k = tile - 1;
       for (;;) {
-        unsigned long long f[4];
+        unsigned long long f[SORT_LB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < SORT_LB; ++j) {
           const int kk = k - t - 64 * j;
           f[j] = kk >= 0 ? __hip_atomic_load(&d.tile_flag[kk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                          : tile_word(epoch, 2u, 0u);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < SORT_LB; ++j) {
           const int kk = k - t - 64 * j;
           int spin = 0;
           while ((uint32_t)(f[j] >> 34) != epoch && ++spin < SORT_SPIN_LIMIT)
@@ -827,7 +840,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
         }
         bool found = false;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < SORT_LB; ++j) {
           if (found) break;
           const unsigned long long has_prefix = __ballot(((uint32_t)(f[j] >> 32) & 3u) == 2u);
           const int stop = has_prefix ? __ffsll((long long)has_prefix) - 1 : 63;
@@ -837,7 +850,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
           found = has_prefix != 0;
         }
         if (found) break;
-        k -= 256;
+        k -= 64 * SORT_LB;
       }
       if (t == 0)
         __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, 2u, excl + total), __ATOMIC_RELAXED,
@@ -936,6 +949,10 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
   Clock& C = d.clk[inst];
   const int t = threadIdx.x, item = t / GL, lane = t % GL;
   const bool act = item < blk.z;
+  // first evaluation: the stored v_max (the fluid part is already in) read
+  // now, so that its latency is hidden; a wave whose ghost maximum is not
+  // above it skips the atomic
+  const uint32_t vcheck = MODE == EV_A && kind != 2 ? __atomic_load_n(&C.vmax_bits, __ATOMIC_RELAXED) : 0u;
   if (kind == 2) {
     // probes: Shepard average of the fluid pressure at fixed wall points
     if (MODE == EV_A && act) {
@@ -975,7 +992,8 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
     if (P.ghost_rho_mode == 0) rg = P.rho0 * (1.0f + p * P.inv_rho0c02);
     else rg = P.rho0 * expf(P.inv_gamma * log1pf(p / P.B));
     const float Pg = p / (rg * rg);
-    const float cg = P.c0 * expf(P.c_exp * log1pf((rg - P.rho0) / P.rho0));
+    const float xg = (rg - P.rho0) / P.rho0, yg = 1.0f + xg;
+    const float cg = P.gamma == 7.0f ? P.c0 * (yg * yg * yg) : P.c0 * expf(P.c_exp * log1pf(xg));
     const float m = disk ? P.m_disk : P.m_wall;
     if (lane == 0) {
       sb.pv[s] = make_float4(pg.x, pg.y, vgx, vgy);
@@ -1008,7 +1026,7 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
   if (MODE == EV_A) {
     // the items of a block belong to one instance
     const float w = wave_max(vmag);
-    if ((t & 63) == 0) vmax_atomic(&C.vmax_bits, w);
+    if ((t & 63) == 0 && w > 0.0f && __float_as_uint(w) > vcheck) atomicMax(&C.vmax_bits, __float_as_uint(w));
   }
 }
 #undef GL
