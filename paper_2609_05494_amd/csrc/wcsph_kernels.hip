@@ -902,7 +902,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     for (int k = 0; k < 16; ++k) {
       const uint32_t x = raw[k];
 #pragma unroll
-      for (int u = 0; u < SORT_SPEC; ++u) r[u] += ((uint32_t)k < n) & (x < e[u]) ? 1u : 0u;
+      for (int u = 0; u < SORT_SPEC; ++u) r[u] += (((uint32_t)k < n) & (x < e[u])) ? 1u : 0u;
     }
     for (uint32_t k = 16; k < n; ++k) {
       const uint32_t x = raw[k];
