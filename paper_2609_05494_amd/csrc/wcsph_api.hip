@@ -251,6 +251,15 @@ InstParams derive(const wcsph_params& p) {
   q.gammad = p.gamma;
   q.p_cavd = p.p_cav;
   q.m_fluidd = p.rho0 * p.dx * p.dx;
+  {
+    const double g = p.gamma, r0 = p.rho0;
+    q.diag_rc = r0 * std::pow(1.0 + p.p_cav / B, 1.0 / g);
+    q.diag_k1 = B / ((g - 1.0) * std::pow(r0, g));
+    q.diag_r0g1 = std::pow(r0, g - 1.0);
+    q.diag_erc = B * ((std::pow(q.diag_rc, g - 1.0) - q.diag_r0g1) / ((g - 1.0) * std::pow(r0, g)) + 1.0 / q.diag_rc -
+                      1.0 / r0);
+    q.diag_inv_r0g = 1.0 / std::pow(r0, g);
+  }
   q.kin_mode = p.kin_mode;
   q.kin_v0 = p.kin_v0;
   q.kin_t_ramp = p.kin_t_ramp;

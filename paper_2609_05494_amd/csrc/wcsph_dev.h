@@ -43,6 +43,10 @@ struct InstParams {
   // FP64 geometry, kinematics and step control
   double L, W, eps_wall, R, disk_x0, disk_y0, disk_mass, cfl, hd, c0d, Bd, rho0d, gammad, p_cavd;
   double m_fluidd;  // rho0 dx^2 for the FP64 diagnostics
+  // FP64 constants of the Tait elastic energy (diagnostics): cutoff density,
+  // B / ((gamma - 1) rho0^gamma), rho0^(gamma - 1), energy at the cutoff,
+  // rho0^-gamma
+  double diag_rc, diag_k1, diag_r0g1, diag_erc, diag_inv_r0g;
   int kin_mode;
   double kin_v0, kin_t_ramp, kin_coef;
   // probes: encoded positions

@@ -1329,10 +1329,7 @@ __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
   const int chunk = (hi - lo + WC_DIAG_BLOCKS - 1) / WC_DIAG_BLOCKS;
   const int a = lo + b * chunk, e = min(hi, a + chunk);
   const double g = P.gammad, r0 = P.rho0d, B = P.Bd, m = P.m_fluidd;
-  const double rc = r0 * pow(1.0 + P.p_cavd / B, 1.0 / g);
-  const double k1 = B / ((g - 1.0) * pow(r0, g)), r0g1 = pow(r0, g - 1.0);
-  const double erc = B * ((pow(rc, g - 1.0) - r0g1) / ((g - 1.0) * pow(r0, g)) + 1.0 / rc - 1.0 / r0);
-  const double inv_r0g = 1.0 / pow(r0, g);
+  const double rc = P.diag_rc, k1 = P.diag_k1, r0g1 = P.diag_r0g1, erc = P.diag_erc, inv_r0g = P.diag_inv_r0g;
   double M = 0, px = 0, py = 0, ke = 0, eel = 0, epot = 0, ncav = 0, bad = 0;
   for (int s = a + (int)threadIdx.x; s < e; s += 256) {
     const int local = (int)X.id[s] - P.id0;
@@ -1372,12 +1369,19 @@ __global__ __launch_bounds__(64) void k_diag_final(Dev d) {
   const int i = blockIdx.x;
   // fixed-order sum of the block partials: lane l adds blocks l, l + 64, ...
   // in order, then a butterfly over the wave
+  static_assert(WC_DIAG_BLOCKS % 64 == 0, "whole waves of block partials");
+  constexpr int NB = WC_DIAG_BLOCKS / 64;
+  double part[NB][8];  // every load in flight before the sums
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) part[j][k] = d.diag_part[((long long)i * WC_DIAG_BLOCKS + threadIdx.x + 64 * j) * 8 + k];
   double tot[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     double v = 0.0;
-    for (int b = (int)threadIdx.x; b < WC_DIAG_BLOCKS; b += 64)
-      v += d.diag_part[((long long)i * WC_DIAG_BLOCKS + b) * 8 + k];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) v += part[j][k];
     tot[k] = wave_sum(v);
   }
   if (threadIdx.x != 0) return;
