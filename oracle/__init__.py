@@ -96,6 +96,7 @@ def lib():
             "orc_get_ghosts": (None, [C.c_void_p, _D, _D, _D]),
             "orc_get_order": (None, [C.c_void_p, _I, _I]),
             "orc_kinematics": (None, [C.c_void_p, C.c_double, _D, _D, _D]),
+            "orc_disk_state": (None, [C.c_void_p, _D, _D, _D]),
             "orc_kernel": (None, [C.c_double, C.c_double, _D, _D]),
             "orc_eos": (None, [P, C.c_double, _D, _D]),
             "orc_elastic_energy": (C.c_double, [P, C.c_double]),
@@ -210,6 +211,13 @@ class Oracle:
     def kinematics(self, t):
         x, v, a = C.c_double(), C.c_double(), C.c_double()
         lib().orc_kinematics(self.h, t, C.byref(x), C.byref(v), C.byref(a))
+        return x.value, v.value, a.value
+
+    def disk_state(self):
+        """Disk centre x, velocity and acceleration at the current time
+        (kin_mode 2: the coupled state once it has started)."""
+        x, v, a = C.c_double(), C.c_double(), C.c_double()
+        lib().orc_disk_state(self.h, C.byref(x), C.byref(v), C.byref(a))
         return x.value, v.value, a.value
 
 

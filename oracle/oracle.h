@@ -61,6 +61,9 @@ void orc_eval_rates(void* s, double* drho, double* ax, double* ay, double* Vx, d
 void orc_get_ghosts(void* s, double* gx, double* gy, double* gm);
 void orc_get_order(void* s, int* order, int* cell_start);
 void orc_kinematics(void* s, double t, double* x, double* v, double* a);
+// disk centre x, velocity, acceleration at the current time (kin_mode 2:
+// the coupled state once the first step after the ramp has started)
+void orc_disk_state(void* s, double* x, double* v, double* a);
 
 /* ---- building blocks (exposed for the pin tests) ------------------------ */
 void orc_kernel(double q, double h, double* W, double* F);

@@ -30,6 +30,9 @@
 //    reflection of the inward relative velocity for the disk.
 //  * prescribed kinematics: ramp (eq. velocity-ramp) then constant
 //    deceleration k v0^2, or the quadratic drag of eq. drag.
+//  * two-way coupling (the extension named in the Conclusions and the
+//    energy-audit discussion, kin_mode 2): after the ramp the disk moves
+//    with the reaction of the ring's x force on the fluid.
 //  * cell-linked list of cell size >= 2h, rebuilt at every evaluation by a
 //    stable sort of the particles by cell key.
 // Ghost state and rates are re-evaluated at both evaluations of a step
@@ -208,6 +211,12 @@ void kinematics(int mode, double v0, double t_ramp, double coef, double x0, doub
   }
   double tau = t - t_ramp;
   double xr = x0 + 0.5 * v0 * t_ramp;
+  if (mode == 2) {  // two-way coupling: this prescribed law only until the first coupled step
+    *vo = v0;
+    *ao = 0;
+    *xo = xr + v0 * tau;
+    return;
+  }
   if (mode == 1) {  // quadratic drag dv/dt = -k v^2
     double k = coef;
     double v = v0 / (1.0 + k * v0 * tau);
@@ -253,6 +262,10 @@ struct Sim {
   long n_clamp = 0, n_enforce = 0;
   // disk state at the current evaluation
   double dx_c = 0, dv = 0, da = 0;
+  // two-way coupling (kin_mode 2): from the first step that starts at or
+  // after the ramp, the disk state at t evolves with the ring's force
+  bool coupled = false;
+  double xc = 0, vc = 0, ac = 0;
 
   int N() const { return Nf + Nw + Nd; }
 
@@ -307,8 +320,17 @@ struct Sim {
     K.B = P.rho0 * c0 * c0 / P.gamma;
   }
 
+  // disk centre, velocity and acceleration at time tt of the current step
+  // (coupled: extrapolated from the state at t with its latest acceleration)
   void disk_state(double tt) {
-    kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, tt, &dx_c, &dv, &da);
+    if (coupled) {
+      const double tau = tt - t;
+      dx_c = xc + tau * vc;
+      dv = vc + tau * ac;
+      da = ac;
+    } else {
+      kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, tt, &dx_c, &dv, &da);
+    }
   }
 
   // disk ghosts at angle 2 pi k / N_g around the centre (eq. adami-p text)
@@ -475,13 +497,12 @@ struct Sim {
     return hit;
   }
 
-  // phi = clamp(phi0 + h D), v = v0 + h a, r = r0 + h V, then enforcement at time te
+  // phi = clamp(phi0 + h D), v = v0 + h a, r = r0 + h V, then enforcement
+  // against the disk at centre x cx, velocity vd
   void advance(const std::vector<T>& x0, const std::vector<T>& y0, const std::vector<T>& vx0,
                const std::vector<T>& vy0, const std::vector<T>& rho0, double hdt,
                const std::vector<T>& D, const std::vector<T>& ax, const std::vector<T>& ay,
-               const std::vector<T>& Vx, const std::vector<T>& Vy, double te) {
-    double cx, vd, ad;
-    kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, te, &cx, &vd, &ad);
+               const std::vector<T>& Vx, const std::vector<T>& Vy, double cx, double vd) {
     const double lo = P.rho_lo * P.rho0, hi = P.rho_hi * P.rho0;
     for (int i = 0; i < Nf; ++i) {
       T r = rho0[i] + hdt * D[i];
@@ -522,6 +543,11 @@ struct Sim {
   void one_step() {
     std::vector<T> pf, D(Nf), ax(Nf), ay(Nf), Vx(Nf), Vy(Nf);
     const std::vector<T> x0 = x, y0 = y, vx0 = vx, vy0 = vy, rho0 = rho;
+    if (P.kin_mode == 2 && !coupled && t >= P.kin_t_ramp) {
+      // the first step at or after the ramp starts from the prescribed state
+      kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, t, &xc, &vc, &ac);
+      coupled = true;
+    }
     // evaluation at state n
     prepare(t, pf);
     probes(pf);
@@ -536,16 +562,47 @@ struct Sim {
     }
     rates(pf, D, ax, ay, Vx, Vy);
     // predictor to t + dt/2
-    advance(x0, y0, vx0, vy0, rho0, 0.5 * dt, D, ax, ay, Vx, Vy, t + 0.5 * dt);
+    disk_state(t + 0.5 * dt);
+    advance(x0, y0, vx0, vy0, rho0, 0.5 * dt, D, ax, ay, Vx, Vy, dx_c, dv);
     // evaluation at the midpoint state
     prepare(t + 0.5 * dt, pf);
     T fdx = rates(pf, D, ax, ay, Vx, Vy);
-    w_boundary += dt * val(fdx) * dv;
+    double x1, v1, a1 = 0.0;
+    if (coupled) {
+      // the disk takes the reaction -f of the ring's force f on the fluid:
+      // M dv/dt = -f with f at t + dt/2, trapezoidal position; the boundary
+      // work uses the mean velocity of the step, so that it equals the
+      // disk's kinetic energy loss
+      a1 = -val(fdx) / P.disk_mass;
+      v1 = vc + dt * a1;
+      x1 = xc + dt * 0.5 * (vc + v1);
+      w_boundary += dt * val(fdx) * (0.5 * (vc + v1));
+    } else {
+      w_boundary += dt * val(fdx) * dv;
+      double a_;
+      kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, t + dt, &x1, &v1, &a_);
+    }
     // corrector from state n with the midpoint rates
-    advance(x0, y0, vx0, vy0, rho0, dt, D, ax, ay, Vx, Vy, t + dt);
+    advance(x0, y0, vx0, vy0, rho0, dt, D, ax, ay, Vx, Vy, x1, v1);
+    if (coupled) {
+      xc = x1;
+      vc = v1;
+      ac = a1;
+    }
     t += dt;
     step++;
     if (P.diag_every > 0 && step % P.diag_every == 0) record_diag(dt, vmax);
+  }
+
+  // the disk state at t
+  void current_disk(double* x_, double* v_, double* a_) const {
+    if (coupled) {
+      *x_ = xc;
+      *v_ = vc;
+      *a_ = ac;
+    } else {
+      kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, t, x_, v_, a_);
+    }
   }
 
   // specific elastic energy of the Tait law with the cutoff branch
@@ -574,7 +631,7 @@ struct Sim {
       if (val(K.B) * (std::pow(r / P.rho0, P.gamma) - 1.0) <= P.p_cav) ncav++;
     }
     double xd, vd, ad;
-    kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, t, &xd, &vd, &ad);
+    current_disk(&xd, &vd, &ad);
     double row[ORC_NDIAG] = {t, dt, vmax, M, px_, py_, ke, eel, epot, 0.5 * P.disk_mass * vd * vd,
                              w_boundary, (double)step, (double)n_clamp, (double)ncav,
                              (double)n_enforce};
@@ -673,6 +730,7 @@ void orc_kinematics(void* s, double t, double* x, double* v, double* a) {
   auto* q = static_cast<SimD*>(s);
   kinematics(q->P.kin_mode, q->P.kin_v0, q->P.kin_t_ramp, q->P.kin_coef, q->P.disk_x0, t, x, v, a);
 }
+void orc_disk_state(void* s, double* x, double* v, double* a) { static_cast<SimD*>(s)->current_disk(x, v, a); }
 
 // ---- building blocks --------------------------------------------------------
 void orc_kernel(double q, double h, double* W, double* F) {
@@ -844,6 +902,10 @@ void orc_pair_rates(const orc_params* p, int n, const double* x, const double* y
 }
 
 void orc_tangent_J(const orc_params* p, int n_steps, const double* dt, double* J, double* dJ) {
+  if (p->kin_mode == 2) {  // the disk's response to the coefficients is not differentiated
+    *J = dJ[0] = dJ[1] = dJ[2] = std::nan("");
+    return;
+  }
   using D3 = Dual<3>;
   Sim<D3> s;
   s.P = *p;

@@ -79,6 +79,16 @@ def C1() -> dict:
     return base(0.080, 0.040, 1.0e-3, 4.0e-3, 600.0, steps=200)
 
 
+def two_way(cfg: dict) -> dict:
+    """The same workload with two-way disk coupling (kin_mode 2): the ramp,
+    then the disk moves with the reaction of the ring's force on the fluid.
+    In the plane the disk is the cross-section of a cylinder of the
+    projectile's density (M_p over the volume of a sphere of radius R_p),
+    so its mass per unit depth is that density times pi R^2."""
+    rho_p = PROJ_MASS / (4.0 / 3.0 * math.pi * PROJ_RADIUS ** 3)
+    return dict(cfg, kin_mode=2, disk_mass=rho_p * math.pi * cfg["disk_R"] ** 2)
+
+
 def C2() -> dict:
     """300x150 mm, dx = 0.5 mm (179,552 fluid), R = 6 mm, 900 m/s, 2,000 steps,
     four wall probes at the PTn / PTf stations x = 30 and 105 mm."""
