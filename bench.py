@@ -181,6 +181,41 @@ def adjoint_vs_fd(wc, workloads, steps: int, ckpt: int):
                 ratio_fd_over_adjoint=round(t_plain / t_adj, 3))
 
 
+def two_way_run(wc, workloads, steps: int, prescribed_value: float):
+    """The headline workload with the two-way coupled disk (the extra disk
+    update launch per step), `steps` steps from t = 0, with the disk's final
+    velocity and the drift of e_disk + w_boundary since the coupling began."""
+    import torch
+    cfg = workloads.two_way(workloads.C2())
+    s = wc.Solver(cfg, "cuda:0")
+    blob = s.save_state()
+    s.step(20)
+    s.synchronize()
+    s.load_state(blob)
+    s.read_diagnostics()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.synchronize()
+    el = time.perf_counter() - t0
+    d = s.read_diagnostics()
+    x, v, _ = s.disk_state()
+    k = np.nonzero(d["t"] > cfg["kin_t_ramp"] + 2 * d["dt"].max())[0]
+    drift = None
+    if k.size:
+        tot = d["e_disk"][k] + d["w_boundary"][k]
+        drift = float(np.abs(tot - tot[0]).max() / d["e_disk"][k[0]])
+    nf = s.nf
+    s.close()
+    value = nf * steps / el
+    return dict(workload="300x150 mm channel, dx 0.5 mm, disk of steel density per unit depth "
+                         f"({cfg['disk_mass']:.4g} kg/m) released at 900 m/s after the ramp",
+                steps=steps, value=value, unit="fluid particle-steps/s",
+                ms_per_step=round(el / steps * 1e3, 5), vs_prescribed=round(value / prescribed_value, 4),
+                disk_v_end=v, disk_x_end=x, energy_drift_rel=drift,
+                unstable=bool(d.get("unstable", False)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +227,8 @@ def main():
                     help="steps of the batched-sweep comparison (0 skips it)")
     ap.add_argument("--adj-steps", type=int, default=500,
                     help="steps of the adjoint comparison (0 skips it)")
+    ap.add_argument("--two-way-steps", type=int, default=2000,
+                    help="steps of the two-way coupled run (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel "
                          "of known traffic for hardware-counter runs)")
@@ -254,6 +291,7 @@ def main():
 
     batched = batched_vs_plain(wc, workloads, args.batch_steps) if args.batch_steps > 0 else None
     adjoint = adjoint_vs_fd(wc, workloads, args.adj_steps, 50) if args.adj_steps > 0 else None
+    two_way = two_way_run(wc, workloads, args.two_way_steps, value) if args.two_way_steps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(cfg)
     out = {
         "metric": "WCSPH fluid particle-steps/s at 180k particles",
@@ -276,6 +314,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_sweep": batched,
         "adjoint": adjoint,
+        "two_way": two_way,
         "unstable": unstable,
         "probe_peak_pa": float(np.abs(p).max()) if p.size else None,
     }

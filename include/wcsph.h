@@ -74,10 +74,19 @@ typedef struct {
  *               n_disk_ghosts ring ghosts of mass rho0 dx 2 pi R / N_g
  *               (eq. adami-p text), ghost_rho_mode 0 = linear acoustic branch
  *               rho0 (1 + p / (rho0 c0^2)) (eq. adami-v), 1 = Tait inverse,
- *               disk_mass for the disk kinetic energy diagnostic.
+ *               disk_mass (per unit depth, kg/m) for the disk kinetic energy
+ *               diagnostic and the coupled disk's inertia.
  *  kinematics : kin_mode 0 = ramp (eq. velocity-ramp) over kin_t_ramp to kin_v0
  *               then constant deceleration kin_coef (m/s^2); 1 = ramp then
- *               quadratic drag dv/dt = -kin_coef v^2 (eq. drag).
+ *               quadratic drag dv/dt = -kin_coef v^2 (eq. drag); 2 = two-way
+ *               coupling (the extension named with the energy audit and in
+ *               the Conclusions): the ramp, then from the first step starting
+ *               at t >= kin_t_ramp the disk obeys disk_mass dv/dt = -f, f the
+ *               x force of the ring on the fluid at the step midpoint (the
+ *               FP64 sum of the per-ghost forces), trapezoidal position; the
+ *               boundary work then uses the step's mean disk velocity, so that
+ *               e_disk + w_boundary stays constant. kin_coef is unused;
+ *               disk_mass > 0 is required.
  *  probes     : n_probes points (x, y) where the Shepard-averaged fluid
  *               pressure is recorded every step.
  *  output     : diag_every steps between diagnostic records; init_mode 0 =
@@ -144,9 +153,12 @@ wcsph_status wcsph_instance_info(const wcsph_ctx* ctx, int inst, int* n_fluid, i
 
 /* ---- driving --------------------------------------------------------------- */
 
-/* Prescribed disk kinematics of instance `inst` (Velocity Ramp, Projectile
- * Dynamics). mode 0: coeffs = {v0, t_ramp, a_d}; mode 1: {v0, t_ramp, k}.
- * n = number of coefficients (3). Takes effect at the next step. */
+/* Disk kinematics of instance `inst` (Velocity Ramp, Projectile Dynamics).
+ * mode 0: coeffs = {v0, t_ramp, a_d}; mode 1: {v0, t_ramp, k}; mode 2
+ * (two-way coupling, see kin_mode): {v0, t_ramp, unused}. n = number of
+ * coefficients (3). Takes effect at the next step, from the disk state the
+ * new law gives at the newest state's time: a coupled disk is released and a
+ * mode-2 disk couples again at its next step at or after t_ramp. */
 wcsph_status wcsph_set_disk_kinematics(wcsph_ctx* ctx, int inst, int mode, const double* coeffs,
                                        int n);
 
@@ -180,6 +192,11 @@ wcsph_status wcsph_read_diagnostics(wcsph_ctx* ctx, int inst, wcsph_diag* out, i
  * lattice, disk interior skipped), decoded to FP64; n = its fluid count. */
 wcsph_status wcsph_get_fluid(wcsph_ctx* ctx, int inst, double* t, double* x, double* y, double* vx,
                              double* vy, double* rho, int n);
+/* Disk centre x, velocity and acceleration (along +x) of instance `inst` at
+ * the newest state's time (any pointer may be NULL). For a coupled disk the
+ * acceleration is that of the last step. Synchronises the context stream. */
+wcsph_status wcsph_get_disk(wcsph_ctx* ctx, int inst, double* x, double* v, double* a);
+
 /* Replace the fluid state of every instance (single-instance contexts only):
  * positions are encoded as (cell, FP32 offset), velocities and density to
  * FP32; storage order is reset to id order and the clock set to t. */
@@ -226,8 +243,9 @@ wcsph_status wcsph_set_coefficients(wcsph_ctx* ctx, int inst, double alpha, doub
 /* Reverse-mode gradient of the summed wall-probe pressure impulse
  *   J = sum_k sum_n p_k^n dt_n   (probes sampled at the state of step n)
  * with respect to (alpha, delta, c0), for a single-instance context with the
- * linear ghost density and the rest initial state, at a fixed time-step
- * table (wcsph_set_dt_table must cover the run, so dt does not depend on c0).
+ * linear ghost density, the rest initial state and a prescribed disk motion
+ * (kin_mode 0 or 1), at a fixed time-step table (wcsph_set_dt_table must
+ * cover the run, so dt does not depend on c0).
  * adj_forward advances n_steps from the current state, keeps a device
  * checkpoint every ckpt_every steps and returns J. adj_backward walks the
  * segments last to first: it restores a checkpoint, replays the segment

@@ -26,7 +26,7 @@ _STATUS = {0: "OK", 1: "E_INVALID", 2: "E_OOM", 3: "E_HIP", 4: "E_STATE", 5: "E_
 SYMBOLS = (
     "wcsph_create", "wcsph_batch_create", "wcsph_destroy", "wcsph_last_error", "wcsph_get_info",
     "wcsph_instance_info", "wcsph_set_disk_kinematics", "wcsph_set_dt_table", "wcsph_step",
-    "wcsph_synchronize", "wcsph_read_probes", "wcsph_read_diagnostics", "wcsph_get_fluid",
+    "wcsph_synchronize", "wcsph_read_probes", "wcsph_read_diagnostics", "wcsph_get_fluid", "wcsph_get_disk",
     "wcsph_set_fluid", "wcsph_save_state", "wcsph_load_state", "wcsph_export_cells",
     "wcsph_export_rates", "wcsph_export_neighbours", "wcsph_time_pair_kernel",
     "wcsph_set_coefficients", "wcsph_adj_forward", "wcsph_adj_backward",
@@ -128,6 +128,7 @@ def lib():
             "wcsph_read_probes": [_V, C.c_int, _D, _D, _F, C.c_int, _I],
             "wcsph_read_diagnostics": [_V, C.c_int, C.POINTER(Diag), C.c_int, _I],
             "wcsph_get_fluid": [_V, C.c_int, _D, _D, _D, _D, _D, _D, C.c_int],
+            "wcsph_get_disk": [_V, C.c_int, _D, _D, _D],
             "wcsph_set_fluid": [_V, C.c_double, _D, _D, _D, _D, _D, C.c_int],
             "wcsph_save_state": [_V, _V, C.c_size_t, C.POINTER(C.c_size_t)],
             "wcsph_load_state": [_V, _V, C.c_size_t],
@@ -291,6 +292,12 @@ class Solver:
         self._check(lib().wcsph_get_fluid(self.handle, inst, C.byref(t),
                                           *[_p(x, C.c_double) for x in a], nf))
         return t.value, a
+
+    def disk_state(self, inst: int = 0):
+        """(x, v, a) of the disk at the newest state's time."""
+        o = [C.c_double() for _ in range(3)]
+        self._check(lib().wcsph_get_disk(self.handle, inst, *[C.byref(x) for x in o]))
+        return tuple(x.value for x in o)
 
     def set_fluid(self, t, x, y, vx, vy, rho):
         arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, vx, vy, rho)]

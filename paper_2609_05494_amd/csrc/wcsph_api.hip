@@ -77,6 +77,7 @@ struct wcsph_ctx {
   std::vector<long long> hist_read, diag_rows, diag_read;
   double* d_dt = nullptr;
   size_t d_dt_cap = 0;
+  double* d_disk = nullptr;  // disk state query output (3 doubles)
   bool dead = false;
   // reverse sweep
   struct Adj {
@@ -153,7 +154,9 @@ void validate(const wcsph_params& p) {
             "disk must lie inside the channel");
     require(p.kin_t_ramp > 0 && p.kin_v0 >= 0 && p.kin_coef >= 0, "kinematics coefficients invalid");
   }
-  require(p.kin_mode == 0 || p.kin_mode == 1, "kin_mode must be 0 or 1");
+  require(p.kin_mode >= 0 && p.kin_mode <= 2, "kin_mode must be 0, 1 or 2");
+  if (p.disk_R > 0 && p.kin_mode == 2)
+    require(p.disk_mass > 0 && std::isfinite(p.disk_mass), "a two-way coupled disk needs disk_mass > 0");
   require(p.n_probes >= 0 && p.n_probes <= WCSPH_MAX_PROBES, "n_probes must lie in [0, 16]");
   const double m = p.ghost_layers * p.dx;
   for (int k = 0; k < p.n_probes; ++k)
@@ -395,6 +398,13 @@ void drop_graphs(wcsph_ctx* c) {
   c->graph_k = nullptr;
 }
 
+// Some instance has a two-way coupled disk: the step launches the disk update.
+bool two_way(const wcsph_ctx* c) {
+  for (const InstParams& q : c->hp)
+    if (q.kin_mode == 2 && q.nd > 0) return true;
+  return false;
+}
+
 // Capture the step graphs: one step, and diag_every steps followed by the
 // diagnostic record (launched when the step count is a multiple of
 // diag_every), so that consecutive steps run without host round trips.
@@ -402,14 +412,14 @@ void capture(wcsph_ctx* c) {
   drop_graphs(c);
   hipGraph_t g = nullptr;
   HC(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-  wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, c->st);
+  wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, two_way(c), c->st);
   HC(hipStreamEndCapture(c->st, &g));
   c->graph = g;
   HC(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
   c->steps_k = c->diag_every > 0 ? c->diag_every : 10;
   g = nullptr;
   HC(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < c->steps_k; ++k) wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, c->st);
+  for (int k = 0; k < c->steps_k; ++k) wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, two_way(c), c->st);
   if (c->diag_every > 0) wc_enqueue_diag(c->d, c->b, true, c->st);
   HC(hipStreamEndCapture(c->st, &g));
   c->graph_k = g;
@@ -513,6 +523,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.diag = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_CAP * WC_NDIAG);
   d.diag_part = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_BLOCKS * 8);
   d.wb_part = dalloc_n<double>(c, (size_t)n_inst * WC_MAX_RING);
+  c->d_disk = dalloc_n<double>(c, 3);
   d.n_vpart = wc_pair_blocks(c->n_slots);
   d.vmax_part = dalloc_n<float>(c, (size_t)d.n_vpart);
   d.xr = dalloc_n<float>(c, (size_t)5 * c->n_slots);
@@ -778,9 +789,13 @@ wcsph_status wcsph_instance_info(const wcsph_ctx* ctx, int inst, int* n_fluid, i
 wcsph_status wcsph_set_disk_kinematics(wcsph_ctx* ctx, int inst, int mode, const double* coeffs, int n) {
   API_BEGIN(ctx)
   require(inst >= 0 && inst < ctx->n_inst, "instance out of range");
-  require(mode == 0 || mode == 1, "mode must be 0 or 1");
+  require(mode >= 0 && mode <= 2, "mode must be 0, 1 or 2");
   require(coeffs != nullptr && n == 3, "three coefficients expected");
   require(coeffs[0] >= 0 && coeffs[1] > 0 && coeffs[2] >= 0, "coefficients must be non-negative, t_ramp > 0");
+  if (mode == 2 && ctx->hp[inst].nd > 0)
+    require(ctx->hp[inst].disk_mass > 0 && std::isfinite(ctx->hp[inst].disk_mass),
+            "a two-way coupled disk needs disk_mass > 0");
+  sync(ctx);
   InstParams& q = ctx->hp[inst];
   q.kin_mode = mode;
   q.kin_v0 = coeffs[0];
@@ -791,9 +806,16 @@ wcsph_status wcsph_set_disk_kinematics(wcsph_ctx* ctx, int inst, int mode, const
   ctx->pin[inst].kin_t_ramp = coeffs[1];
   ctx->pin[inst].kin_coef = coeffs[2];
   HC(hipMemcpyAsync(ctx->d_prm + inst, &q, sizeof(InstParams), hipMemcpyHostToDevice, ctx->st));
+  // the new law starts from the newest state: a coupled disk is released
+  // (mode 2 couples again at its next step at or after t_ramp)
+  const int zero = 0;
+  HC(hipMemcpyAsync(reinterpret_cast<char*>(ctx->d_clk + inst) + offsetof(Clock, coupled), &zero, sizeof zero,
+                    hipMemcpyHostToDevice, ctx->st));
   // the ring of the newest state was placed with the old law: place it again
   rearm(ctx);
   sync(ctx);
+  // the step graph launches the disk update only when some disk is coupled
+  capture(ctx);
   API_END(ctx)
 }
 
@@ -950,6 +972,20 @@ wcsph_status wcsph_get_fluid(wcsph_ctx* ctx, int inst, double* t, double* x, dou
     HC(hipMemcpy(&k, ctx->d_clk + inst, sizeof k, hipMemcpyDeviceToHost));
     *t = k.t_next;
   }
+  API_END(ctx)
+}
+
+wcsph_status wcsph_get_disk(wcsph_ctx* ctx, int inst, double* x, double* v, double* a) {
+  API_BEGIN(ctx)
+  require(inst >= 0 && inst < ctx->n_inst, "instance out of range");
+  wc_enqueue_disk_query(ctx->d, inst, ctx->d_disk, ctx->st);
+  HC(hipGetLastError());
+  double o[3];
+  HC(hipMemcpyAsync(o, ctx->d_disk, sizeof o, hipMemcpyDeviceToHost, ctx->st));
+  sync(ctx);
+  if (x) *x = o[0];
+  if (v) *v = o[1];
+  if (a) *a = o[2];
   API_END(ctx)
 }
 
@@ -1216,6 +1252,8 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   require(!ctx->batch && ctx->n_inst == 1, "the reverse sweep needs a single-instance context");
   require(ctx->pin[0].ghost_rho_mode == 0, "the reverse sweep supports the linear ghost density only");
   require(ctx->pin[0].init_mode == 0, "the reverse sweep needs the rest initial state");
+  require(ctx->hp[0].kin_mode != 2 || ctx->hp[0].nd == 0,
+          "the reverse sweep needs a prescribed disk motion (kin_mode 0 or 1)");
   require(n_steps >= 1 && ckpt_every >= 1, "n_steps and ckpt_every must be >= 1");
   const long long k0 = ctx->steps - ctx->d.dt_step0;
   require(ctx->d.n_dt > 0 && k0 >= 0 && k0 + n_steps <= ctx->d.n_dt,

@@ -63,6 +63,9 @@ struct Clock {
   double t_eval;   // time of the current evaluation
   double xd, vd, ad;  // disk centre x, velocity, acceleration at t_eval
   double xd_next, vd_next;  // disk centre x and velocity at t + dt (from the second evaluation on)
+  double ac_next;     // coupled disk: acceleration over the step (the state at t + dt)
+  double xc, vc, ac;  // coupled disk: centre x, velocity, latest acceleration at t
+  double v_work;      // coupled disk: mean velocity of the step (boundary work)
   double w_boundary;  // integrated work of the disk ghosts on the fluid
   double vmax_used;   // v_max that set dt
   long long step;     // index of the current step (-1 before the first)
@@ -70,6 +73,8 @@ struct Clock {
   unsigned long long n_clamp, n_enforce;
   unsigned int vmax_bits;  // running max of |v| (float bits) for the next dt
   unsigned int bad;        // non-finite / escaped-particle flag
+  int coupled;             // kin_mode 2: the disk moves under the fluid force (from the step at t >= t_ramp)
+  int pad_;
 };
 
 // One particle buffer (structure of arrays in slot order).

@@ -38,7 +38,8 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Prescribed disk motion along +x (velocity ramp, then constant deceleration
-// or quadratic drag), FP64 closed forms.
+// or quadratic drag), FP64 closed forms. Mode 2 (two-way coupling) follows
+// the ramp and then v0 only until its first coupled step.
 __device__ void kinematics(const InstParams& P, double t, double& x, double& v, double& a) {
   const double v0 = P.kin_v0, tr = P.kin_t_ramp;
   if (t < tr) {
@@ -48,6 +49,12 @@ __device__ void kinematics(const InstParams& P, double t, double& x, double& v, 
     return;
   }
   const double tau = t - tr, xr = P.disk_x0 + 0.5 * v0 * tr;
+  if (P.kin_mode == 2) {
+    v = v0;
+    a = 0.0;
+    x = xr + v0 * tau;
+    return;
+  }
   if (P.kin_mode == 1) {
     const double k = P.kin_coef;
     v = v0 / (1.0 + k * v0 * tau);
@@ -65,6 +72,31 @@ __device__ void kinematics(const InstParams& P, double t, double& x, double& v, 
   v = v0 - ad * tau;
   a = -ad;
   x = xr + v0 * tau - 0.5 * ad * tau * tau;
+}
+
+// Disk state at time te of the current step: a coupled disk is extrapolated
+// from its state at t with its latest acceleration, otherwise the prescribed
+// law.
+__device__ void disk_at(const InstParams& P, const Clock& C, double te, double& x, double& v, double& a) {
+  if (P.kin_mode == 2 && C.coupled) {
+    const double tau = te - C.t;
+    x = C.xc + tau * C.vc;
+    v = C.vc + tau * C.ac;
+    a = C.ac;
+  } else {
+    kinematics(P, te, x, v, a);
+  }
+}
+
+// Disk state of the newest particle state (time t_next).
+__device__ void disk_newest(const InstParams& P, const Clock& C, double& x, double& v, double& a) {
+  if (P.kin_mode == 2 && C.coupled) {
+    x = C.xd_next;
+    v = C.vd_next;
+    a = C.ac_next;
+  } else {
+    kinematics(P, C.t_next, x, v, a);
+  }
 }
 
 // Tait pressure with the cavitation cutoff, P = p / rho^2 and the sound speed
@@ -591,6 +623,21 @@ __device__ void clock_commit(const Dev& d, int i) {
     C.t = C.t_next;
     C.step += 1;
     te = C.t;
+    if (P.kin_mode == 2) {
+      if (C.coupled) {
+        C.xc = C.xd_next;
+        C.vc = C.vd_next;
+        C.ac = C.ac_next;
+      } else if (C.t >= P.kin_t_ramp) {
+        // the first step at or after the ramp starts from the prescribed state
+        double x0, v0, a0;
+        kinematics(P, C.t, x0, v0, a0);
+        C.xc = x0;
+        C.vc = v0;
+        C.ac = a0;
+        C.coupled = 1;
+      }
+    }
   } else if (MODE == EV_B) {
     const double dt = step_dt(d, P, C);
     C.dt = dt;
@@ -600,15 +647,18 @@ __device__ void clock_commit(const Dev& d, int i) {
     d.hist_t[row] = C.t;
     d.hist_dt[row] = dt;
     te = C.t + 0.5 * dt;
-    double xn, vn, an;
-    kinematics(P, C.t + dt, xn, vn, an);
-    C.xd_next = xn;
-    C.vd_next = vn;
+    if (!(P.kin_mode == 2 && C.coupled)) {  // a coupled disk's new state comes from k_disk
+      double xn, vn, an;
+      kinematics(P, C.t + dt, xn, vn, an);
+      C.xd_next = xn;
+      C.vd_next = vn;
+    }
   } else {
     te = C.t_next;
   }
   double x, v, a;
-  kinematics(P, te, x, v, a);
+  if (MODE == EV_EXPORT) disk_newest(P, C, x, v, a);
+  else disk_at(P, C, te, x, v, a);
   C.t_eval = te;
   C.xd = x;
   C.vd = v;
@@ -1124,7 +1174,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       double xc = C.xd_next;
       if (MODE == EV_A) {  // disk at t + dt/2
         double vc, ac;
-        kinematics(P, C.t + 0.5 * step_dt(d, P, C), xc, vc, ac);
+        disk_at(P, C, C.t + 0.5 * step_dt(d, P, C), xc, vc, ac);
       }
       place_ring(d, P, inst, ring, xc, out, s, bucket);
     } else {
@@ -1200,7 +1250,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       double xd = C.xd_next, vd = C.vd_next;
       if (MODE == EV_A) {
         double ad;
-        kinematics(P, C.t + 0.5 * dt, xd, vd, ad);
+        disk_at(P, C, C.t + 0.5 * dt, xd, vd, ad);
       }
       const double rx = x - xd, ry = y - P.disk_y0;
       const double d2 = rx * rx + ry * ry;
@@ -1260,12 +1310,45 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
         f = wave_sum(f);
         if (threadIdx.x == 0) {
           Clock& Ci = clk[i];
-          Ci.w_boundary += Ci.dt * f * Ci.vd;
+          Ci.w_boundary += Ci.dt * f * (Pi.kin_mode == 2 && Ci.coupled ? Ci.v_work : Ci.vd);
           Ci.t_next = Ci.t + Ci.dt;
         }
       }
     }
   }
+}
+
+// Two-way coupled disk (kin_mode 2), one wave per instance between the
+// second ghost pass and the second pair pass: the disk takes the reaction of
+// the ring's x force on the fluid at t + dt/2 (the fixed-order sum of the
+// per-ghost forces, the same sum as the boundary work), M dv/dt = -f, with a
+// trapezoidal position. The state at t + dt places the ring and bounds the
+// fluid of the new state; the step's mean velocity carries the boundary work.
+__global__ __launch_bounds__(64) void k_disk(Dev d) {
+  const int i = blockIdx.x;
+  const InstParams& P = d.prm[i];
+  Clock& C = d.clk[i];
+  if (!(P.kin_mode == 2 && C.coupled)) return;
+  double f = 0.0;
+  for (int k = (int)threadIdx.x; k < P.nd; k += 64) f += d.wb_part[i * WC_MAX_RING + k];
+  f = wave_sum(f);
+  if (threadIdx.x == 0) {
+    const double dt = C.dt, a1 = -f / P.disk_mass, v1 = C.vc + dt * a1;
+    C.xd_next = C.xc + dt * 0.5 * (C.vc + v1);
+    C.vd_next = v1;
+    C.ac_next = a1;
+    C.v_work = 0.5 * (C.vc + v1);
+  }
+}
+
+// Disk centre, velocity and acceleration of instance i's newest state.
+__global__ void k_disk_query(Dev d, int i, double* out) {
+  if (threadIdx.x != 0) return;
+  double x, v, a;
+  disk_newest(d.prm[i], d.clk[i], x, v, a);
+  out[0] = x;
+  out[1] = v;
+  out[2] = a;
 }
 
 // Buckets and v_max of a freshly loaded state (slots in any order); the
@@ -1288,7 +1371,7 @@ __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
       v = fast_sqrt(pv.z * pv.z + pv.w * pv.w);
     } else if (local >= P.nf + P.nw) {
       double xc, vc, ac;
-      kinematics(P, d.clk[inst].t_next, xc, vc, ac);
+      disk_newest(P, d.clk[inst], xc, vc, ac);
       place_ring(d, P, inst, local - P.nf - P.nw, xc, X, s, d.bucket_a);
     } else {
       bucket_put_wall(d, P, d.bucket_a, X.cell[s], local - P.nf, (uint32_t)s);
@@ -1389,7 +1472,7 @@ __global__ __launch_bounds__(64) void k_diag_final(Dev d) {
   Clock& C = d.clk[i];
   const long long row = C.diag_row++;
   double xd, vd, ad;
-  kinematics(P, C.t_next, xd, vd, ad);
+  disk_newest(P, C, xd, vd, ad);
   double* o = d.diag + ((long long)i * WC_DIAG_CAP + (row % WC_DIAG_CAP)) * WC_NDIAG;
   o[0] = C.t_next;
   o[1] = C.step >= 0 ? C.dt : 0.0;
@@ -1459,18 +1542,23 @@ static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, co
 }
 
 template <bool BATCH>
-static void enqueue_step_t(const Dev& d, const Bufs& b, int n_gblk, hipStream_t st) {
+static void enqueue_step_t(const Dev& d, const Bufs& b, int n_gblk, bool two_way, hipStream_t st) {
   eval_sort<BATCH>(d, st, EV_A, b.X, b.Y);
   k_ghost<EV_A, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
   k_pair<EV_A, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
   eval_sort<BATCH>(d, st, EV_B, b.Z, b.W);
   k_ghost<EV_B, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.W);
+  if (two_way) k_disk<<<d.n_inst, 64, 0, st>>>(d);
   k_pair<EV_B, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.Y, b.X);
 }
 
-void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, hipStream_t st) {
-  if (batch) enqueue_step_t<true>(d, b, n_gblk, st);
-  else enqueue_step_t<false>(d, b, n_gblk, st);
+void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, bool two_way, hipStream_t st) {
+  if (batch) enqueue_step_t<true>(d, b, n_gblk, two_way, st);
+  else enqueue_step_t<false>(d, b, n_gblk, two_way, st);
+}
+
+void wc_enqueue_disk_query(const Dev& d, int inst, double* out, hipStream_t st) {
+  k_disk_query<<<1, 64, 0, st>>>(d, inst, out);
 }
 
 void wc_enqueue_init(const Dev& d, const Bufs& b, bool batch, hipStream_t st) {

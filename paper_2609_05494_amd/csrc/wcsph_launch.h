@@ -11,7 +11,10 @@ struct Bufs {
   Buf X, Y, Z, W;
 };
 
-void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, hipStream_t st);
+// two_way: some instance has a two-way coupled disk (kin_mode 2)
+void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, bool two_way, hipStream_t st);
+// Disk centre, velocity, acceleration of instance inst's newest state into out[3] (device).
+void wc_enqueue_disk_query(const Dev& d, int inst, double* out, hipStream_t st);
 void wc_enqueue_init(const Dev& d, const Bufs& b, bool batch, hipStream_t st);
 void wc_enqueue_diag(const Dev& d, const Bufs& b, bool sorted, hipStream_t st);
 void wc_enqueue_export_sort(const Dev& d, const Bufs& b, bool batch, hipStream_t st);
