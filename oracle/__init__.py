@@ -16,9 +16,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "wcsph_oracle.cpp")
 MAX_PROBES = 16
-NDIAG = 15
+NDIAG = 21
 DIAG_FIELDS = ("t", "dt", "vmax", "mass", "momx", "momy", "ke", "e_el", "e_pot", "e_disk",
-               "w_boundary", "step", "n_clamp", "n_cav", "n_enforce")
+               "w_boundary", "step", "n_clamp", "n_cav", "n_enforce",
+               "d_av", "d_visc", "w_delta", "w_ghost", "w_enforce", "w_clamp")
 
 
 def build(force: bool = True) -> str:
@@ -93,6 +94,7 @@ def lib():
             "orc_get_diags": (None, [C.c_void_p, _D]),
             "orc_impulse": (C.c_double, [C.c_void_p]),
             "orc_eval_rates": (None, [C.c_void_p] + [_D] * 10),
+            "orc_audit_rates": (None, [C.c_void_p, _D]),
             "orc_get_ghosts": (None, [C.c_void_p, _D, _D, _D]),
             "orc_get_order": (None, [C.c_void_p, _I, _I]),
             "orc_kinematics": (None, [C.c_void_p, C.c_double, _D, _D, _D]),
@@ -212,6 +214,13 @@ class Oracle:
         x, v, a = C.c_double(), C.c_double(), C.c_double()
         lib().orc_kinematics(self.h, t, C.byref(x), C.byref(v), C.byref(a))
         return x.value, v.value, a.value
+
+    def audit_rates(self):
+        """Energy audit rates of the last rate evaluation (eval_rates or the
+        midpoint of the last step): d_av, d_visc, w_delta, w_ghost."""
+        out = np.empty(4)
+        lib().orc_audit_rates(self.h, dptr(out))
+        return dict(zip(("d_av", "d_visc", "w_delta", "w_ghost"), out))
 
     def disk_state(self):
         """Disk centre x, velocity and acceleration at the current time

@@ -17,7 +17,9 @@ extern "C" {
 #endif
 
 #define ORC_MAX_PROBES 16
-#define ORC_NDIAG 15 /* t dt vmax mass momx momy ke e_el e_pot e_disk w_boundary step n_clamp n_cav n_enforce */
+/* t dt vmax mass momx momy ke e_el e_pot e_disk w_boundary step n_clamp n_cav n_enforce
+ * d_av d_visc w_delta w_ghost w_enforce w_clamp (energy audit integrals, J per unit depth) */
+#define ORC_NDIAG 21
 
 typedef struct {
   double L, W, dx, h_over_dx, cell_size;  /* cell_size <= 0 -> 2h */
@@ -58,6 +60,11 @@ double orc_impulse(void* s); /* J = sum_k sum_n p_k^n dt_n */
  * untouched except for the storage order. */
 void orc_eval_rates(void* s, double* drho, double* ax, double* ay, double* Vx, double* Vy,
                     double* gp, double* grho, double* gvx, double* gvy, double* vmax);
+/* Energy audit rates of the last rate evaluation (J/s per unit depth):
+ * D_av' and D_visc' (fluid pairs, >= 0), W_delta', W_ghost' (every
+ * fluid-ghost pair term). For any state, sum_i m_i (v_i.a_i + P_i drho_i
+ * - v_i.g) = W_ghost' - D_av' - D_visc' + W_delta'. */
+void orc_audit_rates(void* s, double* out /* 4 */);
 void orc_get_ghosts(void* s, double* gx, double* gy, double* gm);
 void orc_get_order(void* s, int* order, int* cell_start);
 void orc_kinematics(void* s, double t, double* x, double* v, double* a);

@@ -35,6 +35,15 @@
 //    with the reaction of the ring's x force on the fluid.
 //  * cell-linked list of cell size >= 2h, rebuilt at every evaluation by a
 //    stable sort of the particles by cell key.
+//  * the energy audit of eq. energy-audit, term by term: besides the work
+//    W_boundary of the ring on the fluid, the integrals over time of the
+//    fluid energy rate of every fluid-ghost pair term (W_ghost), of the
+//    irreversible dissipation of the artificial and laminar viscosity
+//    between fluid particles (D_av, D_visc), of the elastic energy rate of
+//    the delta diffusion (W_delta), all from the midpoint rates times dt,
+//    and the energy changed by the enforcement and the density clamp of the
+//    corrector (W_enforce, W_clamp). What they leave of the change of the
+//    fluid energy is the time-integration, XSPH and boundary-position part.
 // Ghost state and rates are re-evaluated at both evaluations of a step
 // (operator split of the Pipeline Provenance section).
 
@@ -154,7 +163,9 @@ struct PV {
 template <class T>
 struct Acc {
   T D, ax, ay, Vx, Vy, fdx;
-  Acc() : D(0.0), ax(0.0), ay(0.0), Vx(0.0), Vy(0.0), fdx(0.0) {}
+  // energy audit, per unit mass of particle a (values only)
+  double av, visc, del, ghost;
+  Acc() : D(0.0), ax(0.0), ay(0.0), Vx(0.0), Vy(0.0), fdx(0.0), av(0), visc(0), del(0), ghost(0) {}
 };
 
 // Contribution of neighbour b to the rates of fluid particle a.
@@ -182,7 +193,9 @@ void pair_law(const PV<T>& a, const PV<T>& b, const orc_params& p, const Geom& g
   acc.D += b.m * vr * F;
   // delta diffusion (fluid pairs): delta h c0 sum_j V_j psi_ij . grad_i W_ij,
   // psi_ij = 2 (rho_j - rho_i) (r_j - r_i) / |r_ij|^2
-  if (b.kind == 0) acc.D += 2.0 * k.delta * g.h * k.c0 * (b.m / b.rho) * (a.rho - b.rho) * F;
+  T dd(0.0);
+  if (b.kind == 0) dd = 2.0 * k.delta * g.h * k.c0 * (b.m / b.rho) * (a.rho - b.rho) * F;
+  acc.D += dd;
   // pressure + artificial viscosity, symmetric form
   T s = a.P + b.P + Pi;
   acc.ax -= b.m * s * F * rx;
@@ -192,6 +205,21 @@ void pair_law(const PV<T>& a, const PV<T>& b, const orc_params& p, const Geom& g
   T lam = b.m * 4.0 * g.nu0 * F * r2 / ((a.rho + b.rho) * denom);
   acc.ax += lam * vxij;
   acc.ay += lam * vyij;
+  // energy audit. Between fluid particles the pressure work cancels the
+  // elastic energy rate of the continuity term pair by pair; what is left is
+  // the dissipation of the viscous terms, half to each particle of the pair:
+  // (1/2) m_j Pi_ij F v_ij.r_ij >= 0 and -(1/2) lam |v_ij|^2 >= 0 (F < 0),
+  // and the delta term's elastic energy rate P_i dd. A ghost pair is counted
+  // whole: the work of its pressure, AV and laminar forces on v_i plus the
+  // elastic energy rate P_i m_g F v_ig.r_ig of its continuity term.
+  if (b.kind == 0) {
+    acc.av += 0.5 * val(b.m * Pi * F * vr);
+    acc.visc -= 0.5 * val(lam * (vxij * vxij + vyij * vyij));
+    acc.del += val(a.P * dd);
+  } else {
+    acc.ghost += val(-b.m * s * F * (rx * a.vx + ry * a.vy) + lam * (vxij * a.vx + vyij * a.vy) +
+                     a.P * b.m * vr * F);
+  }
   // XSPH over fluid neighbours
   if (b.kind == 0) {
     T w = p.eps_xsph * (b.m / rbar) * W;
@@ -260,6 +288,9 @@ struct Sim {
   T J = T(0.0);
   double w_boundary = 0.0;
   long n_clamp = 0, n_enforce = 0;
+  // energy audit integrals: D_av, D_visc, W_delta, W_ghost, W_enforce, W_clamp
+  double audit[6] = {0, 0, 0, 0, 0, 0};
+  mutable double audit_rate[4] = {0, 0, 0, 0};
   // disk state at the current evaluation
   double dx_c = 0, dv = 0, da = 0;
   // two-way coupling (kin_mode 2): from the first step that starts at or
@@ -447,6 +478,7 @@ struct Sim {
   T rates(const std::vector<T>& pf, std::vector<T>& D, std::vector<T>& ax, std::vector<T>& ay,
           std::vector<T>& Vx, std::vector<T>& Vy) const {
     std::vector<T> fdx(Nf);
+    std::vector<double> au(4 * (size_t)Nf);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < Nf; ++i) {
       PV<T> a = view(i, pf);
@@ -461,9 +493,18 @@ struct Sim {
       Vx[i] = vx[i] + acc.Vx;
       Vy[i] = vy[i] + acc.Vy;
       fdx[i] = G.m_fluid * acc.fdx;
+      au[4 * (size_t)i] = acc.av;
+      au[4 * (size_t)i + 1] = acc.visc;
+      au[4 * (size_t)i + 2] = acc.del;
+      au[4 * (size_t)i + 3] = acc.ghost;
     }
     T f(0.0);
     for (int i = 0; i < Nf; ++i) f += fdx[i];
+    for (int q = 0; q < 4; ++q) {
+      double z = 0.0;
+      for (int i = 0; i < Nf; ++i) z += au[4 * (size_t)i + q];
+      audit_rate[q] = G.m_fluid * z;
+    }
     return f;
   }
 
@@ -502,15 +543,23 @@ struct Sim {
   void advance(const std::vector<T>& x0, const std::vector<T>& y0, const std::vector<T>& vx0,
                const std::vector<T>& vy0, const std::vector<T>& rho0, double hdt,
                const std::vector<T>& D, const std::vector<T>& ax, const std::vector<T>& ay,
-               const std::vector<T>& Vx, const std::vector<T>& Vy, double cx, double vd) {
+               const std::vector<T>& Vx, const std::vector<T>& Vy, double cx, double vd,
+               bool corrector) {
     const double lo = P.rho_lo * P.rho0, hi = P.rho_hi * P.rho0;
     for (int i = 0; i < Nf; ++i) {
       T r = rho0[i] + hdt * D[i];
+      const double r_free = val(r);
       if (val(r) < lo) { r = T(lo); n_clamp++; }
       if (val(r) > hi) { r = T(hi); n_clamp++; }
+      // energy the clamp and the enforcement of the new state add (corrector)
+      if (corrector && val(r) != r_free) audit[5] += G.m_fluid * (e_el(val(r)) - e_el(r_free));
       T ux = vx0[i] + hdt * ax[i], uy = vy0[i] + hdt * ay[i];
       T xx = x0[i] + hdt * Vx[i], yy = y0[i] + hdt * Vy[i];
-      if (enforce(xx, yy, ux, uy, cx, P.disk_y0, vd)) n_enforce++;
+      const double k_free = val(ux) * val(ux) + val(uy) * val(uy);
+      if (enforce(xx, yy, ux, uy, cx, P.disk_y0, vd)) {
+        n_enforce++;
+        if (corrector) audit[4] += 0.5 * G.m_fluid * (val(ux) * val(ux) + val(uy) * val(uy) - k_free);
+      }
       x[i] = xx; y[i] = yy; vx[i] = ux; vy[i] = uy; rho[i] = r;
     }
   }
@@ -563,10 +612,11 @@ struct Sim {
     rates(pf, D, ax, ay, Vx, Vy);
     // predictor to t + dt/2
     disk_state(t + 0.5 * dt);
-    advance(x0, y0, vx0, vy0, rho0, 0.5 * dt, D, ax, ay, Vx, Vy, dx_c, dv);
+    advance(x0, y0, vx0, vy0, rho0, 0.5 * dt, D, ax, ay, Vx, Vy, dx_c, dv, false);
     // evaluation at the midpoint state
     prepare(t + 0.5 * dt, pf);
     T fdx = rates(pf, D, ax, ay, Vx, Vy);
+    for (int q = 0; q < 4; ++q) audit[q] += dt * audit_rate[q];
     double x1, v1, a1 = 0.0;
     if (coupled) {
       // the disk takes the reaction -f of the ring's force f on the fluid:
@@ -583,7 +633,7 @@ struct Sim {
       kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, t + dt, &x1, &v1, &a_);
     }
     // corrector from state n with the midpoint rates
-    advance(x0, y0, vx0, vy0, rho0, dt, D, ax, ay, Vx, Vy, x1, v1);
+    advance(x0, y0, vx0, vy0, rho0, dt, D, ax, ay, Vx, Vy, x1, v1, true);
     if (coupled) {
       xc = x1;
       vc = v1;
@@ -634,7 +684,8 @@ struct Sim {
     current_disk(&xd, &vd, &ad);
     double row[ORC_NDIAG] = {t, dt, vmax, M, px_, py_, ke, eel, epot, 0.5 * P.disk_mass * vd * vd,
                              w_boundary, (double)step, (double)n_clamp, (double)ncav,
-                             (double)n_enforce};
+                             (double)n_enforce, audit[0], audit[1], audit[2], audit[3], audit[4],
+                             audit[5]};
     diag_rows.insert(diag_rows.end(), row, row + ORC_NDIAG);
   }
 };
@@ -716,6 +767,10 @@ void orc_eval_rates(void* s, double* drho, double* ax, double* ay, double* Vx, d
     if (gvy) gvy[g] = q->gvy[g];
   }
   if (vmax) *vmax = q->vmax_now();
+}
+void orc_audit_rates(void* s, double* out) {
+  auto* q = static_cast<SimD*>(s);
+  for (int k = 0; k < 4; ++k) out[k] = q->audit_rate[k];
 }
 void orc_get_ghosts(void* s, double* gx, double* gy, double* gm) {
   auto* q = static_cast<SimD*>(s);
