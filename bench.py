@@ -216,6 +216,40 @@ def two_way_run(wc, workloads, steps: int, prescribed_value: float):
                 unstable=bool(d.get("unstable", False)))
 
 
+def audit_run(wc, workloads, steps: int, prescribed_value: float):
+    """The headline workload with the energy audit on (the second pair pass
+    carries the audit sums), `steps` steps from t = 0: its cost and the
+    ledger of eq. energy-audit at the end."""
+    import torch
+    cfg = dict(workloads.C2(), audit=1)
+    s = wc.Solver(cfg, "cuda:0")
+    blob = s.save_state()
+    s.step(20)
+    s.synchronize()
+    s.load_state(blob)
+    s.read_diagnostics()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.synchronize()
+    el = time.perf_counter() - t0
+    d = s.read_diagnostics()
+    nf = s.nf
+    s.close()
+    e = d["ke"] + d["e_el"] + d["e_pot"]
+    keys = ("w_boundary", "w_ghost", "d_av", "d_visc", "w_delta", "w_enforce", "w_clamp")
+    terms = {k: float(d[k][-1]) for k in keys}
+    ledger = (terms["w_ghost"] - terms["d_av"] - terms["d_visc"] + terms["w_delta"] + terms["w_enforce"]
+              + terms["w_clamp"])
+    value = nf * steps / el
+    return dict(workload="300x150 mm channel, dx 0.5 mm, prescribed disk, energy audit on",
+                steps=steps, value=value, unit="fluid particle-steps/s",
+                ms_per_step=round(el / steps * 1e3, 5), vs_plain=round(value / prescribed_value, 4),
+                delta_e_fluid=float(e[-1] - e[0]), **terms,
+                residual_rel=float(((e[-1] - e[0]) - ledger) / abs(terms["w_ghost"])),
+                unstable=bool(d.get("unstable", False)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +263,8 @@ def main():
                     help="steps of the adjoint comparison (0 skips it)")
     ap.add_argument("--two-way-steps", type=int, default=2000,
                     help="steps of the two-way coupled run (0 skips it)")
+    ap.add_argument("--audit-steps", type=int, default=2000,
+                    help="steps of the energy-audit run (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel "
                          "of known traffic for hardware-counter runs)")
@@ -292,6 +328,7 @@ def main():
     batched = batched_vs_plain(wc, workloads, args.batch_steps) if args.batch_steps > 0 else None
     adjoint = adjoint_vs_fd(wc, workloads, args.adj_steps, 50) if args.adj_steps > 0 else None
     two_way = two_way_run(wc, workloads, args.two_way_steps, value) if args.two_way_steps > 0 else None
+    audit = audit_run(wc, workloads, args.audit_steps, value) if args.audit_steps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(cfg)
     out = {
         "metric": "WCSPH fluid particle-steps/s at 180k particles",
@@ -315,6 +352,7 @@ def main():
         "batched_sweep": batched,
         "adjoint": adjoint,
         "two_way": two_way,
+        "energy_audit": audit,
         "unstable": unstable,
         "probe_peak_pa": float(np.abs(p).max()) if p.size else None,
     }

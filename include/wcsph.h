@@ -90,7 +90,9 @@ typedef struct {
  *  probes     : n_probes points (x, y) where the Shepard-averaged fluid
  *               pressure is recorded every step.
  *  output     : diag_every steps between diagnostic records; init_mode 0 =
- *               fluid at rest at rho0, 1 = hydrostatic density. */
+ *               fluid at rest at rho0, 1 = hydrostatic density; audit 1 =
+ *               record the energy audit terms (single-instance contexts; the
+ *               second pair pass then carries four more sums per pair). */
 typedef struct {
   double L, W, dx, h_over_dx, cell_size;
   double rho0, c0, gamma, p_cav;
@@ -104,16 +106,27 @@ typedef struct {
   int diag_every;
   int kin_mode;
   double kin_v0, kin_t_ramp, kin_coef;
+  int audit;
 } wcsph_params;
 
 /* One diagnostic record (FP64 reductions over the fluid of one instance).
  * ke, e_el (Tait elastic energy with the cutoff branch), e_pot (gravity),
  * e_disk = disk_mass v_d^2 / 2, w_boundary = integrated work of the disk
  * ghosts on the fluid (eq. energy-audit), n_clamp / n_enforce = cumulative
- * density-band and enforcement hits, n_cav = particles at the cutoff now. */
+ * density-band and enforcement hits, n_cav = particles at the cutoff now.
+ * Energy audit (audit = 1, else 0), integrals since the set-up, J per unit
+ * depth: d_av and d_visc = irreversible dissipation of the artificial and
+ * laminar viscosity between fluid particles (the D of eq. energy-audit),
+ * w_delta = elastic energy rate of the delta diffusion, w_ghost = fluid
+ * energy rate of every fluid-ghost pair term (walls and ring), all from the
+ * midpoint rates times dt; w_enforce and w_clamp = energy the corrector's
+ * enforcement and density clamp change. The change of ke + e_el + e_pot
+ * equals w_ghost - d_av - d_visc + w_delta + w_enforce + w_clamp up to the
+ * midpoint rule across enforcement and cutoff events (about 1 %). */
 typedef struct {
   double t, dt, vmax, mass, mom[2], ke, e_el, e_pot, e_disk, w_boundary;
   long long step, n_clamp, n_cav, n_enforce;
+  double d_av, d_visc, w_delta, w_ghost, w_enforce, w_clamp;
 } wcsph_diag;
 
 typedef struct {

@@ -55,7 +55,7 @@ class Params(C.Structure):
         ("n_probes", C.c_int), ("probe_xy", C.c_double * (2 * MAX_PROBES)),
         ("diag_every", C.c_int),
         ("kin_mode", C.c_int), ("kin_v0", C.c_double), ("kin_t_ramp", C.c_double),
-        ("kin_coef", C.c_double),
+        ("kin_coef", C.c_double), ("audit", C.c_int),
     ]
 
 
@@ -64,7 +64,9 @@ class Diag(C.Structure):
                 ("mom", C.c_double * 2), ("ke", C.c_double), ("e_el", C.c_double),
                 ("e_pot", C.c_double), ("e_disk", C.c_double), ("w_boundary", C.c_double),
                 ("step", C.c_longlong), ("n_clamp", C.c_longlong), ("n_cav", C.c_longlong),
-                ("n_enforce", C.c_longlong)]
+                ("n_enforce", C.c_longlong), ("d_av", C.c_double), ("d_visc", C.c_double),
+                ("w_delta", C.c_double), ("w_ghost", C.c_double), ("w_enforce", C.c_double),
+                ("w_clamp", C.c_double)]
 
 
 class Info(C.Structure):

@@ -78,6 +78,7 @@ struct wcsph_ctx {
   double* d_dt = nullptr;
   size_t d_dt_cap = 0;
   double* d_disk = nullptr;  // disk state query output (3 doubles)
+  bool audit = false;        // energy audit in the second pair pass (single instance)
   bool dead = false;
   // reverse sweep
   struct Adj {
@@ -164,6 +165,7 @@ void validate(const wcsph_params& p) {
                 p.probe_xy[2 * k + 1] <= p.W + m,
             "probe outside the grid");
   require(p.diag_every >= 0, "diag_every must be >= 0");
+  require(p.audit == 0 || p.audit == 1, "audit must be 0 or 1");
   const long long nx = std::llround(p.L / p.dx), ny = std::llround(p.W / p.dx);
   require(nx >= 1 && ny >= 1 && nx * ny < (1ll << 28), "lattice size out of range");
 }
@@ -373,6 +375,8 @@ void upload_state(wcsph_ctx* c, double t0, const double* fx, const double* fy, c
     k.step = -1;
   }
   HC(hipMemcpyAsync(c->d_clk, clk.data(), clk.size() * sizeof(Clock), hipMemcpyHostToDevice, c->st));
+  if (c->d.audit_part)
+    HC(hipMemsetAsync(c->d.audit_part, 0, (size_t)c->d.n_vpart * 6 * sizeof(double), c->st));
   wc_enqueue_init(c->d, c->b, c->batch, c->st);
   HC(hipGetLastError());
   c->steps = 0;
@@ -412,14 +416,14 @@ void capture(wcsph_ctx* c) {
   drop_graphs(c);
   hipGraph_t g = nullptr;
   HC(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-  wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, two_way(c), c->st);
+  wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, two_way(c), c->audit, c->st);
   HC(hipStreamEndCapture(c->st, &g));
   c->graph = g;
   HC(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
   c->steps_k = c->diag_every > 0 ? c->diag_every : 10;
   g = nullptr;
   HC(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < c->steps_k; ++k) wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, two_way(c), c->st);
+  for (int k = 0; k < c->steps_k; ++k) wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, two_way(c), c->audit, c->st);
   if (c->diag_every > 0) wc_enqueue_diag(c->d, c->b, true, c->st);
   HC(hipStreamEndCapture(c->st, &g));
   c->graph_k = g;
@@ -524,6 +528,8 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.diag_part = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_BLOCKS * 8);
   d.wb_part = dalloc_n<double>(c, (size_t)n_inst * WC_MAX_RING);
   c->d_disk = dalloc_n<double>(c, 3);
+  c->audit = !c->batch && params[0].audit != 0;
+  d.audit_part = c->audit ? dalloc_n<double>(c, (size_t)wc_pair_blocks(c->n_slots) * 6) : nullptr;
   d.n_vpart = wc_pair_blocks(c->n_slots);
   d.vmax_part = dalloc_n<float>(c, (size_t)d.n_vpart);
   d.xr = dalloc_n<float>(c, (size_t)5 * c->n_slots);
@@ -582,6 +588,8 @@ wcsph_status create_impl(const wcsph_params* params, int n_inst, const wcsph_all
     for (int i = 0; i < n_inst; ++i) validate(params[i]);
     for (int i = 1; i < n_inst; ++i)
       require(params[i].diag_every == params[0].diag_every, "batched instances share diag_every");
+    if (batch)
+      for (int i = 0; i < n_inst; ++i) require(params[i].audit == 0, "the energy audit needs a single-instance context");
   } catch (const WcError& e) {
     g_create_error = e.msg;
     return e.st;
@@ -922,6 +930,12 @@ wcsph_status wcsph_read_diagnostics(wcsph_ctx* ctx, int inst, wcsph_diag* out, i
     o.n_clamp = (long long)v[12];
     o.n_cav = (long long)v[13];
     o.n_enforce = (long long)v[14];
+    o.d_av = v[15];
+    o.d_visc = v[16];
+    o.w_delta = v[17];
+    o.w_ghost = v[18];
+    o.w_enforce = v[19];
+    o.w_clamp = v[20];
   }
   rd += rows;
   *n_out = (int)rows;
@@ -1011,15 +1025,16 @@ wcsph_status wcsph_set_fluid(wcsph_ctx* ctx, double t, const double* x, const do
 namespace {
 struct BlobHeader {
   char magic[8];
-  long long n_inst, n_slots, n_cells, n_ghost, steps, batch;
+  long long n_inst, n_slots, n_cells, n_ghost, steps, batch, n_audit;
 };
+size_t audit_bytes(const wcsph_ctx* c) { return c->d.audit_part ? (size_t)c->d.n_vpart * 6 * sizeof(double) : 0; }
 }  // namespace
 
 wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* need) {
   API_BEGIN(ctx)
   const size_t N = ctx->n_slots;
   const size_t sz = sizeof(BlobHeader) + ctx->n_inst * sizeof(Clock) + N * (4 + 4 + 16 + 16 + 2) +
-                    (size_t)ctx->n_ghost * 4;
+                    (size_t)ctx->n_ghost * 4 + audit_bytes(ctx);
   if (need) *need = sz;
   if (!buf) return WCSPH_OK;
   if (cap < sz) throw WcError{WCSPH_E_RANGE, "buffer too small for the state"};
@@ -1027,13 +1042,14 @@ wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* nee
   char* o = static_cast<char*>(buf);
   BlobHeader h;
   std::memset(&h, 0, sizeof h);
-  std::memcpy(h.magic, "WCSPHST2", 8);
+  std::memcpy(h.magic, "WCSPHST3", 8);
   h.n_inst = ctx->n_inst;
   h.n_slots = N;
   h.n_cells = ctx->n_cells;
   h.n_ghost = ctx->n_ghost;
   h.steps = ctx->steps;
   h.batch = ctx->batch;
+  h.n_audit = (long long)audit_bytes(ctx);
   std::memcpy(o, &h, sizeof h);
   o += sizeof h;
   auto put = [&](const void* dev, size_t bytes) {
@@ -1051,6 +1067,7 @@ wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* nee
     o += N * 2;
   }
   put(ctx->d.gslot, (size_t)ctx->n_ghost * 4);
+  if (ctx->d.audit_part) put(ctx->d.audit_part, audit_bytes(ctx));
   API_END(ctx)
 }
 
@@ -1059,13 +1076,14 @@ wcsph_status wcsph_load_state(wcsph_ctx* ctx, const void* buf, size_t n) {
   require(buf != nullptr && n >= sizeof(BlobHeader), "buffer too small");
   BlobHeader h;
   std::memcpy(&h, buf, sizeof h);
-  require(std::memcmp(h.magic, "WCSPHST2", 8) == 0, "not a state blob");
+  require(std::memcmp(h.magic, "WCSPHST3", 8) == 0, "not a state blob");
   require(h.n_inst == ctx->n_inst && h.n_slots == ctx->n_slots && h.n_cells == ctx->n_cells &&
-              h.n_ghost == ctx->n_ghost && h.batch == (long long)ctx->batch,
+              h.n_ghost == ctx->n_ghost && h.batch == (long long)ctx->batch &&
+              h.n_audit == (long long)audit_bytes(ctx),
           "state blob does not match this context");
   const size_t N = ctx->n_slots;
   const size_t sz = sizeof(BlobHeader) + ctx->n_inst * sizeof(Clock) + N * (4 + 4 + 16 + 16 + 2) +
-                    (size_t)ctx->n_ghost * 4;
+                    (size_t)ctx->n_ghost * 4 + audit_bytes(ctx);
   require(n >= sz, "state blob truncated");
   sync(ctx);
   const char* o = static_cast<const char*>(buf) + sizeof h;
@@ -1081,6 +1099,7 @@ wcsph_status wcsph_load_state(wcsph_ctx* ctx, const void* buf, size_t n) {
   if (ctx->batch) get(ctx->b.X.inst, N * 2);
   else o += N * 2;
   get(ctx->d.gslot, (size_t)ctx->n_ghost * 4);
+  if (ctx->d.audit_part) get(ctx->d.audit_part, audit_bytes(ctx));
   rearm(ctx);
   sync(ctx);
   ctx->steps = h.steps;

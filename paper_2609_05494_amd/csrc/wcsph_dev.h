@@ -15,7 +15,7 @@
 #define WC_MAX_PROBES 16
 #define WC_HIST_CAP 65536
 #define WC_DIAG_CAP 4096
-#define WC_NDIAG 15
+#define WC_NDIAG 21
 #define WC_BLOCK 256
 #define WC_GHOST_BLOCK 256
 #define WC_GHOST_LANES 16      // lanes per ghost or probe in the ghost kernel
@@ -119,6 +119,8 @@ struct Dev {
   float* vmax_part;           // single instance: per corrector pair block, max |v| of its new fluid
                               // state (folded into the clock by the next first-evaluation sort)
   int n_vpart;                // entries of vmax_part (pair blocks)
+  double* audit_part;         // energy audit (single instance, or NULL): per corrector pair block,
+                              // running sums of d_av, d_visc, w_delta, w_ghost, w_enforce, w_clamp
   float* xr;                  // export: [5][n_slots] rates per slot
   int* nb_count;              // export: neighbour count per slot
   long long* nb_idsum;        // export: neighbour id sum per slot

@@ -248,6 +248,15 @@ struct PairAcc {
   float D, ax, ay, Vx, Vy;
 };
 
+// Energy audit sums of a fluid particle (second evaluation, audit runs):
+// per unit mass of the particle, the dissipation of the artificial and
+// laminar viscosity of its fluid pairs (half of each pair term), the delta
+// term of its density rate (times P_i afterwards) and the fluid energy rate
+// of its ghost pairs.
+struct AudAcc {
+  float av, visc, del, ghost;
+};
+
 // One of the three cell rows around (cx, cy): slots [rs, re) of its (up to)
 // three cells, middle cell [ms, me).
 struct RowRange {
@@ -275,10 +284,10 @@ __device__ __forceinline__ uint32_t dx_code(uint32_t j, const RowRange& r) {
 // (symmetric form), laminar (Lo-Shao), XSPH. Branch-free: a ghost neighbour
 // (m < 0) contributes nothing to the delta and XSPH terms through m_fl = 0,
 // and the AV switch is min(v_ij . r_ij, 0).
-template <class PP>
+template <bool AUD, class PP>
 __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float rhoi, float Pi,
                                           float ci, float rx, float ry, float r2, const float4& pj,
-                                          const float4& aj, PairAcc& acc) {
+                                          const float4& aj, PairAcc& acc, AudAcc& aud) {
   float W, F;
   wendland(P, r2, W, F);
   const float vxij = pi.z - pj.z, vyij = pi.w - pj.w;
@@ -292,12 +301,29 @@ __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float r
   const float piav = -P.alpha * P.h * (ci + aj.z) * fminf(vr, 0.0f) * inv;
   const float mF = mj * F;
   // continuity + delta diffusion 2 delta h c0 (m_j / rho_j)(rho_i - rho_j) F (fluid pairs)
-  acc.D += mF * vr + P.two_delta_h_c0 * mfl * fast_rcp(aj.x) * (rhoi - aj.x) * F;
+  const float dd = P.two_delta_h_c0 * mfl * fast_rcp(aj.x) * (rhoi - aj.x) * F;
+  acc.D += mF * vr + dd;
   const float sp = Pi + aj.y + piav;
   // laminar (Lo-Shao): 4 nu0 m_j F r^2 / ((rho_i + rho_j)(r^2 + eta^2 h^2)) v_ij
   const float lam = P.four_nu0 * mF * r2 * inv;
   acc.ax += lam * vxij - mF * sp * rx;
   acc.ay += lam * vyij - mF * sp * ry;
+  if constexpr (AUD) {
+    // fluid pairs: the pressure work cancels the elastic energy rate of the
+    // continuity term pair by pair; half of each viscous dissipation
+    // (1/2) m_j Pi_ij F v_ij.r_ij and -(1/2) lam |v_ij|^2 (F < 0), and the
+    // delta term. Ghost pairs whole: the work of the pair's pressure, AV and
+    // laminar forces on v_i plus P_i m_g F v_ig.r_ig of the continuity term,
+    // -m_g F ((P_g + Pi_ig) r.v_i + P_i r.v_g) + lam v_ig.v_i.
+    const float mflF = mfl * F, mgF = mF - mflF;
+    const float v2 = vxij * vxij + vyij * vyij;
+    const float lamg = P.four_nu0 * mgF * r2 * inv;
+    aud.av += 0.5f * mflF * piav * vr;
+    aud.visc -= 0.5f * (lam - lamg) * v2;
+    aud.del += dd;
+    aud.ghost += lamg * (vxij * pi.z + vyij * pi.w) -
+                 mgF * ((aj.y + piav) * (rx * pi.z + ry * pi.w) + Pi * (rx * pj.z + ry * pj.w));
+  }
   // XSPH eps (m_j / rho_bar) W (v_j - v_i) over fluid; 1 / rho_bar = 2 den inv
   const float w = P.eps_xsph * mfl * 2.0f * den * inv * W;
   acc.Vx -= w * vxij;
@@ -372,10 +398,10 @@ __device__ __forceinline__ void wave_sync() {
 // the pair law over the list. A lane's candidate order and every operand
 // of a pair depend on the particle and its neighbours only, not on the
 // other slots of the wave.
-template <bool BATCH>
+template <bool BATCH, bool AUD>
 __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int s, int inst, uint32_t K,
                                                bool fluid, float4 pi, float4 ai, int q, float4* U,
-                                               uint8_t* my, PairAcc& acc) {
+                                               uint8_t* my, PairAcc& acc, AudAcc& aud) {
   const InstParams& IP = d.prm[inst];
   const PairC P = pair_c(IP);
   const float rhoi = ai.x, Pi = ai.y, ci = ai.z;
@@ -439,7 +465,7 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
     auto body = [&](const float4& E, const float4& pj, const float4& aj) __attribute__((always_inline)) {
       const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
       const float ry = pi.y - E.y;
-      pair_body(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc);
+      pair_body<AUD>(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc, aud);
     };
     auto flush = [&]() __attribute__((always_inline)) {
       if (cnt > 0) {
@@ -1087,7 +1113,30 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
 // law with four lanes per slot, then the first wave finishes the slots with
 // one lane each (time integration, enforcement, bucket entries), so the
 // per-slot FP64 work runs on full waves.
-template <int MODE, bool BATCH>
+// r^(gamma - 1) in FP64: repeated products for an integer gamma (the Tait
+// gamma = 7 gives r^6), pow otherwise.
+__device__ __forceinline__ double pow_gm1(double r, double g) {
+  const double e = g - 1.0;
+  if (e == floor(e) && e >= 0.0 && e <= 16.0) {
+    double p = 1.0, b = r;
+    for (int k = (int)e; k > 0; k >>= 1) {
+      if (k & 1) p *= b;
+      b *= b;
+    }
+    return p;
+  }
+  return pow(r, e);
+}
+
+// Specific elastic energy of the Tait law with the cutoff branch below
+// rho_c (the diagnostics' closed form), FP64.
+__device__ __forceinline__ double tait_e_el(const InstParams& P, double r) {
+  const double rg1 = pow_gm1(r, P.gammad);
+  return r >= P.diag_rc ? P.diag_k1 * (rg1 - P.diag_r0g1) + P.Bd * (1.0 / r - 1.0 / P.rho0d)
+                        : P.diag_erc + P.p_cavd * (1.0 / P.diag_rc - 1.0 / r);
+}
+
+template <int MODE, bool BATCH, bool AUD = false>
 #ifdef PAIR_MINW
 __global__ __launch_bounds__(PAIR_BLOCK, PAIR_MINW) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
 #else
@@ -1101,6 +1150,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
   __shared__ uint32_t h_K[PAIR_SLOTS], h_id[PAIR_SLOTS], h_eb[PAIR_SLOTS];
   __shared__ float h_rho[PAIR_SLOTS], h_m[PAIR_SLOTS];
   __shared__ int h_inst[PAIR_SLOTS];
+  __shared__ float h_aud[AUD ? 4 : 1][PAIR_SLOTS];
   // blocks map to XCDs in contiguous slot ranges
   const int s0 = xcd_block(blockIdx.x, gridDim.x) * PAIR_SLOTS;
   {
@@ -1124,7 +1174,9 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       if (MODE == EV_B && fluid) eb = d.perm[s];
     }
     PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    pair_sums_wave<BATCH>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6], lst + threadIdx.x, acc);
+    AudAcc aud = {0.0f, 0.0f, 0.0f, 0.0f};
+    pair_sums_wave<BATCH, AUD>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6], lst + threadIdx.x,
+                               acc, aud);
     // fixed-order combination of the slot's lane partial sums
     acc.D = slot_sum(acc.D);
     acc.ax = slot_sum(acc.ax);
@@ -1145,6 +1197,19 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       h_inst[k] = inst;
       h_id[k] = id;
       h_eb[k] = eb;
+    }
+    if constexpr (AUD) {
+      aud.av = slot_sum(aud.av);
+      aud.visc = slot_sum(aud.visc);
+      aud.del = slot_sum(aud.del);
+      aud.ghost = slot_sum(aud.ghost);
+      if (q == 0) {
+        const int k = (int)(threadIdx.x / PAIR_G);
+        h_aud[0][k] = aud.av;
+        h_aud[1][k] = aud.visc;
+        h_aud[2][k] = ai.y * aud.del;  // elastic energy rate P_i drho_i of the delta term
+        h_aud[3][k] = aud.ghost;
+      }
     }
   }
   __syncthreads();
@@ -1201,6 +1266,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     return;
   }
   bool clamp_hit = false, enf_hit = false;
+  double e_enf = 0.0, e_clamp = 0.0;  // audit: energy of the enforcement and clamp
   float vnew = 0.0f;
   uint32_t newkey = 0u;
   if (lead) {
@@ -1221,6 +1287,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       rb = base.aux[eb].x;
     }
     float rn = rb + hdt * acc.D;
+    const float rn_free = rn;
     if (rn < P.rho_lo) { rn = P.rho_lo; clamp_hit = true; }
     if (rn > P.rho_hi) { rn = P.rho_hi; clamp_hit = true; }
     float vx = pb.z + hdt * acc.ax;
@@ -1239,6 +1306,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       d.tape_pos[fid] = make_double2(x, y);
       d.tape_vel[fid] = make_float4(vx, vy, rb + hdt * acc.D, 0.0f);
     }
+    const double k_free = (double)vx * vx + (double)vy * vy;
     bool moved = false;
     const double e = P.eps_wall;
     if (x < e) { x = e; vx = -vx; moved = true; }
@@ -1287,6 +1355,33 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     newkey = Kn;
     vnew = fast_sqrt(vx * vx + vy * vy);
     if (!(rn == rn) || !(vnew <= 3.0e38f)) atomicOr(&clk[inst].bad, 1u);
+    if constexpr (AUD && MODE == EV_B) {
+      // the energy the enforcement and the density clamp add to the new state
+      const double m = (double)h_m[threadIdx.x];
+      if (moved) e_enf = 0.5 * m * ((double)vx * vx + (double)vy * vy - k_free);
+      if (clamp_hit) e_clamp = m * (tait_e_el(P, (double)rn) - tait_e_el(P, (double)rn_free));
+    }
+  }
+  if constexpr (AUD && MODE == EV_B) {
+    // this block's audit terms, added to its own running sums (a fixed
+    // order for every block, no atomics): the rates times dt, then the
+    // enforcement and clamp energy
+    const double m = lead ? (double)h_m[threadIdx.x] : 0.0;
+    const double rate[4] = {m * h_aud[0][threadIdx.x], m * h_aud[1][threadIdx.x], m * h_aud[2][threadIdx.x],
+                            m * h_aud[3][threadIdx.x]};
+    double tot[6];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tot[k] = wave_sum(lead ? rate[k] : 0.0);
+    tot[4] = wave_sum(e_enf);
+    tot[5] = wave_sum(e_clamp);
+    if (threadIdx.x == 0) {
+      const double dt = clk[0].dt;
+      double* a = d.audit_part + (size_t)blockIdx.x * 6;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[k] += dt * tot[k];
+      a[4] += tot[4];
+      a[5] += tot[5];
+    }
   }
   bucket_put_wave(d, MODE == EV_A ? d.bucket_b : d.bucket_a, lead, newkey, (uint32_t)s);
   count_hits<BATCH>(clk, inst, clamp_hit, enf_hit);
@@ -1381,21 +1476,6 @@ __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
   if (!BATCH && s < d.n_vpart) d.vmax_part[s] = 0.0f;  // the loaded state's max is in the clock
 }
 
-// r^(gamma - 1) in FP64: repeated products for an integer gamma (the Tait
-// gamma = 7 gives r^6), pow otherwise.
-__device__ __forceinline__ double pow_gm1(double r, double g) {
-  const double e = g - 1.0;
-  if (e == floor(e) && e >= 0.0 && e <= 16.0) {
-    double p = 1.0, b = r;
-    for (int k = (int)e; k > 0; k >>= 1) {
-      if (k & 1) p *= b;
-      b *= b;
-    }
-    return p;
-  }
-  return pow(r, e);
-}
-
 // FP64 diagnostics: partial sums over fixed chunks of each instance's slots
 // (grid: WC_DIAG_BLOCKS x n_inst), then one fixed-order pass per instance.
 __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
@@ -1467,6 +1547,15 @@ __global__ __launch_bounds__(64) void k_diag_final(Dev d) {
     for (int j = 0; j < NB; ++j) v += part[j][k];
     tot[k] = wave_sum(v);
   }
+  // energy audit: fixed-order sum of the pair blocks' running sums
+  double aud[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (d.audit_part != nullptr) {
+    for (int b = (int)threadIdx.x; b < d.n_vpart; b += 64)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) aud[k] += d.audit_part[(size_t)b * 6 + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) aud[k] = wave_sum(aud[k]);
+  }
   if (threadIdx.x != 0) return;
   const InstParams& P = d.prm[i];
   Clock& C = d.clk[i];
@@ -1489,6 +1578,8 @@ __global__ __launch_bounds__(64) void k_diag_final(Dev d) {
   o[12] = (double)C.n_clamp;
   o[13] = tot[6];
   o[14] = (double)C.n_enforce;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) o[15 + k] = aud[k];
   if (tot[7] > 0.0 || !(tot[3] == tot[3])) C.bad |= 1u;
 }
 
@@ -1542,19 +1633,21 @@ static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, co
 }
 
 template <bool BATCH>
-static void enqueue_step_t(const Dev& d, const Bufs& b, int n_gblk, bool two_way, hipStream_t st) {
+static void enqueue_step_t(const Dev& d, const Bufs& b, int n_gblk, bool two_way, bool audit, hipStream_t st) {
   eval_sort<BATCH>(d, st, EV_A, b.X, b.Y);
   k_ghost<EV_A, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
   k_pair<EV_A, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
   eval_sort<BATCH>(d, st, EV_B, b.Z, b.W);
   k_ghost<EV_B, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.W);
   if (two_way) k_disk<<<d.n_inst, 64, 0, st>>>(d);
-  k_pair<EV_B, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.Y, b.X);
+  if (!BATCH && audit) k_pair<EV_B, false, true><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.Y, b.X);
+  else k_pair<EV_B, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.Y, b.X);
 }
 
-void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, bool two_way, hipStream_t st) {
-  if (batch) enqueue_step_t<true>(d, b, n_gblk, two_way, st);
-  else enqueue_step_t<false>(d, b, n_gblk, two_way, st);
+void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, bool two_way, bool audit,
+                     hipStream_t st) {
+  if (batch) enqueue_step_t<true>(d, b, n_gblk, two_way, false, st);
+  else enqueue_step_t<false>(d, b, n_gblk, two_way, audit, st);
 }
 
 void wc_enqueue_disk_query(const Dev& d, int inst, double* out, hipStream_t st) {

@@ -12,7 +12,9 @@ struct Bufs {
 };
 
 // two_way: some instance has a two-way coupled disk (kin_mode 2)
-void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, bool two_way, hipStream_t st);
+// audit: single-instance energy audit in the second pair pass
+void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, bool two_way, bool audit,
+                     hipStream_t st);
 // Disk centre, velocity, acceleration of instance inst's newest state into out[3] (device).
 void wc_enqueue_disk_query(const Dev& d, int inst, double* out, hipStream_t st);
 void wc_enqueue_init(const Dev& d, const Bufs& b, bool batch, hipStream_t st);
