@@ -32,8 +32,10 @@ typedef struct {
   int n_probes;
   double probe_xy[2 * ORC_MAX_PROBES];
   int diag_every;
-  int kin_mode; /* 0: ramp then constant deceleration kin_coef; 1: ramp then quadratic drag k=kin_coef */
+  int kin_mode; /* 0: ramp then constant deceleration kin_coef; 1: ramp then quadratic drag k=kin_coef;
+                  2: ramp then two-way coupling */
   double kin_v0, kin_t_ramp, kin_coef;
+  double beta; /* quadratic artificial viscosity coefficient (0: linear term only) */
 } orc_params;
 
 /* ---- whole solver ------------------------------------------------------ */

@@ -11,7 +11,8 @@
 //    (eq. sph-approx); kernel = Wendland C2 in 2D instead of the paper's
 //    cubic B-spline (eq. cubic-kernel).
 //  * momentum in the symmetric form (eq. momentum) with the Monaghan
-//    artificial viscosity, linear term only (eq. artificial-viscosity), plus
+//    artificial viscosity (eq. artificial-viscosity; the linear term, plus
+//    the quadratic beta mu^2 term the paper omits, off unless beta > 0), plus
 //    a laminar term in the Lo-Shao form for the physical viscosity
 //    (the viscosity paragraph of Governing Equations).
 //  * XSPH-smoothed advection velocity over fluid neighbours (eq. xsph).
@@ -188,6 +189,9 @@ void pair_law(const PV<T>& a, const PV<T>& b, const orc_params& p, const Geom& g
   if (val(vr) < 0.0) {
     T mu = g.h * vr / denom;
     Pi = -1.0 * k.alpha * cbar * mu / rbar;
+    // quadratic (von Neumann-Richtmyer) term of the Monaghan form, which the
+    // paper leaves out at its Mach numbers and names for faster impacts
+    Pi = Pi + p.beta * mu * mu / rbar;
   }
   // continuity: d rho_i/dt = sum_j m_j v_ij . grad_i W_ij
   acc.D += b.m * vr * F;
