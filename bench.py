@@ -250,6 +250,33 @@ def audit_run(wc, workloads, steps: int, prescribed_value: float):
                 unstable=bool(d.get("unstable", False)))
 
 
+def qav_run(wc, workloads, steps: int, prescribed_value: float, beta: float = 1.0):
+    """The headline workload with the quadratic artificial viscosity term
+    (beta mu^2 / rho_bar on top of the linear term), `steps` steps from t = 0."""
+    import torch
+    cfg = dict(workloads.C2(), beta=beta)
+    s = wc.Solver(cfg, "cuda:0")
+    blob = s.save_state()
+    s.step(20)
+    s.synchronize()
+    s.load_state(blob)
+    s.read_probes()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.synchronize()
+    el = time.perf_counter() - t0
+    _, _, p = s.read_probes()
+    unstable = bool(s.read_diagnostics().get("unstable", False))
+    nf = s.nf
+    s.close()
+    value = nf * steps / el
+    return dict(workload=f"300x150 mm channel, dx 0.5 mm, 900 m/s, alpha 0.1 and beta {beta}",
+                steps=steps, value=value, unit="fluid particle-steps/s",
+                ms_per_step=round(el / steps * 1e3, 5), vs_linear=round(value / prescribed_value, 4),
+                probe_peak_pa=float(np.abs(p).max()), unstable=unstable)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +292,8 @@ def main():
                     help="steps of the two-way coupled run (0 skips it)")
     ap.add_argument("--audit-steps", type=int, default=2000,
                     help="steps of the energy-audit run (0 skips it)")
+    ap.add_argument("--qav-steps", type=int, default=2000,
+                    help="steps of the quadratic-viscosity run (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel "
                          "of known traffic for hardware-counter runs)")
@@ -329,6 +358,7 @@ def main():
     adjoint = adjoint_vs_fd(wc, workloads, args.adj_steps, 50) if args.adj_steps > 0 else None
     two_way = two_way_run(wc, workloads, args.two_way_steps, value) if args.two_way_steps > 0 else None
     audit = audit_run(wc, workloads, args.audit_steps, value) if args.audit_steps > 0 else None
+    qav = qav_run(wc, workloads, args.qav_steps, value) if args.qav_steps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(cfg)
     out = {
         "metric": "WCSPH fluid particle-steps/s at 180k particles",
@@ -353,6 +383,7 @@ def main():
         "adjoint": adjoint,
         "two_way": two_way,
         "energy_audit": audit,
+        "quadratic_av": qav,
         "unstable": unstable,
         "probe_peak_pa": float(np.abs(p).max()) if p.size else None,
     }

@@ -65,7 +65,9 @@ typedef struct {
  *               smallest float >= 2h), ghost_layers wall-ghost lattice rows.
  *  material   : rho0, Tait c0 and gamma (B = rho0 c0^2 / gamma), cavitation
  *               cutoff p_cav (< 0, eq. eos text).
- *  scheme     : Monaghan alpha and eta2 (eq. artificial-viscosity), delta
+ *  scheme     : Monaghan alpha and eta2 (eq. artificial-viscosity), beta of
+ *               the quadratic term beta mu^2 / rho_bar that the paper omits
+ *               (0 = linear term only, the paper's form), delta
  *               diffusion coefficient, eps_xsph (eq. xsph), dynamic viscosity
  *               mu_dyn (laminar term), CFL number (eq. cfl), gravity_y,
  *               density band [rho_lo, rho_hi] rho0 (Density Summation),
@@ -107,6 +109,7 @@ typedef struct {
   int kin_mode;
   double kin_v0, kin_t_ramp, kin_coef;
   int audit;
+  double beta;
 } wcsph_params;
 
 /* One diagnostic record (FP64 reductions over the fluid of one instance).
@@ -256,8 +259,9 @@ wcsph_status wcsph_set_coefficients(wcsph_ctx* ctx, int inst, double alpha, doub
 /* Reverse-mode gradient of the summed wall-probe pressure impulse
  *   J = sum_k sum_n p_k^n dt_n   (probes sampled at the state of step n)
  * with respect to (alpha, delta, c0), for a single-instance context with the
- * linear ghost density, the rest initial state and a prescribed disk motion
- * (kin_mode 0 or 1), at a fixed time-step table (wcsph_set_dt_table must
+ * linear ghost density, the rest initial state, a prescribed disk motion
+ * (kin_mode 0 or 1) and the linear artificial viscosity (beta = 0), at a
+ * fixed time-step table (wcsph_set_dt_table must
  * cover the run, so dt does not depend on c0).
  * adj_forward advances n_steps from the current state, keeps a device
  * checkpoint every ckpt_every steps and returns J. adj_backward walks the

@@ -55,7 +55,7 @@ class Params(C.Structure):
         ("n_probes", C.c_int), ("probe_xy", C.c_double * (2 * MAX_PROBES)),
         ("diag_every", C.c_int),
         ("kin_mode", C.c_int), ("kin_v0", C.c_double), ("kin_t_ramp", C.c_double),
-        ("kin_coef", C.c_double), ("audit", C.c_int),
+        ("kin_coef", C.c_double), ("audit", C.c_int), ("beta", C.c_double),
     ]
 
 

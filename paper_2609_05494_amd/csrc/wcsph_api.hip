@@ -166,6 +166,7 @@ void validate(const wcsph_params& p) {
             "probe outside the grid");
   require(p.diag_every >= 0, "diag_every must be >= 0");
   require(p.audit == 0 || p.audit == 1, "audit must be 0 or 1");
+  require(p.beta >= 0 && std::isfinite(p.beta), "beta must be finite and >= 0");
   const long long nx = std::llround(p.L / p.dx), ny = std::llround(p.W / p.dx);
   require(nx >= 1 && ny >= 1 && nx * ny < (1ll << 28), "lattice size out of range");
 }
@@ -225,6 +226,7 @@ InstParams derive(const wcsph_params& p) {
   q.B = (float)B;
   q.p_cav = (float)p.p_cav;
   q.alpha = (float)p.alpha;
+  q.beta2h2 = (float)(2.0 * p.beta * h * h);
   q.eps_xsph = (float)p.eps_xsph;
   q.gy = (float)p.gravity_y;
   q.two_delta_h_c0 = (float)(2.0 * p.delta * h * p.c0);
@@ -528,6 +530,9 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.diag_part = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_BLOCKS * 8);
   d.wb_part = dalloc_n<double>(c, (size_t)n_inst * WC_MAX_RING);
   c->d_disk = dalloc_n<double>(c, 3);
+  d.qav = 0;
+  for (int i = 0; i < n_inst; ++i)
+    if (params[i].beta > 0) d.qav = 1;
   c->audit = !c->batch && params[0].audit != 0;
   d.audit_part = c->audit ? dalloc_n<double>(c, (size_t)wc_pair_blocks(c->n_slots) * 6) : nullptr;
   d.n_vpart = wc_pair_blocks(c->n_slots);
@@ -1273,6 +1278,7 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   require(ctx->pin[0].init_mode == 0, "the reverse sweep needs the rest initial state");
   require(ctx->hp[0].kin_mode != 2 || ctx->hp[0].nd == 0,
           "the reverse sweep needs a prescribed disk motion (kin_mode 0 or 1)");
+  require(ctx->pin[0].beta == 0, "the reverse sweep supports the linear artificial viscosity only (beta = 0)");
   require(n_steps >= 1 && ckpt_every >= 1, "n_steps and ckpt_every must be >= 1");
   const long long k0 = ctx->steps - ctx->d.dt_step0;
   require(ctx->d.n_dt > 0 && k0 >= 0 && k0 + n_steps <= ctx->d.n_dt,

@@ -284,7 +284,7 @@ __device__ __forceinline__ uint32_t dx_code(uint32_t j, const RowRange& r) {
 // (symmetric form), laminar (Lo-Shao), XSPH. Branch-free: a ghost neighbour
 // (m < 0) contributes nothing to the delta and XSPH terms through m_fl = 0,
 // and the AV switch is min(v_ij . r_ij, 0).
-template <bool AUD, class PP>
+template <bool AUD, bool QAV, class PP>
 __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float rhoi, float Pi,
                                           float ci, float rx, float ry, float r2, const float4& pj,
                                           const float4& aj, PairAcc& acc, AudAcc& aud) {
@@ -298,7 +298,10 @@ __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float r
   const float den = r2 + P.eta2h2;      // r^2 + eta^2 h^2
   const float inv = fast_rcp(den * rsum);
   // Monaghan AV: -alpha c_bar mu / rho_bar = -alpha (c_i + c_j) h vr inv for vr < 0
-  const float piav = -P.alpha * P.h * (ci + aj.z) * fminf(vr, 0.0f) * inv;
+  const float vrm = fminf(vr, 0.0f);
+  float piav = -P.alpha * P.h * (ci + aj.z) * vrm * inv;
+  // quadratic term beta mu^2 / rho_bar = 2 beta h^2 vr^2 / ((r^2 + eta^2 h^2)^2 2 rho_bar)
+  if constexpr (QAV) piav += P.beta2h2 * vrm * vrm * inv * (rsum * inv);
   const float mF = mj * F;
   // continuity + delta diffusion 2 delta h c0 (m_j / rho_j)(rho_i - rho_j) F (fluid pairs)
   const float dd = P.two_delta_h_c0 * mfl * fast_rcp(aj.x) * (rhoi - aj.x) * F;
@@ -347,7 +350,7 @@ __device__ __forceinline__ float slot_sum(float v) {
 // The parameters of the candidate test and the pair law, held in registers
 // (the list stores below would otherwise force them to be reloaded).
 struct PairC {
-  float dc, four_h2, inv_h, sigma, fgrad, alpha, h, eta2h2, two_delta_h_c0, four_nu0, eps_xsph;
+  float dc, four_h2, inv_h, sigma, fgrad, alpha, h, eta2h2, two_delta_h_c0, four_nu0, eps_xsph, beta2h2;
 };
 __device__ __forceinline__ PairC pair_c(const InstParams& P) {
   PairC c;
@@ -362,6 +365,7 @@ __device__ __forceinline__ PairC pair_c(const InstParams& P) {
   c.two_delta_h_c0 = P.two_delta_h_c0;
   c.four_nu0 = P.four_nu0;
   c.eps_xsph = P.eps_xsph;
+  c.beta2h2 = P.beta2h2;
   return c;
 }
 
@@ -398,7 +402,7 @@ __device__ __forceinline__ void wave_sync() {
 // the pair law over the list. A lane's candidate order and every operand
 // of a pair depend on the particle and its neighbours only, not on the
 // other slots of the wave.
-template <bool BATCH, bool AUD>
+template <bool BATCH, bool AUD, bool QAV>
 __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int s, int inst, uint32_t K,
                                                bool fluid, float4 pi, float4 ai, int q, float4* U,
                                                uint8_t* my, PairAcc& acc, AudAcc& aud) {
@@ -465,7 +469,7 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
     auto body = [&](const float4& E, const float4& pj, const float4& aj) __attribute__((always_inline)) {
       const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
       const float ry = pi.y - E.y;
-      pair_body<AUD>(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc, aud);
+      pair_body<AUD, QAV>(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc, aud);
     };
     auto flush = [&]() __attribute__((always_inline)) {
       if (cnt > 0) {
@@ -1092,7 +1096,8 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
         const float vr = (pj.z - vgx) * rx + (pj.w - vgy) * ry;
         const float rsum = aj.x + rg, den = r2 + P.eta2h2;
         const float inv = fast_rcp(den * rsum);
-        const float piav = vr < 0.0f ? -P.alpha * (aj.z + cg) * P.h * vr * inv : 0.0f;
+        const float piav =
+            vr < 0.0f ? -P.alpha * (aj.z + cg) * P.h * vr * inv + P.beta2h2 * vr * vr * inv * (rsum * inv) : 0.0f;
         fx -= aj.w * m * (aj.y + Pg + piav) * F * rx;
       });
       const double f = group_sum<GL>((double)fx);
@@ -1136,7 +1141,7 @@ __device__ __forceinline__ double tait_e_el(const InstParams& P, double r) {
                         : P.diag_erc + P.p_cavd * (1.0 / P.diag_rc - 1.0 / r);
 }
 
-template <int MODE, bool BATCH, bool AUD = false>
+template <int MODE, bool BATCH, bool AUD, bool QAV>
 #ifdef PAIR_MINW
 __global__ __launch_bounds__(PAIR_BLOCK, PAIR_MINW) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
 #else
@@ -1175,8 +1180,8 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     }
     PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     AudAcc aud = {0.0f, 0.0f, 0.0f, 0.0f};
-    pair_sums_wave<BATCH, AUD>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6], lst + threadIdx.x,
-                               acc, aud);
+    pair_sums_wave<BATCH, AUD, QAV>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6],
+                                    lst + threadIdx.x, acc, aud);
     // fixed-order combination of the slot's lane partial sums
     acc.D = slot_sum(acc.D);
     acc.ax = slot_sum(acc.ax);
@@ -1624,6 +1629,13 @@ __global__ __launch_bounds__(WC_BLOCK) void k_neigh(Dev d, Buf sb) {
 #define NQ(n) (((n) + PAIR_SLOTS - 1) / PAIR_SLOTS)
 int wc_pair_blocks(int n_slots) { return NQ(n_slots); }
 
+// The pair pass with the quadratic AV term when some instance has beta > 0.
+template <int MODE, bool BATCH, bool AUD = false>
+static void launch_pair(const Dev& d, const Buf& sb, const Buf& base, const Buf& out, hipStream_t st) {
+  if (d.qav) k_pair<MODE, BATCH, AUD, true><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, sb, base, out);
+  else k_pair<MODE, BATCH, AUD, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, sb, base, out);
+}
+
 template <bool BATCH>
 static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, const Buf& out) {
   const int nt = (d.n_cells + WC_SORT_TILE - 1) / WC_SORT_TILE;
@@ -1636,12 +1648,12 @@ template <bool BATCH>
 static void enqueue_step_t(const Dev& d, const Bufs& b, int n_gblk, bool two_way, bool audit, hipStream_t st) {
   eval_sort<BATCH>(d, st, EV_A, b.X, b.Y);
   k_ghost<EV_A, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
-  k_pair<EV_A, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
+  launch_pair<EV_A, BATCH>(d, b.Y, b.Y, b.Z, st);
   eval_sort<BATCH>(d, st, EV_B, b.Z, b.W);
   k_ghost<EV_B, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.W);
   if (two_way) k_disk<<<d.n_inst, 64, 0, st>>>(d);
-  if (!BATCH && audit) k_pair<EV_B, false, true><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.Y, b.X);
-  else k_pair<EV_B, BATCH><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.Y, b.X);
+  if (!BATCH && audit) launch_pair<EV_B, false, true>(d, b.W, b.Y, b.X, st);
+  else launch_pair<EV_B, BATCH>(d, b.W, b.Y, b.X, st);
 }
 
 void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, bool two_way, bool audit,
@@ -1675,12 +1687,12 @@ void wc_enqueue_export_ghosts(const Dev& d, const Bufs& b, int n_gblk, hipStream
 }
 
 void wc_enqueue_export_pair(const Dev& d, const Bufs& b, hipStream_t st) {
-  k_pair<EV_EXPORT, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
+  launch_pair<EV_EXPORT, false>(d, b.Y, b.Y, b.Z, st);
 }
 
 void wc_enqueue_pair_a(const Dev& d, const Bufs& b, bool batch, hipStream_t st) {
-  if (batch) k_pair<EV_A, true><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
-  else k_pair<EV_A, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
+  if (batch) launch_pair<EV_A, true>(d, b.Y, b.Y, b.Z, st);
+  else launch_pair<EV_A, false>(d, b.Y, b.Y, b.Z, st);
 }
 
 void wc_enqueue_neigh(const Dev& d, const Bufs& b, hipStream_t st) {
@@ -1691,10 +1703,10 @@ void wc_enqueue_eval(const Dev& d, const Bufs& b, int n_gblk, int mode, hipStrea
   if (mode == EV_A) {
     eval_sort<false>(d, st, EV_A, b.X, b.Y);
     k_ghost<EV_A, false><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
-    k_pair<EV_A, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.Y, b.Y, b.Z);
+    launch_pair<EV_A, false>(d, b.Y, b.Y, b.Z, st);
   } else {
     eval_sort<false>(d, st, EV_B, b.Z, b.W);
     k_ghost<EV_B, false><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.W);
-    k_pair<EV_B, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, b.W, b.Y, b.X);
+    launch_pair<EV_B, false>(d, b.W, b.Y, b.X, st);
   }
 }
