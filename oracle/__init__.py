@@ -47,7 +47,7 @@ class Params(C.Structure):
         ("n_probes", C.c_int), ("probe_xy", C.c_double * (2 * MAX_PROBES)),
         ("diag_every", C.c_int),
         ("kin_mode", C.c_int), ("kin_v0", C.c_double), ("kin_t_ramp", C.c_double),
-        ("kin_coef", C.c_double), ("beta", C.c_double),
+        ("kin_coef", C.c_double), ("beta", C.c_double), ("kernel_type", C.c_int),
     ]
 
 
@@ -100,6 +100,7 @@ def lib():
             "orc_kinematics": (None, [C.c_void_p, C.c_double, _D, _D, _D]),
             "orc_disk_state": (None, [C.c_void_p, _D, _D, _D]),
             "orc_kernel": (None, [C.c_double, C.c_double, _D, _D]),
+            "orc_kernel_type": (None, [C.c_int, C.c_double, C.c_double, _D, _D]),
             "orc_eos": (None, [P, C.c_double, _D, _D]),
             "orc_elastic_energy": (C.c_double, [P, C.c_double]),
             "orc_cfl_dt": (C.c_double, [C.c_double] * 4),
@@ -230,9 +231,9 @@ class Oracle:
         return x.value, v.value, a.value
 
 
-def kernel(q: float, h: float):
+def kernel(q: float, h: float, kernel_type: int = 0):
     W, F = C.c_double(), C.c_double()
-    lib().orc_kernel(q, h, C.byref(W), C.byref(F))
+    lib().orc_kernel_type(kernel_type, q, h, C.byref(W), C.byref(F))
     return W.value, F.value
 
 

@@ -36,6 +36,7 @@ typedef struct {
                   2: ramp then two-way coupling */
   double kin_v0, kin_t_ramp, kin_coef;
   double beta; /* quadratic artificial viscosity coefficient (0: linear term only) */
+  int kernel_type; /* 0: Wendland C2; 1: cubic B-spline (eq. cubic-kernel) */
 } orc_params;
 
 /* ---- whole solver ------------------------------------------------------ */
@@ -76,6 +77,8 @@ void orc_disk_state(void* s, double* x, double* v, double* a);
 
 /* ---- building blocks (exposed for the pin tests) ------------------------ */
 void orc_kernel(double q, double h, double* W, double* F);
+/* Kernel of type 0 (Wendland C2) or 1 (cubic B-spline): W and F = (1/r) dW/dr. */
+void orc_kernel_type(int type, double q, double h, double* W, double* F);
 void orc_eos(const orc_params* p, double rho, double* pres, double* c);
 double orc_elastic_energy(const orc_params* p, double rho);
 double orc_cfl_dt(double cfl, double h, double c0, double vmax);

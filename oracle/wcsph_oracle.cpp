@@ -9,7 +9,7 @@
 // with the scheme choices of the hot path where they differ from the paper:
 //  * SPH interpolant with a compact kernel of support 2h, h = 1.3 dx
 //    (eq. sph-approx); kernel = Wendland C2 in 2D instead of the paper's
-//    cubic B-spline (eq. cubic-kernel).
+//    cubic B-spline (eq. cubic-kernel), which kernel_type 1 selects.
 //  * momentum in the symmetric form (eq. momentum) with the Monaghan
 //    artificial viscosity (eq. artificial-viscosity; the linear term, plus
 //    the quadratic beta mu^2 term the paper omits, off unless beta > 0), plus
@@ -97,6 +97,8 @@ struct Geom {
   int nx, ny, ncx, ncy;
   double sigma;  // Wendland C2 2D normalisation 7 / (4 pi h^2)
   double fgrad;  // gradient factor 35 / (4 pi h^4)
+  int cubic;     // 1: the cubic B-spline of eq. cubic-kernel instead
+  double sigma_c;  // its 2D normalisation 10 / (7 pi h^2)
   double m_fluid, m_wall, m_disk, nu0;
 };
 
@@ -113,6 +115,8 @@ Geom make_geom(const orc_params& p) {
   g.ncy = (int)std::ceil((p.W + 2.0 * p.ghost_layers * p.dx) / g.dc);
   g.sigma = 7.0 / (4.0 * M_PI * g.h * g.h);
   g.fgrad = 35.0 / (4.0 * M_PI * g.h * g.h * g.h * g.h);
+  g.cubic = p.kernel_type == 1;
+  g.sigma_c = 10.0 / (7.0 * M_PI * g.h * g.h);
   g.m_fluid = p.rho0 * p.dx * p.dx;
   g.m_wall = p.rho0 * p.dx * p.dx;
   g.m_disk = p.n_disk_ghosts > 0 ? p.rho0 * p.dx * 2.0 * M_PI * p.disk_R / p.n_disk_ghosts : 0.0;
@@ -129,6 +133,20 @@ int cell_coord(double x, double lo, double dc, int n) {
 // with F = -(35 / (4 pi h^4)) (1 - q/2)^3 (derivative of W divided by r).
 template <class T>
 void kernel_WF(const T& q, const Geom& g, T& W, T& F) {
+  if (g.cubic) {
+    // cubic B-spline (eq. cubic-kernel): w(q) = 1 - 3/2 q^2 + 3/4 q^3 on
+    // [0, 1], (2 - q)^3 / 4 on (1, 2]; F = (1/r) dW/dr = w'(q) / (h r)
+    const double h2 = g.h * g.h;
+    if (val(q) <= 1.0) {
+      W = g.sigma_c * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
+      F = g.sigma_c * (-3.0 + 2.25 * q) / h2;
+    } else {
+      T s = 2.0 - q;
+      W = g.sigma_c * 0.25 * s * s * s;
+      F = -0.75 * g.sigma_c * s * s / (h2 * q);
+    }
+    return;
+  }
   T s = 1.0 - 0.5 * q;
   T s2 = s * s;
   W = g.sigma * s2 * s2 * (2.0 * q + 1.0);
@@ -792,10 +810,11 @@ void orc_kinematics(void* s, double t, double* x, double* v, double* a) {
 void orc_disk_state(void* s, double* x, double* v, double* a) { static_cast<SimD*>(s)->current_disk(x, v, a); }
 
 // ---- building blocks --------------------------------------------------------
-void orc_kernel(double q, double h, double* W, double* F) {
+void orc_kernel(double q, double h, double* W, double* F) { orc_kernel_type(0, q, h, W, F); }
+void orc_kernel_type(int type, double q, double h, double* W, double* F) {
   orc_params p;
   std::memset(&p, 0, sizeof p);
-  p.dx = h; p.h_over_dx = 1.0; p.rho0 = 1.0; p.L = p.W = 1.0;
+  p.dx = h; p.h_over_dx = 1.0; p.rho0 = 1.0; p.L = p.W = 1.0; p.kernel_type = type;
   Geom g = make_geom(p);
   if (!(q < 2.0)) { *W = 0; *F = 0; return; }
   kernel_WF(q, g, *W, *F);
