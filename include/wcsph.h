@@ -60,6 +60,8 @@ typedef struct {
 } wcsph_allocator;
 
 /* Problem and scheme parameters (copied at create).
+ *  kernel     : kernel_type 0 = Wendland C2 (the hot path's), 1 = the cubic
+ *               B-spline of eq. cubic-kernel (the paper's); support 2h both.
  *  geometry   : channel [0,L]x[0,W], lattice spacing dx, h = h_over_dx dx
  *               (1.3: SPH Fundamentals), cell edge cell_size >= 2h (<= 0 -> the
  *               smallest float >= 2h), ghost_layers wall-ghost lattice rows.
@@ -110,6 +112,7 @@ typedef struct {
   double kin_v0, kin_t_ramp, kin_coef;
   int audit;
   double beta;
+  int kernel_type;
 } wcsph_params;
 
 /* One diagnostic record (FP64 reductions over the fluid of one instance).

@@ -56,6 +56,7 @@ class Params(C.Structure):
         ("diag_every", C.c_int),
         ("kin_mode", C.c_int), ("kin_v0", C.c_double), ("kin_t_ramp", C.c_double),
         ("kin_coef", C.c_double), ("audit", C.c_int), ("beta", C.c_double),
+        ("kernel_type", C.c_int),
     ]
 
 

@@ -239,6 +239,10 @@ __device__ __forceinline__ void tcand(const TRow& r0, const TRow& r1, const TRow
   dy = a0 ? -1 : (a1 ? 0 : 1);
   dx = j < r.ms ? -1 : (j < r.me ? 0 : 1);
 }
+#ifndef ADJ_FG
+#define ADJ_FG 4  // lanes per fluid slot in the fluid adjoint kernel
+#endif
+
 template <int G>
 __device__ __forceinline__ float gsum(float v) {
   for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
@@ -398,8 +402,8 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
   // four lanes per slot (quad lane g) share its 3x3 candidates
   __shared__ double shd[4];
   const InstParams& P = d.prm[0];
-  const int s = (int)((blockIdx.x * 256 + threadIdx.x) >> 2);
-  const int g = (int)(threadIdx.x & 3);
+  const int s = (int)((blockIdx.x * 256 + threadIdx.x) / ADJ_FG);
+  const int g = (int)(threadIdx.x % ADJ_FG);
   const int N = d.n_slots;
   const PairK<float> k = pair_k(P);
   double th_a = 0.0, th_d = 0.0, th_c = 0.0;
@@ -419,7 +423,7 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
       cxy(P, K, cx, cy);
       const TRow r0 = trow(te, P, cx, cy, -1), r1 = trow(te, P, cx, cy, 0), r2 = trow(te, P, cx, cy, 1);
     const TCount blk = tcount(r0, r1, r2);
-      for (uint32_t c = (uint32_t)g; c < blk.n; c += 4) {
+      for (uint32_t c = (uint32_t)g; c < blk.n; c += ADJ_FG) {
         uint32_t j;
         int dx, dy;
         tcand(r0, r1, r2, blk, c, j, dx, dy);
@@ -497,14 +501,14 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
         }
       }
       // fixed-order quad sums
-      urx = gsum<4>(urx);
-      ury = gsum<4>(ury);
-      uvx = gsum<4>(uvx);
-      uvy = gsum<4>(uvy);
-      ur = gsum<4>(ur);
-      uP = gsum<4>(uP);
-      uc = gsum<4>(uc);
-      uc0 = gsum<4>(uc0);
+      urx = gsum<ADJ_FG>(urx);
+      ury = gsum<ADJ_FG>(ury);
+      uvx = gsum<ADJ_FG>(uvx);
+      uvy = gsum<ADJ_FG>(uvy);
+      ur = gsum<ADJ_FG>(ur);
+      uP = gsum<ADJ_FG>(uP);
+      uc = gsum<ADJ_FG>(uc);
+      uc0 = gsum<ADJ_FG>(uc0);
       if (g == 0) {
         // EOS chain: P(rho; c0), c(rho; c0)
         ur += uP * ei.dPdr + uc * ei.dcdr;
@@ -551,7 +555,7 @@ __global__ void k_adj_theta(AdjPtrs a, int nblk) {
 // Backward pass of one evaluation's rates (ghost adjoints, fluid adjoints,
 // coefficient partials). lam_f (by id) -> lam_base (by id).
 static int adj_ghost_blocks(int n_ghost_probe) { return (n_ghost_probe * AG_L + 255) / 256; }
-static int adj_fluid_blocks(int n_slots) { return (n_slots * 4 + 255) / 256; }
+static int adj_fluid_blocks(int n_slots) { return (n_slots * ADJ_FG + 255) / 256; }
 
 int wc_adj_partial_blocks(int n_ghost_probe, int n_slots) {
   return adj_ghost_blocks(n_ghost_probe) + adj_fluid_blocks(n_slots);

@@ -167,6 +167,7 @@ void validate(const wcsph_params& p) {
   require(p.diag_every >= 0, "diag_every must be >= 0");
   require(p.audit == 0 || p.audit == 1, "audit must be 0 or 1");
   require(p.beta >= 0 && std::isfinite(p.beta), "beta must be finite and >= 0");
+  require(p.kernel_type == 0 || p.kernel_type == 1, "kernel_type must be 0 (Wendland C2) or 1 (cubic spline)");
   const long long nx = std::llround(p.L / p.dx), ny = std::llround(p.W / p.dx);
   require(nx >= 1 && ny >= 1 && nx * ny < (1ll << 28), "lattice size out of range");
 }
@@ -227,6 +228,9 @@ InstParams derive(const wcsph_params& p) {
   q.p_cav = (float)p.p_cav;
   q.alpha = (float)p.alpha;
   q.beta2h2 = (float)(2.0 * p.beta * h * h);
+  q.kernel_type = p.kernel_type;
+  q.kc_sigma = (float)(10.0 / (7.0 * M_PI * h * h));
+  q.kc_a = (float)(10.0 / (7.0 * M_PI * h * h * h * h));
   q.eps_xsph = (float)p.eps_xsph;
   q.gy = (float)p.gravity_y;
   q.two_delta_h_c0 = (float)(2.0 * p.delta * h * p.c0);
@@ -530,9 +534,9 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.diag_part = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_BLOCKS * 8);
   d.wb_part = dalloc_n<double>(c, (size_t)n_inst * WC_MAX_RING);
   c->d_disk = dalloc_n<double>(c, 3);
-  d.qav = 0;
+  d.var = params[0].kernel_type == 1 ? 2 : 0;
   for (int i = 0; i < n_inst; ++i)
-    if (params[i].beta > 0) d.qav = 1;
+    if (params[i].beta > 0) d.var |= 1;
   c->audit = !c->batch && params[0].audit != 0;
   d.audit_part = c->audit ? dalloc_n<double>(c, (size_t)wc_pair_blocks(c->n_slots) * 6) : nullptr;
   d.n_vpart = wc_pair_blocks(c->n_slots);
@@ -595,6 +599,8 @@ wcsph_status create_impl(const wcsph_params* params, int n_inst, const wcsph_all
       require(params[i].diag_every == params[0].diag_every, "batched instances share diag_every");
     if (batch)
       for (int i = 0; i < n_inst; ++i) require(params[i].audit == 0, "the energy audit needs a single-instance context");
+    for (int i = 1; i < n_inst; ++i)
+      require(params[i].kernel_type == params[0].kernel_type, "batched instances share the kernel");
   } catch (const WcError& e) {
     g_create_error = e.msg;
     return e.st;
@@ -1279,6 +1285,7 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   require(ctx->hp[0].kin_mode != 2 || ctx->hp[0].nd == 0,
           "the reverse sweep needs a prescribed disk motion (kin_mode 0 or 1)");
   require(ctx->pin[0].beta == 0, "the reverse sweep supports the linear artificial viscosity only (beta = 0)");
+  require(ctx->pin[0].kernel_type == 0, "the reverse sweep supports the Wendland C2 kernel only");
   require(n_steps >= 1 && ckpt_every >= 1, "n_steps and ckpt_every must be >= 1");
   const long long k0 = ctx->steps - ctx->d.dt_step0;
   require(ctx->d.n_dt > 0 && k0 >= 0 && k0 + n_steps <= ctx->d.n_dt,

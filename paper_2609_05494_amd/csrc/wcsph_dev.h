@@ -37,6 +37,8 @@ struct InstParams {
   float h, inv_h, four_h2, sigma, fgrad, eta2h2;
   float rho0, c0, B, p_cav, alpha, eps_xsph, gy;
   float beta2h2;  // 2 beta h^2: quadratic AV term beta mu^2 / rho_bar (0: linear term only)
+  int kernel_type;       // 0 Wendland C2, 1 cubic B-spline
+  float kc_sigma, kc_a;  // cubic spline: 10 / (7 pi h^2) and that over h^2
   float two_delta_h_c0, four_nu0, delta, two_h_c0;
   float m_fluid, m_wall, m_disk;
   float rho_lo, rho_hi, inv_rho0c02, c_exp, gamma, inv_gamma;
@@ -120,7 +122,7 @@ struct Dev {
   float* vmax_part;           // single instance: per corrector pair block, max |v| of its new fluid
                               // state (folded into the clock by the next first-evaluation sort)
   int n_vpart;                // entries of vmax_part (pair blocks)
-  int qav;                    // some instance has beta > 0: the pair pass carries the quadratic AV term
+  int var;                    // pair-pass variant: bit 0 quadratic AV (some beta > 0), bit 1 cubic spline
   double* audit_part;         // energy audit (single instance, or NULL): per corrector pair block,
                               // running sums of d_av, d_visc, w_delta, w_ghost, w_enforce, w_clamp
   float* xr;                  // export: [5][n_slots] rates per slot

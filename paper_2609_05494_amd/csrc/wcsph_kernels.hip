@@ -130,6 +130,24 @@ __device__ __forceinline__ void wendland(const PP& P, float r2, float& W, float&
   F = -P.fgrad * s2 * s;
 }
 
+// Cubic B-spline of eq. cubic-kernel in 2D (the paper's kernel), sigma_c =
+// 10 / (7 pi h^2): W = sigma_c (1 - 3/2 q^2 + 3/4 q^3) for q <= 1 and
+// sigma_c (2 - q)^3 / 4 for 1 < q < 2; F = (1/r) dW/dr = (sigma_c / h^2)
+// (9/4 q - 3) inside, -(3/4)(sigma_c / h^2)(2 - q)^2 / q outside.
+template <class PP>
+__device__ __forceinline__ void cubic_spline(const PP& P, float r2, float& W, float& F) {
+  const float q = fast_sqrt(r2) * P.inv_h;
+  const float s = 2.0f - q;
+  const bool in = q <= 1.0f;
+  const float w_in = P.kc_sigma * (1.0f + q * q * (0.75f * q - 1.5f));
+  const float f_in = P.kc_a * (2.25f * q - 3.0f);
+  const float w_out = 0.25f * P.kc_sigma * s * s * s;
+  const float f_out = -0.75f * P.kc_a * s * s * fast_rcp(in ? 1.0f : q);
+  W = in ? w_in : w_out;
+  F = in ? f_in : f_out;
+}
+
+
 __device__ __forceinline__ void cell_xy(const InstParams& P, uint32_t K, int& cx, int& cy) {
   const int local = (int)K - P.cell_off;
   cy = local / P.ncx;
@@ -284,12 +302,14 @@ __device__ __forceinline__ uint32_t dx_code(uint32_t j, const RowRange& r) {
 // (symmetric form), laminar (Lo-Shao), XSPH. Branch-free: a ghost neighbour
 // (m < 0) contributes nothing to the delta and XSPH terms through m_fl = 0,
 // and the AV switch is min(v_ij . r_ij, 0).
-template <bool AUD, bool QAV, class PP>
+// VAR: bit 0 the quadratic AV term, bit 1 the cubic spline kernel.
+template <bool AUD, int VAR, class PP>
 __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float rhoi, float Pi,
                                           float ci, float rx, float ry, float r2, const float4& pj,
                                           const float4& aj, PairAcc& acc, AudAcc& aud) {
   float W, F;
-  wendland(P, r2, W, F);
+  if constexpr ((VAR & 2) != 0) cubic_spline(P, r2, W, F);
+  else wendland(P, r2, W, F);
   const float vxij = pi.z - pj.z, vyij = pi.w - pj.w;
   const float vr = vxij * rx + vyij * ry;
   const float mj = fabsf(aj.w);
@@ -301,7 +321,7 @@ __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float r
   const float vrm = fminf(vr, 0.0f);
   float piav = -P.alpha * P.h * (ci + aj.z) * vrm * inv;
   // quadratic term beta mu^2 / rho_bar = 2 beta h^2 vr^2 / ((r^2 + eta^2 h^2)^2 2 rho_bar)
-  if constexpr (QAV) piav += P.beta2h2 * vrm * vrm * inv * (rsum * inv);
+  if constexpr ((VAR & 1) != 0) piav += P.beta2h2 * vrm * vrm * inv * (rsum * inv);
   const float mF = mj * F;
   // continuity + delta diffusion 2 delta h c0 (m_j / rho_j)(rho_i - rho_j) F (fluid pairs)
   const float dd = P.two_delta_h_c0 * mfl * fast_rcp(aj.x) * (rhoi - aj.x) * F;
@@ -351,6 +371,7 @@ __device__ __forceinline__ float slot_sum(float v) {
 // (the list stores below would otherwise force them to be reloaded).
 struct PairC {
   float dc, four_h2, inv_h, sigma, fgrad, alpha, h, eta2h2, two_delta_h_c0, four_nu0, eps_xsph, beta2h2;
+  float kc_sigma, kc_a;
 };
 __device__ __forceinline__ PairC pair_c(const InstParams& P) {
   PairC c;
@@ -366,6 +387,8 @@ __device__ __forceinline__ PairC pair_c(const InstParams& P) {
   c.four_nu0 = P.four_nu0;
   c.eps_xsph = P.eps_xsph;
   c.beta2h2 = P.beta2h2;
+  c.kc_sigma = P.kc_sigma;
+  c.kc_a = P.kc_a;
   return c;
 }
 
@@ -402,7 +425,7 @@ __device__ __forceinline__ void wave_sync() {
 // the pair law over the list. A lane's candidate order and every operand
 // of a pair depend on the particle and its neighbours only, not on the
 // other slots of the wave.
-template <bool BATCH, bool AUD, bool QAV>
+template <bool BATCH, bool AUD, int VAR>
 __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int s, int inst, uint32_t K,
                                                bool fluid, float4 pi, float4 ai, int q, float4* U,
                                                uint8_t* my, PairAcc& acc, AudAcc& aud) {
@@ -469,7 +492,7 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
     auto body = [&](const float4& E, const float4& pj, const float4& aj) __attribute__((always_inline)) {
       const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
       const float ry = pi.y - E.y;
-      pair_body<AUD, QAV>(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc, aud);
+      pair_body<AUD, VAR>(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc, aud);
     };
     auto flush = [&]() __attribute__((always_inline)) {
       if (cnt > 0) {
@@ -607,7 +630,7 @@ __device__ __forceinline__ double group_sum(double v) {
 struct Shep {
   float W, p, rx, ry, vx, vy;
 };
-template <int G>
+template <int G, bool CUB>
 __device__ __forceinline__ Shep shepard(const Dev& d, const InstParams& P, const Buf& sb, uint32_t K, float ox,
                                         float oy, int lane) {
   Shep S = {0, 0, 0, 0, 0, 0};
@@ -617,7 +640,8 @@ __device__ __forceinline__ Shep shepard(const Dev& d, const InstParams& P, const
     const float r2 = rx * rx + ry * ry;
     if (!(aj.w > 0.0f) || !(r2 < P.four_h2)) return;  // fluid in support only
     float W, F;
-    wendland(P, r2, W, F);
+    if constexpr (CUB) cubic_spline(P, r2, W, F);
+    else wendland(P, r2, W, F);
     const float pj_ = aj.y * aj.x * aj.x;  // p = P rho^2
     S.W += W;
     S.p += pj_ * W;
@@ -1020,7 +1044,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
 // table entry: (instance, first item, item count, kind); kind 0 wall ghosts,
 // 1 ring ghosts, 2 probes.
 #define GL WC_GHOST_LANES
-template <int MODE, bool BATCH>
+template <int MODE, bool BATCH, bool CUB>
 __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(d.sort_epoch, 1u);  // for the next sort
   const int4 blk = d.gblk[blockIdx.x];
@@ -1037,7 +1061,7 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
     // probes: Shepard average of the fluid pressure at fixed wall points
     if (MODE == EV_A && act) {
       const int k = blk.y + item;
-      const Shep S = shepard<GL>(d, P, sb, P.probe_cell[k], P.probe_ox[k], P.probe_oy[k], lane);
+      const Shep S = shepard<GL, CUB>(d, P, sb, P.probe_cell[k], P.probe_ox[k], P.probe_oy[k], lane);
       if (lane == 0) {
         const long long row = (long long)inst * WC_HIST_CAP + (C.step % WC_HIST_CAP);
         d.hist_p[row * WC_MAX_PROBES + k] = S.W > 0.0f ? S.p / S.W : 0.0f;
@@ -1052,7 +1076,7 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
     const uint32_t s = d.gslot[P.gmap0 + g];
     const uint32_t K = d.gcell[P.gmap0 + g];
     const float2 pg = d.gpos[P.gmap0 + g];
-    const Shep S = shepard<GL>(d, P, sb, K, pg.x, pg.y, lane);
+    const Shep S = shepard<GL, CUB>(d, P, sb, K, pg.x, pg.y, lane);
     const float vwx = disk ? (float)C.vd : 0.0f;
     const float awx = disk ? (float)C.ad : 0.0f;
     float p, vgx, vgy;
@@ -1092,7 +1116,8 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
         const float r2 = rx * rx + ry * ry;
         if (!(r2 < P.four_h2)) return;
         float W, F;
-        wendland(P, r2, W, F);
+        if constexpr (CUB) cubic_spline(P, r2, W, F);
+        else wendland(P, r2, W, F);
         const float vr = (pj.z - vgx) * rx + (pj.w - vgy) * ry;
         const float rsum = aj.x + rg, den = r2 + P.eta2h2;
         const float inv = fast_rcp(den * rsum);
@@ -1141,7 +1166,7 @@ __device__ __forceinline__ double tait_e_el(const InstParams& P, double r) {
                         : P.diag_erc + P.p_cavd * (1.0 / P.diag_rc - 1.0 / r);
 }
 
-template <int MODE, bool BATCH, bool AUD, bool QAV>
+template <int MODE, bool BATCH, bool AUD, int VAR>
 #ifdef PAIR_MINW
 __global__ __launch_bounds__(PAIR_BLOCK, PAIR_MINW) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
 #else
@@ -1180,7 +1205,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     }
     PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     AudAcc aud = {0.0f, 0.0f, 0.0f, 0.0f};
-    pair_sums_wave<BATCH, AUD, QAV>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6],
+    pair_sums_wave<BATCH, AUD, VAR>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6],
                                     lst + threadIdx.x, acc, aud);
     // fixed-order combination of the slot's lane partial sums
     acc.D = slot_sum(acc.D);
@@ -1629,11 +1654,24 @@ __global__ __launch_bounds__(WC_BLOCK) void k_neigh(Dev d, Buf sb) {
 #define NQ(n) (((n) + PAIR_SLOTS - 1) / PAIR_SLOTS)
 int wc_pair_blocks(int n_slots) { return NQ(n_slots); }
 
-// The pair pass with the quadratic AV term when some instance has beta > 0.
+// The ghost pass with the context's kernel.
+template <int MODE, bool BATCH>
+static void launch_ghost(const Dev& d, int n_gblk, const Buf& sb, hipStream_t st) {
+  if (d.var & 2) k_ghost<MODE, BATCH, true><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, sb);
+  else k_ghost<MODE, BATCH, false><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, sb);
+}
+
+// The pair pass of the context's scheme variant: bit 0 the quadratic AV
+// term (some instance has beta > 0), bit 1 the cubic spline kernel.
 template <int MODE, bool BATCH, bool AUD = false>
 static void launch_pair(const Dev& d, const Buf& sb, const Buf& base, const Buf& out, hipStream_t st) {
-  if (d.qav) k_pair<MODE, BATCH, AUD, true><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, sb, base, out);
-  else k_pair<MODE, BATCH, AUD, false><<<NQ(d.n_slots), PAIR_BLOCK, 0, st>>>(d, sb, base, out);
+  const dim3 g(NQ(d.n_slots)), b(PAIR_BLOCK);
+  switch (d.var) {
+    case 0: k_pair<MODE, BATCH, AUD, 0><<<g, b, 0, st>>>(d, sb, base, out); break;
+    case 1: k_pair<MODE, BATCH, AUD, 1><<<g, b, 0, st>>>(d, sb, base, out); break;
+    case 2: k_pair<MODE, BATCH, AUD, 2><<<g, b, 0, st>>>(d, sb, base, out); break;
+    default: k_pair<MODE, BATCH, AUD, 3><<<g, b, 0, st>>>(d, sb, base, out); break;
+  }
 }
 
 template <bool BATCH>
@@ -1647,10 +1685,10 @@ static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, co
 template <bool BATCH>
 static void enqueue_step_t(const Dev& d, const Bufs& b, int n_gblk, bool two_way, bool audit, hipStream_t st) {
   eval_sort<BATCH>(d, st, EV_A, b.X, b.Y);
-  k_ghost<EV_A, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
+  launch_ghost<EV_A, BATCH>(d, n_gblk, b.Y, st);
   launch_pair<EV_A, BATCH>(d, b.Y, b.Y, b.Z, st);
   eval_sort<BATCH>(d, st, EV_B, b.Z, b.W);
-  k_ghost<EV_B, BATCH><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.W);
+  launch_ghost<EV_B, BATCH>(d, n_gblk, b.W, st);
   if (two_way) k_disk<<<d.n_inst, 64, 0, st>>>(d);
   if (!BATCH && audit) launch_pair<EV_B, false, true>(d, b.W, b.Y, b.X, st);
   else launch_pair<EV_B, BATCH>(d, b.W, b.Y, b.X, st);
@@ -1683,7 +1721,7 @@ void wc_enqueue_export_sort(const Dev& d, const Bufs& b, bool batch, hipStream_t
 }
 
 void wc_enqueue_export_ghosts(const Dev& d, const Bufs& b, int n_gblk, hipStream_t st) {
-  k_ghost<EV_EXPORT, false><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
+  launch_ghost<EV_EXPORT, false>(d, n_gblk, b.Y, st);
 }
 
 void wc_enqueue_export_pair(const Dev& d, const Bufs& b, hipStream_t st) {
@@ -1702,11 +1740,11 @@ void wc_enqueue_neigh(const Dev& d, const Bufs& b, hipStream_t st) {
 void wc_enqueue_eval(const Dev& d, const Bufs& b, int n_gblk, int mode, hipStream_t st) {
   if (mode == EV_A) {
     eval_sort<false>(d, st, EV_A, b.X, b.Y);
-    k_ghost<EV_A, false><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.Y);
+    launch_ghost<EV_A, false>(d, n_gblk, b.Y, st);
     launch_pair<EV_A, false>(d, b.Y, b.Y, b.Z, st);
   } else {
     eval_sort<false>(d, st, EV_B, b.Z, b.W);
-    k_ghost<EV_B, false><<<n_gblk, WC_GHOST_BLOCK, 0, st>>>(d, b.W);
+    launch_ghost<EV_B, false>(d, n_gblk, b.W, st);
     launch_pair<EV_B, false>(d, b.W, b.Y, b.X, st);
   }
 }
