@@ -11,7 +11,9 @@
   accelerated disk with the cavitation cutoff lifted (force of the added
   mass pi R^2 rho0 dU/dt within [0.8, 1.8] of the potential-flow value, the
   surface pressure shaped as rho0 R dU/dt cos(theta) + rho0 U^2 (1/2 - 2
-  sin^2(theta))); both bars are the oracle's own (coarse lattice).
+  sin^2(theta))); both bars are the oracle's own (coarse lattice); and a
+  planar pressure pulse reflected at the rigid ghost wall (R = 1 and twice
+  the incident pressure on the wall, within 3 %).
 """
 import math
 
@@ -20,6 +22,7 @@ import pytest
 
 import oracle
 import workloads
+from tests.test_oracle_physics import _pulse_case, pulse_reflection
 
 pytestmark = pytest.mark.gpu
 
@@ -132,3 +135,16 @@ def test_accelerated_disk_added_mass():
     print(f"surface pressure: correlation {corr:.3f}, projection {ratio:.3f}")
     assert corr > 0.9
     assert 0.8 < ratio < 1.5
+
+
+def test_rigid_wall_reflects_a_pressure_pulse():
+    cfg, init, n, t_wall = _pulse_case()
+    s = _solver(cfg)
+    x, y, vx, vy, rho = init.T
+    s.set_fluid(0.0, x, y, vx, vy, rho)
+    s.step(n)
+    t, _, p = s.read_probes()
+    s.close()
+    R, wall = pulse_reflection(t, p.astype(np.float64), t_wall)
+    print(f"R = {R:.4f}, wall / (2 incident) = {wall:.4f}")
+    assert abs(R - 1.0) <= 0.03 and abs(wall - 1.0) <= 0.03

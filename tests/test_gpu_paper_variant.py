@@ -81,3 +81,32 @@ def test_cubic_batch_equals_single_runs():
 def test_mixed_kernels_in_a_batch_rejected():
     with pytest.raises(wc.WcsphError):
         wc.Solver([workloads.tiny(), dict(workloads.tiny(), kernel_type=1)], "cuda:0")
+
+
+def test_paper_geometry_matches_oracle():
+    """The paper's 750x150 mm channel at dx = 1.5 mm with its kernel and
+    single-line walls, 300 steps (the pulse has reached the near station):
+    probe histories within 1e-3 of the largest probe peak."""
+    cfg = workloads.paper_geometry()
+    n = 300
+    print(f"[gpu] paper geometry, {n} steps", flush=True)
+    s = wc.Solver(cfg, "cuda:0")
+    assert s.nf == 49947
+    s.step(n)
+    _, dtg, pg = s.read_probes()
+    dg = s.read_diagnostics()
+    s.close()
+    o = oracle.Oracle(cfg)
+    o.step(n)
+    _, dto, po = o.probes()
+    do = o.diags()
+    assert np.abs(dtg / dto - 1).max() < 1e-5
+    scale = np.abs(po).max()
+    assert scale > 1e5  # the near station has seen the pulse
+    for k in range(po.shape[1]):
+        err = np.abs(pg[:, k] - po[:, k]).max() / scale
+        print(f"probe {k}: max err {err:.3e} of the largest peak")
+        assert err <= 1e-3
+    assert np.abs(dg["mass"] - dg["mass"][0]).max() <= 1e-12 * dg["mass"][0]
+    for k in ("ke", "e_el", "w_boundary"):
+        assert abs(dg[k][-1] - do[k][-1]) <= 1e-3 * abs(do[k][-1]), k

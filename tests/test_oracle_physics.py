@@ -4,6 +4,8 @@ protocols, run where they can discriminate).
 * Hydrostatic column at reduced c0 (Verification Status: a reduced sound
   speed makes the static check meaningful): wall probes and interior
   pressure follow rho0 |g| (H - y).
+* A planar pressure pulse reflected at the rigid ghost wall (reflection
+  coefficient 1 in the limit of an infinite wall impedance).
 * Impulsively accelerated disk without the cavitation cutoff and without
   artificial viscosity (Verification Protocols, eq. sphere-analytical):
   the ring's surface pressure follows rho0 R dU/dt cos(theta) and the force
@@ -71,3 +73,44 @@ def test_accelerated_disk_added_mass_sign_and_shape(golden):
     ref = 1000 * R * Ud * np.cos(th) + 1000 * v * v * (0.5 - 2 * np.sin(th) ** 2)
     assert np.corrcoef(gp, ref)[0, 1] > 0.9
     assert 0.8 < (gp @ ref) / (ref @ ref) < 1.5
+
+
+def _pulse_case():
+    """A planar pressure pulse running toward the bottom wall of a 10x100 mm
+    column at reduced c0 (no gravity, no artificial viscosity or delta
+    term), probes at y = 40 mm (centre line) and on the bottom wall."""
+    c0, H, L, dx = 50.0, 0.1, 0.01, 0.5e-3
+    cfg = workloads.base(L, H, dx, 0.0, 0.0, c0=c0, alpha=0.0, delta=0.0)
+    cfg.update(disk_R=0.0, n_disk_ghosts=0, gravity_y=0.0, mu_dyn=0.0, diag_every=0, p_cav=-1e9,
+               probes=[(0.5 * L, 0.04), (0.5 * L, 0.0)])
+    o = oracle.Oracle(cfg)
+    _, (x, y, _, _, _) = o.fluid()
+    eps, y0, sw = 1e-3, 0.08, 5e-3
+    g = np.exp(-0.5 * ((y - y0) / sw) ** 2)
+    # a simple wave moving toward -y: v = -c0 (rho - rho0) / rho0
+    init = np.stack([x, y, np.zeros_like(x), -c0 * eps * g, 1000.0 * (1.0 + eps * g)], 1)
+    h = cfg["h_over_dx"] * dx
+    n = int((y0 + 0.05) / c0 / (0.2 * h / (c0 * (1 + eps))))
+    return cfg, init, n, y0 / c0
+
+
+def pulse_reflection(t, p, t_wall):
+    """Incident and reflected peaks at the interior probe, and the wall
+    probe's peak over twice the incident one."""
+    a = p[:, 0]
+    inc, ref = a[t < t_wall].max(), a[t > t_wall].max()
+    return ref / inc, p[:, 1].max() / (2.0 * inc)
+
+
+def test_rigid_wall_reflects_a_pressure_pulse():
+    """Acoustic reflection at the Adami ghost wall (Verification Protocols,
+    the reflection coefficient R = (Z2 - Z1) / (Z2 + Z1)): the ghost wall is
+    rigid, Z2 -> infinity, so R = 1 and the wall sees twice the incident
+    pressure, within 3 %."""
+    cfg, init, n, t_wall = _pulse_case()
+    o = oracle.Oracle(cfg, init=init)
+    o.step(n)
+    t, _, p = o.probes()
+    R, wall = pulse_reflection(t, p, t_wall)
+    print(f"R = {R:.4f}, wall / (2 incident) = {wall:.4f}")
+    assert abs(R - 1.0) <= 0.03 and abs(wall - 1.0) <= 0.03

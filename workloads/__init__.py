@@ -89,6 +89,17 @@ def two_way(cfg: dict) -> dict:
     return dict(cfg, kin_mode=2, disk_mass=rho_p * math.pi * cfg["disk_R"] ** 2)
 
 
+def paper_geometry(v0: float = 900.0) -> dict:
+    """The paper's own channel (Validation Problem Setup): 750x150 mm at
+    dx = 1.5 mm, a disk of the projectile's radius 6.25 mm, probes at the PTn
+    and PTf stations x = 30 and 105 mm on both walls, with the paper's cubic
+    B-spline kernel, alpha = 0.03 and single-line wall ghosts. Density
+    (continuity with delta), EOS (Tait) and the update (predictor-corrector)
+    stay those of the hot path."""
+    cfg = base(0.750, 0.150, 1.5e-3, PROJ_RADIUS, v0, alpha=0.03, probes_x=(0.030, 0.105), steps=2000)
+    return dict(cfg, kernel_type=1, ghost_layers=1)
+
+
 def C2() -> dict:
     """300x150 mm, dx = 0.5 mm (179,552 fluid), R = 6 mm, 900 m/s, 2,000 steps,
     four wall probes at the PTn / PTf stations x = 30 and 105 mm."""
