@@ -277,6 +277,41 @@ def qav_run(wc, workloads, steps: int, prescribed_value: float, beta: float = 1.
                 probe_peak_pa=float(np.abs(p).max()), unstable=unstable)
 
 
+def paper_production_run(wc, workloads, t_end: float = 150e-6):
+    """The paper's production case in its own geometry (750x150 mm channel,
+    dx = 1.5 mm, 49,947 fluid, 900 m/s) with the paper's kernel, alpha and
+    single-line walls, simulated to 150 us as the paper's run was; the
+    paper's wall clock for that run (0.23 min on a TITAN RTX with its own
+    scheme: summation density, Mie-Grueneisen EOS, leapfrog) is context."""
+    import torch
+    cfg = workloads.paper_geometry()
+    s = wc.Solver(cfg, "cuda:0")
+    blob = s.save_state()
+    s.step(20)
+    s.synchronize()
+    s.load_state(blob)
+    s.read_probes()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    while s.fluid()[0] < t_end:
+        s.step(100)
+        steps += 100
+    s.synchronize()
+    el = time.perf_counter() - t0
+    t_sim = s.fluid()[0]
+    _, _, p = s.read_probes()
+    nf = s.nf
+    unstable = bool(s.read_diagnostics().get("unstable", False))
+    s.close()
+    return dict(workload="750x150 mm channel, dx 1.5 mm, 49,947 fluid, 900 m/s, cubic spline kernel, "
+                         "alpha 0.03, single-line walls, to 150 us",
+                steps=steps, simulated_us=round(t_sim * 1e6, 3), wall_s=round(el, 4),
+                value=nf * steps / el, unit="fluid particle-steps/s", ms_per_step=round(el / steps * 1e3, 5),
+                paper_wall_s=13.8, paper_hardware="NVIDIA TITAN RTX, Numba-CUDA, the paper's own scheme",
+                probe_peak_pa=float(np.abs(p).max()), unstable=unstable)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +329,8 @@ def main():
                     help="steps of the energy-audit run (0 skips it)")
     ap.add_argument("--qav-steps", type=int, default=2000,
                     help="steps of the quadratic-viscosity run (0 skips it)")
+    ap.add_argument("--paper-run", type=int, default=1,
+                    help="1: time the paper's production case to 150 us (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel "
                          "of known traffic for hardware-counter runs)")
@@ -359,6 +396,7 @@ def main():
     two_way = two_way_run(wc, workloads, args.two_way_steps, value) if args.two_way_steps > 0 else None
     audit = audit_run(wc, workloads, args.audit_steps, value) if args.audit_steps > 0 else None
     qav = qav_run(wc, workloads, args.qav_steps, value) if args.qav_steps > 0 else None
+    paper = paper_production_run(wc, workloads) if args.paper_run else None
     cpu = None if args.no_cpu else cpu_baseline(cfg)
     out = {
         "metric": "WCSPH fluid particle-steps/s at 180k particles",
@@ -384,6 +422,7 @@ def main():
         "two_way": two_way,
         "energy_audit": audit,
         "quadratic_av": qav,
+        "paper_production_run": paper,
         "unstable": unstable,
         "probe_peak_pa": float(np.abs(p).max()) if p.size else None,
     }
