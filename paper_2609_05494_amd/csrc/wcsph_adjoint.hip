@@ -109,16 +109,14 @@ __device__ __forceinline__ GhostD ghost_d(const InstParams& P, float p) {
 
 }  // namespace
 
-// Transpose of the update + enforcement of one evaluation for every fluid
-// particle (by id). lam_out: adjoint of the evaluation's output state
+// Transpose of the update + enforcement of one evaluation for fluid particle
+// i (by id). lam_out: adjoint of the evaluation's output state
 // (x, y, vx, vy, rho); pre: pre-enforcement state taped by the forward
 // kernel; te: time of the enforcement; hdt: dt/2 (eval A) or dt (eval B).
-// Writes lam_base (+= when accumulate) and the rate adjoints
-// lam_f = hdt * (lam_pre_rho -> D, lam_pre_v -> a, lam_pre_r -> V).
-__global__ __launch_bounds__(256) void k_adj_enforce(Dev d, AdjPtrs a, double te, float hdt, int accumulate) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const InstParams& P = d.prm[0];
-  if (i >= P.nf) return;
+// Writes lam_base (+= when accumulate) and returns the rate adjoints
+// lf = hdt * (lam_pre_rho -> D, lam_pre_v -> a, lam_pre_r -> V).
+__device__ __forceinline__ void adj_enforce_one(const InstParams& P, const AdjPtrs& a, int i, double te, float hdt,
+                                                int accumulate, float* lf) {
   const int n = P.nf;
   float lx = a.lam_out[i], ly = a.lam_out[n + i], lvx = a.lam_out[2 * n + i], lvy = a.lam_out[3 * n + i],
         lr = a.lam_out[4 * n + i];
@@ -183,22 +181,26 @@ __global__ __launch_bounds__(256) void k_adj_enforce(Dev d, AdjPtrs a, double te
     lb[i] = lx; lb[n + i] = ly; lb[2 * n + i] = lvx; lb[3 * n + i] = lvy; lb[4 * n + i] = lr;
   }
   // rates: rho' = rho + h D, v' = v + h a, r' = r + h V
-  a.lam_f[i] = hdt * lr;
-  a.lam_f[n + i] = hdt * lvx;
-  a.lam_f[2 * n + i] = hdt * lvy;
-  a.lam_f[3 * n + i] = hdt * lx;
-  a.lam_f[4 * n + i] = hdt * ly;
+  lf[0] = hdt * lr;
+  lf[1] = hdt * lvx;
+  lf[2] = hdt * lvy;
+  lf[3] = hdt * lx;
+  lf[4] = hdt * ly;
 }
 
-// Rate adjoints (by id) into the sorted slot order of the taped evaluation;
-// zero for ghost slots.
-__global__ __launch_bounds__(256) void k_adj_gather(Dev d, AdjPtrs a, TapeEval te) {
+// The enforcement transpose of every fluid particle, written straight into
+// the sorted slot order of the taped evaluation (each fluid id holds one
+// slot; ghost slots get zero): lam_base by id, the rate adjoints lam_s by
+// slot.
+__global__ __launch_bounds__(256) void k_adj_enforce_gather(Dev d, AdjPtrs a, TapeEval te, double t_enf, float hdt,
+                                                            int accumulate) {
   const int s = blockIdx.x * 256 + threadIdx.x;
   if (s >= d.n_slots) return;
   const InstParams& P = d.prm[0];
   const int id = (int)te.id[s] - P.id0;
-  const bool fl = id >= 0 && id < P.nf;
-  for (int c = 0; c < 5; ++c) a.lam_s[c * d.n_slots + s] = fl ? a.lam_f[c * P.nf + id] : 0.0f;
+  float lf[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (id >= 0 && id < P.nf) adj_enforce_one(P, a, id, t_enf, hdt, accumulate, lf);
+  for (int c = 0; c < 5; ++c) a.lam_s[c * d.n_slots + s] = lf[c];
 }
 
 // The 3x3 block of cells around (cx, cy) in a taped cell list as three row
@@ -384,11 +386,7 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
     }
   }
   const double tot = block_sum(c0bar, shd);
-  if (threadIdx.x == 0) {
-    a.theta_part[(size_t)blockIdx.x * 3 + 0] = 0.0;
-    a.theta_part[(size_t)blockIdx.x * 3 + 1] = 0.0;
-    a.theta_part[(size_t)blockIdx.x * 3 + 2] = tot;
-  }
+  if (threadIdx.x == 0) a.theta_part[(size_t)blockIdx.x * 3 + 2] += tot;
 }
 
 // Fluid adjoints (pull form) for every fluid slot j of the taped
@@ -527,14 +525,15 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
   const double ta = block_sum(th_a, shd), td = block_sum(th_d, shd), tc = block_sum(th_c, shd);
   if (threadIdx.x == 0) {
     double* o = a.theta_part + (size_t)(block0 + blockIdx.x) * 3;
-    o[0] = ta;
-    o[1] = td;
-    o[2] = tc;
+    o[0] += ta;
+    o[1] += td;
+    o[2] += tc;
   }
 }
 
-// theta += sum of the per-block partials (FP64, fixed order: lane l adds
-// blocks l, l + 64, ... in order, then a butterfly over the wave).
+// theta += sum of the per-block running sums (FP64, fixed order: lane l
+// adds blocks l, l + 64, ... in order, then a butterfly over the wave); once,
+// after the reverse sweep.
 __global__ void k_adj_theta(AdjPtrs a, int nblk) {
   if (blockIdx.x != 0) return;
   double t[3];
@@ -553,7 +552,8 @@ __global__ void k_adj_theta(AdjPtrs a, int nblk) {
 
 // ---------------------------------------------------------------------------
 // Backward pass of one evaluation's rates (ghost adjoints, fluid adjoints,
-// coefficient partials). lam_f (by id) -> lam_base (by id).
+// coefficient partials added to each block's running sums). lam_s (by
+// slot) -> lam_base (by id).
 static int adj_ghost_blocks(int n_ghost_probe) { return (n_ghost_probe * AG_L + 255) / 256; }
 static int adj_fluid_blocks(int n_slots) { return (n_slots * ADJ_FG + 255) / 256; }
 
@@ -563,18 +563,15 @@ int wc_adj_partial_blocks(int n_ghost_probe, int n_slots) {
 
 void wc_enqueue_adj_rates(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_eval, float probe_seed,
                           bool accumulate, hipStream_t st) {
-  const InstParams* P = nullptr;
-  (void)P;
-  const int ns = (d.n_slots + 255) / 256;
-  k_adj_gather<<<ns, 256, 0, st>>>(d, a, te);
   const int ngb = adj_ghost_blocks(a.n_ghost_probe);
   k_adj_ghost<<<ngb, 256, 0, st>>>(d, a, te, t_eval, ngb);
   const int nfb = adj_fluid_blocks(d.n_slots);
   k_adj_fluid<<<nfb, 256, 0, st>>>(d, a, te, probe_seed, accumulate ? 1 : 0, ngb);
-  k_adj_theta<<<1, 64, 0, st>>>(a, ngb + nfb);
 }
 
-void wc_enqueue_adj_enforce(const Dev& d, const AdjPtrs& a, int nf, double te, float hdt, bool accumulate,
-                            hipStream_t st) {
-  k_adj_enforce<<<(nf + 255) / 256, 256, 0, st>>>(d, a, te, hdt, accumulate ? 1 : 0);
+void wc_enqueue_adj_theta(const AdjPtrs& a, int nblk, hipStream_t st) { k_adj_theta<<<1, 64, 0, st>>>(a, nblk); }
+
+void wc_enqueue_adj_enforce_gather(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_enf, float hdt,
+                                   bool accumulate, hipStream_t st) {
+  k_adj_enforce_gather<<<(d.n_slots + 255) / 256, 256, 0, st>>>(d, a, te, t_enf, hdt, accumulate ? 1 : 0);
 }

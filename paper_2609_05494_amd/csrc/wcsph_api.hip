@@ -1349,7 +1349,6 @@ wcsph_status wcsph_adj_backward(wcsph_ctx* ctx, double dJ, double* grad) {
     A.L0 = dalloc_n<float>(ctx, (size_t)5 * nf);
     A.L1 = dalloc_n<float>(ctx, (size_t)5 * nf);
     A.Ls = dalloc_n<float>(ctx, (size_t)5 * nf);
-    A.a.lam_f = dalloc_n<float>(ctx, (size_t)5 * nf);
     A.a.lam_s = dalloc_n<float>(ctx, (size_t)5 * ctx->n_slots);
     A.a.gadj = dalloc_n<float>(ctx, (size_t)10 * ctx->n_slots);
     A.a.padj = dalloc_n<float>(ctx, 2 * WC_MAX_PROBES);
@@ -1360,6 +1359,7 @@ wcsph_status wcsph_adj_backward(wcsph_ctx* ctx, double dJ, double* grad) {
   }
   HC(hipMemsetAsync(A.L1, 0, (size_t)5 * nf * 4, ctx->st));
   HC(hipMemsetAsync(A.a.theta, 0, 3 * 8, ctx->st));
+  HC(hipMemsetAsync(A.a.theta_part, 0, (size_t)3 * A.nblk * 8, ctx->st));
   const long long steps_after = ctx->steps;
   for (int g = A.n_seg - 1; g >= 0; --g) {
     const int n = std::min(A.ckpt, A.n_steps - g * A.ckpt);
@@ -1374,7 +1374,7 @@ wcsph_status wcsph_adj_backward(wcsph_ctx* ctx, double dJ, double* grad) {
       a.lam_base = A.L0;
       a.pre_pos = A.pB[k];
       a.pre_vel = A.vB[k];
-      wc_enqueue_adj_enforce(ctx->d, a, nf, t + dt, (float)dt, false, ctx->st);
+      wc_enqueue_adj_enforce_gather(ctx->d, a, A.tB[k], t + dt, (float)dt, false, ctx->st);
       a.lam_base = A.Ls;
       wc_enqueue_adj_rates(ctx->d, a, A.tB[k], t + 0.5 * dt, 0.0f, false, ctx->st);
       // predictor: U* = E_A(U^n + dt/2 f(U^n)); probes of step n
@@ -1382,12 +1382,14 @@ wcsph_status wcsph_adj_backward(wcsph_ctx* ctx, double dJ, double* grad) {
       a.lam_base = A.L0;
       a.pre_pos = A.pA[k];
       a.pre_vel = A.vA[k];
-      wc_enqueue_adj_enforce(ctx->d, a, nf, t + 0.5 * dt, (float)(0.5 * dt), true, ctx->st);
+      wc_enqueue_adj_enforce_gather(ctx->d, a, A.tA[k], t + 0.5 * dt, (float)(0.5 * dt), true, ctx->st);
       wc_enqueue_adj_rates(ctx->d, a, A.tA[k], t, (float)(dJ * dt), true, ctx->st);
       HC(hipGetLastError());
       std::swap(A.L0, A.L1);
     }
   }
+  wc_enqueue_adj_theta(A.a, A.nblk, ctx->st);
+  HC(hipGetLastError());
   // back to the state at the end of the forward run
   ckpt_copy(ctx, A.ckpt_dev[A.n_seg], false);
   ctx->steps = steps_after;

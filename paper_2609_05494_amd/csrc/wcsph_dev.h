@@ -147,13 +147,12 @@ struct TapeEval {
 struct AdjPtrs {
   float* lam_out;      // [5][nf] adjoint of the evaluation's output state (x, y, vx, vy, rho)
   float* lam_base;     // [5][nf] adjoint of the base / evaluated state
-  float* lam_f;        // [5][nf] rate adjoints (D, ax, ay, Vx, Vy)
   float* lam_s;        // [5][n_slots] rate adjoints in sorted slot order
   float* gadj;         // [n_slots][10] ghost adjoint and Shepard data
   float* padj;         // [16][2] probe Shepard sums
   double2* pre_pos;    // taped pre-enforcement state of the evaluation
   float4* pre_vel;
-  double* theta_part;  // per-block partial coefficient gradients [blocks][3]
+  double* theta_part;  // per-block running sums of the coefficient gradients over the sweep [blocks][3]
   double* theta;       // dJ/d(alpha, delta, c0), FP64
   int n_ghost_probe;
 };

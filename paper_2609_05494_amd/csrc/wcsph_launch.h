@@ -35,5 +35,8 @@ int wc_pair_blocks(int n_slots);
 int wc_adj_partial_blocks(int n_ghost_probe, int n_slots);
 void wc_enqueue_adj_rates(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_eval, float probe_seed,
                           bool accumulate, hipStream_t st);
-void wc_enqueue_adj_enforce(const Dev& d, const AdjPtrs& a, int nf, double te, float hdt, bool accumulate,
-                            hipStream_t st);
+// the enforcement transpose of one evaluation, written into the taped slot order
+void wc_enqueue_adj_enforce_gather(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_enf, float hdt,
+                                   bool accumulate, hipStream_t st);
+// theta += the per-block running sums of the coefficient partials (after the sweep)
+void wc_enqueue_adj_theta(const AdjPtrs& a, int nblk, hipStream_t st);
