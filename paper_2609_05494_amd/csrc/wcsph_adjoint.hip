@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void k_adj_enforce_gather(Dev d, AdjPtrs a, Ta
   const int id = (int)te.id[s] - P.id0;
   float lf[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   if (id >= 0 && id < P.nf) adj_enforce_one(P, a, id, t_enf, hdt, accumulate, lf);
-  for (int c = 0; c < 5; ++c) a.lam_s[c * d.n_slots + s] = lf[c];
+  reinterpret_cast<float4*>(a.lam_s)[s] = make_float4(lf[0], lf[1], lf[2], lf[3]);
+  a.lam_s[4 * d.n_slots + s] = lf[4];
 }
 
 // The 3x3 block of cells around (cx, cy) in a taped cell list as three row
@@ -300,7 +301,8 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
       in.ra = aj.x; in.rb = ag.x; in.Pa = aj.y; in.Pb = ag.y; in.ca = aj.z; in.cb = ag.z;
       in.mb = mg; in.fl = 0.0f;
       PairGrad<float> g;
-      pair_vjp(in, k, ls[j], ls[N + j], ls[2 * N + j], ls[3 * N + j], ls[4 * N + j], g, d_sqrt);
+      const float4 lj = reinterpret_cast<const float4*>(ls)[j];
+      pair_vjp(in, k, lj.x, lj.y, lj.z, lj.w, ls[4 * N + j], g, d_sqrt);
       gr += g.rb;
       gP += g.P;
       gc += g.c;
@@ -412,7 +414,8 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
       const float4 pi = te.pv[s];
       const uint32_t K = te.cell[s];
       const float* ls = a.lam_s;
-      const float lD = ls[s], lax = ls[N + s], lay = ls[2 * N + s], lVx = ls[3 * N + s], lVy = ls[4 * N + s];
+      const float4 l4 = reinterpret_cast<const float4*>(ls)[s];
+      const float lD = l4.x, lax = l4.y, lay = l4.z, lVx = l4.w, lVy = ls[4 * N + s];
       const EosD<float> ei = eos_d<float>(ai.x, P.rho0, P.c0, P.gamma, P.p_cav, d_pow);
       // the XSPH identity term V = v + ... enters once (lane 0)
       float urx = 0, ury = 0, uvx = g == 0 ? lVx : 0.0f, uvy = g == 0 ? lVy : 0.0f, ur = 0, uP = 0, uc = 0,
@@ -451,7 +454,8 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
           jn.ra = aj.x; jn.rb = ai.x; jn.Pa = aj.y; jn.Pb = ai.y; jn.ca = aj.z; jn.cb = ai.z;
           jn.mb = ai.w; jn.fl = 1.0f;
           PairGrad<float> h;
-          pair_vjp(jn, k, ls[j], ls[N + j], ls[2 * N + j], ls[3 * N + j], ls[4 * N + j], h, d_sqrt);
+          const float4 lj = reinterpret_cast<const float4*>(ls)[j];
+          pair_vjp(jn, k, lj.x, lj.y, lj.z, lj.w, ls[4 * N + j], h, d_sqrt);
           urx -= h.rx; ury -= h.ry; uvx -= h.vx; uvy -= h.vy; ur += h.rb; uP += h.P; uc += h.c;
         } else {
           // ghost j: this particle enters the ghost's Shepard sums

@@ -147,7 +147,7 @@ struct TapeEval {
 struct AdjPtrs {
   float* lam_out;      // [5][nf] adjoint of the evaluation's output state (x, y, vx, vy, rho)
   float* lam_base;     // [5][nf] adjoint of the base / evaluated state
-  float* lam_s;        // [5][n_slots] rate adjoints in sorted slot order
+  float* lam_s;        // rate adjoints in sorted slot order: float4 (D, ax, ay, Vx) [n_slots], then Vy [n_slots]
   float* gadj;         // [n_slots][10] ghost adjoint and Shepard data
   float* padj;         // [16][2] probe Shepard sums
   double2* pre_pos;    // taped pre-enforcement state of the evaluation
