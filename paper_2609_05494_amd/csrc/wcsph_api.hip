@@ -898,15 +898,21 @@ wcsph_status wcsph_read_probes(wcsph_ctx* ctx, int inst, double* t, double* dt, 
   const long long rows = std::min<long long>(ctx->steps - rd, max_rows);
   const int np = ctx->hp[inst].n_probes;
   const size_t base = (size_t)inst * WC_HIST_CAP;
-  std::vector<float> row(WC_MAX_PROBES);
-  for (long long r = 0; r < rows; ++r) {
-    const size_t k = base + (size_t)((rd + r) % WC_HIST_CAP);
-    if (t) HC(hipMemcpy(t + r, ctx->d.hist_t + k, 8, hipMemcpyDeviceToHost));
-    if (dt) HC(hipMemcpy(dt + r, ctx->d.hist_dt + k, 8, hipMemcpyDeviceToHost));
+  // the rows are at most two contiguous runs of the ring
+  std::vector<float> rowbuf;
+  for (long long r = 0; r < rows;) {
+    const size_t k0 = (size_t)((rd + r) % WC_HIST_CAP);
+    const long long run = std::min<long long>(rows - r, (long long)(WC_HIST_CAP - k0));
+    if (t) HC(hipMemcpy(t + r, ctx->d.hist_t + base + k0, (size_t)run * 8, hipMemcpyDeviceToHost));
+    if (dt) HC(hipMemcpy(dt + r, ctx->d.hist_dt + base + k0, (size_t)run * 8, hipMemcpyDeviceToHost));
     if (p && np) {
-      HC(hipMemcpy(row.data(), ctx->d.hist_p + k * WC_MAX_PROBES, WC_MAX_PROBES * 4, hipMemcpyDeviceToHost));
-      std::copy(row.begin(), row.begin() + np, p + r * np);
+      rowbuf.resize((size_t)run * WC_MAX_PROBES);
+      HC(hipMemcpy(rowbuf.data(), ctx->d.hist_p + (base + k0) * WC_MAX_PROBES, rowbuf.size() * 4,
+                   hipMemcpyDeviceToHost));
+      for (long long q = 0; q < run; ++q)
+        std::copy(rowbuf.begin() + q * WC_MAX_PROBES, rowbuf.begin() + q * WC_MAX_PROBES + np, p + (r + q) * np);
     }
+    r += run;
   }
   rd += rows;
   *rows_out = (int)rows;
@@ -921,10 +927,17 @@ wcsph_status wcsph_read_diagnostics(wcsph_ctx* ctx, int inst, wcsph_diag* out, i
   long long& rd = ctx->diag_read[inst];
   if (ctx->diag_rows[inst] - rd > WC_DIAG_CAP) rd = ctx->diag_rows[inst] - WC_DIAG_CAP;
   const long long rows = std::min<long long>(ctx->diag_rows[inst] - rd, max);
-  double v[WC_NDIAG];
+  // the rows are at most two contiguous runs of the ring
+  std::vector<double> all((size_t)rows * WC_NDIAG);
+  for (long long r = 0; r < rows;) {
+    const size_t k0 = (size_t)((rd + r) % WC_DIAG_CAP);
+    const long long run = std::min<long long>(rows - r, (long long)(WC_DIAG_CAP - k0));
+    HC(hipMemcpy(all.data() + (size_t)r * WC_NDIAG, ctx->d.diag + ((size_t)inst * WC_DIAG_CAP + k0) * WC_NDIAG,
+                 (size_t)run * WC_NDIAG * sizeof(double), hipMemcpyDeviceToHost));
+    r += run;
+  }
   for (long long r = 0; r < rows; ++r) {
-    const size_t k = ((size_t)inst * WC_DIAG_CAP + (size_t)((rd + r) % WC_DIAG_CAP)) * WC_NDIAG;
-    HC(hipMemcpy(v, ctx->d.diag + k, sizeof v, hipMemcpyDeviceToHost));
+    const double* v = all.data() + (size_t)r * WC_NDIAG;
     wcsph_diag& o = out[r];
     o.t = v[0];
     o.dt = v[1];
