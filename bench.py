@@ -46,9 +46,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_traffic.json")
 
 
 def kernels_sha256() -> str:
+    """Digest of the kernel source, and of the autotuned scan shapes when
+    there are any (a different shape is a different binary)."""
     import hashlib
+    h = hashlib.sha256()
     with open(KERNELS_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+        h.update(f.read())
+    tuned = os.path.join(os.path.dirname(KERNELS_SRC), "wcsph_tuned.h")
+    if os.path.exists(tuned):
+        with open(tuned, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def pair_traffic():

@@ -1,0 +1,153 @@
+"""Autotuner for the scan shapes of the pair pass (union pass size UCAP, hit
+list length LCAP, candidates per scan step PU).
+
+Every shape sums each particle's pairs in the same order, so every variant
+must give the same state bit for bit; the tuner checks that and keeps the
+fastest. Two phases, because libraries are built on the build host and
+timed on the GPU:
+
+    python -m paper_2609_05494_amd.autotune build DIR
+    python -m paper_2609_05494_amd.autotune time DIR [--workload C4|C2] [--steps N] [--header PATH]
+
+`build` compiles one library per shape into DIR. `time` runs each one in a
+child process on the GPU (the same seeded workload, state reset between
+warm-up and timing), rejects any whose final state differs from the default
+shape's, and writes the winner as wcsph_tuned.h (by default into the
+package's csrc/, where the next build picks it up).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import itertools
+import json
+import os
+import subprocess
+import sys
+
+from . import build as _build
+
+DEFAULT = {"UCAP": 192, "LCAP": 16, "PU": 4}
+# shapes whose LDS and list bounds hold: the byte hit list indexes a pass
+# (UCAP <= 256), a scan step fits the list (PU <= LCAP - PU)
+SPACE = [dict(UCAP=u, LCAP=l, PU=p) for u, l, p in itertools.product((128, 192, 256), (16, 24), (4, 8))]
+HEADER = os.path.join(_build.CSRC, "wcsph_tuned.h")
+REPS = 3
+
+
+def tag(shape: dict) -> str:
+    return "u{UCAP}_l{LCAP}_p{PU}".format(**shape)
+
+
+def valid(shape: dict) -> bool:
+    return 64 <= shape["UCAP"] <= 256 and 1 <= shape["PU"] <= shape["LCAP"] - shape["PU"]
+
+
+def build_variants(out_dir: str) -> list:
+    os.makedirs(out_dir, exist_ok=True)
+    done = []
+    for shape in SPACE:
+        assert valid(shape), shape
+        lib = os.path.join(out_dir, f"libwcsph_{tag(shape)}.so")
+        cmd = _build.command()
+        cmd[cmd.index("-o") + 1] = lib
+        cmd = cmd[:1] + [f"-D{k}={v}" for k, v in shape.items()] + cmd[1:]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stderr[-3000:])
+            raise RuntimeError(f"hipcc failed for {shape}")
+        print(f"built {tag(shape)}", flush=True)
+        done.append(lib)
+    return done
+
+
+def _measure(lib: str, workload: str, steps: int) -> dict:
+    """One library, one workload: ms per step (fastest of REPS runs from the
+    same state) and a digest of the final state."""
+    import time
+    import torch
+    import numpy as np
+    import workloads
+    import paper_2609_05494_amd as wc
+    wc.LIB_PATH = lib
+    cfg = workloads.C4() if workload == "C4" else getattr(workloads, workload)()
+    s = wc.Solver(cfg, "cuda:0")
+    blob = s.save_state()
+    s.step(20)
+    s.synchronize()
+    el = float("inf")
+    for _ in range(REPS):  # the fastest of a few timings of the same run
+        s.load_state(blob)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.synchronize()
+        el = min(el, time.perf_counter() - t0)
+    h = hashlib.sha256()
+    for k in range(s.n_inst):
+        for a in s.fluid(k)[1]:
+            h.update(np.ascontiguousarray(a).tobytes())
+    s.close()
+    return {"ms_per_step": el / steps * 1e3, "digest": h.hexdigest()}
+
+
+def time_variants(lib_dir: str, workload: str = "C4", steps: int = 200, header: str = HEADER) -> dict:
+    results = []
+    root = _build.ROOT
+    for shape in SPACE:
+        lib = os.path.join(lib_dir, f"libwcsph_{tag(shape)}.so")
+        r = subprocess.run([sys.executable, "-m", "paper_2609_05494_amd.autotune", "measure", lib, workload,
+                            str(steps)], capture_output=True, text=True, cwd=root, timeout=300)
+        if r.returncode != 0:
+            sys.stderr.write(r.stderr[-3000:])
+            raise RuntimeError(f"measuring {tag(shape)} failed")
+        m = json.loads(r.stdout.strip().splitlines()[-1])
+        m["shape"] = shape
+        results.append(m)
+        print(f"{tag(shape)}: {m['ms_per_step']:.4f} ms/step", flush=True)
+    ref = [m for m in results if m["shape"] == DEFAULT][0]["digest"]
+    same = [m for m in results if m["digest"] == ref]
+    rejected = [tag(m["shape"]) for m in results if m["digest"] != ref]
+    best = min(same, key=lambda m: m["ms_per_step"])
+    write_header(header, best["shape"], workload, steps, results, rejected)
+    return {"best": best["shape"], "results": results, "rejected": rejected}
+
+
+def write_header(path: str, shape: dict, workload: str, steps: int, results: list, rejected: list) -> None:
+    lines = ["// Scan shapes of the pair pass, written by paper_2609_05494_amd/autotune.py.",
+             f"// Workload {workload}, {steps} timed steps; ms per step of every shape:"]
+    for m in sorted(results, key=lambda m: m["ms_per_step"]):
+        lines.append(f"//   {tag(m['shape'])}: {m['ms_per_step']:.4f}")
+    if rejected:
+        lines.append("// rejected (state differs from the default shape): " + ", ".join(rejected))
+    lines.append("#pragma once")
+    for k in ("UCAP", "LCAP", "PU"):
+        lines.append(f"#define {k} {int(shape[k])}")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main(argv=None) -> None:
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "measure":
+        print(json.dumps(_measure(argv[1], argv[2], int(argv[3]))), flush=True)
+        return
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    b = sub.add_parser("build")
+    b.add_argument("dir")
+    t = sub.add_parser("time")
+    t.add_argument("dir")
+    t.add_argument("--workload", default="C4")
+    t.add_argument("--steps", type=int, default=200)
+    t.add_argument("--header", default=HEADER)
+    a = ap.parse_args(argv)
+    if a.cmd == "build":
+        build_variants(a.dir)
+    else:
+        r = time_variants(a.dir, a.workload, a.steps, a.header)
+        print(json.dumps({"best": r["best"], "rejected": r["rejected"]}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

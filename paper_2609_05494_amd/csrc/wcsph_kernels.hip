@@ -18,6 +18,14 @@
 
 #include "wcsph_launch.h"
 
+// Scan shapes of the pair pass (UCAP, LCAP, PU) picked for this GPU by the
+// autotuner (paper_2609_05494_amd/autotune.py), when it has been run; the
+// defaults below otherwise. They change speed only: every shape sums each
+// particle's pairs in the same order.
+#if __has_include("wcsph_tuned.h")
+#include "wcsph_tuned.h"
+#endif
+
 namespace {
 
 template <bool BATCH>
