@@ -156,6 +156,18 @@ __device__ __forceinline__ void cubic_spline(const PP& P, float r2, float& W, fl
 }
 
 
+// Element j of a slot array through a 32-bit byte offset (the library
+// keeps j * 16 below 2^32), so that the load is a scalar base plus one
+// 32-bit lane offset rather than a 64-bit address per lane.
+template <class T>
+__device__ __forceinline__ T at32(const T* base, uint32_t j) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + j * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void put32(T* base, uint32_t j, const T& v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + j * (uint32_t)sizeof(T)) = v;
+}
+
 __device__ __forceinline__ void cell_xy(const InstParams& P, uint32_t K, int& cx, int& cy) {
   const int local = (int)K - P.cell_off;
   cy = local / P.ncx;
@@ -494,8 +506,8 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
     auto fetch = [&](int k, float4& E, float4& pj, float4& aj) __attribute__((always_inline)) {
       E = U[my[min(k, cnt - 1) * PAIR_BLOCK]];
       const uint32_t j = __float_as_uint(E.w);
-      pj = sb.pv[j];
-      aj = sb.aux[j];
+      pj = at32(sb.pv, j);
+      aj = at32(sb.aux, j);
     };
     auto body = [&](const float4& E, const float4& pj, const float4& aj) __attribute__((always_inline)) {
       const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
@@ -526,8 +538,8 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
         const uint32_t j = a0 ? urs[0] + u : (a1 ? urs[1] + (u - ub1) : urs[2] + (u - ub2));
         const int kr = a0 ? k0[0] : (a1 ? k0[1] : k0[2]);
         const float sy = a0 ? -gdc : (a1 ? 0.0f : gdc);
-        const float4 pj = sb.pv[j];
-        const int cxj = (int)sb.cell[j] - kr;
+        const float4 pj = at32(sb.pv, j);
+        const int cxj = (int)at32(sb.cell, j) - kr;
         U[t] = make_float4(pj.x, pj.y + sy, (float)(cxj - cxa), __uint_as_float(j));
       }
       wave_sync();
@@ -604,8 +616,8 @@ __device__ __forceinline__ void for_candidates(const Dev& d, const InstParams& P
       const RowRange& r = row == 0 ? r0 : (row == 1 ? r1 : r2);
       const uint32_t j = r.rs + c - (row == 0 ? 0u : (row == 1 ? n0 : n01));
       code[u] = (row << 2) | dx_code(j, r);
-      pq[u] = sb.pv[j];
-      aq[u] = sb.aux[j];
+      pq[u] = at32(sb.pv, j);
+      aq[u] = at32(sb.aux, j);
     }
 #pragma unroll
     for (int u = 0; u < SCAN_UNROLL; ++u)
@@ -846,10 +858,10 @@ __device__ __forceinline__ Loaded sort_load(const Dev& d, const Buf& pre, uint32
   const bool ok = e < (uint32_t)d.n_slots;  // else a corrupted bucket: flagged when stored
   const uint32_t x = ok ? e : 0u;
   v.inst = inst_at<BATCH>(pre, (int)x);
-  v.cell = pre.cell[x];
-  v.id = pre.id[x];
-  v.pv = pre.pv[x];
-  v.rho = pre.aux[x].x;
+  v.cell = at32(pre.cell, x);
+  v.id = at32(pre.id, x);
+  v.pv = at32(pre.pv, x);
+  v.rho = at32(pre.aux, x).x;
   if (!ok) v.inst = -1;
   return v;
 }
@@ -886,10 +898,10 @@ __device__ __forceinline__ void sort_store(const Dev& d, const Buf& out, uint32_
     d.gcell[gi] = v.cell;
     d.gpos[gi] = make_float2(v.pv.x, v.pv.y);
   }
-  out.cell[dst] = v.cell;
-  out.id[dst] = v.id;
-  out.pv[dst] = v.pv;
-  out.aux[dst] = v.aux;
+  put32(out.cell, (uint32_t)dst, v.cell);
+  put32(out.id, (uint32_t)dst, v.id);
+  put32(out.pv, (uint32_t)dst, v.pv);
+  put32(out.aux, (uint32_t)dst, v.aux);
   if constexpr (BATCH) out.inst[dst] = (uint16_t)v.inst;
   d.perm[dst] = e;
 }
@@ -1320,9 +1332,9 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     } else {
       // state n of this particle: the sort of this evaluation took it from
       // slot perm[s] of the step's first sorted state
-      Kb = base.cell[eb];
-      pb = base.pv[eb];
-      rb = base.aux[eb].x;
+      Kb = at32(base.cell, eb);
+      pb = at32(base.pv, eb);
+      rb = at32(base.aux, eb).x;
     }
     float rn = rb + hdt * acc.D;
     const float rn_free = rn;
