@@ -163,10 +163,7 @@ template <class T>
 __device__ __forceinline__ T at32(const T* base, uint32_t j) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + j * (uint32_t)sizeof(T));
 }
-template <class T>
-__device__ __forceinline__ void put32(T* base, uint32_t j, const T& v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + j * (uint32_t)sizeof(T)) = v;
-}
+
 
 __device__ __forceinline__ void cell_xy(const InstParams& P, uint32_t K, int& cx, int& cy) {
   const int local = (int)K - P.cell_off;
@@ -306,10 +303,10 @@ __device__ __forceinline__ RowRange row_range(const Dev& d, const InstParams& P,
   if (yy < 0 || yy >= P.ncy) return r;
   const int xlo = max(cx - 1, 0), xhi = min(cx + 1, P.ncx - 1);
   const uint32_t k0 = (uint32_t)(P.cell_off + yy * P.ncx);
-  r.rs = d.start[k0 + xlo];
-  r.ms = d.start[k0 + cx];
-  r.me = d.start[k0 + cx + 1];
-  r.re = d.start[k0 + xhi + 1];
+  r.rs = at32(d.start, k0 + (uint32_t)xlo);
+  r.ms = at32(d.start, k0 + (uint32_t)cx);
+  r.me = at32(d.start, k0 + (uint32_t)cx + 1u);
+  r.re = at32(d.start, k0 + (uint32_t)xhi + 1u);
   return r;
 }
 // cell shift code of slot j inside a row: 0 left, 1 middle, 2 right
@@ -476,8 +473,8 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
       const int yy = gcy + r - 1;
       if (yy >= 0 && yy < gncy) {
         k0[r] = goff + yy * gncx;
-        urs[r] = d.start[k0[r] + max(cxa - 1, 0)];
-        un[r] = d.start[k0[r] + min(cxb + 1, gncx - 1) + 1] - urs[r];
+        urs[r] = at32(d.start, (uint32_t)(k0[r] + max(cxa - 1, 0)));
+        un[r] = at32(d.start, (uint32_t)(k0[r] + min(cxb + 1, gncx - 1) + 1)) - urs[r];
       }
     }
     const uint32_t ub1 = un[0], ub2 = un[0] + un[1], n = ub2 + un[2];
@@ -488,8 +485,8 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         if (un[r] != 0u) {
-          ors[r] = d.start[k0[r] + max(cx - 1, 0)];
-          on[r] = d.start[k0[r] + min(cx + 1, gncx - 1) + 1] - ors[r];
+          ors[r] = at32(d.start, (uint32_t)(k0[r] + max(cx - 1, 0)));
+          on[r] = at32(d.start, (uint32_t)(k0[r] + min(cx + 1, gncx - 1) + 1)) - ors[r];
         }
       }
       p1 = on[0];
@@ -858,10 +855,10 @@ __device__ __forceinline__ Loaded sort_load(const Dev& d, const Buf& pre, uint32
   const bool ok = e < (uint32_t)d.n_slots;  // else a corrupted bucket: flagged when stored
   const uint32_t x = ok ? e : 0u;
   v.inst = inst_at<BATCH>(pre, (int)x);
-  v.cell = at32(pre.cell, x);
-  v.id = at32(pre.id, x);
-  v.pv = at32(pre.pv, x);
-  v.rho = at32(pre.aux, x).x;
+  v.cell = pre.cell[x];
+  v.id = pre.id[x];
+  v.pv = pre.pv[x];
+  v.rho = pre.aux[x].x;
   if (!ok) v.inst = -1;
   return v;
 }
@@ -898,10 +895,10 @@ __device__ __forceinline__ void sort_store(const Dev& d, const Buf& out, uint32_
     d.gcell[gi] = v.cell;
     d.gpos[gi] = make_float2(v.pv.x, v.pv.y);
   }
-  put32(out.cell, (uint32_t)dst, v.cell);
-  put32(out.id, (uint32_t)dst, v.id);
-  put32(out.pv, (uint32_t)dst, v.pv);
-  put32(out.aux, (uint32_t)dst, v.aux);
+  out.cell[dst] = v.cell;
+  out.id[dst] = v.id;
+  out.pv[dst] = v.pv;
+  out.aux[dst] = v.aux;
   if constexpr (BATCH) out.inst[dst] = (uint16_t)v.inst;
   d.perm[dst] = e;
 }
