@@ -330,7 +330,7 @@ __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float r
   const float vxij = pi.z - pj.z, vyij = pi.w - pj.w;
   const float vr = vxij * rx + vyij * ry;
   const float mj = fabsf(aj.w);
-  const float mfl = fmaxf(aj.w, 0.0f);  // m_j for fluid, 0 for ghosts
+  const float mfl2 = aj.w + mj;  // 2 m_j for fluid, 0 for ghosts (the halves below are exact)
   const float rsum = rhoi + aj.x;       // 2 rho_bar
   const float den = r2 + P.eta2h2;      // r^2 + eta^2 h^2
   const float inv = fast_rcp(den * rsum);
@@ -341,7 +341,7 @@ __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float r
   if constexpr ((VAR & 1) != 0) piav += P.beta2h2 * vrm * vrm * inv * (rsum * inv);
   const float mF = mj * F;
   // continuity + delta diffusion 2 delta h c0 (m_j / rho_j)(rho_i - rho_j) F (fluid pairs)
-  const float dd = P.two_delta_h_c0 * mfl * fast_rcp(aj.x) * (rhoi - aj.x) * F;
+  const float dd = (0.5f * P.two_delta_h_c0) * mfl2 * fast_rcp(aj.x) * (rhoi - aj.x) * F;
   acc.D += mF * vr + dd;
   const float sp = Pi + aj.y + piav;
   // laminar (Lo-Shao): 4 nu0 m_j F r^2 / ((rho_i + rho_j)(r^2 + eta^2 h^2)) v_ij
@@ -355,7 +355,7 @@ __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float r
     // delta term. Ghost pairs whole: the work of the pair's pressure, AV and
     // laminar forces on v_i plus P_i m_g F v_ig.r_ig of the continuity term,
     // -m_g F ((P_g + Pi_ig) r.v_i + P_i r.v_g) + lam v_ig.v_i.
-    const float mflF = mfl * F, mgF = mF - mflF;
+    const float mflF = 0.5f * mfl2 * F, mgF = mF - mflF;
     const float v2 = vxij * vxij + vyij * vyij;
     const float lamg = P.four_nu0 * mgF * r2 * inv;
     aud.av += 0.5f * mflF * piav * vr;
@@ -365,7 +365,7 @@ __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float r
                  mgF * ((aj.y + piav) * (rx * pi.z + ry * pi.w) + Pi * (rx * pj.z + ry * pj.w));
   }
   // XSPH eps (m_j / rho_bar) W (v_j - v_i) over fluid; 1 / rho_bar = 2 den inv
-  const float w = P.eps_xsph * mfl * 2.0f * den * inv * W;
+  const float w = P.eps_xsph * mfl2 * den * inv * W;
   acc.Vx -= w * vxij;
   acc.Vy -= w * vyij;
 }
