@@ -48,6 +48,8 @@ class Params(C.Structure):
         ("diag_every", C.c_int),
         ("kin_mode", C.c_int), ("kin_v0", C.c_double), ("kin_t_ramp", C.c_double),
         ("kin_coef", C.c_double), ("beta", C.c_double), ("kernel_type", C.c_int),
+        ("eos_type", C.c_int), ("mg_s1", C.c_double), ("mg_gamma0", C.c_double),
+        ("mg_mu_max", C.c_double),
     ]
 
 
@@ -103,6 +105,7 @@ def lib():
             "orc_kernel_type": (None, [C.c_int, C.c_double, C.c_double, _D, _D]),
             "orc_eos": (None, [P, C.c_double, _D, _D]),
             "orc_elastic_energy": (C.c_double, [P, C.c_double]),
+            "orc_eos_rho": (C.c_double, [P, C.c_double]),
             "orc_cfl_dt": (C.c_double, [C.c_double] * 4),
             "orc_cell_list": (C.c_int, [P, C.c_int, _D, _D, _I, _I, _I]),
             "orc_brute_pairs": (C.c_long, [P, C.c_int, _D, _D, _I, C.c_long]),
@@ -245,6 +248,11 @@ def eos(cfg: dict, rho: float):
 
 def elastic_energy(cfg: dict, rho: float) -> float:
     return lib().orc_elastic_energy(C.byref(params(cfg)), rho)
+
+
+def eos_rho(cfg: dict, pres: float) -> float:
+    """Density at pressure pres (>= p_cav) on the workload's EOS."""
+    return lib().orc_eos_rho(C.byref(params(cfg)), pres)
 
 
 def cfl_dt(cfl, h, c0, vmax) -> float:

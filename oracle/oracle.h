@@ -37,6 +37,8 @@ typedef struct {
   double kin_v0, kin_t_ramp, kin_coef;
   double beta; /* quadratic artificial viscosity coefficient (0: linear term only) */
   int kernel_type; /* 0: Wendland C2; 1: cubic B-spline (eq. cubic-kernel) */
+  int eos_type;    /* 0: Tait; 1: Mie-Grueneisen of eq. eos at zero specific internal energy */
+  double mg_s1, mg_gamma0, mg_mu_max; /* its Hugoniot slope S1, gamma0 and compression cap */
 } orc_params;
 
 /* ---- whole solver ------------------------------------------------------ */
@@ -80,6 +82,8 @@ void orc_kernel(double q, double h, double* W, double* F);
 /* Kernel of type 0 (Wendland C2) or 1 (cubic B-spline): W and F = (1/r) dW/dr. */
 void orc_kernel_type(int type, double q, double h, double* W, double* F);
 void orc_eos(const orc_params* p, double rho, double* pres, double* c);
+/* Density at pressure pres >= p_cav on the EOS of p (its inverse, no cutoff branch). */
+double orc_eos_rho(const orc_params* p, double pres);
 double orc_elastic_energy(const orc_params* p, double rho);
 double orc_cfl_dt(double cfl, double h, double c0, double vmax);
 /* Cell list of n points given in current storage order: keys[k] of slot k,

@@ -160,15 +160,71 @@ struct Coef {
   T alpha, delta, c0, B;
 };
 
-// Tait EOS with cavitation cutoff; sound speed c = c0 (rho/rho0)^((gamma-1)/2).
+// Mie-Grueneisen law of eq. eos (eos_type 1) with the specific internal
+// energy held at zero: no energy equation is evolved, so the
+// (gamma0 + a mu) rho e term drops out and p depends on rho alone. With
+// mu = rho/rho0 - 1 capped at mg_mu_max and C = c0:
+//   compression (mu >= 0): p = rho0 C^2 mu [1 + (1 - gamma0/2) mu] / [1 - (S1 - 1) mu]^2,
+//   tension (mu < 0):      p = rho0 C^2 mu.
+template <class T>
+T mg_p(const T& rho, const orc_params& p, const Coef<T>& k) {
+  T mu = rho / p.rho0 - 1.0;
+  if (val(mu) > p.mg_mu_max) mu = T(p.mg_mu_max);
+  const T K = p.rho0 * (k.c0 * k.c0);
+  if (val(mu) < 0.0) return K * mu;
+  const T den = 1.0 - (p.mg_s1 - 1.0) * mu;
+  return K * mu * (1.0 + (1.0 - 0.5 * p.mg_gamma0) * mu) / (den * den);
+}
+// Its sound speed, c^2 = dp/drho of the same law (taken at the capped mu):
+// C^2 [1 + (2 - gamma0 + S1 - 1) mu] / [1 - (S1 - 1) mu]^3 in compression, C^2 in tension.
+template <class T>
+T mg_c(const T& rho, const orc_params& p, const Coef<T>& k) {
+  T mu = rho / p.rho0 - 1.0;
+  if (val(mu) > p.mg_mu_max) mu = T(p.mg_mu_max);
+  if (val(mu) < 0.0) return k.c0;
+  const double b = p.mg_s1 - 1.0;
+  const T den = 1.0 - b * mu;
+  return k.c0 * sqrt((1.0 + (2.0 - p.mg_gamma0 + b) * mu) / (den * den * den));
+}
+// The density at pressure q of the same law (ghost_rho_mode 1, the
+// hydrostatic start): the tension branch inverted, or in compression the
+// root in [0, 1/(S1 - 1)) of q (1 - b mu)^2 = K mu (1 + k1 mu), i.e. of
+// (q b^2 - K k1) mu^2 - (2 q b + K) mu + q = 0, written as 2q / (B + sqrt(B^2 - 4Aq));
+// capped at mg_mu_max.
+template <class T>
+T mg_rho(const T& q, const orc_params& p, const Coef<T>& k) {
+  const T K = p.rho0 * (k.c0 * k.c0);
+  if (val(q) < 0.0) return p.rho0 * (1.0 + q / K);
+  const double b = p.mg_s1 - 1.0, k1 = 1.0 - 0.5 * p.mg_gamma0;
+  const T A = q * (b * b) - K * k1, Bq = 2.0 * b * q + K;
+  T mu = 2.0 * q / (Bq + sqrt(Bq * Bq - 4.0 * A * q));
+  if (val(mu) > p.mg_mu_max) mu = T(p.mg_mu_max);
+  return p.rho0 * (1.0 + mu);
+}
+
+// EOS with the cavitation cutoff p >= p_cav: Tait (eos_type 0),
+// p = B((rho/rho0)^gamma - 1), c = c0 (rho/rho0)^((gamma-1)/2), or the
+// Mie-Grueneisen law above.
+template <class T>
+T eos_p_uncut(const T& rho, const orc_params& p, const Coef<T>& k) {
+  if (p.eos_type == 1) return mg_p(rho, p, k);
+  return k.B * (pow(rho / p.rho0, p.gamma) - 1.0);
+}
 template <class T>
 T eos_p(const T& rho, const orc_params& p, const Coef<T>& k) {
-  T pr = k.B * (pow(rho / p.rho0, p.gamma) - 1.0);
+  T pr = eos_p_uncut(rho, p, k);
   return val(pr) < p.p_cav ? T(p.p_cav) : pr;
 }
 template <class T>
 T eos_c(const T& rho, const orc_params& p, const Coef<T>& k) {
+  if (p.eos_type == 1) return mg_c(rho, p, k);
   return k.c0 * pow(rho / p.rho0, 0.5 * (p.gamma - 1.0));
+}
+// inverse of the EOS for a pressure q >= p_cav (no cutoff branch)
+template <class T>
+T eos_rho(const T& q, const orc_params& p, const Coef<T>& k) {
+  if (p.eos_type == 1) return mg_rho(q, p, k);
+  return p.rho0 * pow(1.0 + q / k.B, 1.0 / p.gamma);
 }
 
 // A particle as seen by the pair law.
@@ -333,10 +389,10 @@ struct Sim {
           double xx = (i + 0.5) * p.dx, yy = (j + 0.5) * p.dx;
           if (R > 0 && (xx - cx) * (xx - cx) + (yy - cy) * (yy - cy) < R * R) continue;
           double r0 = p.rho0;
-          if (p.init_mode == 1) {  // hydrostatic: Tait inverse of rho0 |g| (W - y)
-            double ph = p.rho0 * std::fabs(p.gravity_y) * (p.W - yy);
-            double B = p.rho0 * p.c0 * p.c0 / p.gamma;
-            r0 = p.rho0 * std::pow(1.0 + ph / B, 1.0 / p.gamma);
+          if (p.init_mode == 1) {  // hydrostatic: the EOS inverse of rho0 |g| (W - y)
+            Coef<double> k;
+            k.c0 = p.c0; k.B = p.rho0 * p.c0 * p.c0 / p.gamma;
+            r0 = eos_rho(p.rho0 * std::fabs(p.gravity_y) * (p.W - yy), p, k);
           }
           x.push_back(xx); y.push_back(yy); vx.push_back(0.0); vy.push_back(0.0); rho.push_back(r0);
         }
@@ -473,7 +529,7 @@ struct Sim {
       if (val(pg) < P.p_cav) pg = T(P.p_cav);
       T rg;
       if (P.ghost_rho_mode == 0) rg = P.rho0 * (1.0 + pg / (P.rho0 * K.c0 * K.c0));  // linear branch
-      else rg = P.rho0 * pow(1.0 + pg / K.B, 1.0 / P.gamma);
+      else rg = eos_rho(pg, P, K);
       gp[g] = pg; grho[g] = rg; gvx[g] = vgx; gvy[g] = vgy;
     }
   }
@@ -677,8 +733,27 @@ struct Sim {
     }
   }
 
-  // specific elastic energy of the Tait law with the cutoff branch
+  // specific elastic energy int_{rho0}^{r} p / rho^2 drho of the EOS with its
+  // cutoff branch: closed form for Tait; for the Mie-Grueneisen law, per unit
+  // mu = rho/rho0 - 1 the integrand is p / (rho0 (1 + mu)^2), summed by the
+  // composite Simpson rule over each of its smooth pieces (breaks at the
+  // cutoff and at the compression cap)
   double e_el(double r) const {
+    if (P.eos_type == 1) {
+      Coef<double> k;
+      k.c0 = val(K.c0); k.B = val(K.B);
+      auto f = [&](double m) { return eos_p(P.rho0 * (1.0 + m), P, k) / (P.rho0 * (1.0 + m) * (1.0 + m)); };
+      auto simpson = [&](double a, double b) {
+        const int n = 256;
+        double sum = f(a) + f(b);
+        for (int i = 1; i < n; ++i) sum += (i % 2 ? 4.0 : 2.0) * f(a + (b - a) * i / n);
+        return sum * (b - a) / (3.0 * n);
+      };
+      const double mu = r / P.rho0 - 1.0;
+      const double mu_cav = P.p_cav / (P.rho0 * k.c0 * k.c0);
+      const double brk = mu < 0.0 ? std::max(mu, mu_cav) : std::min(mu, P.mg_mu_max);
+      return simpson(0.0, brk) + simpson(brk, mu);
+    }
     const double g = P.gamma, r0 = P.rho0, B = val(K.B);
     auto e_tait = [&](double q) {
       return B * ((std::pow(q, g - 1.0) - std::pow(r0, g - 1.0)) / ((g - 1.0) * std::pow(r0, g)) +
@@ -700,7 +775,7 @@ struct Sim {
       ke += 0.5 * m * (u * u + w * w);
       epot += m * (-P.gravity_y) * val(y[i]);
       eel += m * e_el(r);
-      if (val(K.B) * (std::pow(r / P.rho0, P.gamma) - 1.0) <= P.p_cav) ncav++;
+      if (val(eos_p_uncut(T(r), P, K)) <= P.p_cav) ncav++;
     }
     double xd, vd, ad;
     current_disk(&xd, &vd, &ad);
@@ -827,6 +902,12 @@ void orc_eos(const orc_params* p, double rho, double* pres, double* c) {
   *c = eos_c(rho, *p, k);
 }
 
+double orc_eos_rho(const orc_params* p, double pres) {
+  Coef<double> k;
+  k.c0 = p->c0; k.B = p->rho0 * p->c0 * p->c0 / p->gamma; k.alpha = p->alpha; k.delta = p->delta;
+  return eos_rho(pres, *p, k);
+}
+
 double orc_elastic_energy(const orc_params* p, double rho) {
   SimD s;
   s.P = *p;
@@ -947,10 +1028,10 @@ void orc_ghost_point(const orc_params* p, double gx, double gy, const double* vw
     q = 0; ux = vw[0]; uy = vw[1];
   }
   if (q < p->p_cav) q = p->p_cav;
-  double B = p->rho0 * p->c0 * p->c0 / p->gamma;
+  Coef<double> k;
+  k.c0 = p->c0; k.B = p->rho0 * p->c0 * p->c0 / p->gamma;
   *pg = q;
-  *rhog = p->ghost_rho_mode == 0 ? p->rho0 * (1.0 + q / (p->rho0 * p->c0 * p->c0))
-                                 : p->rho0 * std::pow(1.0 + q / B, 1.0 / p->gamma);
+  *rhog = p->ghost_rho_mode == 0 ? p->rho0 * (1.0 + q / (p->rho0 * p->c0 * p->c0)) : eos_rho(q, *p, k);
   vg[0] = ux; vg[1] = uy;
 }
 

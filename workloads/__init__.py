@@ -34,6 +34,13 @@ K_DRAG = 0.5 * PROJ_CD * RHO_F * math.pi * PROJ_RADIUS ** 2 / PROJ_MASS
 
 C4_SEED = 2609
 
+# Mie-Grueneisen water (eq. eos and its parameter table): bulk sound speed C,
+# Hugoniot slope S1, gamma0, compression cap of mu = rho/rho0 - 1
+MG_C = 1448.0
+MG_S1 = 1.979
+MG_GAMMA0 = 0.11
+MG_MU_MAX = 0.25
+
 
 def _cell_size(dx: float, h_over_dx: float) -> float:
     """Smallest float32 that is >= 2h: the cell edge both sides use.
@@ -70,6 +77,7 @@ def base(L: float, W: float, dx: float, R: float, v0: float, *,
         disk_R=R, disk_x0=R, disk_y0=0.5 * W, disk_mass=PROJ_MASS,
         probes=probes, diag_every=10,
         kin_mode=0, kin_v0=v0, kin_t_ramp=5.0e-6, kin_coef=K_DRAG * v0 * v0,
+        eos_type=0, mg_s1=MG_S1, mg_gamma0=MG_GAMMA0, mg_mu_max=MG_MU_MAX,
         steps=steps,
     )
 
@@ -98,6 +106,13 @@ def paper_geometry(v0: float = 900.0) -> dict:
     stay those of the hot path."""
     cfg = base(0.750, 0.150, 1.5e-3, PROJ_RADIUS, v0, alpha=0.03, probes_x=(0.030, 0.105), steps=2000)
     return dict(cfg, kernel_type=1, ghost_layers=1)
+
+
+def mie_grueneisen(cfg: dict) -> dict:
+    """The same workload with the paper's Mie-Grueneisen EOS (eos_type 1) at
+    zero specific internal energy in place of Tait, and the reference
+    celerity c0 = C = 1448 m/s that the paper ties to it."""
+    return dict(cfg, eos_type=1, c0=MG_C)
 
 
 def C2() -> dict:
