@@ -285,6 +285,34 @@ def qav_run(wc, workloads, steps: int, prescribed_value: float, beta: float = 1.
                 probe_peak_pa=float(np.abs(p).max()), unstable=unstable)
 
 
+def mg_run(wc, workloads, steps: int, tait_value: float):
+    """The headline workload with the paper's Mie-Grueneisen EOS at zero
+    specific internal energy (C = c0 = 1448 m/s) in place of Tait, `steps`
+    steps from t = 0."""
+    import torch
+    cfg = workloads.mie_grueneisen(workloads.C2())
+    s = wc.Solver(cfg, "cuda:0")
+    blob = s.save_state()
+    s.step(20)
+    s.synchronize()
+    s.load_state(blob)
+    s.read_probes()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.synchronize()
+    el = time.perf_counter() - t0
+    _, _, p = s.read_probes()
+    unstable = bool(s.read_diagnostics().get("unstable", False))
+    nf = s.nf
+    s.close()
+    value = nf * steps / el
+    return dict(workload="300x150 mm channel, dx 0.5 mm, 900 m/s, Mie-Grueneisen EOS (e = 0), C = 1448 m/s",
+                steps=steps, value=value, unit="fluid particle-steps/s",
+                ms_per_step=round(el / steps * 1e3, 5), vs_tait=round(value / tait_value, 4),
+                probe_peak_pa=float(np.abs(p).max()), unstable=unstable)
+
+
 def paper_production_run(wc, workloads, t_end: float = 150e-6):
     """The paper's production case in its own geometry (750x150 mm channel,
     dx = 1.5 mm, 49,947 fluid, 900 m/s) with the paper's kernel, alpha and
@@ -337,6 +365,8 @@ def main():
                     help="steps of the energy-audit run (0 skips it)")
     ap.add_argument("--qav-steps", type=int, default=2000,
                     help="steps of the quadratic-viscosity run (0 skips it)")
+    ap.add_argument("--mg-steps", type=int, default=2000,
+                    help="steps of the Mie-Grueneisen run (0 skips it)")
     ap.add_argument("--paper-run", type=int, default=1,
                     help="1: time the paper's production case to 150 us (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -404,6 +434,7 @@ def main():
     two_way = two_way_run(wc, workloads, args.two_way_steps, value) if args.two_way_steps > 0 else None
     audit = audit_run(wc, workloads, args.audit_steps, value) if args.audit_steps > 0 else None
     qav = qav_run(wc, workloads, args.qav_steps, value) if args.qav_steps > 0 else None
+    mg = mg_run(wc, workloads, args.mg_steps, value) if args.mg_steps > 0 else None
     paper = paper_production_run(wc, workloads) if args.paper_run else None
     cpu = None if args.no_cpu else cpu_baseline(cfg)
     out = {
@@ -430,6 +461,7 @@ def main():
         "two_way": two_way,
         "energy_audit": audit,
         "quadratic_av": qav,
+        "mie_grueneisen": mg,
         "paper_production_run": paper,
         "unstable": unstable,
         "probe_peak_pa": float(np.abs(p).max()) if p.size else None,

@@ -66,7 +66,18 @@ typedef struct {
  *               (1.3: SPH Fundamentals), cell edge cell_size >= 2h (<= 0 -> the
  *               smallest float >= 2h), ghost_layers wall-ghost lattice rows.
  *  material   : rho0, Tait c0 and gamma (B = rho0 c0^2 / gamma), cavitation
- *               cutoff p_cav (< 0, eq. eos text).
+ *               cutoff p_cav (< 0, eq. eos text). eos_type 0 = Tait; 1 = the
+ *               Mie-Grueneisen law of eq. eos with the specific internal
+ *               energy held at zero (no energy equation is evolved, so its
+ *               (gamma0 + a mu) rho e term vanishes): with mu = rho/rho0 - 1
+ *               capped at mg_mu_max and C = c0, p = rho0 C^2 mu [1 +
+ *               (1 - mg_gamma0/2) mu] / [1 - (mg_s1 - 1) mu]^2 in compression,
+ *               rho0 C^2 mu in tension, the same cutoff, c^2 = dp/drho; then
+ *               ghost_rho_mode 1 is its inverse, e_el its elastic energy, and
+ *               gamma is unused. Requires mg_s1 >= 1, 0 <= mg_gamma0 < 2,
+ *               mg_mu_max > 0, (mg_s1 - 1) mg_mu_max < 0.9. Batched
+ *               instances may mix the two laws. The reverse sweep takes Tait
+ *               only.
  *  scheme     : Monaghan alpha and eta2 (eq. artificial-viscosity), beta of
  *               the quadratic term beta mu^2 / rho_bar that the paper omits
  *               (0 = linear term only, the paper's form), delta
@@ -113,6 +124,8 @@ typedef struct {
   int audit;
   double beta;
   int kernel_type;
+  int eos_type;
+  double mg_s1, mg_gamma0, mg_mu_max;
 } wcsph_params;
 
 /* One diagnostic record (FP64 reductions over the fluid of one instance).

@@ -56,7 +56,8 @@ class Params(C.Structure):
         ("diag_every", C.c_int),
         ("kin_mode", C.c_int), ("kin_v0", C.c_double), ("kin_t_ramp", C.c_double),
         ("kin_coef", C.c_double), ("audit", C.c_int), ("beta", C.c_double),
-        ("kernel_type", C.c_int),
+        ("kernel_type", C.c_int), ("eos_type", C.c_int), ("mg_s1", C.c_double),
+        ("mg_gamma0", C.c_double), ("mg_mu_max", C.c_double),
     ]
 
 

@@ -168,8 +168,23 @@ void validate(const wcsph_params& p) {
   require(p.audit == 0 || p.audit == 1, "audit must be 0 or 1");
   require(p.beta >= 0 && std::isfinite(p.beta), "beta must be finite and >= 0");
   require(p.kernel_type == 0 || p.kernel_type == 1, "kernel_type must be 0 (Wendland C2) or 1 (cubic spline)");
+  require(p.eos_type == 0 || p.eos_type == 1, "eos_type must be 0 (Tait) or 1 (Mie-Grueneisen)");
+  if (p.eos_type == 1)
+    require(p.mg_s1 >= 1.0 && p.mg_gamma0 >= 0.0 && p.mg_gamma0 < 2.0 && p.mg_mu_max > 0.0 &&
+                (p.mg_s1 - 1.0) * p.mg_mu_max < 0.9 && std::isfinite(p.mg_s1 + p.mg_gamma0 + p.mg_mu_max),
+            "Mie-Grueneisen parameters need S1 >= 1, 0 <= gamma0 < 2, mu_max > 0, (S1 - 1) mu_max < 0.9");
   const long long nx = std::llround(p.L / p.dx), ny = std::llround(p.W / p.dx);
   require(nx >= 1 && ny >= 1 && nx * ny < (1ll << 28), "lattice size out of range");
+}
+
+// Density at pressure q >= 0 on the instance's EOS (the hydrostatic start):
+// the Tait inverse, or for the Mie-Grueneisen law the root in [0, 1/b) of
+// s (1 - b mu)^2 = mu (1 + k1 mu), s = q / (rho0 C^2), capped at mu_max.
+double eos_density(const wcsph_params& p, double B, double q) {
+  if (p.eos_type == 0) return p.rho0 * std::pow(1.0 + q / B, 1.0 / p.gamma);
+  const double s = q / (p.rho0 * p.c0 * p.c0), b = p.mg_s1 - 1.0, k1 = 1.0 - 0.5 * p.mg_gamma0;
+  const double mu = 2.0 * s / ((1.0 + 2.0 * b * s) + std::sqrt(1.0 + 4.0 * s * (b + k1)));
+  return p.rho0 * (1.0 + std::min(mu, p.mg_mu_max));
 }
 
 // Problem set-up of one instance: fluid lattice ((i+1/2)dx, (j+1/2)dx) with
@@ -187,7 +202,7 @@ HostInst build_geometry(const wcsph_params& p) {
         if (ux * ux + uy * uy < p.disk_R * p.disk_R) continue;
       }
       double r = p.rho0;
-      if (p.init_mode == 1) r = p.rho0 * std::pow(1.0 + p.rho0 * std::fabs(p.gravity_y) * (p.W - y) / B, 1.0 / p.gamma);
+      if (p.init_mode == 1) r = eos_density(p, B, p.rho0 * std::fabs(p.gravity_y) * (p.W - y));
       g.fx.push_back(x);
       g.fy.push_back(y);
       g.frho.push_back(r);
@@ -247,6 +262,20 @@ InstParams derive(const wcsph_params& p) {
   q.gamma = (float)p.gamma;
   q.inv_gamma = (float)(1.0 / p.gamma);
   q.ghost_rho_mode = p.ghost_rho_mode;
+  q.eos_type = p.eos_type;
+  {
+    const double K = p.rho0 * p.c0 * p.c0, b = p.mg_s1 - 1.0, k1 = 1.0 - 0.5 * p.mg_gamma0, m = p.mg_mu_max;
+    q.mg_K = (float)K;
+    q.mg_k1 = (float)k1;
+    q.mg_b = (float)b;
+    q.mg_mu_max = (float)m;
+    q.mg_Kd = K;
+    q.mg_k1d = k1;
+    q.mg_bd = b;
+    q.mg_mu_maxd = m;
+    q.mg_mu_cavd = p.p_cav / K;
+    q.mg_p_capd = K * m * (1.0 + k1 * m) / ((1.0 - b * m) * (1.0 - b * m));
+  }
   q.L = p.L;
   q.W = p.W;
   q.eps_wall = p.eps_wall;
@@ -535,8 +564,10 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.wb_part = dalloc_n<double>(c, (size_t)n_inst * WC_MAX_RING);
   c->d_disk = dalloc_n<double>(c, 3);
   d.var = params[0].kernel_type == 1 ? 2 : 0;
-  for (int i = 0; i < n_inst; ++i)
+  for (int i = 0; i < n_inst; ++i) {
     if (params[i].beta > 0) d.var |= 1;
+    if (params[i].eos_type == 1) d.var |= 4;
+  }
   c->audit = !c->batch && params[0].audit != 0;
   d.audit_part = c->audit ? dalloc_n<double>(c, (size_t)wc_pair_blocks(c->n_slots) * 6) : nullptr;
   d.n_vpart = wc_pair_blocks(c->n_slots);
@@ -1298,6 +1329,7 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   require(ctx->hp[0].kin_mode != 2 || ctx->hp[0].nd == 0,
           "the reverse sweep needs a prescribed disk motion (kin_mode 0 or 1)");
   require(ctx->pin[0].beta == 0, "the reverse sweep supports the linear artificial viscosity only (beta = 0)");
+  require(ctx->pin[0].eos_type == 0, "the reverse sweep supports the Tait EOS only");
   require(ctx->pin[0].kernel_type == 0, "the reverse sweep supports the Wendland C2 kernel only");
   require(n_steps >= 1 && ckpt_every >= 1, "n_steps and ckpt_every must be >= 1");
   const long long k0 = ctx->steps - ctx->d.dt_step0;

@@ -56,6 +56,13 @@ struct InstParams {
   int n_probes;
   uint32_t probe_cell[WC_MAX_PROBES];
   float probe_ox[WC_MAX_PROBES], probe_oy[WC_MAX_PROBES];
+  // EOS (kept last: the fields above keep their offsets): 0 Tait; 1 the Mie-Grueneisen law at zero internal energy, with
+  // K = rho0 C^2 (C = c0), k1 = 1 - gamma0/2, b = S1 - 1 and the cap of mu
+  int eos_type;
+  float mg_K, mg_k1, mg_b, mg_mu_max;
+  // the same law in FP64 (diagnostics): K, k1, b, the cap, mu at the cutoff
+  // p_cav / K and the pressure at the cap
+  double mg_Kd, mg_k1d, mg_bd, mg_mu_maxd, mg_mu_cavd, mg_p_capd;
 };
 
 // Per-instance clock and accumulators (device-resident, FP64 time).
@@ -122,7 +129,8 @@ struct Dev {
   float* vmax_part;           // single instance: per corrector pair block, max |v| of its new fluid
                               // state (folded into the clock by the next first-evaluation sort)
   int n_vpart;                // entries of vmax_part (pair blocks)
-  int var;                    // pair-pass variant: bit 0 quadratic AV (some beta > 0), bit 1 cubic spline
+  int var;                    // pass variants: bit 0 quadratic AV (some beta > 0), bit 1 cubic spline,
+                              // bit 2 some instance uses the Mie-Grueneisen EOS (sort pass)
   double* audit_part;         // energy audit (single instance, or NULL): per corrector pair block,
                               // running sums of d_av, d_visc, w_delta, w_ghost, w_enforce, w_clamp
   float* xr;                  // export: [5][n_slots] rates per slot

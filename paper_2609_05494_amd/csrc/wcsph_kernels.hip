@@ -111,10 +111,30 @@ __device__ void disk_newest(const InstParams& P, const Clock& C, double& x, doub
 // c0 (rho/rho0)^((gamma-1)/2), with x = rho/rho0 - 1 so that p stays accurate
 // near rho0 in FP32. For gamma = 7, (1 + x)^7 - 1 is x times its binomial
 // polynomial and the sound speed exponent is 3; otherwise log1p/expm1.
+// The Mie-Grueneisen law at zero internal energy (eos_type 1) at
+// mu = rho/rho0 - 1: capped at mu_max; K mu (1 + k1 mu) / (1 - b mu)^2 and
+// c = C sqrt((1 + (2 k1 + b) mu) / (1 - b mu)^3) in compression, K mu and C
+// in tension (before the cutoff).
+__device__ __forceinline__ void mg_eos(const InstParams& P, float x, float& p, float& c) {
+  const float mu = fminf(x, P.mg_mu_max);
+  if (mu >= 0.0f) {
+    const float den = 1.0f - P.mg_b * mu, iden = 1.0f / den;
+    p = P.mg_K * mu * (1.0f + P.mg_k1 * mu) * (iden * iden);
+    c = P.c0 * sqrtf((1.0f + (2.0f * P.mg_k1 + P.mg_b) * mu) * (iden * iden * iden));
+  } else {
+    p = P.mg_K * mu;
+    c = P.c0;
+  }
+}
+
+// MG: some instance uses the Mie-Grueneisen law (else the check is compiled out).
+template <bool MG>
 __device__ __forceinline__ void fluid_eos(const InstParams& P, float rho, float& Pq, float& c) {
   const float x = (rho - P.rho0) / P.rho0;
   float p;
-  if (P.gamma == 7.0f) {
+  if (MG && P.eos_type == 1) {
+    mg_eos(P, x, p, c);
+  } else if (P.gamma == 7.0f) {
     const float y = 1.0f + x;
     p = P.B * (x * (7.0f + x * (21.0f + x * (35.0f + x * (35.0f + x * (21.0f + x * (7.0f + x)))))));
     c = P.c0 * (y * y * y);
@@ -862,6 +882,7 @@ __device__ __forceinline__ Loaded sort_load(const Dev& d, const Buf& pre, uint32
   if (!ok) v.inst = -1;
   return v;
 }
+template <bool MG>
 __device__ __forceinline__ Gathered sort_finish(const Dev& d, const Loaded& l) {
   Gathered v;
   v.inst = l.inst;
@@ -873,7 +894,7 @@ __device__ __forceinline__ Gathered sort_finish(const Dev& d, const Loaded& l) {
   const int local = (int)l.id - P.id0;
   if (local < P.nf) {
     float Pq, c;
-    fluid_eos(P, l.rho, Pq, c);
+    fluid_eos<MG>(P, l.rho, Pq, c);
     v.aux = make_float4(l.rho, Pq, c, P.m_fluid);
     v.ghost = -1;
   } else {
@@ -903,7 +924,7 @@ __device__ __forceinline__ void sort_store(const Dev& d, const Buf& out, uint32_
   d.perm[dst] = e;
 }
 
-template <int MODE, bool BATCH>
+template <int MODE, bool BATCH, bool MG>
 __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
   constexpr int T = WC_SORT_TILE;
   __shared__ uint32_t s_off[T + 1];  // exclusive offsets of the tile's cells, total at [T]
@@ -1031,7 +1052,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
       for (int u = 0; u < SORT_SPEC; ++u) r[u] += x < e[u] ? 1u : 0u;
     }
 #pragma unroll
-    for (int u = 0; u < SORT_SPEC; ++u) gv[u] = sort_finish(d, lv[u]);  // EOS while the look-back runs
+    for (int u = 0; u < SORT_SPEC; ++u) gv[u] = sort_finish<MG>(d, lv[u]);  // EOS while the look-back runs
     if (fold) {
       const float w = wave_max(vp);
       if (ct == 0 && w > 0.0f) atomicMax(&d.clk[0].vmax_bits, __float_as_uint(w));
@@ -1052,7 +1073,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     const uint32_t ei = raw[i];
     uint32_t ri = 0u;
     for (uint32_t k = 0; k < n; ++k) ri += raw[k] < ei ? 1u : 0u;
-    sort_store<BATCH>(d, out, ei, base + ri, sort_finish(d, sort_load<BATCH>(d, pre, ei)));
+    sort_store<BATCH>(d, out, ei, base + ri, sort_finish<MG>(d, sort_load<BATCH>(d, pre, ei)));
   }
 }
 
@@ -1109,12 +1130,25 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
       vgy = 0.0f;
     }
     p = fmaxf(p, P.p_cav);
-    float rg;
-    if (P.ghost_rho_mode == 0) rg = P.rho0 * (1.0f + p * P.inv_rho0c02);
-    else rg = P.rho0 * expf(P.inv_gamma * log1pf(p / P.B));
+    float rg, cg;
+    if (P.eos_type == 1) {
+      // Mie-Grueneisen inverse: tension line, or the root in [0, 1/b) of
+      // s (1 - b mu)^2 = mu (1 + k1 mu), s = p / K; capped at mu_max
+      const float sp = p / P.mg_K;
+      float mu = sp;
+      if (P.ghost_rho_mode != 0 && sp > 0.0f)
+        mu = fminf(2.0f * sp / ((1.0f + 2.0f * P.mg_b * sp) + sqrtf(1.0f + 4.0f * sp * (P.mg_b + P.mg_k1))),
+                   P.mg_mu_max);
+      rg = P.rho0 * (1.0f + mu);
+      float pu;
+      mg_eos(P, mu, pu, cg);
+    } else {
+      if (P.ghost_rho_mode == 0) rg = P.rho0 * (1.0f + p * P.inv_rho0c02);
+      else rg = P.rho0 * expf(P.inv_gamma * log1pf(p / P.B));
+      const float xg = (rg - P.rho0) / P.rho0, yg = 1.0f + xg;
+      cg = P.gamma == 7.0f ? P.c0 * (yg * yg * yg) : P.c0 * expf(P.c_exp * log1pf(xg));
+    }
     const float Pg = p / (rg * rg);
-    const float xg = (rg - P.rho0) / P.rho0, yg = 1.0f + xg;
-    const float cg = P.gamma == 7.0f ? P.c0 * (yg * yg * yg) : P.c0 * expf(P.c_exp * log1pf(xg));
     const float m = disk ? P.m_disk : P.m_wall;
     if (lane == 0) {
       sb.pv[s] = make_float4(pg.x, pg.y, vgx, vgy);
@@ -1181,6 +1215,33 @@ __device__ __forceinline__ double tait_e_el(const InstParams& P, double r) {
   const double rg1 = pow_gm1(r, P.gammad);
   return r >= P.diag_rc ? P.diag_k1 * (rg1 - P.diag_r0g1) + P.Bd * (1.0 / r - 1.0 / P.rho0d)
                         : P.diag_erc + P.p_cavd * (1.0 / P.diag_rc - 1.0 / r);
+}
+
+// Specific elastic energy of the Mie-Grueneisen law at zero internal energy
+// (int p / rho^2 drho from rho0), FP64. Per unit mu the integrand is
+// p(mu) / (rho0 (1 + mu)^2): 8-point Gauss-Legendre on the smooth piece from
+// 0 to mu clamped to [mu_cav, mu_max], the constant-pressure pieces beyond
+// the cutoff and the cap in closed form.
+__device__ __forceinline__ double mg_e_el(const InstParams& P, double r) {
+  constexpr double xg[4] = {0.18343464249564978, 0.52553240991632899, 0.79666647741362673, 0.96028985649753618};
+  constexpr double wg[4] = {0.36268378337836177, 0.31370664587788705, 0.22238103445337434, 0.10122853629037669};
+  const double mu = r / P.rho0d - 1.0;
+  const double m = fmin(fmax(mu, P.mg_mu_cavd), P.mg_mu_maxd);
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double u = 0.5 * m * (1.0 + ((k & 1) ? -xg[k >> 1] : xg[k >> 1]));
+    const double den = 1.0 - P.mg_bd * u;
+    const double p = m >= 0.0 ? P.mg_Kd * u * (1.0 + P.mg_k1d * u) / (den * den) : P.mg_Kd * u;
+    sum += wg[k >> 1] * p / ((1.0 + u) * (1.0 + u));
+  }
+  double e = 0.5 * m * sum / P.rho0d;
+  if (mu > m) e += P.mg_p_capd / P.rho0d * (1.0 / (1.0 + m) - 1.0 / (1.0 + mu));
+  else if (mu < m) e += P.p_cavd / P.rho0d * (1.0 / (1.0 + m) - 1.0 / (1.0 + mu));
+  return e;
+}
+__device__ __forceinline__ double eos_e_el(const InstParams& P, double r) {
+  return P.eos_type == 1 ? mg_e_el(P, r) : tait_e_el(P, r);
 }
 
 template <int MODE, bool BATCH, bool AUD, int VAR>
@@ -1406,7 +1467,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       // the energy the enforcement and the density clamp add to the new state
       const double m = (double)h_m[threadIdx.x];
       if (moved) e_enf = 0.5 * m * ((double)vx * vx + (double)vy * vy - k_free);
-      if (clamp_hit) e_clamp = m * (tait_e_el(P, (double)rn) - tait_e_el(P, (double)rn_free));
+      if (clamp_hit) e_clamp = m * (eos_e_el(P, (double)rn) - eos_e_el(P, (double)rn_free));
     }
   }
   if constexpr (AUD && MODE == EV_B) {
@@ -1554,11 +1615,17 @@ __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
     px += m * u;
     py += m * w;
     ke += 0.5 * m * (u * u + w * w);
-    const double rg1 = pow_gm1(r, g);
-    // specific elastic energy of the Tait law, cutoff branch below rho_c
-    eel += m * (r >= rc ? k1 * (rg1 - r0g1) + B * (1.0 / r - 1.0 / r0) : erc + P.p_cavd * (1.0 / rc - 1.0 / r));
+    if (P.eos_type == 1) {
+      eel += m * mg_e_el(P, r);
+      const double mu = r / r0 - 1.0;
+      ncav += (mu < 0.0 && P.mg_Kd * mu <= P.p_cavd) ? 1.0 : 0.0;
+    } else {
+      const double rg1 = pow_gm1(r, g);
+      // specific elastic energy of the Tait law, cutoff branch below rho_c
+      eel += m * (r >= rc ? k1 * (rg1 - r0g1) + B * (1.0 / r - 1.0 / r0) : erc + P.p_cavd * (1.0 / rc - 1.0 / r));
+      ncav += (B * (rg1 * r * inv_r0g - 1.0) <= P.p_cavd) ? 1.0 : 0.0;
+    }
     epot += m * (-(double)P.gy) * y;
-    ncav += (B * (rg1 * r * inv_r0g - 1.0) <= P.p_cavd) ? 1.0 : 0.0;
     if (!(r == r) || !(fabs(u) < 1e30) || !(fabs(w) < 1e30)) bad += 1.0;
   }
   const double v[8] = {M, px, py, ke, eel, epot, ncav, bad};
@@ -1683,7 +1750,7 @@ static void launch_ghost(const Dev& d, int n_gblk, const Buf& sb, hipStream_t st
 template <int MODE, bool BATCH, bool AUD = false>
 static void launch_pair(const Dev& d, const Buf& sb, const Buf& base, const Buf& out, hipStream_t st) {
   const dim3 g(NQ(d.n_slots)), b(PAIR_BLOCK);
-  switch (d.var) {
+  switch (d.var & 3) {
     case 0: k_pair<MODE, BATCH, AUD, 0><<<g, b, 0, st>>>(d, sb, base, out); break;
     case 1: k_pair<MODE, BATCH, AUD, 1><<<g, b, 0, st>>>(d, sb, base, out); break;
     case 2: k_pair<MODE, BATCH, AUD, 2><<<g, b, 0, st>>>(d, sb, base, out); break;
@@ -1694,9 +1761,15 @@ static void launch_pair(const Dev& d, const Buf& sb, const Buf& base, const Buf&
 template <bool BATCH>
 static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, const Buf& out) {
   const int nt = (d.n_cells + WC_SORT_TILE - 1) / WC_SORT_TILE;
-  if (mode == EV_A) k_sort<EV_A, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
-  else if (mode == EV_B) k_sort<EV_B, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
-  else k_sort<EV_EXPORT, BATCH><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+  if (d.var & 4) {
+    if (mode == EV_A) k_sort<EV_A, BATCH, true><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+    else if (mode == EV_B) k_sort<EV_B, BATCH, true><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+    else k_sort<EV_EXPORT, BATCH, true><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+  } else {
+    if (mode == EV_A) k_sort<EV_A, BATCH, false><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+    else if (mode == EV_B) k_sort<EV_B, BATCH, false><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+    else k_sort<EV_EXPORT, BATCH, false><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+  }
 }
 
 template <bool BATCH>

@@ -39,7 +39,8 @@ def test_invalid_parameters_rejected_before_allocation():
     fake_stream = C.c_void_p(0x1)  # never used: validation fails first
     out = C.c_void_p()
     for bad in (dict(dx=0.0), dict(h_over_dx=0.5), dict(disk_x0=1.0), dict(cell_size=1e-4),
-                dict(probes=[(5.0, 5.0)]), dict(cfl=0.0), dict(n_disk_ghosts=500)):
+                dict(probes=[(5.0, 5.0)]), dict(cfl=0.0), dict(n_disk_ghosts=500), dict(eos_type=2),
+                dict(eos_type=1, mg_s1=0.5), dict(eos_type=1, mg_mu_max=2.0), dict(eos_type=1, mg_gamma0=-1.0)):
         cfg = dict(workloads.C1(), **bad)
         st = L.wcsph_create(C.byref(wc.params(cfg)), None, fake_stream, C.byref(out))
         assert st == wc.E_INVALID, bad
