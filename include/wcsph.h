@@ -211,7 +211,13 @@ wcsph_status wcsph_synchronize(wcsph_ctx* ctx);
 
 /* Probe history of instance `inst` since the last read: per step n, the time
  * t_n, the step dt_n and n_probes pressures (row-major). The device ring holds
- * the last 65536 steps; older rows are dropped. */
+ * the last 65536 steps; older rows are dropped.
+ *
+ * Validity: this reader, wcsph_get_fluid, wcsph_get_disk, wcsph_adj_forward
+ * and wcsph_adj_backward return E_UNSTABLE, after writing their outputs, when
+ * the device state carries a validity flag (a non-finite value or escaped
+ * particle, a cell with more than 64 particles, a broken permutation or a
+ * cell-list scan that gave up); wcsph_last_error names the flags. */
 wcsph_status wcsph_read_probes(wcsph_ctx* ctx, int inst, double* t, double* dt, float* p,
                                int max_rows, int* rows_out);
 /* Diagnostic records of instance `inst` since the last read (ring of 4096).

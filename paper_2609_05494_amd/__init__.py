@@ -39,6 +39,15 @@ class WcsphError(RuntimeError):
         self.status = status
 
 
+class WcsphUnstable(WcsphError):
+    """E_UNSTABLE: the device state carries a validity flag. `result` holds
+    what the call read (kept for inspection)."""
+
+    def __init__(self, msg: str, result=None):
+        super().__init__(E_UNSTABLE, msg)
+        self.result = result
+
+
 class Params(C.Structure):
     _fields_ = [
         ("L", C.c_double), ("W", C.c_double), ("dx", C.c_double), ("h_over_dx", C.c_double),
@@ -232,9 +241,11 @@ class Solver:
         self.n_probes = [len(c.get("probes", [])) for c in self.cfgs]
         _live.add(self)
 
-    def _check(self, st):
+    def _check(self, st, result=None):
         if st != OK:
             msg = lib().wcsph_last_error(self.handle).decode() if self.handle else ""
+            if st == E_UNSTABLE:
+                raise WcsphUnstable(msg, result)
             raise WcsphError(st, msg)
 
     def close(self):
@@ -270,12 +281,17 @@ class Solver:
         t = np.empty(max_rows)
         dt = np.empty(max_rows)
         p = np.empty((max_rows, max(np_, 1)), dtype=np.float32)
-        self._check(lib().wcsph_read_probes(self.handle, inst, _p(t, C.c_double), _p(dt, C.c_double),
-                                            _p(p, C.c_float), max_rows, C.byref(rows)))
+        st = lib().wcsph_read_probes(self.handle, inst, _p(t, C.c_double), _p(dt, C.c_double),
+                                     _p(p, C.c_float), max_rows, C.byref(rows))
         n = rows.value
-        return t[:n].copy(), dt[:n].copy(), p[:n, :np_].copy()
+        out = (t[:n].copy(), dt[:n].copy(), p[:n, :np_].copy())
+        self._check(st, out)
+        return out
 
-    def read_diagnostics(self, inst: int = 0, max_rows: int = 4096):
+    def read_diagnostics(self, inst: int = 0, max_rows: int = 4096, check: bool = True):
+        """Diagnostic records since the last read. A flagged state raises
+        WcsphUnstable (with the records as .result), or with check=False
+        returns them with out["unstable"] = True."""
         buf = (Diag * max_rows)()
         n = C.c_int()
         st = lib().wcsph_read_diagnostics(self.handle, inst, buf, max_rows, C.byref(n))
@@ -283,25 +299,27 @@ class Solver:
         out = {k: np.array([getattr(r, k) for r in rows]) for k, _ in Diag._fields_ if k != "mom"}
         out["momx"] = np.array([r.mom[0] for r in rows])
         out["momy"] = np.array([r.mom[1] for r in rows])
-        if st == E_UNSTABLE:
+        if st == E_UNSTABLE and not check:
             out["unstable"] = True
-        else:
-            self._check(st)
+            return out
+        self._check(st, out)
         return out
 
     def fluid(self, inst: int = 0):
         nf = self.sizes[inst][0]
         t = C.c_double()
         a = [np.empty(nf) for _ in range(5)]
-        self._check(lib().wcsph_get_fluid(self.handle, inst, C.byref(t),
-                                          *[_p(x, C.c_double) for x in a], nf))
+        st = lib().wcsph_get_fluid(self.handle, inst, C.byref(t), *[_p(x, C.c_double) for x in a], nf)
+        self._check(st, (t.value, a))
         return t.value, a
 
     def disk_state(self, inst: int = 0):
         """(x, v, a) of the disk at the newest state's time."""
         o = [C.c_double() for _ in range(3)]
-        self._check(lib().wcsph_get_disk(self.handle, inst, *[C.byref(x) for x in o]))
-        return tuple(x.value for x in o)
+        st = lib().wcsph_get_disk(self.handle, inst, *[C.byref(x) for x in o])
+        out = tuple(x.value for x in o)
+        self._check(st, out)
+        return out
 
     def set_fluid(self, t, x, y, vx, vy, rho):
         arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, vx, vy, rho)]

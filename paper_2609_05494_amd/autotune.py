@@ -120,9 +120,11 @@ def write_header(path: str, shape: dict, workload: str, steps: int, results: lis
         lines.append(f"//   {tag(m['shape'])}: {m['ms_per_step']:.4f}")
     if rejected:
         lines.append("// rejected (state differs from the default shape): " + ", ".join(rejected))
+    lines.append("// A shape given on the command line (-DUCAP=... when the tuner builds its")
+    lines.append("// variants) takes precedence over the one recorded here.")
     lines.append("#pragma once")
     for k in ("UCAP", "LCAP", "PU"):
-        lines.append(f"#define {k} {int(shape[k])}")
+        lines += [f"#ifndef {k}", f"#define {k} {int(shape[k])}", "#endif"]
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -342,6 +342,26 @@ void alloc_buf(wcsph_ctx* c, Buf& b) {
 
 void sync(wcsph_ctx* c) { HC(hipStreamSynchronize(c->st)); }
 
+// The validity flags of instance inst's state (after a sync): 1 non-finite
+// state (this instance); on instance 0 for the whole context: 4 corrupted
+// permutation, 8 a cell holds more than WC_BUCKET particles, 16 the sort's
+// look-back scan gave up waiting. Sets the error text and returns true when
+// any is set; the outputs already written stay for inspection.
+bool state_invalid(wcsph_ctx* ctx, int inst) {
+  Clock k, k0;
+  HC(hipMemcpy(&k, ctx->d_clk + inst, sizeof k, hipMemcpyDeviceToHost));
+  HC(hipMemcpy(&k0, ctx->d_clk, sizeof k0, hipMemcpyDeviceToHost));
+  const unsigned bad = k.bad | (k0.bad & ~1u);
+  if (!bad) return false;
+  std::string m;
+  if (bad & 1u) m += " non-finite or escaped particle;";
+  if (bad & 4u) m += " corrupted cell-list permutation;";
+  if (bad & 8u) m += " more than " + std::to_string(WC_BUCKET) + " particles in one cell;";
+  if (bad & 16u) m += " cell-list scan timed out;";
+  ctx->err = "state invalid (flags " + std::to_string(bad) + "):" + m;
+  return true;
+}
+
 // Refill the buckets of the next sort from the state in X (after the state,
 // the clocks or the disk law changed from the host).
 void rearm(wcsph_ctx* c) {
@@ -947,6 +967,7 @@ wcsph_status wcsph_read_probes(wcsph_ctx* ctx, int inst, double* t, double* dt, 
   }
   rd += rows;
   *rows_out = (int)rows;
+  if (state_invalid(ctx, inst)) return WCSPH_E_UNSTABLE;
   API_END(ctx)
 }
 
@@ -994,22 +1015,7 @@ wcsph_status wcsph_read_diagnostics(wcsph_ctx* ctx, int inst, wcsph_diag* out, i
   }
   rd += rows;
   *n_out = (int)rows;
-  // flags: 1 non-finite state (this instance); on instance 0 for the whole
-  // context: 4 corrupted permutation, 8 a cell holds more than WC_BUCKET
-  // particles, 16 the sort's look-back scan gave up waiting
-  Clock k, k0;
-  HC(hipMemcpy(&k, ctx->d_clk + inst, sizeof k, hipMemcpyDeviceToHost));
-  HC(hipMemcpy(&k0, ctx->d_clk, sizeof k0, hipMemcpyDeviceToHost));
-  const unsigned bad = k.bad | (k0.bad & ~1u);
-  if (bad) {
-    std::string m;
-    if (bad & 1u) m += " non-finite or escaped particle;";
-    if (bad & 4u) m += " corrupted cell-list permutation;";
-    if (bad & 8u) m += " more than " + std::to_string(WC_BUCKET) + " particles in one cell;";
-    if (bad & 16u) m += " cell-list scan timed out;";
-    ctx->err = "state invalid (flags " + std::to_string(bad) + "):" + m;
-    return WCSPH_E_UNSTABLE;
-  }
+  if (state_invalid(ctx, inst)) return WCSPH_E_UNSTABLE;
   API_END(ctx)
 }
 
@@ -1041,6 +1047,7 @@ wcsph_status wcsph_get_fluid(wcsph_ctx* ctx, int inst, double* t, double* x, dou
     HC(hipMemcpy(&k, ctx->d_clk + inst, sizeof k, hipMemcpyDeviceToHost));
     *t = k.t_next;
   }
+  if (state_invalid(ctx, inst)) return WCSPH_E_UNSTABLE;
   API_END(ctx)
 }
 
@@ -1055,6 +1062,7 @@ wcsph_status wcsph_get_disk(wcsph_ctx* ctx, int inst, double* x, double* v, doub
   if (x) *x = o[0];
   if (v) *v = o[1];
   if (a) *a = o[2];
+  if (state_invalid(ctx, inst)) return WCSPH_E_UNSTABLE;
   API_END(ctx)
 }
 
@@ -1377,8 +1385,10 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   }
   ctx->hist_read[0] = ctx->steps;
   A.J = Jv;
-  A.fwd_done = true;
   if (J) *J = Jv;
+  // a run that left the valid state gives no J to differentiate
+  if (state_invalid(ctx, 0)) return WCSPH_E_UNSTABLE;
+  A.fwd_done = true;
   API_END(ctx)
 }
 
@@ -1440,6 +1450,7 @@ wcsph_status wcsph_adj_backward(wcsph_ctx* ctx, double dJ, double* grad) {
   ctx->steps = steps_after;
   sync(ctx);
   HC(hipMemcpy(grad, A.a.theta, 3 * 8, hipMemcpyDeviceToHost));
+  if (state_invalid(ctx, 0)) return WCSPH_E_UNSTABLE;
   API_END(ctx)
 }
 

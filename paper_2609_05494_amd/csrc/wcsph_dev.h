@@ -166,3 +166,16 @@ struct AdjPtrs {
 };
 
 enum { EV_A = 0, EV_B = 1, EV_EXPORT = 2 };
+
+// Look-back flag of one sort tile: the low 30 bits of the sort's epoch
+// (bits 34..63), a status (bits 32..33: 1 aggregate, 2 inclusive prefix) and
+// the value (bits 0..31). The epoch counter moves on after every sort launch
+// and wraps its 30 bits after 2^30 sorts; the match compares those bits only.
+#define WC_EPOCH_MASK 0x3fffffffu
+__host__ __device__ inline unsigned long long tile_word(uint32_t epoch, uint32_t status, uint32_t v) {
+  return ((unsigned long long)(epoch & WC_EPOCH_MASK) << 34) | ((unsigned long long)(status & 3u) << 32) |
+         (unsigned long long)v;
+}
+__host__ __device__ inline bool tile_epoch_is(unsigned long long f, uint32_t epoch) {
+  return (((uint32_t)(f >> 34) ^ epoch) & WC_EPOCH_MASK) == 0u;
+}

@@ -850,9 +850,6 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
 #ifndef SORT_LB
 #define SORT_LB 4    // look-back window: SORT_LB x 64 tiles
 #endif
-__device__ __forceinline__ unsigned long long tile_word(uint32_t epoch, uint32_t status, uint32_t v) {
-  return ((unsigned long long)epoch << 34) | ((unsigned long long)status << 32) | (unsigned long long)v;
-}
 
 // State of one particle at its old slot e, as loaded (before the EOS).
 struct Loaded {
@@ -973,9 +970,9 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
         for (int j = 0; j < SORT_LB; ++j) {
           const int kk = k - t - 64 * j;
           int spin = 0;
-          while ((uint32_t)(f[j] >> 34) != epoch && ++spin < SORT_SPIN_LIMIT)
+          while (!tile_epoch_is(f[j], epoch) && ++spin < SORT_SPIN_LIMIT)
             f[j] = __hip_atomic_load(&d.tile_flag[kk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if ((uint32_t)(f[j] >> 34) != epoch) {  // never published: give up, flag the sort
+          if (!tile_epoch_is(f[j], epoch)) {  // never published: give up, flag the sort
             atomicOr(&d.clk[0].bad, 16u);
             f[j] = tile_word(epoch, 2u, 0u);
           }

@@ -12,7 +12,15 @@
 //   u192_l16_p8: 0.0993
 //   u128_l16_p8: 0.0995
 //   u256_l16_p8: 0.1006
+// A shape given on the command line (-DUCAP=... when the tuner builds its
+// variants) takes precedence over the one recorded here.
 #pragma once
+#ifndef UCAP
 #define UCAP 128
+#endif
+#ifndef LCAP
 #define LCAP 16
+#endif
+#ifndef PU
 #define PU 4
+#endif

@@ -21,3 +21,20 @@ def test_header_defines_the_winner(tmp_path):
     got = dict(re.findall(r"#define (\w+) (\d+)", text))
     assert got == {k: str(v) for k, v in autotune.SPACE[3].items()}
     assert "rejected" in text and text.count("//   ") == len(autotune.SPACE)
+
+
+def test_command_line_shape_wins_over_the_recorded_header():
+    """A variant built with -DUCAP=... must get that shape, not the one the
+    committed header records (the preprocessor output of the kernels file)."""
+    import os
+    import subprocess
+    from paper_2609_05494_amd import build as hb
+    src = os.path.join(hb.CSRC, "wcsph_kernels.hip")
+    probe = "int ucap_probe = UCAP; int lcap_probe = LCAP; int pu_probe = PU;\n"
+    text = open(src).read() + "\n" + probe
+    cmd = [hb.hipcc(), "-x", "hip", "--offload-arch=gfx950", "--cuda-host-only", "-E", "-std=c++17",
+           "-I", os.path.join(hb.ROOT, "include"), "-I", hb.CSRC, "-DUCAP=256", "-DPU=8", "-"]
+    out = subprocess.run(cmd, input=text, capture_output=True, text=True, check=True).stdout
+    got = dict(re.findall(r"int (\w+)_probe = (\d+);", out))
+    assert got["ucap"] == "256" and got["pu"] == "8"
+    assert got["lcap"] == re.search(r"#define LCAP (\d+)", open(autotune.HEADER).read()).group(1)

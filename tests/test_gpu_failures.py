@@ -45,12 +45,21 @@ def test_non_finite_state_is_reported_at_the_next_record():
     s.load_state(_plant_nan_velocity(s, s.save_state()))
     print("[gpu] stepping a state with one non-finite velocity", flush=True)
     s.step(cfg["diag_every"])
-    d = s.read_diagnostics()
-    assert d.get("unstable", False)
-    msg = wc.lib().wcsph_last_error(s.handle).decode()
-    assert "non-finite" in msg
+    with pytest.raises(wc.WcsphUnstable) as e:
+        s.read_diagnostics()
+    assert e.value.status == wc.E_UNSTABLE and "non-finite" in str(e.value)
+    assert e.value.result["mass"].size >= 1  # the records are still returned
+    assert s.read_diagnostics(check=False)["unstable"]
+    # every reader of the flagged state says so, and still returns what it read
+    with pytest.raises(wc.WcsphUnstable) as e:
+        s.read_probes()
+    assert e.value.result[2].shape[0] == cfg["diag_every"]
+    with pytest.raises(wc.WcsphUnstable):
+        s.disk_state()
+    with pytest.raises(wc.WcsphUnstable) as e:
+        s.fluid()
     # the other particles are untouched by the planted value
-    _, (x, y, vx, vy, rho) = s.fluid()
+    _, (x, y, vx, vy, rho) = e.value.result
     assert np.isfinite(rho).sum() >= rho.size - 1
     s.close()
 

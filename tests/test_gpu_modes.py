@@ -1,0 +1,117 @@
+"""GPU parity of two configuration modes against the FP64 oracle.
+
+* The paper's own projectile law (kin_mode 1): after the velocity ramp of
+  eq. velocity-ramp the disk follows the quadratic drag of eq. drag,
+  v = v0 / (1 + k v0 tau) (Projectile Dynamics).
+* The Tait inverse for the ghost density (ghost_rho_mode 1) instead of the
+  linear acoustic branch printed with eq. adami-v.
+
+Bars as for the default workload: one evaluation from a shared state within
+1e-4 of each field's maximum; 200-step probe histories within 1e-3 of each
+probe's own peak and the step sizes within 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import shared_state
+
+pytestmark = pytest.mark.gpu
+
+wc = pytest.importorskip("paper_2609_05494_amd")
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _drag(cfg, v0=600.0):
+    """C1 with the paper's drag law from v0 (k = C_d rho_f pi R_p^2 / (2 M_p))."""
+    return dict(cfg, kin_mode=1, kin_v0=v0, kin_coef=workloads.K_DRAG)
+
+
+def _history(cfg, n):
+    print(f"[gpu] {n} steps kin_mode={cfg['kin_mode']} ghost_rho_mode={cfg['ghost_rho_mode']}", flush=True)
+    s = wc.Solver(cfg, "cuda:0")
+    s.step(n)
+    tg, dtg, pg = s.read_probes()
+    xg = s.disk_state()
+    o = oracle.Oracle(cfg)
+    o.step(n)
+    to, dto, po = o.probes()
+    xo = o.disk_state()
+    d = s.read_diagnostics()
+    s.close()
+    return (tg, dtg, pg, xg, d), (to, dto, po, xo, o.diags())
+
+
+def _check_history(g, o):
+    tg, dtg, pg, xg, d = g
+    to, dto, po, xo, do = o
+    assert pg.shape == po.shape
+    assert np.abs(dtg / dto - 1).max() < 1e-5
+    assert np.abs(tg - to).max() < 1e-5 * to[-1]
+    for k in range(po.shape[1]):
+        err = np.abs(pg[:, k] - po[:, k]).max() / np.abs(po[:, k]).max()
+        print(f"probe {k}: max rel err {err:.3e} of its peak {np.abs(po[:, k]).max():.4g} Pa")
+        assert err <= 1e-3
+    assert np.abs(d["mass"] - d["mass"][0]).max() <= 1e-12 * d["mass"][0]
+    for k in ("ke", "e_el", "w_boundary"):
+        assert abs(d[k][-1] - do[k][-1]) <= 1e-3 * abs(do[k][-1]), k
+
+
+def test_quadratic_drag_C1_200_steps():
+    cfg = _drag(workloads.C1())
+    g, o = _history(cfg, 200)
+    _check_history(g, o)
+    # the disk state after 200 steps is the closed form of eq. drag at each
+    # side's own time (the times agree to the dt bar above):
+    # v = v0 / (1 + k v0 tau), x = x0 + v0 t_ramp / 2 + ln(1 + k v0 tau) / k
+    k, v0 = cfg["kin_coef"], cfg["kin_v0"]
+    for (t, dt, _, xs, _) in (g, o):
+        tau = t[-1] + dt[-1] - cfg["kin_t_ramp"]
+        v = v0 / (1.0 + k * v0 * tau)
+        x = cfg["disk_x0"] + 0.5 * v0 * cfg["kin_t_ramp"] + np.log1p(k * v0 * tau) / k
+        assert abs(xs[1] - v) <= 1e-12 * v and abs(xs[0] - x) <= 1e-12 * x
+    # the constant-deceleration law would differ by k^2 v0^3 tau^2 at second order
+    assert abs(g[3][1] - (v0 - k * v0 * v0 * tau)) > 1e3 * 1e-12 * v0
+
+
+def test_quadratic_drag_one_evaluation_mid_run():
+    cfg = _drag(workloads.C1())
+    print("[gpu] drag law, shared state after 120 oracle steps", flush=True)
+    s, o = shared_state.shared(cfg, 120, wc, oracle)
+    g = s.export_rates()
+    r = o.eval_rates()
+    for k in ("drho", "Vx", "Vy", "gp", "gvx"):
+        assert _rel(g[k], r[k]) <= 1e-4, k
+    assert np.hypot(g["ax"] - r["ax"], g["ay"] - r["ay"]).max() <= 1e-4 * np.hypot(r["ax"], r["ay"]).max()
+    s.close()
+
+
+@pytest.mark.parametrize("steps", [0, 100])
+def test_tait_inverse_ghost_density_one_evaluation(steps):
+    cfg = dict(workloads.C1(), ghost_rho_mode=1)
+    print(f"[gpu] Tait ghost density, shared state after {steps} oracle steps", flush=True)
+    s, o = shared_state.shared(cfg, steps, wc, oracle)
+    g = s.export_rates()
+    r = o.eval_rates()
+    assert _rel(g["drho"], r["drho"]) <= 1e-4
+    d = np.hypot(g["ax"] - r["ax"], g["ay"] - r["ay"]).max()
+    assert d <= 1e-4 * np.hypot(r["ax"], r["ay"]).max()
+    for k in ("Vx", "Vy", "gp", "gvx"):
+        assert _rel(g[k], r[k]) <= 1e-4, k
+    # ghost density: the Tait inverse rho0 (1 + p/B)^(1/gamma), compared as rho - rho0
+    assert _rel(g["grho"] - cfg["rho0"], r["grho"] - cfg["rho0"]) <= 1e-3
+    if steps:
+        B = cfg["rho0"] * cfg["c0"] ** 2 / cfg["gamma"]
+        want = cfg["rho0"] * (1.0 + np.maximum(r["gp"], cfg["p_cav"]) / B) ** (1.0 / cfg["gamma"])
+        assert np.abs(r["grho"] / want - 1).max() <= 1e-12
+    s.close()
+
+
+def test_tait_inverse_ghost_density_C1_200_steps():
+    cfg = dict(workloads.C1(), ghost_rho_mode=1)
+    g, o = _history(cfg, 200)
+    _check_history(g, o)
