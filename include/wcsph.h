@@ -216,8 +216,8 @@ wcsph_status wcsph_synchronize(wcsph_ctx* ctx);
  * Validity: this reader, wcsph_get_fluid, wcsph_get_disk, wcsph_adj_forward
  * and wcsph_adj_backward return E_UNSTABLE, after writing their outputs, when
  * the device state carries a validity flag (a non-finite value or escaped
- * particle, a cell with more than 64 particles, a broken permutation or a
- * cell-list scan that gave up); wcsph_last_error names the flags. */
+ * particle, a cell with more than 64 particles or a broken permutation);
+ * wcsph_last_error names the flags. */
 wcsph_status wcsph_read_probes(wcsph_ctx* ctx, int inst, double* t, double* dt, float* p,
                                int max_rows, int* rows_out);
 /* Diagnostic records of instance `inst` since the last read (ring of 4096).
@@ -265,6 +265,14 @@ wcsph_status wcsph_export_rates(wcsph_ctx* ctx, float* drho, float* ax, float* a
  * sorted order), plus decoded positions; single instance. */
 wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, long long* idsum,
                                      double* x, double* y, size_t cap_slots);
+/* The in-support neighbours of every fluid particle as the pair-sum kernel
+ * of one evaluation on the current state finds them (single instance):
+ * count[k] and the ids nbr[k * max_per + i], i < count[k], of fluid
+ * particle k, in no particular order (ids: fluid, then wall ghosts, then
+ * ring ghosts). The state is left unchanged. E_RANGE if a
+ * particle has more than max_per (or 64) neighbours. */
+wcsph_status wcsph_export_neighbour_lists(wcsph_ctx* ctx, int* count, unsigned* nbr, int max_per,
+                                          int n_fluid);
 /* Measurement hook: average duration (ms) of the pair-sum kernel of the
  * first evaluation, re-launched `reps` (1..1000) times back to back on the
  * current sorted state between two HIP events on the context stream. The

@@ -48,6 +48,7 @@ struct HostInst {
 
 struct wcsph_ctx {
   std::string err;
+  uint32_t* nb_ids = nullptr;  // neighbour-list export buffer (allocated on first use)
   hipStream_t st = nullptr;
   wcsph_allocator al{};
   bool custom_alloc = false;
@@ -65,6 +66,8 @@ struct wcsph_ctx {
   InstParams* d_prm = nullptr;
   Clock* d_clk = nullptr;
   uint32_t* d_wallcount = nullptr;
+  uint32_t* d_wall_tot = nullptr;  // static wall-ghost entries per sort tile
+  size_t n_tiles = 0;
   uint32_t* d_gslot_save = nullptr;
   std::vector<uint32_t> h_wallcount, h_wrank;
   std::vector<int4> h_gblk;
@@ -344,8 +347,7 @@ void sync(wcsph_ctx* c) { HC(hipStreamSynchronize(c->st)); }
 
 // The validity flags of instance inst's state (after a sync): 1 non-finite
 // state (this instance); on instance 0 for the whole context: 4 corrupted
-// permutation, 8 a cell holds more than WC_BUCKET particles, 16 the sort's
-// look-back scan gave up waiting. Sets the error text and returns true when
+// permutation, 8 a cell holds more than WC_BUCKET particles. Sets the error text and returns true when
 // any is set; the outputs already written stay for inspection.
 bool state_invalid(wcsph_ctx* ctx, int inst) {
   Clock k, k0;
@@ -357,15 +359,18 @@ bool state_invalid(wcsph_ctx* ctx, int inst) {
   if (bad & 1u) m += " non-finite or escaped particle;";
   if (bad & 4u) m += " corrupted cell-list permutation;";
   if (bad & 8u) m += " more than " + std::to_string(WC_BUCKET) + " particles in one cell;";
-  if (bad & 16u) m += " cell-list scan timed out;";
   ctx->err = "state invalid (flags " + std::to_string(bad) + "):" + m;
   return true;
 }
 
 // Refill the buckets of the next sort from the state in X (after the state,
 // the clocks or the disk law changed from the host).
-void rearm(wcsph_ctx* c) {
+void arm_counts(wcsph_ctx* c) {
   HC(hipMemcpyAsync(c->d.count, c->d_wallcount, (size_t)c->n_cells * 4, hipMemcpyDeviceToDevice, c->st));
+  HC(hipMemcpyAsync(c->d.tot_a, c->d_wall_tot, c->n_tiles * 4, hipMemcpyDeviceToDevice, c->st));
+}
+void rearm(wcsph_ctx* c) {
+  arm_counts(c);
   wc_enqueue_init(c->d, c->b, c->batch, c->st);
   HC(hipGetLastError());
 }
@@ -421,7 +426,7 @@ void upload_state(wcsph_ctx* c, double t0, const double* fx, const double* fy, c
   HC(hipMemcpyAsync(c->b.X.aux, aux.data(), n * 16, hipMemcpyHostToDevice, c->st));
   if (c->batch) HC(hipMemcpyAsync(c->b.X.inst, inst.data(), n * 2, hipMemcpyHostToDevice, c->st));
   HC(hipMemcpyAsync(c->d.gslot, gslot.data(), gslot.size() * 4, hipMemcpyHostToDevice, c->st));
-  HC(hipMemcpyAsync(c->d.count, c->d_wallcount, (size_t)c->n_cells * 4, hipMemcpyDeviceToDevice, c->st));
+  arm_counts(c);
   std::vector<Clock> clk(c->n_inst);
   for (auto& k : clk) {
     std::memset(&k, 0, sizeof k);
@@ -554,9 +559,13 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.wallcount = c->d_wallcount;
   d.bucket_a = dalloc_n<uint32_t>(c, (size_t)c->n_cells * WC_BUCKET);
   d.bucket_b = dalloc_n<uint32_t>(c, (size_t)c->n_cells * WC_BUCKET);
+  // per sort tile: bucket entries (two sets) and the static wall-ghost entries
   const size_t n_tiles = ((size_t)c->n_cells + WC_SORT_TILE - 1) / WC_SORT_TILE;
-  d.tile_flag = dalloc_n<unsigned long long>(c, n_tiles);
-  d.sort_epoch = dalloc_n<uint32_t>(c, 4);
+  d.tot_a = dalloc_n<uint32_t>(c, n_tiles);
+  d.tot_b = dalloc_n<uint32_t>(c, n_tiles);
+  c->d_wall_tot = dalloc_n<uint32_t>(c, n_tiles);
+  d.wall_tot = c->d_wall_tot;
+  c->n_tiles = n_tiles;
   // (cos, sin) of the ring angles 2 pi k / nd, per instance
   std::vector<double2> ring((size_t)n_inst * WC_MAX_RING, make_double2(0.0, 0.0));
   for (int i = 0; i < n_inst; ++i)
@@ -605,10 +614,14 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   HC(hipMemsetAsync(d.hist_p, 0, (size_t)n_inst * WC_HIST_CAP * WC_MAX_PROBES * 4, c->st));
   HC(hipMemsetAsync(d.wb_part, 0, (size_t)n_inst * WC_MAX_RING * 8, c->st));
   HC(hipMemsetAsync(d.vmax_part, 0, (size_t)d.n_vpart * 4, c->st));
-  // look-back flags carry epoch 0, the first sort runs with epoch 1
-  HC(hipMemsetAsync(d.tile_flag, 0, n_tiles * 8, c->st));
-  const uint32_t epoch0[4] = {1u, 0u, 0u, 0u};
-  HC(hipMemcpyAsync(d.sort_epoch, epoch0, sizeof epoch0, hipMemcpyHostToDevice, c->st));
+  {
+    std::vector<uint32_t> wt(n_tiles, 0u);
+    for (size_t K = 0; K < (size_t)c->n_cells; ++K) wt[K / WC_SORT_TILE] += c->h_wallcount[K];
+    HC(hipMemcpyAsync(c->d_wall_tot, wt.data(), n_tiles * 4, hipMemcpyHostToDevice, c->st));
+    // set b is re-armed by the first sort; set a is armed with every fill of bucket a
+    HC(hipMemcpyAsync(d.tot_b, wt.data(), n_tiles * 4, hipMemcpyHostToDevice, c->st));
+    sync(c);  // the host vector goes out of scope
+  }
   sync(c);
   c->hist_read.assign(n_inst, 0);
   c->diag_rows.assign(n_inst, 0);
@@ -1272,6 +1285,40 @@ wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, 
     if (y) y[s] = yy;
   }
   guard.restore();
+  API_END(ctx)
+}
+
+wcsph_status wcsph_export_neighbour_lists(wcsph_ctx* ctx, int* count, unsigned* nbr, int max_per, int n_fluid) {
+  API_BEGIN(ctx)
+  require(!ctx->batch, "single-instance contexts only");
+  require(max_per >= 1 && count != nullptr && nbr != nullptr, "count and nbr required");
+  const InstParams& q = ctx->hp[0];
+  if (n_fluid < q.nf) throw WcError{WCSPH_E_RANGE, "output arrays shorter than the fluid count"};
+  if (!ctx->nb_ids) ctx->nb_ids = dalloc_n<uint32_t>(ctx, (size_t)ctx->n_slots * WC_NB_CAP);
+  HookGuard guard(ctx);
+  wc_enqueue_export_sort(ctx->d, ctx->b, false, ctx->st);
+  wc_enqueue_export_ghosts(ctx->d, ctx->b, ctx->n_gblk, ctx->st);
+  HC(hipMemsetAsync(ctx->d.nb_count, 0, (size_t)ctx->n_slots * sizeof(int), ctx->st));
+  Dev dl = ctx->d;
+  dl.nb_ids = ctx->nb_ids;
+  wc_enqueue_export_pair(dl, ctx->b, ctx->st);
+  HC(hipGetLastError());
+  sync(ctx);
+  const size_t N = ctx->n_slots;
+  auto id = d2h(ctx, ctx->b.Y.id, N);
+  auto nc = d2h(ctx, ctx->d.nb_count, N);
+  auto nb = d2h(ctx, ctx->nb_ids, N * WC_NB_CAP);
+  bool over = false;
+  for (size_t s = 0; s < N; ++s) {
+    const int k = (int)id[s] - q.id0;
+    if (k < 0 || k >= q.nf) continue;
+    count[k] = nc[s];
+    const int m = std::min(std::min(nc[s], WC_NB_CAP), max_per);
+    over |= nc[s] > m;
+    for (int i = 0; i < m; ++i) nbr[(size_t)k * max_per + i] = nb[s * WC_NB_CAP + i];
+  }
+  guard.restore();
+  if (over) throw WcError{WCSPH_E_RANGE, "a particle has more neighbours than the list holds"};
   API_END(ctx)
 }
 

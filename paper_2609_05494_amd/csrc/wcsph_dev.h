@@ -23,6 +23,7 @@
 #define WC_DIAG_BLOCKS 256     // diagnostic partial sums per instance
 #define WC_BUCKET 64           // capacity of one cell bucket (particles per cell)
 #define WC_SORT_TILE 64        // cells per block of the sort kernel
+#define WC_NB_CAP 64           // neighbour ids per particle in the neighbour-list export
 
 // Per-instance constants (read-only in kernels).
 struct InstParams {
@@ -108,8 +109,11 @@ struct Dev {
   // bucket_a by eval B (and at load) for eval A, bucket_b by eval A for eval B
   uint32_t* bucket_a;
   uint32_t* bucket_b;
-  unsigned long long* tile_flag;  // per sort tile: (epoch, status, prefix) of the look-back scan
-  uint32_t* sort_epoch;       // moved on after every sort launch
+  // entries per sort tile of the bucket set a / b, filled with the buckets;
+  // the static wall-ghost entries they are re-armed with
+  uint32_t* tot_a;
+  uint32_t* tot_b;
+  const uint32_t* wall_tot;
   uint32_t* perm;             // per slot: perm[new] = old of the last sort
   const double2* ring_cs;     // [n_inst][WC_MAX_RING] (cos, sin) of the ring angles
   uint32_t* gslot;            // per ghost: current slot
@@ -126,16 +130,17 @@ struct Dev {
   double* diag;               // [n_inst][WC_DIAG_CAP][WC_NDIAG]
   double* diag_part;          // [n_inst][WC_DIAG_BLOCKS][8] partial sums
   double* wb_part;            // [n_inst][WC_MAX_RING] x force of each ring ghost on the fluid
-  float* vmax_part;           // single instance: per corrector pair block, max |v| of its new fluid
+  float* vmax_part;           // single instance: per corrector pair wave, max |v| of its new fluid
                               // state (folded into the clock by the next first-evaluation sort)
-  int n_vpart;                // entries of vmax_part (pair blocks)
+  int n_vpart;                // entries of vmax_part and audit_part (waves of the pair pass)
   int var;                    // pass variants: bit 0 quadratic AV (some beta > 0), bit 1 cubic spline,
                               // bit 2 some instance uses the Mie-Grueneisen EOS (sort pass)
-  double* audit_part;         // energy audit (single instance, or NULL): per corrector pair block,
+  double* audit_part;         // energy audit (single instance, or NULL): per corrector pair wave,
                               // running sums of d_av, d_visc, w_delta, w_ghost, w_enforce, w_clamp
   float* xr;                  // export: [5][n_slots] rates per slot
   int* nb_count;              // export: neighbour count per slot
   long long* nb_idsum;        // export: neighbour id sum per slot
+  uint32_t* nb_ids;           // export: in-support neighbour ids per slot, [n_slots][WC_NB_CAP] (or NULL)
   double2* tape_pos;          // reverse sweep: pre-enforcement position per fluid id (or NULL)
   float4* tape_vel;           // reverse sweep: pre-enforcement (vx, vy, rho, 0) per fluid id
 };
@@ -167,15 +172,4 @@ struct AdjPtrs {
 
 enum { EV_A = 0, EV_B = 1, EV_EXPORT = 2 };
 
-// Look-back flag of one sort tile: the low 30 bits of the sort's epoch
-// (bits 34..63), a status (bits 32..33: 1 aggregate, 2 inclusive prefix) and
-// the value (bits 0..31). The epoch counter moves on after every sort launch
-// and wraps its 30 bits after 2^30 sorts; the match compares those bits only.
-#define WC_EPOCH_MASK 0x3fffffffu
-__host__ __device__ inline unsigned long long tile_word(uint32_t epoch, uint32_t status, uint32_t v) {
-  return ((unsigned long long)(epoch & WC_EPOCH_MASK) << 34) | ((unsigned long long)(status & 3u) << 32) |
-         (unsigned long long)v;
-}
-__host__ __device__ inline bool tile_epoch_is(unsigned long long f, uint32_t epoch) {
-  return (((uint32_t)(f >> 34) ^ epoch) & WC_EPOCH_MASK) == 0u;
-}
+

@@ -2,7 +2,7 @@
 //
 // One step = two evaluations (predictor-corrector). Each evaluation runs:
 //   k_sort     the cell list: stable counting sort of the slots by cell key
-//              from the cell buckets (look-back scan of the counts -> cell
+//              from the cell buckets (per-tile entry totals -> cell
 //              ranges, buckets ordered by old slot, gather into sorted
 //              order, per-particle EOS P = p/rho^2 and c); its first block
 //              advances the clock and the prescribed disk kinematics
@@ -462,7 +462,9 @@ __device__ __forceinline__ void wave_sync() {
 // the pair law over the list. A lane's candidate order and every operand
 // of a pair depend on the particle and its neighbours only, not on the
 // other slots of the wave.
-template <bool BATCH, bool AUD, int VAR>
+// EXP (export hook): every in-support neighbour's id also goes to
+// d.nb_ids[s * WC_NB_CAP + k], counted by d.nb_count[s] (zeroed by the host).
+template <bool BATCH, bool AUD, int VAR, bool EXP = false>
 __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int s, int inst, uint32_t K,
                                                bool fluid, float4 pi, float4 ai, int q, float4* U,
                                                uint8_t* my, PairAcc& acc, AudAcc& aud) {
@@ -530,6 +532,10 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
       const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
       const float ry = pi.y - E.y;
       pair_body<AUD, VAR>(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc, aud);
+      if constexpr (EXP) {
+        const uint32_t k = atomicAdd(reinterpret_cast<uint32_t*>(&d.nb_count[s]), 1u);
+        if (k < (uint32_t)WC_NB_CAP) d.nb_ids[(size_t)s * WC_NB_CAP + k] = at32(sb.id, __float_as_uint(E.w));
+      }
     };
     auto flush = [&]() __attribute__((always_inline)) {
       if (cnt > 0) {
@@ -762,57 +768,89 @@ __device__ __forceinline__ void flag_overflow(const Dev& d) {
     atomicOr(&d.clk[0].bad, 8u);
 }
 
+// The bucket set one evaluation fills for the next sort: the cell buckets,
+// and per sort tile (WC_SORT_TILE cells) the number of entries, so that the
+// sort finds each tile's place without a scan across blocks.
+struct Fill {
+  uint32_t* bucket;
+  uint32_t* tot;
+};
+__device__ __forceinline__ Fill fill_a(const Dev& d) { return Fill{d.bucket_a, d.tot_a}; }
+__device__ __forceinline__ Fill fill_b(const Dev& d) { return Fill{d.bucket_b, d.tot_b}; }
+#define WC_TILE_SHIFT 6   // log2 WC_SORT_TILE
+static_assert(WC_SORT_TILE == 1 << WC_TILE_SHIFT, "tile shift");
+
 // Slot s into the bucket of cell K for the next sort (bucket slot from the
-// cell's fill counter); an overfull cell is flagged and the slot dropped.
-__device__ __forceinline__ void bucket_put(const Dev& d, uint32_t* bucket, uint32_t K, uint32_t s) {
+// cell's fill counter); an overfull cell is flagged and the slot dropped
+// (its tile still counts it, so every later slot keeps its place).
+__device__ __forceinline__ void bucket_put(const Dev& d, const Fill& f, uint32_t K, uint32_t s) {
   const uint32_t b = atomicAdd(&d.count[K], 1u);
-  if (b < WC_BUCKET) bucket[(size_t)K * WC_BUCKET + b] = s;
+  if (b < WC_BUCKET) f.bucket[(size_t)K * WC_BUCKET + b] = s;
   else flag_overflow(d);
+  atomicAdd(&f.tot[K >> WC_TILE_SHIFT], 1u);
 }
-// bucket_put for the lanes with `act` set, one atomic per run: consecutive
-// active lanes (slots in sorted order, mostly keeping their cell) with the
-// same key share one fill-counter update and take consecutive bucket slots.
-__device__ __forceinline__ void bucket_put_wave(const Dev& d, uint32_t* bucket, bool act, uint32_t K,
-                                                uint32_t s) {
+
+// Runs of consecutive active lanes (mask A) with the same value v: whether
+// this lane heads its run, the run's head lane h and length (on the head).
+struct Run {
+  bool head;
+  int h;
+  uint32_t len, rank;
+};
+__device__ __forceinline__ Run lane_run(unsigned long long A, bool act, uint32_t v) {
   const int lane = (int)(threadIdx.x & 63);
-  const unsigned long long A = __ballot(act);
-  if (A == 0ull) return;
-  // previous active lane (below this one) and its key
+  // previous active lane (below this one) and its value
   const unsigned long long below = A & ((1ull << lane) - 1ull);
   const int prev = below ? 63 - __clzll((long long)below) : -1;
-  const uint32_t kprev = __shfl(K, prev < 0 ? lane : prev);
-  const bool head = act && (prev < 0 || kprev != K);
-  const unsigned long long H = __ballot(head);
+  const uint32_t vprev = __shfl(v, prev < 0 ? lane : prev);
+  Run r;
+  r.head = act && (prev < 0 || vprev != v);
+  const unsigned long long H = __ballot(r.head);
   // this lane's run head and the next head above it
   const unsigned long long upto = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
   const unsigned long long hb = H & upto;
-  const int h = hb ? 63 - __clzll((long long)hb) : 0;
+  r.h = hb ? 63 - __clzll((long long)hb) : 0;
   const unsigned long long above = H & ~upto;
   const int nh = above ? __ffsll((long long)above) - 1 : 64;
-  const unsigned long long from_h = ~((1ull << h) - 1ull);
+  const unsigned long long from_h = ~((1ull << r.h) - 1ull);
   const unsigned long long to_nh = nh == 64 ? ~0ull : ((1ull << nh) - 1ull);
-  const uint32_t len = (uint32_t)__popcll(A & from_h & to_nh);
-  const uint32_t rank = (uint32_t)__popcll(A & from_h & ((1ull << lane) - 1ull));
+  r.len = (uint32_t)__popcll(A & from_h & to_nh);
+  r.rank = (uint32_t)__popcll(A & from_h & ((1ull << lane) - 1ull));
+  return r;
+}
+
+// bucket_put for the lanes with `act` set, one atomic per run: consecutive
+// active lanes (slots in sorted order, mostly keeping their cell) with the
+// same key share one fill-counter update and take consecutive bucket slots;
+// the tile totals take one (non-returning) atomic per run of their own.
+__device__ __forceinline__ void bucket_put_wave(const Dev& d, const Fill& f, bool act, uint32_t K, uint32_t s) {
+  const unsigned long long A = __ballot(act);
+  if (A == 0ull) return;
+  const Run rk = lane_run(A, act, K);
   uint32_t b0 = 0;
-  if (head) b0 = atomicAdd(&d.count[K], len);
-  b0 = __shfl(b0, h);
+  if (rk.head) b0 = atomicAdd(&d.count[K], rk.len);
+  const Run rt = lane_run(A, act, K >> WC_TILE_SHIFT);
+  if (rt.head) atomicAdd(&f.tot[K >> WC_TILE_SHIFT], rt.len);
+  b0 = __shfl(b0, rk.h);
   if (!act) return;
-  const uint32_t b = b0 + rank;
-  if (b < WC_BUCKET) bucket[(size_t)K * WC_BUCKET + b] = s;
+  const uint32_t b = b0 + rk.rank;
+  if (b < WC_BUCKET) f.bucket[(size_t)K * WC_BUCKET + b] = s;
   else flag_overflow(d);
 }
 
 // Wall ghost g (static position) into its fixed place at the front of its bucket.
-__device__ __forceinline__ void bucket_put_wall(const Dev& d, const InstParams& P, uint32_t* bucket, uint32_t K,
+// (Wall ghosts are counted in the static per-cell and per-tile totals the
+// counters are re-armed with.)
+__device__ __forceinline__ void bucket_put_wall(const Dev& d, const InstParams& P, const Fill& f, uint32_t K,
                                                 int g, uint32_t s) {
-  bucket[(size_t)K * WC_BUCKET + d.wrank[P.gmap0 + g]] = s;
+  f.bucket[(size_t)K * WC_BUCKET + d.wrank[P.gmap0 + g]] = s;
 }
 
 // Disk-ring ghost k of instance inst for a disk centre at x = xc:
 // r_k = (xc, y0) + R (cos 2 pi k / nd, sin 2 pi k / nd), encoded, and put
 // into its bucket for the next sort.
 __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, int inst, int k, double xc,
-                                           const Buf& out, int s, uint32_t* bucket) {
+                                           const Buf& out, int s, const Fill& bucket) {
   const double2 cs = d.ring_cs[inst * WC_MAX_RING + k];
   const double x = xc + P.R * cs.x, y = P.disk_y0 + P.R * cs.y;
   int cx, cy;
@@ -828,28 +866,24 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
 // ---------------------------------------------------------------------------
 // The cell-list build of one evaluation in one launch: a stable counting
 // sort of the slots by cell key. The previous evaluation left every slot in
-// the bucket of its new cell (bucket order arbitrary, from atomics). Block b
+// the bucket of its new cell (bucket order arbitrary, from atomics), and
+// counted the entries per cell and per tile of WC_SORT_TILE cells. Block b
 // owns cells [b T, (b+1) T) (T = WC_SORT_TILE). Its first wave turns the
-// cells' counts into local offsets and the tile total, publishes the total
-// at once, and resolves the exclusive prefix over the preceding tiles by
-// decoupled look-back on per-tile flags (epoch-tagged, so no clearing
-// between launches) -> start[]. Meanwhile the other waves, four lanes per
-// cell, copy each bucket into LDS, fetch the state of their entries, and
-// rank each entry by old slot within its bucket (rank = number of smaller
-// entries: the sort is stable with respect to the current order). After one
-// block barrier every entry is stored at its sorted place with the
-// per-particle EOS; ghost slots and perm[new] = old are recorded. The first
-// block also advances the clocks. The epoch is moved on by the kernel that
-// follows every sort (the ghost kernel, or k_init after a test hook), so
-// each sort launch sees an epoch of its own.
+// cells' counts into local offsets and finds the tile's first sorted slot as
+// the sum of the totals of the tiles before it (a few loads per lane, no
+// waiting on other blocks) -> start[]. Meanwhile the other waves, four lanes per cell,
+// copy each bucket into LDS, fetch the state of their entries, and rank each
+// entry by old slot within its bucket (rank = number of smaller entries: the
+// sort is stable with respect to the current order). After one block
+// barrier every entry is stored at its sorted place with the per-particle
+// EOS; ghost slots and perm[new] = old are recorded. The first block also
+// advances the clocks. Each block re-arms its tile's total of the other
+// bucket set with the static wall-ghost entries, for the fills of the
+// evaluation that follows.
 #define SORT_CELL_WAVES (WC_SORT_TILE / 16)     // four lanes per cell
 #define SORT_BLOCK (64 * (1 + SORT_CELL_WAVES))  // plus the offsets wave
 #define SORT_SPEC 3  // bucket entries per lane fetched with the counts
-#define SORT_SPIN_LIMIT (1 << 20)
 #define SORT_FOLD 8  // per-block v_max entries per lane folded by a tile
-#ifndef SORT_LB
-#define SORT_LB 4    // look-back window: SORT_LB x 64 tiles
-#endif
 
 // State of one particle at its old slot e, as loaded (before the EOS).
 struct Loaded {
@@ -935,10 +969,12 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
   Loaded lv[SORT_SPEC];
   Gathered gv[SORT_SPEC];
   if (t < 64) {
-    // the tile's local offsets; the aggregate is published at once so that
-    // later tiles can look past it
-    const uint32_t epoch = *d.sort_epoch;
+    // the tile's local offsets, and the sorted slots before the tile: the
+    // entry totals of the tiles before it (filled with the buckets)
     const int K = tile * T + t;
+    const uint32_t* tot = MODE == EV_B ? d.tot_b : d.tot_a;
+    uint32_t excl = 0u;
+    for (int u = t; u < tile; u += 64) excl += tot[u];
     const uint32_t cnt = K < d.n_cells ? min(d.count[K], (uint32_t)WC_BUCKET) : 0u;  // overflow was flagged
     uint32_t incl = cnt;
     for (int o = 1; o < 64; o <<= 1) {
@@ -948,53 +984,9 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     const uint32_t total = __shfl(incl, 63);
     s_off[t] = incl - cnt;
     if (t == 63) s_off[T] = total;
-    if (t == 0)
-      __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, tile == 0 ? 2u : 1u, total), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t excl = 0;
-    if (tile > 0) {
-      // Look back over windows of SORT_LB x 64 tiles: lane l inspects tiles
-      // k - l - 64 j (j < SORT_LB), nearest first. Stop at the nearest tile
-      // holding its inclusive prefix, adding the aggregates of the tiles in
-      // between.
-      int k = tile - 1;
-      for (;;) {
-        unsigned long long f[SORT_LB];
-#pragma unroll
-        for (int j = 0; j < SORT_LB; ++j) {
-          const int kk = k - t - 64 * j;
-          f[j] = kk >= 0 ? __hip_atomic_load(&d.tile_flag[kk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                         : tile_word(epoch, 2u, 0u);
-        }
-#pragma unroll
-        for (int j = 0; j < SORT_LB; ++j) {
-          const int kk = k - t - 64 * j;
-          int spin = 0;
-          while (!tile_epoch_is(f[j], epoch) && ++spin < SORT_SPIN_LIMIT)
-            f[j] = __hip_atomic_load(&d.tile_flag[kk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (!tile_epoch_is(f[j], epoch)) {  // never published: give up, flag the sort
-            atomicOr(&d.clk[0].bad, 16u);
-            f[j] = tile_word(epoch, 2u, 0u);
-          }
-        }
-        bool found = false;
-#pragma unroll
-        for (int j = 0; j < SORT_LB; ++j) {
-          if (found) break;
-          const unsigned long long has_prefix = __ballot(((uint32_t)(f[j] >> 32) & 3u) == 2u);
-          const int stop = has_prefix ? __ffsll((long long)has_prefix) - 1 : 63;
-          uint32_t v = t <= stop ? (uint32_t)f[j] : 0u;
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-          excl += v;
-          found = has_prefix != 0;
-        }
-        if (found) break;
-        k -= 64 * SORT_LB;
-      }
-      if (t == 0)
-        __hip_atomic_store(&d.tile_flag[tile], tile_word(epoch, 2u, excl + total), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
+    for (int o = 32; o > 0; o >>= 1) excl += __shfl_xor(excl, o);
+    // re-arm the other bucket set's total of this tile
+    if (t == 0) (MODE == EV_B ? d.tot_a : d.tot_b)[tile] = d.wall_tot[tile];
     if (t == 0) s_base = excl;
     if (K < d.n_cells) d.start[K] = excl + (incl - cnt);
     if (K == d.n_cells - 1) d.start[d.n_cells] = excl + incl;
@@ -1028,7 +1020,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     for (int u = 0; u < SORT_SPEC; ++u)
       if ((uint32_t)(sub + 4 * u) < n) raw[sub + 4 * u] = e[u];
     // the state of the lane's entries is in flight during the ranking and
-    // the look-back (issued without branches; entries past the count load
+    // the offsets (issued without branches; entries past the count load
     // slot 0 and are not used)
 #pragma unroll
     for (int u = 0; u < SORT_SPEC; ++u) lv[u] = sort_load<BATCH>(d, pre, (uint32_t)(sub + 4 * u) < n ? e[u] : 0u);
@@ -1049,7 +1041,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
       for (int u = 0; u < SORT_SPEC; ++u) r[u] += x < e[u] ? 1u : 0u;
     }
 #pragma unroll
-    for (int u = 0; u < SORT_SPEC; ++u) gv[u] = sort_finish<MG>(d, lv[u]);  // EOS while the look-back runs
+    for (int u = 0; u < SORT_SPEC; ++u) gv[u] = sort_finish<MG>(d, lv[u]);  // EOS while the offsets are found
     if (fold) {
       const float w = wave_max(vp);
       if (ct == 0 && w > 0.0f) atomicMax(&d.clk[0].vmax_bits, __float_as_uint(w));
@@ -1081,7 +1073,6 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
 #define GL WC_GHOST_LANES
 template <int MODE, bool BATCH, bool CUB>
 __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(d.sort_epoch, 1u);  // for the next sort
   const int4 blk = d.gblk[blockIdx.x];
   const int inst = blk.x, kind = blk.w;
   const InstParams& P = d.prm[inst];
@@ -1280,8 +1271,12 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     }
     PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     AudAcc aud = {0.0f, 0.0f, 0.0f, 0.0f};
-    pair_sums_wave<BATCH, AUD, VAR>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6],
-                                    lst + threadIdx.x, acc, aud);
+    if (MODE == EV_EXPORT && d.nb_ids != nullptr)
+      pair_sums_wave<BATCH, AUD, VAR, true>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6],
+                                            lst + threadIdx.x, acc, aud);
+    else
+      pair_sums_wave<BATCH, AUD, VAR>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6],
+                                      lst + threadIdx.x, acc, aud);
     // fixed-order combination of the slot's lane partial sums
     acc.D = slot_sum(acc.D);
     acc.ax = slot_sum(acc.ax);
@@ -1339,7 +1334,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     out.id[s] = id;
     out.aux[s] = make_float4(rho_i, 0.0f, 0.0f, 0.0f);
     if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
-    uint32_t* bucket = MODE == EV_A ? d.bucket_b : d.bucket_a;
+    const Fill bucket = MODE == EV_A ? fill_b(d) : fill_a(d);
     if (ring >= 0) {
       double xc = C.xd_next;
       if (MODE == EV_A) {  // disk at t + dt/2
@@ -1488,7 +1483,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       a[5] += tot[5];
     }
   }
-  bucket_put_wave(d, MODE == EV_A ? d.bucket_b : d.bucket_a, lead, newkey, (uint32_t)s);
+  bucket_put_wave(d, MODE == EV_A ? fill_b(d) : fill_a(d), lead, newkey, (uint32_t)s);
   count_hits<BATCH>(clk, inst, clamp_hit, enf_hit);
   if (MODE == EV_B) {
     if constexpr (BATCH) {
@@ -1556,7 +1551,6 @@ __global__ void k_disk_query(Dev d, int i, double* out) {
 template <bool BATCH>
 __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
   const int s = blockIdx.x * WC_BLOCK + threadIdx.x;
-  if (s == 0) atomicAdd(d.sort_epoch, 1u);  // for the next sort
   const bool inr = s < d.n_slots;
   const int inst = inr ? inst_at<BATCH>(X, s) : 0;
   const InstParams& P = d.prm[inst];
@@ -1566,17 +1560,18 @@ __global__ __launch_bounds__(WC_BLOCK) void k_init(Dev d, Buf X) {
     const int local = (int)X.id[s] - P.id0;
     fl = local < P.nf;
     if (fl) {
-      bucket_put(d, d.bucket_a, X.cell[s], (uint32_t)s);
       const float4 pv = X.pv[s];
       v = fast_sqrt(pv.z * pv.z + pv.w * pv.w);
     } else if (local >= P.nf + P.nw) {
       double xc, vc, ac;
       disk_newest(P, d.clk[inst], xc, vc, ac);
-      place_ring(d, P, inst, local - P.nf - P.nw, xc, X, s, d.bucket_a);
+      place_ring(d, P, inst, local - P.nf - P.nw, xc, X, s, fill_a(d));
     } else {
-      bucket_put_wall(d, P, d.bucket_a, X.cell[s], local - P.nf, (uint32_t)s);
+      bucket_put_wall(d, P, fill_a(d), X.cell[s], local - P.nf, (uint32_t)s);
     }
   }
+  // fluid slots into their buckets, one counter update per run of equal keys
+  bucket_put_wave(d, fill_a(d), fl, fl ? X.cell[s] : 0u, (uint32_t)s);
   vmax_update<BATCH>(d.clk, inst, fl, v);
   if (!BATCH && s < d.n_vpart) d.vmax_part[s] = 0.0f;  // the loaded state's max is in the clock
 }

@@ -88,10 +88,56 @@ def test_cell_list_bit_exact(steps):
     s.close()
 
 
+def _oracle_neighbour_lists(cfg, x, y, nf, tol=1e-5):
+    """In-support neighbour sets of the nf fluid particles by O(N^2) search
+    over all particles (x, y: fluid then ghosts, index = particle id), and the
+    pairs within tol of the support radius (|r^2 - 4h^2| < tol 4h^2), where
+    the FP32 test of the encoded state may fall either side."""
+    h = cfg["h_over_dx"] * cfg["dx"]
+    s2 = 4.0 * h * h
+    wide = dict(cfg, h_over_dx=cfg["h_over_dx"] * np.sqrt(1.0 + 2.0 * tol))
+    pr = oracle.brute_pairs(wide, x, y)
+    r2 = (x[pr[:, 0]] - x[pr[:, 1]]) ** 2 + (y[pr[:, 0]] - y[pr[:, 1]]) ** 2
+    border = np.abs(r2 - s2) < tol * s2
+    inside = (r2 < s2) & ~border
+    sets = [set() for _ in range(nf)]
+    near = [set() for _ in range(nf)]
+    for (i, j), a, b in zip(pr, inside, border):
+        for u, v in ((i, j), (j, i)):
+            if u < nf:
+                if a:
+                    sets[u].add(int(v))
+                elif b:
+                    near[u].add(int(v))
+    return sets, near
+
+
+@pytest.mark.parametrize("case,steps", [("tiny", 15), ("C1", 40)])
+def test_neighbour_lists_bit_exact(case, steps):
+    """The in-support neighbour list of every fluid particle, element by
+    element, as the pair kernel finds and sums it, against the oracle's
+    O(N^2) search from the same state. Only single pairs within 1e-5 of the
+    support radius (W ~ 1e-20 there) are left out, and they are counted."""
+    cfg = workloads.tiny() if case == "tiny" else workloads.C1()
+    s, o, x, y = _sort_inputs(cfg, steps)
+    gl = s.export_neighbour_lists()
+    want, near = _oracle_neighbour_lists(cfg, x, y, s.nf)
+    n_near = sum(len(b) for b in near)
+    n_pairs = sum(len(a) for a in want)
+    print(f"[gpu] {case}: {n_pairs} in-support pair entries, {n_near} within 1e-5 of 2h")
+    assert n_near <= 1e-3 * n_pairs + 4
+    for k in range(s.nf):
+        got = gl[k].astype(np.int64)
+        assert np.unique(got).size == got.size, k  # no neighbour twice
+        assert set(got.tolist()) - near[k] == want[k], k
+    s.close()
+
+
 def test_neighbour_sets_bit_exact():
     """In-support neighbour count and neighbour-id sum of every particle from
-    the same state; pairs within 1e-5 of the support radius (W ~ 0) may fall
-    either side in FP32 and are excluded."""
+    the same state (the test hook's own walk of the 3x3 cells); pairs within
+    1e-5 of the support radius (W ~ 0) may fall either side in FP32 and are
+    excluded."""
     cfg = workloads.C1()
     s, o, x, y = _sort_inputs(cfg, 40)
     nb = s.export_neighbours()
