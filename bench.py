@@ -32,10 +32,11 @@ sys.path.insert(0, ROOT)
 
 # algorithmic work of one pair-kernel launch: per fluid particle, every
 # candidate of its 3x3 cells costs the distance test and every in-support
-# neighbour the pair law
-FLOP_PER_CANDIDATE = 7     # r_ij from cell-relative offsets, |r|^2, compare
-FLOP_PER_PAIR = 60         # kernel, continuity + delta, pressure + AV, laminar, XSPH
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (published)
+# neighbour the pair law (FMA = 2 flops; sqrt and reciprocals not counted)
+FLOP_PER_CANDIDATE = 5     # the two coordinate differences and |r|^2 as a multiply and an FMA
+FLOP_PER_PAIR = 53         # kernel, continuity + delta, pressure + AV, laminar, XSPH
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (published; packed FP32)
+PEAK_FP32_SCALAR_TFLOPS = 78.6  # the same without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E peak (published)
 # algorithmic HBM bytes of one fluid particle-step (two evaluations): the
 # state read and written by each evaluation plus the cell-list rebuild
@@ -98,21 +99,53 @@ def pair_flops(s) -> float:
         float(n_cand.mean()), float(n_pair.mean())
 
 
-def cpu_baseline(cfg, budget_s: float = 15.0):
-    import oracle
-    o = oracle.Oracle(cfg)
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        o.step(5)
-        n += 5
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=o.nf * n / dt, unit="fluid particle-steps/s", cores=threads, kind="oracle",
-                sample=f"first {n} steps of the same 300x150 mm / dx 0.5 mm workload from t = 0, "
-                       f"FP64 oracle (C++17, OpenMP), {dt:.1f} s wall")
+def host_cpu():
+    """CPU model, physical cores and logical CPUs of the host (/proc/cpuinfo),
+    and the CPUs this process may run on."""
+    model, cores, logical = "unknown", set(), 0
+    try:
+        phys = core = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name":
+                    model = v
+                    logical += 1
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return model, len(cores) or logical, logical, avail
+
+
+def cpu_baseline(steps_1: int = 12, steps_n: int = 240):
+    """The FP64 oracle on the host cores (test infrastructure, as it stands):
+    the first steps of the same 300x150 mm workload, once on one thread and
+    once on every thread the process may use, each run a fresh process."""
+    import subprocess
+    model, phys, logical, avail = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", avail))
+    threads = max(1, min(threads, avail))
+    runs = {}
+    for n_thr, steps in ((1, steps_1), (threads, steps_n)):
+        r = subprocess.run([sys.executable, "-m", "oracle.timing", "C2", str(steps), str(n_thr)],
+                           capture_output=True, text=True, check=True, cwd=ROOT, timeout=600)
+        runs[n_thr] = json.loads(r.stdout.strip().splitlines()[-1])
+    one, alln = runs[1], runs[threads]
+    return dict(value=alln["value"], unit="fluid particle-steps/s", cores=threads, kind="oracle",
+                value_1thread=one["value"], cpu_model=model, physical_cores=phys, logical_cpus=logical,
+                sample=f"FP64 oracle (C++17, OpenMP) on the same 300x150 mm / dx 0.5 mm workload from "
+                       f"t = 0: first {alln['steps']} steps on {threads} threads ({alln['wall_s']} s) and "
+                       f"first {one['steps']} steps on 1 thread ({one['wall_s']} s), stepping only")
 
 
 def batched_vs_plain(wc, workloads, steps: int):
@@ -419,9 +452,11 @@ def main():
     achieved = flops / (pair_ms * 1e-3) / 1e12
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=pair_traffic(),
+                peak_scalar=PEAK_FP32_SCALAR_TFLOPS,
+                frac_scalar=round(achieved / PEAK_FP32_SCALAR_TFLOPS, 4),
                 kernel="k_pair<EV_A>", kernel_ms=round(pair_ms, 5),
-                flop_per_launch=flops, mean_candidates=round(mean_cand, 2),
-                mean_pairs=round(mean_pair, 2))
+                flop_per_launch=flops, flop_per_candidate=FLOP_PER_CANDIDATE, flop_per_pair=FLOP_PER_PAIR,
+                mean_candidates=round(mean_cand, 2), mean_pairs=round(mean_pair, 2))
     step_gbs = ALG_BYTES_PER_PARTICLE_STEP * value / 1e9
     step_roof = dict(bound="hbm", alg_bytes_per_particle_step=ALG_BYTES_PER_PARTICLE_STEP,
                      achieved=round(step_gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
@@ -436,7 +471,7 @@ def main():
     qav = qav_run(wc, workloads, args.qav_steps, value) if args.qav_steps > 0 else None
     mg = mg_run(wc, workloads, args.mg_steps, value) if args.mg_steps > 0 else None
     paper = paper_production_run(wc, workloads) if args.paper_run else None
-    cpu = None if args.no_cpu else cpu_baseline(cfg)
+    cpu = None if args.no_cpu else cpu_baseline()
     out = {
         "metric": "WCSPH fluid particle-steps/s at 180k particles",
         "value": value,

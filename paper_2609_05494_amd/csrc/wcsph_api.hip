@@ -692,24 +692,35 @@ wcsph_status create_impl(const wcsph_params* params, int n_inst, const wcsph_all
 // and clocks (the state in X itself is left untouched by the hooks).
 struct HookGuard {
   wcsph_ctx* c;
-  std::vector<Clock> clk;
-  explicit HookGuard(wcsph_ctx* cc) : c(cc), clk(cc->n_inst) {
+  Clock one;                // single-instance contexts: no host allocation
+  std::vector<Clock> many;  // batched contexts
+  Clock* clk;
+  explicit HookGuard(wcsph_ctx* cc) : c(cc), clk(&one) {
     sync(c);
-    HC(hipMemcpy(clk.data(), c->d_clk, clk.size() * sizeof(Clock), hipMemcpyDeviceToHost));
+    if (c->n_inst > 1) {
+      many.resize(c->n_inst);
+      clk = many.data();
+    }
+    HC(hipMemcpy(clk, c->d_clk, (size_t)c->n_inst * sizeof(Clock), hipMemcpyDeviceToHost));
     HC(hipMemcpyAsync(c->d_gslot_save, c->d.gslot, (size_t)c->n_ghost * 4, hipMemcpyDeviceToDevice, c->st));
   }
   void restore() {
     HC(hipMemcpyAsync(c->d.gslot, c->d_gslot_save, (size_t)c->n_ghost * 4, hipMemcpyDeviceToDevice, c->st));
-    std::vector<Clock> k = clk;
-    for (auto& q : k) q.vmax_bits = 0u;
-    HC(hipMemcpyAsync(c->d_clk, k.data(), k.size() * sizeof(Clock), hipMemcpyHostToDevice, c->st));
+    sync(c);
+    for (int i = 0; i < c->n_inst; ++i) {
+      Clock k = clk[i];
+      k.vmax_bits = 0u;
+      HC(hipMemcpy(c->d_clk + i, &k, sizeof(Clock), hipMemcpyHostToDevice));
+    }
     rearm(c);
     sync(c);
     // the fluid |v| max is recomputed; keep the larger of it and the saved value
-    std::vector<Clock> now(c->n_inst);
-    HC(hipMemcpy(now.data(), c->d_clk, now.size() * sizeof(Clock), hipMemcpyDeviceToHost));
-    for (int i = 0; i < c->n_inst; ++i) now[i].vmax_bits = std::max(now[i].vmax_bits, clk[i].vmax_bits);
-    HC(hipMemcpy(c->d_clk, now.data(), now.size() * sizeof(Clock), hipMemcpyHostToDevice));
+    for (int i = 0; i < c->n_inst; ++i) {
+      Clock now;
+      HC(hipMemcpy(&now, c->d_clk + i, sizeof(Clock), hipMemcpyDeviceToHost));
+      now.vmax_bits = std::max(now.vmax_bits, clk[i].vmax_bits);
+      HC(hipMemcpy(c->d_clk + i, &now, sizeof(Clock), hipMemcpyHostToDevice));
+    }
   }
 };
 
@@ -718,6 +729,38 @@ std::vector<T> d2h(wcsph_ctx* c, const T* p, size_t n) {
   std::vector<T> v(n);
   if (n) HC(hipMemcpy(v.data(), p, n * sizeof(T), hipMemcpyDeviceToHost));
   return v;
+}
+
+// The neighbour-list export: one cell-list build, ghost pass and pair pass
+// of the current state with the export buffer `buf` (per fluid index: the
+// count, then WC_NB_CAP ids), copied into the caller's count[nf] and
+// nbr[nf][max_per] arrays. No allocation; the caller restores the state.
+void check_list_export(wcsph_ctx* ctx, const int* count, const unsigned* nbr, int max_per, int n_fluid) {
+  require(!ctx->batch, "single-instance contexts only");
+  require(max_per >= 1 && count != nullptr && nbr != nullptr, "count and nbr required");
+  if (n_fluid < ctx->hp[0].nf) throw WcError{WCSPH_E_RANGE, "output arrays shorter than the fluid count"};
+}
+size_t list_export_words(const wcsph_ctx* ctx) { return (size_t)ctx->hp[0].nf * (WC_NB_CAP + 1); }
+void list_export(wcsph_ctx* ctx, uint32_t* buf, int* count, unsigned* nbr, int max_per) {
+  const size_t nf = (size_t)ctx->hp[0].nf;
+  wc_enqueue_export_sort(ctx->d, ctx->b, false, ctx->st);
+  wc_enqueue_export_ghosts(ctx->d, ctx->b, ctx->n_gblk, ctx->st);
+  HC(hipMemsetAsync(buf, 0, nf * sizeof(uint32_t), ctx->st));
+  Dev dl = ctx->d;
+  dl.nb_ids = buf;
+  wc_enqueue_export_pair(dl, ctx->b, ctx->st);
+  HC(hipGetLastError());
+  HC(hipMemcpyAsync(count, buf, nf * sizeof(int), hipMemcpyDeviceToHost, ctx->st));
+  const size_t w = (size_t)std::min(max_per, WC_NB_CAP) * sizeof(uint32_t);
+  HC(hipMemcpy2DAsync(nbr, (size_t)max_per * sizeof(unsigned), buf + nf, WC_NB_CAP * sizeof(uint32_t), w, nf,
+                      hipMemcpyDeviceToHost, ctx->st));
+  sync(ctx);
+}
+bool list_export_over(const wcsph_ctx* ctx, const int* count, int max_per) {
+  const int cap = std::min(max_per, WC_NB_CAP);
+  for (int k = 0; k < ctx->hp[0].nf; ++k)
+    if (count[k] > cap) return true;
+  return false;
 }
 
 // Device-side checkpoint of the whole evolving state (X buffer, clocks,
@@ -1290,35 +1333,12 @@ wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, 
 
 wcsph_status wcsph_export_neighbour_lists(wcsph_ctx* ctx, int* count, unsigned* nbr, int max_per, int n_fluid) {
   API_BEGIN(ctx)
-  require(!ctx->batch, "single-instance contexts only");
-  require(max_per >= 1 && count != nullptr && nbr != nullptr, "count and nbr required");
-  const InstParams& q = ctx->hp[0];
-  if (n_fluid < q.nf) throw WcError{WCSPH_E_RANGE, "output arrays shorter than the fluid count"};
-  if (!ctx->nb_ids) ctx->nb_ids = dalloc_n<uint32_t>(ctx, (size_t)ctx->n_slots * WC_NB_CAP);
+  check_list_export(ctx, count, nbr, max_per, n_fluid);
+  if (!ctx->nb_ids) ctx->nb_ids = dalloc_n<uint32_t>(ctx, list_export_words(ctx));
   HookGuard guard(ctx);
-  wc_enqueue_export_sort(ctx->d, ctx->b, false, ctx->st);
-  wc_enqueue_export_ghosts(ctx->d, ctx->b, ctx->n_gblk, ctx->st);
-  HC(hipMemsetAsync(ctx->d.nb_count, 0, (size_t)ctx->n_slots * sizeof(int), ctx->st));
-  Dev dl = ctx->d;
-  dl.nb_ids = ctx->nb_ids;
-  wc_enqueue_export_pair(dl, ctx->b, ctx->st);
-  HC(hipGetLastError());
-  sync(ctx);
-  const size_t N = ctx->n_slots;
-  auto id = d2h(ctx, ctx->b.Y.id, N);
-  auto nc = d2h(ctx, ctx->d.nb_count, N);
-  auto nb = d2h(ctx, ctx->nb_ids, N * WC_NB_CAP);
-  bool over = false;
-  for (size_t s = 0; s < N; ++s) {
-    const int k = (int)id[s] - q.id0;
-    if (k < 0 || k >= q.nf) continue;
-    count[k] = nc[s];
-    const int m = std::min(std::min(nc[s], WC_NB_CAP), max_per);
-    over |= nc[s] > m;
-    for (int i = 0; i < m; ++i) nbr[(size_t)k * max_per + i] = nb[s * WC_NB_CAP + i];
-  }
+  list_export(ctx, ctx->nb_ids, count, nbr, max_per);
   guard.restore();
-  if (over) throw WcError{WCSPH_E_RANGE, "a particle has more neighbours than the list holds"};
+  if (list_export_over(ctx, count, max_per)) throw WcError{WCSPH_E_RANGE, "a particle has more neighbours than the list holds"};
   API_END(ctx)
 }
 

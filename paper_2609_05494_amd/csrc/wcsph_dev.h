@@ -140,7 +140,7 @@ struct Dev {
   float* xr;                  // export: [5][n_slots] rates per slot
   int* nb_count;              // export: neighbour count per slot
   long long* nb_idsum;        // export: neighbour id sum per slot
-  uint32_t* nb_ids;           // export: in-support neighbour ids per slot, [n_slots][WC_NB_CAP] (or NULL)
+  uint32_t* nb_ids;           // export: per fluid index, neighbour count [nf], then ids [nf][WC_NB_CAP] (or NULL)
   double2* tape_pos;          // reverse sweep: pre-enforcement position per fluid id (or NULL)
   float4* tape_vel;           // reverse sweep: pre-enforcement (vx, vy, rho, 0) per fluid id
 };

@@ -462,8 +462,9 @@ __device__ __forceinline__ void wave_sync() {
 // the pair law over the list. A lane's candidate order and every operand
 // of a pair depend on the particle and its neighbours only, not on the
 // other slots of the wave.
-// EXP (export hook): every in-support neighbour's id also goes to
-// d.nb_ids[s * WC_NB_CAP + k], counted by d.nb_count[s] (zeroed by the host).
+// EXP (export hook, single instance): every in-support neighbour's id also
+// goes to the export buffer d.nb_ids by fluid index f: the count at [f]
+// (zeroed by the host), the ids at [nf + f * WC_NB_CAP + k].
 template <bool BATCH, bool AUD, int VAR, bool EXP = false>
 __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int s, int inst, uint32_t K,
                                                bool fluid, float4 pi, float4 ai, int q, float4* U,
@@ -533,8 +534,10 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
       const float ry = pi.y - E.y;
       pair_body<AUD, VAR>(P, pi, rhoi, Pi, ci, rx, ry, rx * rx + ry * ry, pj, aj, acc, aud);
       if constexpr (EXP) {
-        const uint32_t k = atomicAdd(reinterpret_cast<uint32_t*>(&d.nb_count[s]), 1u);
-        if (k < (uint32_t)WC_NB_CAP) d.nb_ids[(size_t)s * WC_NB_CAP + k] = at32(sb.id, __float_as_uint(E.w));
+        const uint32_t f = at32(sb.id, (uint32_t)s) - (uint32_t)IP.id0;
+        const uint32_t k = atomicAdd(&d.nb_ids[f], 1u);
+        if (k < (uint32_t)WC_NB_CAP)
+          d.nb_ids[(size_t)IP.nf + (size_t)f * WC_NB_CAP + k] = at32(sb.id, __float_as_uint(E.w));
       }
     };
     auto flush = [&]() __attribute__((always_inline)) {
