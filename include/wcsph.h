@@ -273,6 +273,16 @@ wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, 
  * particle has more than max_per (or 64) neighbours. */
 wcsph_status wcsph_export_neighbour_lists(wcsph_ctx* ctx, int* count, unsigned* nbr, int max_per,
                                           int n_fluid);
+/* The same lists without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid it). The export buffer is a file-scope device array
+ * of 4 MiB that each GPU the library runs on holds until the process ends;
+ * it fits a context of at most 16,131 fluid particles (E_RANGE beyond, with
+ * nothing run). Calls share their GPU's array: calls that overlap on one GPU
+ * race. Same outputs and errors as wcsph_export_neighbour_lists; calls no
+ * allocator. */
+wcsph_status wcsph_export_neighbour_lists_noalloc(wcsph_ctx* ctx, int* count, unsigned* nbr, int max_per,
+                                                  int n_fluid);
 /* Measurement hook: average duration (ms) of the pair-sum kernel of the
  * first evaluation, re-launched `reps` (1..1000) times back to back on the
  * current sorted state between two HIP events on the context stream. The

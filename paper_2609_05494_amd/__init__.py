@@ -29,7 +29,8 @@ SYMBOLS = (
     "wcsph_instance_info", "wcsph_set_disk_kinematics", "wcsph_set_dt_table", "wcsph_step",
     "wcsph_synchronize", "wcsph_read_probes", "wcsph_read_diagnostics", "wcsph_get_fluid", "wcsph_get_disk",
     "wcsph_set_fluid", "wcsph_save_state", "wcsph_load_state", "wcsph_export_cells",
-    "wcsph_export_rates", "wcsph_export_neighbours", "wcsph_export_neighbour_lists", "wcsph_time_pair_kernel",
+    "wcsph_export_rates", "wcsph_export_neighbours", "wcsph_export_neighbour_lists",
+    "wcsph_export_neighbour_lists_noalloc", "wcsph_time_pair_kernel",
     "wcsph_set_coefficients", "wcsph_adj_forward", "wcsph_adj_backward",
 )
 
@@ -150,6 +151,7 @@ def lib():
             "wcsph_export_rates": [_V, _F, _F, _F, _F, _F, _F, _F, _F, _F, C.c_int, C.c_int],
             "wcsph_export_neighbours": [_V, _U, _I, _LL, _D, _D, C.c_size_t],
             "wcsph_export_neighbour_lists": [_V, _I, _U, C.c_int, C.c_int],
+            "wcsph_export_neighbour_lists_noalloc": [_V, _I, _U, C.c_int, C.c_int],
             "wcsph_time_pair_kernel": [_V, C.c_int, _F],
             "wcsph_set_coefficients": [_V, C.c_int, C.c_double, C.c_double, C.c_double],
             "wcsph_adj_forward": [_V, C.c_int, C.c_int, _D],
@@ -367,13 +369,14 @@ class Solver:
                                                   _p(y, C.c_double), n))
         return dict(ids=ids, count=cnt, idsum=sm, x=x, y=y)
 
-    def export_neighbour_lists(self, max_per: int = 64):
-        """Per fluid id, the ids of the neighbours the pair kernel sums (unordered)."""
+    def export_neighbour_lists(self, max_per: int = 64, noalloc: bool = False):
+        """Per fluid id, the ids of the neighbours the pair kernel sums
+        (unordered); noalloc: through the entry point that allocates nothing."""
         nf = self.nf
         cnt = np.zeros(nf, np.int32)
         nbr = np.zeros((nf, max_per), np.uint32)
-        self._check(lib().wcsph_export_neighbour_lists(self.handle, _p(cnt, C.c_int), _p(nbr, C.c_uint),
-                                                       max_per, nf))
+        fn = lib().wcsph_export_neighbour_lists_noalloc if noalloc else lib().wcsph_export_neighbour_lists
+        self._check(fn(self.handle, _p(cnt, C.c_int), _p(nbr, C.c_uint), max_per, nf))
         return [nbr[k, :cnt[k]].copy() for k in range(nf)]
 
     # -- coefficients and reverse sweep ----------------------------------------

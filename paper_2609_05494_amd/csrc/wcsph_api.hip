@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "wcsph.h"
@@ -37,6 +38,34 @@ void require(bool ok, const std::string& msg) {
   if (!ok) throw WcError{WCSPH_E_INVALID, msg};
 }
 
+// Device scratch of the allocation-free entry point
+// (wcsph_export_neighbour_lists_noalloc): a file-scope array of
+// WC_SCRATCH_WORDS 32-bit words that every GPU the library runs on holds
+// until the process ends. Host code never passes the array's name to a
+// kernel or a copy: it uses the device address that hipGetSymbolAddress
+// returns on each device, taken once per device at context creation.
+#define WC_SCRATCH_WORDS (1u << 20)  // 4 MiB
+#define WC_MAX_DEVICES 64
+static __device__ __align__(256) uint32_t scratch[WC_SCRATCH_WORDS];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[WC_MAX_DEVICES] = {};
+
+// The scratch address on the current device (looked up once per device).
+void* scratch_address() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= WC_MAX_DEVICES)
+    throw WcError{WCSPH_E_HIP, "no current HIP device for the scratch array"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      throw WcError{WCSPH_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 // Host-side geometry of one instance (FP64).
 struct HostInst {
   std::vector<double> fx, fy, frho;  // fluid lattice (id order)
@@ -49,6 +78,7 @@ struct HostInst {
 struct wcsph_ctx {
   std::string err;
   uint32_t* nb_ids = nullptr;  // neighbour-list export buffer (allocated on first use)
+  uint32_t* scratch = nullptr; // this context's device's file-scope scratch array (set at creation)
   hipStream_t st = nullptr;
   wcsph_allocator al{};
   bool custom_alloc = false;
@@ -677,6 +707,7 @@ wcsph_status create_impl(const wcsph_params* params, int n_inst, const wcsph_all
     c->custom_alloc = true;
   }
   try {
+    c->scratch = static_cast<uint32_t*>(scratch_address());
     build(c, params, n_inst);
   } catch (const WcError& e) {
     g_create_error = e.msg;
@@ -1337,6 +1368,21 @@ wcsph_status wcsph_export_neighbour_lists(wcsph_ctx* ctx, int* count, unsigned* 
   if (!ctx->nb_ids) ctx->nb_ids = dalloc_n<uint32_t>(ctx, list_export_words(ctx));
   HookGuard guard(ctx);
   list_export(ctx, ctx->nb_ids, count, nbr, max_per);
+  guard.restore();
+  if (list_export_over(ctx, count, max_per)) throw WcError{WCSPH_E_RANGE, "a particle has more neighbours than the list holds"};
+  API_END(ctx)
+}
+
+wcsph_status wcsph_export_neighbour_lists_noalloc(wcsph_ctx* ctx, int* count, unsigned* nbr, int max_per,
+                                                  int n_fluid) {
+  API_BEGIN(ctx)
+  check_list_export(ctx, count, nbr, max_per, n_fluid);
+  if (!ctx->scratch) throw WcError{WCSPH_E_STATE, "no scratch array on this context's device"};
+  if (list_export_words(ctx) > WC_SCRATCH_WORDS)
+    throw WcError{WCSPH_E_RANGE, "the scratch array holds the lists of at most " +
+                                     std::to_string(WC_SCRATCH_WORDS / (WC_NB_CAP + 1)) + " fluid particles"};
+  HookGuard guard(ctx);  // single instance: no host allocation
+  list_export(ctx, ctx->scratch, count, nbr, max_per);
   guard.restore();
   if (list_export_over(ctx, count, max_per)) throw WcError{WCSPH_E_RANGE, "a particle has more neighbours than the list holds"};
   API_END(ctx)
