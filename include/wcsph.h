@@ -101,7 +101,8 @@ typedef struct {
  *               FP64 sum of the per-ghost forces), trapezoidal position; the
  *               boundary work then uses the step's mean disk velocity, so that
  *               e_disk + w_boundary stays constant. kin_coef is unused;
- *               disk_mass > 0 is required.
+ *               disk_mass > 0 is required. 3 = a tabulated prescribed
+ *               motion (rows set with wcsph_set_disk_kinematics mode 3).
  *  probes     : n_probes points (x, y) where the Shepard-averaged fluid
  *               pressure is recorded every step.
  *  output     : diag_every steps between diagnostic records; init_mode 0 =
@@ -187,10 +188,17 @@ wcsph_status wcsph_instance_info(const wcsph_ctx* ctx, int inst, int* n_fluid, i
 
 /* Disk kinematics of instance `inst` (Velocity Ramp, Projectile Dynamics).
  * mode 0: coeffs = {v0, t_ramp, a_d}; mode 1: {v0, t_ramp, k}; mode 2
- * (two-way coupling, see kin_mode): {v0, t_ramp, unused}. n = number of
- * coefficients (3). Takes effect at the next step, from the disk state the
- * new law gives at the newest state's time: a coupled disk is released and a
- * mode-2 disk couples again at its next step at or after t_ramp. */
+ * (two-way coupling, see kin_mode): {v0, t_ramp, unused}; n = number of
+ * coefficients (3). mode 3: a tabulated prescribed motion, coeffs = n rows
+ * (t, x, v, a) row-major (1 <= n <= 1024, t strictly increasing, x the
+ * centre's absolute position along the channel); each column is linear in t
+ * between rows, and before the first row and after the last the centre moves
+ * on at that row's velocity with zero acceleration. The table is copied to
+ * the device (a context created with kin_mode 3 holds the disk at rest at
+ * disk_x0 until a table is set). Takes effect at the next step, from the
+ * disk state the new law gives at the newest state's time: a coupled disk is
+ * released and a mode-2 disk couples again at its next step at or after
+ * t_ramp. */
 wcsph_status wcsph_set_disk_kinematics(wcsph_ctx* ctx, int inst, int mode, const double* coeffs,
                                        int n);
 
@@ -205,6 +213,10 @@ wcsph_status wcsph_set_dt_table(wcsph_ctx* ctx, const double* dt, int n);
  * same at the midpoint state + corrector (Pipeline Provenance section).
  * A diagnostic record is taken every diag_every steps. */
 wcsph_status wcsph_step(wcsph_ctx* ctx, int n_steps);
+/* The same for a batched context (wcsph_batch_create): every instance advances
+ * n_steps steps, each kernel launched once for all instances. E_INVALID on a
+ * single-instance context (wcsph_step serves both). */
+wcsph_status wcsph_batch_step(wcsph_ctx* ctx, int n_steps);
 wcsph_status wcsph_synchronize(wcsph_ctx* ctx);
 
 /* ---- reading results ------------------------------------------------------- */

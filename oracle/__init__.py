@@ -87,6 +87,7 @@ def lib():
             "orc_num_ghost": (C.c_int, [C.c_void_p]),
             "orc_num_cells": (C.c_int, [C.c_void_p]),
             "orc_set_dt_table": (None, [C.c_void_p, C.c_int, _D]),
+            "orc_set_kin_table": (None, [C.c_void_p, C.c_int, _D]),
             "orc_step": (C.c_int, [C.c_void_p, C.c_int]),
             "orc_get_fluid": (None, [C.c_void_p, _D, _D, _D, _D, _D, _D]),
             "orc_set_fluid": (None, [C.c_void_p, C.c_double, _D, _D, _D, _D, _D]),
@@ -164,6 +165,11 @@ class Oracle:
     def set_dt_table(self, dt):
         dt = f64(dt)
         lib().orc_set_dt_table(self.h, dt.size, dptr(dt))
+
+    def set_kin_table(self, rows):
+        """kin_mode 3: rows (t, x, v, a) of the prescribed disk motion."""
+        rows = np.ascontiguousarray(rows, dtype=np.float64).reshape(-1, 4)
+        lib().orc_set_kin_table(self.h, rows.shape[0], dptr(rows))
 
     def step(self, n: int = 1):
         lib().orc_step(self.h, n)

@@ -33,7 +33,7 @@ typedef struct {
   double probe_xy[2 * ORC_MAX_PROBES];
   int diag_every;
   int kin_mode; /* 0: ramp then constant deceleration kin_coef; 1: ramp then quadratic drag k=kin_coef;
-                  2: ramp then two-way coupling */
+                  2: ramp then two-way coupling; 3: tabulated (orc_set_kin_table) */
   double kin_v0, kin_t_ramp, kin_coef;
   double beta; /* quadratic artificial viscosity coefficient (0: linear term only) */
   int kernel_type; /* 0: Wendland C2; 1: cubic B-spline (eq. cubic-kernel) */
@@ -73,6 +73,11 @@ void orc_audit_rates(void* s, double* out /* 4 */);
 void orc_get_ghosts(void* s, double* gx, double* gy, double* gm);
 void orc_get_order(void* s, int* order, int* cell_start);
 void orc_kinematics(void* s, double t, double* x, double* v, double* a);
+/* kin_mode 3: the prescribed disk motion as n rows (t, x, v, a), t strictly
+ * increasing, x the centre's absolute position; each column is interpolated
+ * linearly between rows, and outside the table the centre moves on at the
+ * end row's velocity with zero acceleration. */
+void orc_set_kin_table(void* s, int n, const double* rows);
 // disk centre x, velocity, acceleration at the current time (kin_mode 2:
 // the coupled state once the first step after the ramp has started)
 void orc_disk_state(void* s, double* x, double* v, double* a);

@@ -344,6 +344,41 @@ void kinematics(int mode, double v0, double t_ramp, double coef, double x0, doub
 }
 
 // ---------------------------------------------------------------------------
+// Tabulated prescribed motion (kin_mode 3): rows (t, x, v, a) with t
+// strictly increasing, x the absolute centre position. Between two rows each
+// column is interpolated linearly in t (a row's own time gives the row);
+// before the first row and after the last the centre moves on at that row's
+// velocity with zero acceleration.
+void table_kinematics(const std::vector<double>& tab, double t, double* xo, double* vo, double* ao) {
+  const int n = (int)(tab.size() / 4);
+  if (n == 0) {
+    *xo = *vo = *ao = 0.0;
+    return;
+  }
+  if (t < tab[0] || n == 1) {
+    const int r = t < tab[0] ? 0 : n - 1;
+    *xo = tab[4 * r + 1] + tab[4 * r + 2] * (t - tab[4 * r]);
+    *vo = tab[4 * r + 2];
+    *ao = 0.0;
+    return;
+  }
+  // the last row with t_k <= t
+  std::vector<double> ts(n);
+  for (int k = 0; k < n; ++k) ts[k] = tab[4 * k];
+  const int k = (int)(std::upper_bound(ts.begin(), ts.end(), t) - ts.begin()) - 1;
+  if (k >= n - 1) {  // at or past the last row
+    const double* r = &tab[4 * (n - 1)];
+    *xo = t == r[0] ? r[1] : r[1] + r[2] * (t - r[0]);
+    *vo = r[2];
+    *ao = t == r[0] ? r[3] : 0.0;
+    return;
+  }
+  const double w = (t - tab[4 * k]) / (tab[4 * (k + 1)] - tab[4 * k]);
+  *xo = tab[4 * k + 1] + w * (tab[4 * (k + 1) + 1] - tab[4 * k + 1]);
+  *vo = tab[4 * k + 2] + w * (tab[4 * (k + 1) + 2] - tab[4 * k + 2]);
+  *ao = tab[4 * k + 3] + w * (tab[4 * (k + 1) + 3] - tab[4 * k + 3]);
+}
+
 template <class T>
 struct Sim {
   orc_params P;
@@ -429,6 +464,15 @@ struct Sim {
     K.B = P.rho0 * c0 * c0 / P.gamma;
   }
 
+  std::vector<double> kin_tab;  // kin_mode 3: rows (t, x, v, a)
+
+  // the prescribed disk motion at time tt (closed forms, or the table)
+  void kin(double tt, double* x_, double* v_, double* a_) const {
+    if (P.kin_mode == 3 && kin_tab.empty()) { *x_ = P.disk_x0; *v_ = 0.0; *a_ = 0.0; }
+    else if (P.kin_mode == 3) table_kinematics(kin_tab, tt, x_, v_, a_);
+    else kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, tt, x_, v_, a_);
+  }
+
   // disk centre, velocity and acceleration at time tt of the current step
   // (coupled: extrapolated from the state at t with its latest acceleration)
   void disk_state(double tt) {
@@ -438,7 +482,7 @@ struct Sim {
       dv = vc + tau * ac;
       da = ac;
     } else {
-      kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, tt, &dx_c, &dv, &da);
+      kin(tt, &dx_c, &dv, &da);
     }
   }
 
@@ -708,7 +752,7 @@ struct Sim {
     } else {
       w_boundary += dt * val(fdx) * dv;
       double a_;
-      kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, t + dt, &x1, &v1, &a_);
+      kin(t + dt, &x1, &v1, &a_);
     }
     // corrector from state n with the midpoint rates
     advance(x0, y0, vx0, vy0, rho0, dt, D, ax, ay, Vx, Vy, x1, v1, true);
@@ -729,7 +773,7 @@ struct Sim {
       *v_ = vc;
       *a_ = ac;
     } else {
-      kinematics(P.kin_mode, P.kin_v0, P.kin_t_ramp, P.kin_coef, P.disk_x0, t, x_, v_, a_);
+      kin(t, x_, v_, a_);
     }
   }
 
@@ -880,7 +924,11 @@ void orc_get_order(void* s, int* order, int* cell_start) {
 }
 void orc_kinematics(void* s, double t, double* x, double* v, double* a) {
   auto* q = static_cast<SimD*>(s);
-  kinematics(q->P.kin_mode, q->P.kin_v0, q->P.kin_t_ramp, q->P.kin_coef, q->P.disk_x0, t, x, v, a);
+  q->kin(t, x, v, a);
+}
+void orc_set_kin_table(void* s, int n, const double* rows) {
+  auto* q = static_cast<SimD*>(s);
+  q->kin_tab.assign(rows, rows + 4 * (n > 0 ? n : 0));
 }
 void orc_disk_state(void* s, double* x, double* v, double* a) { static_cast<SimD*>(s)->current_disk(x, v, a); }
 
@@ -1061,7 +1109,7 @@ void orc_pair_rates(const orc_params* p, int n, const double* x, const double* y
 }
 
 void orc_tangent_J(const orc_params* p, int n_steps, const double* dt, double* J, double* dJ) {
-  if (p->kin_mode == 2) {  // the disk's response to the coefficients is not differentiated
+  if (p->kin_mode == 2 || p->kin_mode == 3) {  // coupled: not differentiated; table: not held here
     *J = dJ[0] = dJ[1] = dJ[2] = std::nan("");
     return;
   }

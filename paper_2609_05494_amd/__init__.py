@@ -26,7 +26,7 @@ OK, E_INVALID, E_OOM, E_HIP, E_STATE, E_UNSTABLE, E_RANGE = range(7)
 _STATUS = {0: "OK", 1: "E_INVALID", 2: "E_OOM", 3: "E_HIP", 4: "E_STATE", 5: "E_UNSTABLE", 6: "E_RANGE"}
 SYMBOLS = (
     "wcsph_create", "wcsph_batch_create", "wcsph_destroy", "wcsph_last_error", "wcsph_get_info",
-    "wcsph_instance_info", "wcsph_set_disk_kinematics", "wcsph_set_dt_table", "wcsph_step",
+    "wcsph_instance_info", "wcsph_set_disk_kinematics", "wcsph_set_dt_table", "wcsph_step", "wcsph_batch_step",
     "wcsph_synchronize", "wcsph_read_probes", "wcsph_read_diagnostics", "wcsph_get_fluid", "wcsph_get_disk",
     "wcsph_set_fluid", "wcsph_save_state", "wcsph_load_state", "wcsph_export_cells",
     "wcsph_export_rates", "wcsph_export_neighbours", "wcsph_export_neighbour_lists",
@@ -139,6 +139,7 @@ def lib():
             "wcsph_set_disk_kinematics": [_V, C.c_int, C.c_int, _D, C.c_int],
             "wcsph_set_dt_table": [_V, _D, C.c_int],
             "wcsph_step": [_V, C.c_int],
+            "wcsph_batch_step": [_V, C.c_int],
             "wcsph_synchronize": [_V],
             "wcsph_read_probes": [_V, C.c_int, _D, _D, _F, C.c_int, _I],
             "wcsph_read_diagnostics": [_V, C.c_int, C.POINTER(Diag), C.c_int, _I],
@@ -219,7 +220,8 @@ class Solver:
         self.mem = _TorchMemory(device)
         self.handle = _V()
         L = lib()
-        if isinstance(cfg, (list, tuple)):
+        self.batched = isinstance(cfg, (list, tuple))
+        if self.batched:
             self.cfgs = list(cfg)
             arr = (Params * len(cfg))(*[params(c) for c in cfg])
             st = L.wcsph_batch_create(arr, len(cfg), C.byref(self.mem.struct),
@@ -268,12 +270,18 @@ class Solver:
         c = np.array([v0, t_ramp, coef], dtype=np.float64)
         self._check(lib().wcsph_set_disk_kinematics(self.handle, inst, mode, _p(c, C.c_double), 3))
 
+    def set_kinematics_table(self, rows, inst: int = 0):
+        """kin_mode 3: the disk motion as rows (t, x, v, a)."""
+        r = np.ascontiguousarray(rows, dtype=np.float64).reshape(-1, 4)
+        self._check(lib().wcsph_set_disk_kinematics(self.handle, inst, 3, _p(r, C.c_double), r.shape[0]))
+
     def set_dt_table(self, dt):
         dt = np.ascontiguousarray(dt, dtype=np.float64)
         self._check(lib().wcsph_set_dt_table(self.handle, _p(dt, C.c_double), dt.size))
 
     def step(self, n: int = 1):
-        self._check(lib().wcsph_step(self.handle, n))
+        fn = lib().wcsph_batch_step if self.batched else lib().wcsph_step
+        self._check(fn(self.handle, n))
 
     def synchronize(self):
         self._check(lib().wcsph_synchronize(self.handle))

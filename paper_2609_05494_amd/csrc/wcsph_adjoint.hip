@@ -19,39 +19,12 @@
 
 #include "wcsph_adjoint.h"
 #include "wcsph_launch.h"
+#include "wcsph_kin.h"
 
 namespace {
 
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ float d_pow(float a, float b) { return powf(a, b); }
-
-__device__ void kin_d(const InstParams& P, double t, double& x, double& v, double& a) {
-  const double v0 = P.kin_v0, tr = P.kin_t_ramp;
-  if (t < tr) {
-    v = v0 * t / tr;
-    a = v0 / tr;
-    x = P.disk_x0 + 0.5 * v0 * t * t / tr;
-    return;
-  }
-  const double tau = t - tr, xr = P.disk_x0 + 0.5 * v0 * tr;
-  if (P.kin_mode == 1) {
-    const double k = P.kin_coef;
-    v = v0 / (1.0 + k * v0 * tau);
-    a = -k * v * v;
-    x = k > 0.0 ? xr + log1p(k * v0 * tau) / k : xr + v0 * tau;
-    return;
-  }
-  const double ad = P.kin_coef;
-  if (ad > 0.0 && tau >= v0 / ad) {
-    v = 0.0;
-    a = 0.0;
-    x = xr + 0.5 * v0 * v0 / ad;
-    return;
-  }
-  v = v0 - ad * tau;
-  a = -ad;
-  x = xr + v0 * tau - 0.5 * ad * tau * tau;
-}
 
 __device__ __forceinline__ PairK<float> pair_k(const InstParams& P) {
   PairK<float> k;
@@ -136,7 +109,7 @@ __device__ __forceinline__ void adj_enforce_one(const InstParams& P, const AdjPt
   // disk: radial pull-out and reflection of the inward relative velocity
   if (P.nd > 0) {
     double xd, vd, ad;
-    kin_d(P, te, xd, vd, ad);
+    kinematics(P, te, xd, vd, ad);
     const double dx = xw - xd, dy = yw - P.disk_y0;
     const double d2 = dx * dx + dy * dy;
     if (d2 < P.R * P.R) {
@@ -274,7 +247,7 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
     const float4 ag = te.aux[s];  // rho_g, P_g, c_g, -m
     const bool disk = t >= P.nw;
     double xd, vd, ad;
-    kin_d(P, t_eval, xd, vd, ad);
+    kinematics(P, t_eval, xd, vd, ad);
     const float awx = disk ? (float)ad : 0.0f;
     const float mg = -ag.w;
     int cx, cy;

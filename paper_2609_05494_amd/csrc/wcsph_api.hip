@@ -97,6 +97,7 @@ struct wcsph_ctx {
   Clock* d_clk = nullptr;
   uint32_t* d_wallcount = nullptr;
   uint32_t* d_wall_tot = nullptr;  // static wall-ghost entries per sort tile
+  double* d_kin_tab = nullptr;      // per instance: WC_KIN_ROWS rows (t, x, v, a) of a tabulated disk motion
   size_t n_tiles = 0;
   uint32_t* d_gslot_save = nullptr;
   std::vector<uint32_t> h_wallcount, h_wrank;
@@ -188,7 +189,7 @@ void validate(const wcsph_params& p) {
             "disk must lie inside the channel");
     require(p.kin_t_ramp > 0 && p.kin_v0 >= 0 && p.kin_coef >= 0, "kinematics coefficients invalid");
   }
-  require(p.kin_mode >= 0 && p.kin_mode <= 2, "kin_mode must be 0, 1 or 2");
+  require(p.kin_mode >= 0 && p.kin_mode <= 3, "kin_mode must be 0, 1, 2 or 3");
   if (p.disk_R > 0 && p.kin_mode == 2)
     require(p.disk_mass > 0 && std::isfinite(p.disk_mass), "a two-way coupled disk needs disk_mass > 0");
   require(p.n_probes >= 0 && p.n_probes <= WCSPH_MAX_PROBES, "n_probes must lie in [0, 16]");
@@ -576,6 +577,12 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   alloc_buf(c, c->b.W);
   Dev& d = c->d;
   c->d_prm = dalloc_n<InstParams>(c, n_inst);
+  // tabulated disk motion (kin_mode 3): WC_KIN_ROWS rows per instance, empty until set
+  c->d_kin_tab = dalloc_n<double>(c, (size_t)n_inst * WC_KIN_ROWS * 4);
+  for (int i = 0; i < n_inst; ++i) {
+    c->hp[i].kin_tab = c->d_kin_tab + (size_t)i * WC_KIN_ROWS * 4;
+    c->hp[i].kin_tab_n = 0;
+  }
   c->d_clk = dalloc_n<Clock>(c, n_inst);
   d.prm = c->d_prm;
   d.clk = c->d_clk;
@@ -946,22 +953,34 @@ wcsph_status wcsph_instance_info(const wcsph_ctx* ctx, int inst, int* n_fluid, i
 wcsph_status wcsph_set_disk_kinematics(wcsph_ctx* ctx, int inst, int mode, const double* coeffs, int n) {
   API_BEGIN(ctx)
   require(inst >= 0 && inst < ctx->n_inst, "instance out of range");
-  require(mode >= 0 && mode <= 2, "mode must be 0, 1 or 2");
-  require(coeffs != nullptr && n == 3, "three coefficients expected");
-  require(coeffs[0] >= 0 && coeffs[1] > 0 && coeffs[2] >= 0, "coefficients must be non-negative, t_ramp > 0");
+  require(mode >= 0 && mode <= 3, "mode must be 0, 1, 2 or 3");
+  require(coeffs != nullptr, "coefficients required");
+  if (mode == 3) {
+    require(n >= 1 && n <= WC_KIN_ROWS, "a table of 1 to " + std::to_string(WC_KIN_ROWS) + " rows expected");
+    for (int k = 0; k < 4 * n; ++k) require(std::isfinite(coeffs[k]), "the table must be finite");
+    for (int k = 1; k < n; ++k) require(coeffs[4 * k] > coeffs[4 * (k - 1)], "table times must increase");
+  } else {
+    require(n == 3, "three coefficients expected");
+    require(coeffs[0] >= 0 && coeffs[1] > 0 && coeffs[2] >= 0, "coefficients must be non-negative, t_ramp > 0");
+  }
   if (mode == 2 && ctx->hp[inst].nd > 0)
     require(ctx->hp[inst].disk_mass > 0 && std::isfinite(ctx->hp[inst].disk_mass),
             "a two-way coupled disk needs disk_mass > 0");
   sync(ctx);
   InstParams& q = ctx->hp[inst];
   q.kin_mode = mode;
-  q.kin_v0 = coeffs[0];
-  q.kin_t_ramp = coeffs[1];
-  q.kin_coef = coeffs[2];
   ctx->pin[inst].kin_mode = mode;
-  ctx->pin[inst].kin_v0 = coeffs[0];
-  ctx->pin[inst].kin_t_ramp = coeffs[1];
-  ctx->pin[inst].kin_coef = coeffs[2];
+  if (mode == 3) {
+    HC(hipMemcpy(const_cast<double*>(q.kin_tab), coeffs, (size_t)n * 4 * sizeof(double), hipMemcpyHostToDevice));
+    q.kin_tab_n = n;
+  } else {
+    q.kin_v0 = coeffs[0];
+    q.kin_t_ramp = coeffs[1];
+    q.kin_coef = coeffs[2];
+    ctx->pin[inst].kin_v0 = coeffs[0];
+    ctx->pin[inst].kin_t_ramp = coeffs[1];
+    ctx->pin[inst].kin_coef = coeffs[2];
+  }
   HC(hipMemcpyAsync(ctx->d_prm + inst, &q, sizeof(InstParams), hipMemcpyHostToDevice, ctx->st));
   // the new law starts from the newest state: a coupled disk is released
   // (mode 2 couples again at its next step at or after t_ramp)
@@ -1017,6 +1036,14 @@ wcsph_status wcsph_step(wcsph_ctx* ctx, int n_steps) {
     }
   }
   API_END(ctx)
+}
+
+wcsph_status wcsph_batch_step(wcsph_ctx* ctx, int n_steps) {
+  if (ctx && !ctx->dead && !ctx->batch) {
+    ctx->err = "wcsph_batch_step needs a context from wcsph_batch_create";
+    return WCSPH_E_INVALID;
+  }
+  return wcsph_step(ctx, n_steps);
 }
 
 wcsph_status wcsph_synchronize(wcsph_ctx* ctx) {
@@ -1435,6 +1462,7 @@ wcsph_status wcsph_set_coefficients(wcsph_ctx* ctx, int inst, double alpha, doub
     q.probe_oy[k] = o.probe_oy[k];
   }
   q.kin_mode = o.kin_mode; q.kin_v0 = o.kin_v0; q.kin_t_ramp = o.kin_t_ramp; q.kin_coef = o.kin_coef;
+  q.kin_tab = o.kin_tab; q.kin_tab_n = o.kin_tab_n;
   o = q;
   ctx->pin[inst] = p;
   sync(ctx);
@@ -1447,8 +1475,8 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   require(!ctx->batch && ctx->n_inst == 1, "the reverse sweep needs a single-instance context");
   require(ctx->pin[0].ghost_rho_mode == 0, "the reverse sweep supports the linear ghost density only");
   require(ctx->pin[0].init_mode == 0, "the reverse sweep needs the rest initial state");
-  require(ctx->hp[0].kin_mode != 2 || ctx->hp[0].nd == 0,
-          "the reverse sweep needs a prescribed disk motion (kin_mode 0 or 1)");
+  require((ctx->hp[0].kin_mode != 2 && ctx->hp[0].kin_mode != 3) || ctx->hp[0].nd == 0,
+          "the reverse sweep needs a closed-form prescribed disk motion (kin_mode 0 or 1)");
   require(ctx->pin[0].beta == 0, "the reverse sweep supports the linear artificial viscosity only (beta = 0)");
   require(ctx->pin[0].eos_type == 0, "the reverse sweep supports the Tait EOS only");
   require(ctx->pin[0].kernel_type == 0, "the reverse sweep supports the Wendland C2 kernel only");

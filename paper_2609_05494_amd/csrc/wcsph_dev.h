@@ -24,6 +24,7 @@
 #define WC_BUCKET 64           // capacity of one cell bucket (particles per cell)
 #define WC_SORT_TILE 64        // cells per block of the sort kernel
 #define WC_NB_CAP 64           // neighbour ids per particle in the neighbour-list export
+#define WC_KIN_ROWS 1024       // rows of a tabulated disk motion per instance
 
 // Per-instance constants (read-only in kernels).
 struct InstParams {
@@ -64,6 +65,9 @@ struct InstParams {
   // the same law in FP64 (diagnostics): K, k1, b, the cap, mu at the cutoff
   // p_cav / K and the pressure at the cap
   double mg_Kd, mg_k1d, mg_bd, mg_mu_maxd, mg_mu_cavd, mg_p_capd;
+  // kin_mode 3: the instance's table of prescribed motion, kin_tab_n rows (t, x, v, a) (device)
+  const double* kin_tab;
+  int kin_tab_n;
 };
 
 // Per-instance clock and accumulators (device-resident, FP64 time).

@@ -17,6 +17,7 @@
 // enforcement geometry and diagnostics are FP64.
 
 #include "wcsph_launch.h"
+#include "wcsph_kin.h"
 
 // Scan shapes of the pair pass (UCAP, LCAP, PU) picked for this GPU by the
 // autotuner (paper_2609_05494_amd/autotune.py), when it has been run; the
@@ -44,43 +45,6 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk) {
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-
-// Prescribed disk motion along +x (velocity ramp, then constant deceleration
-// or quadratic drag), FP64 closed forms. Mode 2 (two-way coupling) follows
-// the ramp and then v0 only until its first coupled step.
-__device__ void kinematics(const InstParams& P, double t, double& x, double& v, double& a) {
-  const double v0 = P.kin_v0, tr = P.kin_t_ramp;
-  if (t < tr) {
-    v = v0 * t / tr;
-    a = v0 / tr;
-    x = P.disk_x0 + 0.5 * v0 * t * t / tr;
-    return;
-  }
-  const double tau = t - tr, xr = P.disk_x0 + 0.5 * v0 * tr;
-  if (P.kin_mode == 2) {
-    v = v0;
-    a = 0.0;
-    x = xr + v0 * tau;
-    return;
-  }
-  if (P.kin_mode == 1) {
-    const double k = P.kin_coef;
-    v = v0 / (1.0 + k * v0 * tau);
-    a = -k * v * v;
-    x = k > 0.0 ? xr + log1p(k * v0 * tau) / k : xr + v0 * tau;
-    return;
-  }
-  const double ad = P.kin_coef;
-  if (ad > 0.0 && tau >= v0 / ad) {
-    v = 0.0;
-    a = 0.0;
-    x = xr + 0.5 * v0 * v0 / ad;
-    return;
-  }
-  v = v0 - ad * tau;
-  a = -ad;
-  x = xr + v0 * tau - 0.5 * ad * tau * tau;
-}
 
 // Disk state at time te of the current step: a coupled disk is extrapolated
 // from its state at t with its latest acceleration, otherwise the prescribed

@@ -89,3 +89,10 @@ def test_full_C4_sweep_sampled_instances():
             assert np.array_equal(u, v), k
         assert np.array_equal(pb, ps)
     b.close()
+
+
+def test_batch_step_needs_a_batched_context():
+    s = wc.Solver(workloads.tiny(), "cuda:0")
+    assert wc.lib().wcsph_batch_step(s.handle, 1) == wc.E_INVALID
+    s.step(1)  # the plain entry point serves it, and the context is still usable
+    s.close()
