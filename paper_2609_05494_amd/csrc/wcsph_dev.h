@@ -25,6 +25,7 @@
 #define WC_SORT_TILE 64        // cells per block of the sort kernel
 #define WC_NB_CAP 64           // neighbour ids per particle in the neighbour-list export
 #define WC_KIN_ROWS 1024       // rows of a tabulated disk motion per instance
+#define WC_NO_ID 0xffffffffu   // particle id of an inert sorted entry (a gap left by a bucket overflow)
 
 // Per-instance constants (read-only in kernels).
 struct InstParams {

@@ -1018,6 +1018,26 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
   if (t < 64) {
     const int K = tile * T + t;
     if (K < d.n_cells) d.count[K] = d.wallcount[K];  // re-arm for the next sort (every count was read)
+    // a cell that took more entries than its bucket (flagged when filled)
+    // leaves a gap in the tile's slot range, and the particles it dropped
+    // leave the slots past the last tile unfilled from then on: both are
+    // filled with inert entries (no particle id, zero mass, the tile's last
+    // cell, old slot 0) so that every sorted slot holds a valid cell key and
+    // a finite state that no later kernel moves or counts
+    const uint32_t* tot = MODE == EV_B ? d.tot_b : d.tot_a;
+    const uint32_t stored = s_off[T];
+    const uint32_t end = tile == (int)gridDim.x - 1 ? (uint32_t)d.n_slots - s_base : tot[tile];
+    const uint32_t kin = (uint32_t)min(tile * T + T - 1, d.n_cells - 1);
+    for (uint32_t g = stored + (uint32_t)t; g < end; g += 64) {
+      const uint32_t dst = s_base + g;
+      if (dst >= (uint32_t)d.n_slots) break;
+      out.cell[dst] = kin;
+      out.id[dst] = WC_NO_ID;
+      out.pv[dst] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      out.aux[dst] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+      if constexpr (BATCH) out.inst[dst] = 0;
+      d.perm[dst] = 0u;
+    }
     return;
   }
   const uint32_t base = s_base + s_off[c];
@@ -1293,7 +1313,8 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
   const uint32_t id_i = h_id[threadIdx.x];
   const bool fluid = inr && h_m[threadIdx.x] > 0.0f;
   const uint32_t eb = h_eb[threadIdx.x];
-  if (MODE != EV_EXPORT && inr && !fluid) {
+  const int gid = (int)id_i - P.id0 - P.nf;  // ghost index (an inert entry has none)
+  if (MODE != EV_EXPORT && inr && !fluid && gid >= 0 && gid < P.nw + P.nd) {
     // ghosts: wall ghosts are carried, the disk ring is placed at the time of
     // the next evaluation (t + dt/2 after eval A, t + dt after eval B)
     const uint32_t id = id_i;

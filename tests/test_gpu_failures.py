@@ -104,3 +104,37 @@ def test_failing_allocator_gives_e_oom_and_returns_every_block(fail_at):
     assert st == wc.E_OOM, st
     assert not h.value
     assert calls[0] >= fail_at and not live
+
+
+def test_cell_overflow_is_flagged_and_kernels_finish():
+    """More than 64 particles in one cell (bucket capacity), forced from the
+    host through set_fluid: the fill flags it, the sort fills the slots the
+    dropped entries leave with inert entries, every kernel finishes, and every
+    reader reports E_UNSTABLE with the cause."""
+    cfg = workloads.tiny()
+    s = wc.Solver(cfg, "cuda:0")
+    t, (x, y, vx, vy, rho) = s.fluid()
+    x, y = x.copy(), y.copy()
+    dc = cfg["cell_size"]
+    lo = -cfg["ghost_layers"] * cfg["dx"]
+    # 72 fluid particles on a 9 x 8 grid inside the cell whose corner is (4 dc, 3 dc) + lo
+    cx0, cy0 = lo + 4 * dc, lo + 3 * dc
+    gx, gy = np.meshgrid(cx0 + (np.arange(9) + 0.5) * dc / 9, cy0 + (np.arange(8) + 0.5) * dc / 8)
+    far = np.argsort(-np.hypot(x - cfg["disk_x0"], y - cfg["disk_y0"]))[:72]
+    x[far], y[far] = gx.ravel(), gy.ravel()
+    assert x.max() < cfg["L"] and y.max() < cfg["W"]
+    s.set_fluid(t, x, y, vx, vy, rho)
+    print("[gpu] 72 particles in one cell, stepping", flush=True)
+    s.step(cfg["diag_every"])
+    s.synchronize()
+    with pytest.raises(wc.WcsphUnstable) as e:
+        s.read_diagnostics()
+    assert "more than 64 particles in one cell" in str(e.value)
+    with pytest.raises(wc.WcsphUnstable):
+        s.fluid()
+    s.close()
+    # the GPU is still fine: a fresh context runs normally
+    s2 = wc.Solver(cfg, "cuda:0")
+    s2.step(5)
+    assert "unstable" not in s2.read_diagnostics()
+    s2.close()
