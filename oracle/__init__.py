@@ -16,10 +16,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "wcsph_oracle.cpp")
 MAX_PROBES = 16
-NDIAG = 21
+NDIAG = 22
 DIAG_FIELDS = ("t", "dt", "vmax", "mass", "momx", "momy", "ke", "e_el", "e_pot", "e_disk",
                "w_boundary", "step", "n_clamp", "n_cav", "n_enforce",
-               "d_av", "d_visc", "w_delta", "w_ghost", "w_enforce", "w_clamp")
+               "d_av", "d_visc", "w_delta", "w_ghost", "w_enforce", "w_clamp", "e_th")
 
 
 def build(force: bool = True) -> str:
@@ -49,7 +49,7 @@ class Params(C.Structure):
         ("kin_mode", C.c_int), ("kin_v0", C.c_double), ("kin_t_ramp", C.c_double),
         ("kin_coef", C.c_double), ("beta", C.c_double), ("kernel_type", C.c_int),
         ("eos_type", C.c_int), ("mg_s1", C.c_double), ("mg_gamma0", C.c_double),
-        ("mg_mu_max", C.c_double),
+        ("mg_mu_max", C.c_double), ("scheme", C.c_int), ("mg_a", C.c_double),
     ]
 
 
@@ -117,6 +117,10 @@ def lib():
                                 + [_D, _D, _D]),
             "orc_pair_rates": (None, [P, C.c_int] + [_D] * 7 + [_I] + [_D] * 5),
             "orc_tangent_J": (None, [P, C.c_int, _D, _D, _D]),
+            "orc_eval_density": (None, [C.c_void_p, _D, _D]),
+            "orc_get_energy": (None, [C.c_void_p, _D]),
+            "orc_eos_pe": (C.c_double, [P, C.c_double, C.c_double]),
+            "orc_lattice_mass": (C.c_double, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -152,6 +156,8 @@ class Oracle:
         else:
             init = f64(init).reshape(-1, 5)
             self.h = L.orc_create(C.byref(self.p), init.shape[0], dptr(init))
+        if not self.h:
+            raise ValueError("scheme 1 with the coupled disk (kin_mode 2) is not built")
         self.nf = L.orc_num_fluid(self.h)
         self.ng = L.orc_num_ghost(self.h)
         self.ncells = L.orc_num_cells(self.h)
@@ -208,6 +214,19 @@ class Oracle:
         d = dict(zip(keys, out))
         d["vmax"] = float(vmax[0])
         return d
+
+    def eval_density(self):
+        """Fluid density and pressure by id (scheme 1: the clamped summation at
+        the current positions, which the oracle then stores)."""
+        rho = np.empty(self.nf); p = np.empty(self.nf)
+        lib().orc_eval_density(self.h, dptr(rho), dptr(p))
+        return rho, p
+
+    def energy(self):
+        """Specific internal energy by fluid id (scheme 1)."""
+        e = np.empty(self.nf)
+        lib().orc_get_energy(self.h, dptr(e))
+        return e
 
     def ghosts(self):
         g = [np.empty(self.ng) for _ in range(3)]
@@ -334,3 +353,15 @@ def tangent_J(cfg: dict, dt):
     dJ = np.empty(3)
     lib().orc_tangent_J(C.byref(params(cfg)), dt.size, dptr(dt), C.byref(J), dptr(dJ))
     return J.value, dJ
+
+
+def eos_pe(cfg: dict, rho: float, e: float) -> float:
+    """Pressure of eq. eos with the cutoff at density rho and specific
+    internal energy e."""
+    return lib().orc_eos_pe(C.byref(params(cfg)), rho, e)
+
+
+def lattice_mass(cfg: dict) -> float:
+    """The particle mass of scheme 1: rho0 over the kernel sum of the square
+    lattice of spacing dx."""
+    return lib().orc_lattice_mass(C.byref(params(cfg)))

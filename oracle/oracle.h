@@ -18,8 +18,9 @@ extern "C" {
 
 #define ORC_MAX_PROBES 16
 /* t dt vmax mass momx momy ke e_el e_pot e_disk w_boundary step n_clamp n_cav n_enforce
- * d_av d_visc w_delta w_ghost w_enforce w_clamp (energy audit integrals, J per unit depth) */
-#define ORC_NDIAG 21
+ * d_av d_visc w_delta w_ghost w_enforce w_clamp (energy audit integrals, J per unit depth)
+ * e_th (sum of m e, the internal energy of scheme 1) */
+#define ORC_NDIAG 22
 
 typedef struct {
   double L, W, dx, h_over_dx, cell_size;  /* cell_size <= 0 -> 2h */
@@ -39,6 +40,11 @@ typedef struct {
   int kernel_type; /* 0: Wendland C2; 1: cubic B-spline (eq. cubic-kernel) */
   int eos_type;    /* 0: Tait; 1: Mie-Grueneisen of eq. eos at zero specific internal energy */
   double mg_s1, mg_gamma0, mg_mu_max; /* its Hugoniot slope S1, gamma0 and compression cap */
+  int scheme;  /* 0: continuity + delta term, predictor-corrector;
+                  1: the paper as published: summation density (eq. density-sum, ghosts in
+                  the sum, lattice-normalised masses) with its clamp, leapfrog, and the
+                  specific internal energy heated by the artificial viscosity */
+  double mg_a; /* the a of eq. eos (scheme 1 with eos_type 1) */
 } orc_params;
 
 /* ---- whole solver ------------------------------------------------------ */
@@ -71,6 +77,18 @@ void orc_eval_rates(void* s, double* drho, double* ax, double* ay, double* Vx, d
  * - v_i.g) = W_ghost' - D_av' - D_visc' + W_delta'. */
 void orc_audit_rates(void* s, double* out /* 4 */);
 void orc_get_ghosts(void* s, double* gx, double* gy, double* gm);
+/* Fluid density and pressure by fluid id at the current state: scheme 0 the
+ * stored density; scheme 1 the clamped summation over fluid and ghosts at
+ * the current positions (disk ring at the current time), which is stored.
+ * Pressure with the cutoff and, scheme 1, the internal energy. */
+void orc_eval_density(void* s, double* rho, double* p);
+/* specific internal energy by fluid id (scheme 1; zero otherwise) */
+void orc_get_energy(void* s, double* e);
+/* pressure of eq. eos with the cutoff at density rho and specific internal energy e */
+double orc_eos_pe(const orc_params* p, double rho, double e);
+/* the lattice-normalised particle mass of scheme 1: rho0 / sum_j W(r_j) over
+ * the points r_j = (i dx, j dx) in support */
+double orc_lattice_mass(const orc_params* p);
 void orc_get_order(void* s, int* order, int* cell_start);
 void orc_kinematics(void* s, double t, double* x, double* v, double* a);
 /* kin_mode 3: the prescribed disk motion as n rows (t, x, v, a), t strictly

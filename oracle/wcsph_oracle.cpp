@@ -102,6 +102,9 @@ struct Geom {
   double m_fluid, m_wall, m_disk, nu0;
 };
 
+template <class T>
+void kernel_WF(const T& q, const Geom& g, T& W, T& F);
+
 Geom make_geom(const orc_params& p) {
   Geom g;
   g.dx = p.dx;
@@ -118,8 +121,23 @@ Geom make_geom(const orc_params& p) {
   g.cubic = p.kernel_type == 1;
   g.sigma_c = 10.0 / (7.0 * M_PI * g.h * g.h);
   g.m_fluid = p.rho0 * p.dx * p.dx;
-  g.m_wall = p.rho0 * p.dx * p.dx;
-  g.m_disk = p.n_disk_ghosts > 0 ? p.rho0 * p.dx * 2.0 * M_PI * p.disk_R / p.n_disk_ghosts : 0.0;
+  if (p.scheme == 1) {
+    // summation density (Density Summation): the mass that makes the kernel
+    // sum of the undisturbed square lattice equal rho0
+    double S = 0.0;
+    for (int j = -4; j <= 4; ++j)
+      for (int i = -4; i <= 4; ++i) {
+        const double q = std::sqrt((double)(i * i + j * j)) * p.dx / g.h;
+        if (q >= 2.0) continue;
+        double W, F;
+        kernel_WF(q, g, W, F);
+        S += W;
+      }
+    g.m_fluid = p.rho0 / S;
+  }
+  g.m_wall = g.m_fluid;
+  // the ring: one particle layer of the fluid's areal mass density per unit arc length
+  g.m_disk = p.n_disk_ghosts > 0 ? g.m_fluid / p.dx * 2.0 * M_PI * p.disk_R / p.n_disk_ghosts : 0.0;
   g.nu0 = p.mu_dyn / p.rho0;
   return g;
 }
@@ -166,14 +184,19 @@ struct Coef {
 // mu = rho/rho0 - 1 capped at mg_mu_max and C = c0:
 //   compression (mu >= 0): p = rho0 C^2 mu [1 + (1 - gamma0/2) mu] / [1 - (S1 - 1) mu]^2,
 //   tension (mu < 0):      p = rho0 C^2 mu.
+//
+// Scheme 1 evolves the specific internal energy e and adds the energy term
+// of eq. eos, (gamma0 + a mu) rho e in compression and gamma0 rho e in
+// tension, with rho = rho0 (1 + mu) at the same capped mu.
 template <class T>
-T mg_p(const T& rho, const orc_params& p, const Coef<T>& k) {
+T mg_p(const T& rho, const orc_params& p, const Coef<T>& k, const T& e) {
   T mu = rho / p.rho0 - 1.0;
   if (val(mu) > p.mg_mu_max) mu = T(p.mg_mu_max);
   const T K = p.rho0 * (k.c0 * k.c0);
-  if (val(mu) < 0.0) return K * mu;
+  const T rh = p.rho0 * (1.0 + mu);
+  if (val(mu) < 0.0) return K * mu + p.mg_gamma0 * rh * e;
   const T den = 1.0 - (p.mg_s1 - 1.0) * mu;
-  return K * mu * (1.0 + (1.0 - 0.5 * p.mg_gamma0) * mu) / (den * den);
+  return K * mu * (1.0 + (1.0 - 0.5 * p.mg_gamma0) * mu) / (den * den) + (p.mg_gamma0 + p.mg_a * mu) * rh * e;
 }
 // Its sound speed, c^2 = dp/drho of the same law (taken at the capped mu):
 // C^2 [1 + (2 - gamma0 + S1 - 1) mu] / [1 - (S1 - 1) mu]^3 in compression, C^2 in tension.
@@ -205,14 +228,16 @@ T mg_rho(const T& q, const orc_params& p, const Coef<T>& k) {
 // EOS with the cavitation cutoff p >= p_cav: Tait (eos_type 0),
 // p = B((rho/rho0)^gamma - 1), c = c0 (rho/rho0)^((gamma-1)/2), or the
 // Mie-Grueneisen law above.
+// (e: the specific internal energy, zero except in scheme 1; the Tait law
+// does not depend on it)
 template <class T>
-T eos_p_uncut(const T& rho, const orc_params& p, const Coef<T>& k) {
-  if (p.eos_type == 1) return mg_p(rho, p, k);
+T eos_p_uncut(const T& rho, const orc_params& p, const Coef<T>& k, const T& e = T(0.0)) {
+  if (p.eos_type == 1) return mg_p(rho, p, k, e);
   return k.B * (pow(rho / p.rho0, p.gamma) - 1.0);
 }
 template <class T>
-T eos_p(const T& rho, const orc_params& p, const Coef<T>& k) {
-  T pr = eos_p_uncut(rho, p, k);
+T eos_p(const T& rho, const orc_params& p, const Coef<T>& k, const T& e = T(0.0)) {
+  T pr = eos_p_uncut(rho, p, k, e);
   return val(pr) < p.p_cav ? T(p.p_cav) : pr;
 }
 template <class T>
@@ -238,9 +263,10 @@ struct PV {
 template <class T>
 struct Acc {
   T D, ax, ay, Vx, Vy, fdx;
+  T E;  // scheme 1: rate of the specific internal energy (artificial-viscosity heating)
   // energy audit, per unit mass of particle a (values only)
   double av, visc, del, ghost;
-  Acc() : D(0.0), ax(0.0), ay(0.0), Vx(0.0), Vy(0.0), fdx(0.0), av(0), visc(0), del(0), ghost(0) {}
+  Acc() : D(0.0), ax(0.0), ay(0.0), Vx(0.0), Vy(0.0), fdx(0.0), E(0.0), av(0), visc(0), del(0), ghost(0) {}
 };
 
 // Contribution of neighbour b to the rates of fluid particle a.
@@ -279,6 +305,9 @@ void pair_law(const PV<T>& a, const PV<T>& b, const orc_params& p, const Geom& g
   acc.ax -= b.m * s * F * rx;
   acc.ay -= b.m * s * F * ry;
   if (b.kind == 2) acc.fdx -= b.m * s * F * rx;
+  // internal energy (scheme 1): half of the pair's artificial-viscosity
+  // dissipation, (1/2) m_j Pi_ij v_ij . grad_i W_ij >= 0, over every neighbour
+  acc.E += 0.5 * b.m * Pi * F * vr;
   // laminar viscosity (Lo-Shao): sum_j 4 nu0 m_j (r_ij . grad W) / ((rho_i + rho_j)(r^2 + eta^2 h^2)) v_ij
   T lam = b.m * 4.0 * g.nu0 * F * r2 / ((a.rho + b.rho) * denom);
   acc.ax += lam * vxij;
@@ -385,8 +414,10 @@ struct Sim {
   Geom G;
   Coef<T> K;
   int Nf = 0, Nw = 0, Nd = 0;
-  // fluid state by fluid id
-  std::vector<T> x, y, vx, vy, rho;
+  // fluid state by fluid id (scheme 1: v at the half step, rho the last
+  // summed density, e the specific internal energy)
+  std::vector<T> x, y, vx, vy, rho, e;
+  double dt_prev = 0.0;  // scheme 1: dt of the previous step (0 before the first)
   // ghosts by ghost index: walls first, then the disk ring
   std::vector<double> gx, gy, gm;
   std::vector<T> gp, grho, gvx, gvy;
@@ -438,6 +469,7 @@ struct Sim {
       }
     }
     Nf = (int)x.size();
+    e.assign(Nf, T(0.0));
     // wall ghosts (S2): the lattice continued ghost_layers deep around the box, j outer
     const int Lg = p.ghost_layers;
     for (int j = -Lg; j < G.ny + Lg; ++j)
@@ -609,7 +641,7 @@ struct Sim {
         if (j == i) return;
         pair_law(a, view(j, pf), P, G, K, acc);
       });
-      D[i] = acc.D;
+      D[i] = P.scheme == 1 ? acc.E : acc.D;
       ax[i] = acc.ax;
       ay[i] = acc.ay + P.gravity_y;
       Vx[i] = vx[i] + acc.Vx;
@@ -632,7 +664,37 @@ struct Sim {
 
   void fluid_pressure(std::vector<T>& pf) const {
     pf.resize(Nf);
-    for (int i = 0; i < Nf; ++i) pf[i] = eos_p(rho[i], P, K);
+    for (int i = 0; i < Nf; ++i) pf[i] = eos_p(rho[i], P, K, e[i]);
+  }
+
+  // Summation density (eq. density-sum) of every fluid particle over the fluid
+  // and ghosts in support, itself included, clamped to [rho_lo, rho_hi] rho0
+  void sum_density() {
+    const double lo = P.rho_lo * P.rho0, hi = P.rho_hi * P.rho0;
+    long nc = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nc)
+    for (int i = 0; i < Nf; ++i) {
+      T sum(0.0);
+      for_neighbours(val(x[i]), val(y[i]), [&](int j) {
+        if (j == i) {  // the particle itself, at r = 0
+          T W0, F0;
+          kernel_WF(T(0.0), G, W0, F0);
+          sum += G.m_fluid * W0;
+          return;
+        }
+        T rx = j < Nf ? x[i] - x[j] : x[i] - gx[j - Nf];
+        T ry = j < Nf ? y[i] - y[j] : y[i] - gy[j - Nf];
+        T r2 = rx * rx + ry * ry;
+        if (!(val(r2) < 4.0 * G.h * G.h)) return;
+        T W, F;
+        kernel_WF(sqrt(r2) / G.h, G, W, F);
+        sum += (j < Nf ? G.m_fluid : gm[j - Nf]) * W;
+      });
+      if (val(sum) < lo) { sum = T(lo); nc++; }
+      if (val(sum) > hi) { sum = T(hi); nc++; }
+      rho[i] = sum;
+    }
+    n_clamp += nc;
   }
 
   // hard walls (Channel Walls section) then the disk: radial pull-out to
@@ -707,11 +769,54 @@ struct Sim {
   void prepare(double te, std::vector<T>& pf) {
     place_disk(te);
     build_cells();
+    if (P.scheme == 1) sum_density();
     fluid_pressure(pf);
     ghosts(pf);
   }
 
+  // Scheme 1 (the paper as published), one evaluation per step at state n
+  // (positions r^n, half-step velocities v^(n-1/2), internal energy e^n):
+  // the summed and clamped density with the energy term of the EOS, the
+  // ghosts, probes and CFL step at t^n, then the merged leapfrog kick
+  // v^(n+1/2) = v^(n-1/2) + (dt^(n-1) + dt^n)/2 a^n (velocity-Stormer-Verlet
+  // with a variable step; dt^(-1) = 0 starts it with a half kick), the drift
+  // r^(n+1) = r^n + dt^n (v^(n+1/2) + the XSPH correction of eq. xsph),
+  // e^(n+1) = e^n + dt^n de/dt^n, and the wall and disk enforcement at t^(n+1).
+  void one_step_leapfrog() {
+    std::vector<T> pf, D(Nf), ax(Nf), ay(Nf), Vx(Nf), Vy(Nf);
+    prepare(t, pf);
+    probes(pf);
+    const double vmax = vmax_now();
+    const double dt = (step < (long)dt_table.size()) ? dt_table[step] : P.cfl * G.h / (val(K.c0) + vmax);
+    probe_rows.push_back(t);
+    probe_rows.push_back(dt);
+    for (int k = 0; k < P.n_probes; ++k) {
+      probe_rows.push_back(val(probe_vals[k]));
+      J += probe_vals[k] * dt;
+    }
+    const T fdx = rates(pf, D, ax, ay, Vx, Vy);
+    w_boundary += dt * val(fdx) * dv;
+    double x1, v1, a1;
+    kin(t + dt, &x1, &v1, &a1);
+    const double kick = 0.5 * (dt_prev + dt);
+    for (int i = 0; i < Nf; ++i) {
+      T ux = vx[i] + kick * ax[i], uy = vy[i] + kick * ay[i];
+      T xx = x[i] + dt * (ux + (Vx[i] - vx[i])), yy = y[i] + dt * (uy + (Vy[i] - vy[i]));
+      e[i] = e[i] + dt * D[i];
+      if (enforce(xx, yy, ux, uy, x1, P.disk_y0, v1)) n_enforce++;
+      x[i] = xx; y[i] = yy; vx[i] = ux; vy[i] = uy;
+    }
+    dt_prev = dt;
+    t += dt;
+    step++;
+    if (P.diag_every > 0 && step % P.diag_every == 0) record_diag(dt, vmax);
+  }
+
   void one_step() {
+    if (P.scheme == 1) {
+      one_step_leapfrog();
+      return;
+    }
     std::vector<T> pf, D(Nf), ax(Nf), ay(Nf), Vx(Nf), Vy(Nf);
     const std::vector<T> x0 = x, y0 = y, vx0 = vx, vy0 = vy, rho0 = rho;
     if (P.kin_mode == 2 && !coupled && t >= P.kin_t_ramp) {
@@ -809,7 +914,7 @@ struct Sim {
   }
 
   void record_diag(double dt, double vmax) {
-    double M = 0, px_ = 0, py_ = 0, ke = 0, eel = 0, epot = 0;
+    double M = 0, px_ = 0, py_ = 0, ke = 0, eel = 0, epot = 0, eth = 0;
     long ncav = 0;
     for (int i = 0; i < Nf; ++i) {
       double m = G.m_fluid, u = val(vx[i]), w = val(vy[i]), r = val(rho[i]);
@@ -819,14 +924,15 @@ struct Sim {
       ke += 0.5 * m * (u * u + w * w);
       epot += m * (-P.gravity_y) * val(y[i]);
       eel += m * e_el(r);
-      if (val(eos_p_uncut(T(r), P, K)) <= P.p_cav) ncav++;
+      eth += m * val(e[i]);
+      if (val(eos_p_uncut(T(r), P, K, e[i])) <= P.p_cav) ncav++;
     }
     double xd, vd, ad;
     current_disk(&xd, &vd, &ad);
     double row[ORC_NDIAG] = {t, dt, vmax, M, px_, py_, ke, eel, epot, 0.5 * P.disk_mass * vd * vd,
                              w_boundary, (double)step, (double)n_clamp, (double)ncav,
                              (double)n_enforce, audit[0], audit[1], audit[2], audit[3], audit[4],
-                             audit[5]};
+                             audit[5], eth};
     diag_rows.insert(diag_rows.end(), row, row + ORC_NDIAG);
   }
 };
@@ -839,6 +945,7 @@ using SimD = Sim<double>;
 extern "C" {
 
 void* orc_create(const orc_params* p, int n_init, const double* init) {
+  if (p->scheme == 1 && p->kin_mode == 2) return nullptr;  // the coupled disk is not built for scheme 1
   SimD* s = new SimD();
   s->P = *p;
   s->set_coef(p->alpha, p->delta, p->c0);
@@ -870,7 +977,9 @@ void orc_set_fluid(void* s, double t, const double* x, const double* y, const do
   q->t = t;
   for (int i = 0; i < q->Nf; ++i) {
     q->x[i] = x[i]; q->y[i] = y[i]; q->vx[i] = vx[i]; q->vy[i] = vy[i]; q->rho[i] = rho[i];
+    q->e[i] = 0.0;
   }
+  q->dt_prev = 0.0;
   for (int k = 0; k < q->N(); ++k) q->order[k] = k;
 }
 int orc_probe_rows(void* s) {
@@ -908,6 +1017,34 @@ void orc_eval_rates(void* s, double* drho, double* ax, double* ay, double* Vx, d
     if (gvy) gvy[g] = q->gvy[g];
   }
   if (vmax) *vmax = q->vmax_now();
+}
+void orc_eval_density(void* s, double* rho, double* p) {
+  auto* q = static_cast<SimD*>(s);
+  if (q->P.scheme == 1) {
+    q->place_disk(q->t);
+    q->build_cells();
+    q->sum_density();
+  }
+  std::vector<double> pf;
+  q->fluid_pressure(pf);
+  for (int i = 0; i < q->Nf; ++i) {
+    rho[i] = q->rho[i];
+    p[i] = pf[i];
+  }
+}
+void orc_get_energy(void* s, double* e) {
+  auto* q = static_cast<SimD*>(s);
+  for (int i = 0; i < q->Nf; ++i) e[i] = q->e[i];
+}
+double orc_eos_pe(const orc_params* p, double rho, double e) {
+  Coef<double> k;
+  k.c0 = p->c0; k.B = p->rho0 * p->c0 * p->c0 / p->gamma; k.alpha = p->alpha; k.delta = p->delta;
+  return eos_p(rho, *p, k, e);
+}
+double orc_lattice_mass(const orc_params* p) {
+  orc_params q = *p;
+  q.scheme = 1;
+  return make_geom(q).m_fluid;
 }
 void orc_audit_rates(void* s, double* out) {
   auto* q = static_cast<SimD*>(s);
@@ -1109,7 +1246,7 @@ void orc_pair_rates(const orc_params* p, int n, const double* x, const double* y
 }
 
 void orc_tangent_J(const orc_params* p, int n_steps, const double* dt, double* J, double* dJ) {
-  if (p->kin_mode == 2 || p->kin_mode == 3) {  // coupled: not differentiated; table: not held here
+  if (p->kin_mode == 2 || p->kin_mode == 3 || p->scheme == 1) {  // coupled: not differentiated; table: not held here; scheme 1: not built
     *J = dJ[0] = dJ[1] = dJ[2] = std::nan("");
     return;
   }

@@ -234,20 +234,24 @@ def test_deterministic_and_checkpoint_roundtrip():
 
 def test_full_size_C2_evaluation():
     """C2 (179,552 fluid, 185,088 particles) in the launch configuration the
-    benchmark times: one evaluation from a shared state after 20 oracle
-    steps, the cell list, and 20 GPU steps' mass."""
+    benchmark times: one evaluation from a shared state after 20 oracle steps
+    (density rate, acceleration, XSPH velocity, ghost pressure and velocity),
+    the cell keys, permutation and ranges, and 20 GPU steps' mass."""
     cfg = workloads.C2()
     s, o = _shared_state(cfg, 20)
     g = s.export_rates()
     r = o.eval_rates()
     assert _rel(g["drho"], r["drho"]) <= 1e-4
     assert _relvec(g["ax"], g["ay"], r["ax"], r["ay"]) <= 1e-4
+    assert _rel(g["Vx"], r["Vx"]) <= 1e-4 and _rel(g["Vy"], r["Vy"]) <= 1e-4
     assert _rel(g["gp"], r["gp"]) <= 1e-4
+    assert _rel(g["gvx"], r["gvx"]) <= 1e-4
     ex = s.export_cells()
     o.eval_rates()
     _, f = o.fluid()
     x, y = _all_positions(o, f)
     keys, perm, cs = oracle.cell_list(cfg, x, y)
+    assert np.array_equal(keys, ex["keys"].astype(np.int32))
     assert np.array_equal(perm, ex["perm"].astype(np.int32))
     assert np.array_equal(cs, ex["cell_start"].astype(np.int32))
     s.step(20)

@@ -40,6 +40,7 @@ MG_C = 1448.0
 MG_S1 = 1.979
 MG_GAMMA0 = 0.11
 MG_MU_MAX = 0.25
+MG_A = 3.0
 
 
 def _cell_size(dx: float, h_over_dx: float) -> float:
@@ -78,6 +79,7 @@ def base(L: float, W: float, dx: float, R: float, v0: float, *,
         probes=probes, diag_every=10,
         kin_mode=0, kin_v0=v0, kin_t_ramp=5.0e-6, kin_coef=K_DRAG * v0 * v0,
         eos_type=0, mg_s1=MG_S1, mg_gamma0=MG_GAMMA0, mg_mu_max=MG_MU_MAX,
+        scheme=0, mg_a=MG_A,
         steps=steps,
     )
 
@@ -113,6 +115,15 @@ def mie_grueneisen(cfg: dict) -> dict:
     zero specific internal energy in place of Tait, and the reference
     celerity c0 = C = 1448 m/s that the paper ties to it."""
     return dict(cfg, eos_type=1, c0=MG_C)
+
+
+def paper_scheme(cfg: dict) -> dict:
+    """The same workload with the paper's scheme as published (scheme 1):
+    summation density over fluid and ghosts with the [0.5, 1.5] rho0 clamp
+    (Density Summation), no delta term, the Mie-Grueneisen EOS of eq. eos with
+    an evolving specific internal energy, c0 = C = 1448 m/s, the cubic
+    B-spline kernel, and the leapfrog update at CFL 0.25 (eq. cfl)."""
+    return dict(cfg, scheme=1, eos_type=1, c0=MG_C, kernel_type=1, cfl=0.25, delta=0.0)
 
 
 def C2() -> dict:
