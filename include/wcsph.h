@@ -108,7 +108,31 @@ typedef struct {
  *  output     : diag_every steps between diagnostic records; init_mode 0 =
  *               fluid at rest at rho0, 1 = hydrostatic density; audit 1 =
  *               record the energy audit terms (single-instance contexts; the
- *               second pair pass then carries four more sums per pair). */
+ *               second pair pass then carries four more sums per pair).
+ *  update     : scheme 0 = continuity with the delta term and the
+ *               predictor-corrector (two evaluations per step); 1 = the
+ *               paper's scheme as published, one evaluation per step:
+ *               density by summation (eq. density-sum) over the fluid and
+ *               ghosts in support, the particle itself included, with masses
+ *               normalised so that the undisturbed square lattice sums to
+ *               rho0 (fluid and wall ghosts rho0 / sum_j W_j, the ring that
+ *               mass per dx of arc), clamped to [rho_lo, rho_hi] rho0 (Density
+ *               Summation); delta unused; the leapfrog of Time Integration
+ *               with a merged kick v^(n+1/2) = v^(n-1/2) + (dt^(n-1) + dt^n)/2
+ *               a^n (dt^(-1) = 0 after create, set_fluid and load), drift
+ *               r^(n+1) = r^n + dt^n (v^(n+1/2) + the XSPH correction), and a
+ *               specific internal energy e^(n+1) = e^n + dt^n de/dt, de/dt =
+ *               (1/2) sum_j m_j Pi_ij v_ij . grad W_ij (the artificial
+ *               viscosity's heating, over fluid and ghosts); with eos_type 1
+ *               the Mie-Grueneisen law gains its energy term (mg_gamma0 +
+ *               mg_a mu) rho e (mg_gamma0 rho e in tension), rho = rho0 (1 +
+ *               mu) at the capped mu; c stays the e = 0 law's. The stored
+ *               state is then (r^(n+1), v^(n+1/2), e^(n+1)) with rho the
+ *               step's summed density (at r^n), which is what the readers,
+ *               the diagnostics (ke of v^(n+1/2), e_el of that rho, e_th = sum
+ *               m e) and save/load see. Scheme 1 requires kin_mode != 2 and
+ *               audit = 0, and every instance of a batch must share it; the
+ *               reverse sweep takes scheme 0 only. */
 typedef struct {
   double L, W, dx, h_over_dx, cell_size;
   double rho0, c0, gamma, p_cav;
@@ -127,6 +151,8 @@ typedef struct {
   int kernel_type;
   int eos_type;
   double mg_s1, mg_gamma0, mg_mu_max;
+  int scheme;
+  double mg_a;
 } wcsph_params;
 
 /* One diagnostic record (FP64 reductions over the fluid of one instance).
@@ -147,6 +173,7 @@ typedef struct {
   double t, dt, vmax, mass, mom[2], ke, e_el, e_pot, e_disk, w_boundary;
   long long step, n_clamp, n_cav, n_enforce;
   double d_av, d_visc, w_delta, w_ghost, w_enforce, w_clamp;
+  double e_th; /* scheme 1: sum of m e, the internal energy (0 in scheme 0) */
 } wcsph_diag;
 
 typedef struct {
@@ -242,6 +269,10 @@ wcsph_status wcsph_read_diagnostics(wcsph_ctx* ctx, int inst, wcsph_diag* out, i
  * lattice, disk interior skipped), decoded to FP64; n = its fluid count. */
 wcsph_status wcsph_get_fluid(wcsph_ctx* ctx, int inst, double* t, double* x, double* y, double* vx,
                              double* vy, double* rho, int n);
+/* Scheme 1: specific internal energy e (J/kg) of instance `inst` in
+ * particle-id order (zero in scheme 0); n = its fluid count (E_RANGE if
+ * smaller). Same validity rule as wcsph_get_fluid. */
+wcsph_status wcsph_get_internal_energy(wcsph_ctx* ctx, int inst, double* e, int n);
 /* Disk centre x, velocity and acceleration (along +x) of instance `inst` at
  * the newest state's time (any pointer may be NULL). For a coupled disk the
  * acceleration is that of the last step. Synchronises the context stream. */
@@ -249,7 +280,8 @@ wcsph_status wcsph_get_disk(wcsph_ctx* ctx, int inst, double* x, double* v, doub
 
 /* Replace the fluid state of every instance (single-instance contexts only):
  * positions are encoded as (cell, FP32 offset), velocities and density to
- * FP32; storage order is reset to id order and the clock set to t. */
+ * FP32; storage order is reset to id order and the clock set to t (scheme 1:
+ * the internal energy to zero, the previous step to none). */
 wcsph_status wcsph_set_fluid(wcsph_ctx* ctx, double t, const double* x, const double* y,
                              const double* vx, const double* vy, const double* rho, int n);
 
@@ -269,10 +301,17 @@ wcsph_status wcsph_export_cells(wcsph_ctx* ctx, unsigned* keys, unsigned* ids_pr
                                 size_t cap_slots, size_t cap_cells);
 /* One evaluation on the current state (ghosts then pair sums, single
  * instance): density rate, acceleration and XSPH velocity per fluid id, ghost
- * pressure / density / velocity per ghost index (walls then ring). */
+ * pressure / density / velocity per ghost index (walls then ring). Scheme 1
+ * (summed density first): drho holds the internal-energy rate de/dt. */
 wcsph_status wcsph_export_rates(wcsph_ctx* ctx, float* drho, float* ax, float* ay, float* Vx,
                                 float* Vy, float* gp, float* grho, float* gvx, float* gvy,
                                 int n_fluid, int n_ghost);
+/* Density and pressure of every fluid particle at the current state, by
+ * fluid id (single instance): scheme 0 the stored density and its EOS
+ * pressure; scheme 1 the clamped summation (eq. density-sum) at the current
+ * positions and the pressure with the internal energy. The state is left
+ * unchanged. n_fluid smaller than the fluid count -> E_RANGE. */
+wcsph_status wcsph_export_density(wcsph_ctx* ctx, float* rho, float* p, int n_fluid);
 /* In-support neighbour count and neighbour-id sum per particle (ids in
  * sorted order), plus decoded positions; single instance. */
 wcsph_status wcsph_export_neighbours(wcsph_ctx* ctx, unsigned* ids, int* count, long long* idsum,

@@ -32,6 +32,7 @@ SYMBOLS = (
     "wcsph_export_rates", "wcsph_export_neighbours", "wcsph_export_neighbour_lists",
     "wcsph_export_neighbour_lists_noalloc", "wcsph_time_pair_kernel",
     "wcsph_set_coefficients", "wcsph_adj_forward", "wcsph_adj_backward",
+    "wcsph_get_internal_energy", "wcsph_export_density",
 )
 
 
@@ -68,7 +69,7 @@ class Params(C.Structure):
         ("kin_mode", C.c_int), ("kin_v0", C.c_double), ("kin_t_ramp", C.c_double),
         ("kin_coef", C.c_double), ("audit", C.c_int), ("beta", C.c_double),
         ("kernel_type", C.c_int), ("eos_type", C.c_int), ("mg_s1", C.c_double),
-        ("mg_gamma0", C.c_double), ("mg_mu_max", C.c_double),
+        ("mg_gamma0", C.c_double), ("mg_mu_max", C.c_double), ("scheme", C.c_int), ("mg_a", C.c_double),
     ]
 
 
@@ -79,7 +80,7 @@ class Diag(C.Structure):
                 ("step", C.c_longlong), ("n_clamp", C.c_longlong), ("n_cav", C.c_longlong),
                 ("n_enforce", C.c_longlong), ("d_av", C.c_double), ("d_visc", C.c_double),
                 ("w_delta", C.c_double), ("w_ghost", C.c_double), ("w_enforce", C.c_double),
-                ("w_clamp", C.c_double)]
+                ("w_clamp", C.c_double), ("e_th", C.c_double)]
 
 
 class Info(C.Structure):
@@ -145,6 +146,8 @@ def lib():
             "wcsph_read_diagnostics": [_V, C.c_int, C.POINTER(Diag), C.c_int, _I],
             "wcsph_get_fluid": [_V, C.c_int, _D, _D, _D, _D, _D, _D, C.c_int],
             "wcsph_get_disk": [_V, C.c_int, _D, _D, _D],
+            "wcsph_get_internal_energy": [_V, C.c_int, _D, C.c_int],
+            "wcsph_export_density": [_V, _F, _F, C.c_int],
             "wcsph_set_fluid": [_V, C.c_double, _D, _D, _D, _D, _D, C.c_int],
             "wcsph_save_state": [_V, _V, C.c_size_t, C.POINTER(C.c_size_t)],
             "wcsph_load_state": [_V, _V, C.c_size_t],
@@ -324,6 +327,23 @@ class Solver:
         st = lib().wcsph_get_fluid(self.handle, inst, C.byref(t), *[_p(x, C.c_double) for x in a], nf)
         self._check(st, (t.value, a))
         return t.value, a
+
+    def internal_energy(self, inst: int = 0):
+        """Specific internal energy per fluid id (scheme 1; zeros otherwise)."""
+        nf = self.sizes[inst][0]
+        e = np.empty(nf)
+        st = lib().wcsph_get_internal_energy(self.handle, inst, _p(e, C.c_double), nf)
+        self._check(st, e)
+        return e
+
+    def export_density(self):
+        """Density and pressure per fluid id at the current state (scheme 1:
+        the clamped summation at the current positions)."""
+        nf = self.nf
+        rho = np.empty(nf, np.float32)
+        p = np.empty(nf, np.float32)
+        self._check(lib().wcsph_export_density(self.handle, _p(rho, C.c_float), _p(p, C.c_float), nf))
+        return rho, p
 
     def disk_state(self, inst: int = 0):
         """(x, v, a) of the disk at the newest state's time."""

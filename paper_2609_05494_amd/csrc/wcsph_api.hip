@@ -106,6 +106,11 @@ struct wcsph_ctx {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph_k = nullptr;     // steps_k steps and a diagnostic record
   hipGraphExec_t gexec_k = nullptr;
+  // scheme 1: the same two graphs starting on bucket set b (the ones above start on set a)
+  hipGraph_t graph1 = nullptr, graph_k1 = nullptr;
+  hipGraphExec_t gexec1 = nullptr, gexec_k1 = nullptr;
+  int scheme = 0;  // 0 predictor-corrector, 1 leapfrog with summation density
+  int lf_set = 0;  // scheme 1: the bucket set the next step's sort reads
   int steps_k = 0;
   long long steps = 0;
   std::vector<long long> hist_read, diag_rows, diag_read;
@@ -202,6 +207,12 @@ void validate(const wcsph_params& p) {
   require(p.audit == 0 || p.audit == 1, "audit must be 0 or 1");
   require(p.beta >= 0 && std::isfinite(p.beta), "beta must be finite and >= 0");
   require(p.kernel_type == 0 || p.kernel_type == 1, "kernel_type must be 0 (Wendland C2) or 1 (cubic spline)");
+  require(p.scheme == 0 || p.scheme == 1, "scheme must be 0 (predictor-corrector) or 1 (leapfrog, summation density)");
+  if (p.scheme == 1) {
+    require(p.kin_mode != 2, "scheme 1 does not take the two-way coupled disk (kin_mode 2)");
+    require(p.audit == 0, "scheme 1 does not take the energy audit");
+    require(p.mg_a >= 0.0 && std::isfinite(p.mg_a), "mg_a must be finite and >= 0");
+  }
   require(p.eos_type == 0 || p.eos_type == 1, "eos_type must be 0 (Tait) or 1 (Mie-Grueneisen)");
   if (p.eos_type == 1)
     require(p.mg_s1 >= 1.0 && p.mg_gamma0 >= 0.0 && p.mg_gamma0 < 2.0 && p.mg_mu_max > 0.0 &&
@@ -252,6 +263,27 @@ HostInst build_geometry(const wcsph_params& p) {
   return g;
 }
 
+// Scheme 1 particle mass: rho0 over the kernel sum of the square lattice of
+// spacing dx (every lattice point within 2h of a particle, itself included),
+// so that the undisturbed lattice sums to rho0 (Density Summation).
+double lattice_mass(const wcsph_params& p) {
+  const double h = p.h_over_dx * p.dx;
+  double S = 0.0;
+  for (int j = -4; j <= 4; ++j)
+    for (int i = -4; i <= 4; ++i) {
+      const double q = std::sqrt((double)(i * i + j * j)) * p.dx / h;
+      if (q >= 2.0) continue;
+      if (p.kernel_type == 1) {
+        const double sg = 10.0 / (7.0 * M_PI * h * h);
+        S += q <= 1.0 ? sg * (1.0 - 1.5 * q * q + 0.75 * q * q * q) : sg * 0.25 * (2.0 - q) * (2.0 - q) * (2.0 - q);
+      } else {
+        const double u = 1.0 - 0.5 * q;
+        S += 7.0 / (4.0 * M_PI * h * h) * u * u * u * u * (2.0 * q + 1.0);
+      }
+    }
+  return p.rho0 / S;
+}
+
 InstParams derive(const wcsph_params& p) {
   InstParams q;
   std::memset(&q, 0, sizeof q);
@@ -286,9 +318,15 @@ InstParams derive(const wcsph_params& p) {
   q.four_nu0 = (float)(4.0 * p.mu_dyn / p.rho0);
   q.delta = (float)p.delta;
   q.two_h_c0 = (float)(2.0 * h * p.c0);
-  q.m_fluid = (float)(p.rho0 * p.dx * p.dx);
-  q.m_wall = (float)(p.rho0 * p.dx * p.dx);
-  q.m_disk = p.n_disk_ghosts > 0 ? (float)(p.rho0 * p.dx * 2.0 * M_PI * p.disk_R / p.n_disk_ghosts) : 0.0f;
+  const double m_part = p.scheme == 1 ? lattice_mass(p) : p.rho0 * p.dx * p.dx;
+  q.m_fluid = (float)m_part;
+  q.m_wall = (float)m_part;
+  q.m_disk = p.n_disk_ghosts > 0 ? (float)(m_part / p.dx * 2.0 * M_PI * p.disk_R / p.n_disk_ghosts) : 0.0f;
+  q.scheme = p.scheme;
+  q.mg_a = (float)p.mg_a;
+  q.mg_g0 = (float)p.mg_gamma0;
+  q.mg_ad = p.mg_a;
+  q.mg_g0d = p.mg_gamma0;
   q.rho_lo = (float)(p.rho_lo * p.rho0);
   q.rho_hi = (float)(p.rho_hi * p.rho0);
   q.inv_rho0c02 = (float)(1.0 / (p.rho0 * p.c0 * p.c0));
@@ -324,7 +362,7 @@ InstParams derive(const wcsph_params& p) {
   q.rho0d = p.rho0;
   q.gammad = p.gamma;
   q.p_cavd = p.p_cav;
-  q.m_fluidd = p.rho0 * p.dx * p.dx;
+  q.m_fluidd = m_part;
   {
     const double g = p.gamma, r0 = p.rho0;
     q.diag_rc = r0 * std::pow(1.0 + p.p_cav / B, 1.0 / g);
@@ -404,6 +442,7 @@ void rearm(wcsph_ctx* c) {
   arm_counts(c);
   wc_enqueue_init(c->d, c->b, c->batch, c->st);
   HC(hipGetLastError());
+  c->lf_set = 0;  // bucket set a now holds the next sort's entries
 }
 
 // Write the set-up (or a given fluid state for instance 0) into X in id
@@ -455,6 +494,7 @@ void upload_state(wcsph_ctx* c, double t0, const double* fx, const double* fy, c
   HC(hipMemcpyAsync(c->b.X.id, id.data(), n * 4, hipMemcpyHostToDevice, c->st));
   HC(hipMemcpyAsync(c->b.X.pv, pv.data(), n * 16, hipMemcpyHostToDevice, c->st));
   HC(hipMemcpyAsync(c->b.X.aux, aux.data(), n * 16, hipMemcpyHostToDevice, c->st));
+  if (c->b.X.e) HC(hipMemsetAsync(c->b.X.e, 0, n * 4, c->st));  // scheme 1: no internal energy yet
   if (c->batch) HC(hipMemcpyAsync(c->b.X.inst, inst.data(), n * 2, hipMemcpyHostToDevice, c->st));
   HC(hipMemcpyAsync(c->d.gslot, gslot.data(), gslot.size() * 4, hipMemcpyHostToDevice, c->st));
   arm_counts(c);
@@ -483,14 +523,14 @@ void upload_state(wcsph_ctx* c, double t0, const double* fx, const double* fy, c
 }
 
 void drop_graphs(wcsph_ctx* c) {
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->graph) hipGraphDestroy(c->graph);
-  if (c->gexec_k) hipGraphExecDestroy(c->gexec_k);
-  if (c->graph_k) hipGraphDestroy(c->graph_k);
-  c->gexec = nullptr;
-  c->graph = nullptr;
-  c->gexec_k = nullptr;
-  c->graph_k = nullptr;
+  for (hipGraphExec_t* e : {&c->gexec, &c->gexec_k, &c->gexec1, &c->gexec_k1}) {
+    if (*e) hipGraphExecDestroy(*e);
+    *e = nullptr;
+  }
+  for (hipGraph_t* g : {&c->graph, &c->graph_k, &c->graph1, &c->graph_k1}) {
+    if (*g) hipGraphDestroy(*g);
+    *g = nullptr;
+  }
 }
 
 // Some instance has a two-way coupled disk: the step launches the disk update.
@@ -503,26 +543,39 @@ bool two_way(const wcsph_ctx* c) {
 // Capture the step graphs: one step, and diag_every steps followed by the
 // diagnostic record (launched when the step count is a multiple of
 // diag_every), so that consecutive steps run without host round trips.
-void capture(wcsph_ctx* c) {
-  drop_graphs(c);
+// One step of the context's scheme; a leapfrog step reads bucket set `set`.
+void enqueue_one_step(wcsph_ctx* c, int set) {
+  if (c->scheme == 1) wc_enqueue_step_lf(c->d, c->b, c->n_gblk, c->batch, set, c->st);
+  else wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, two_way(c), c->audit, c->st);
+}
+void capture_pair(wcsph_ctx* c, int set, hipGraph_t* g1, hipGraphExec_t* e1, hipGraph_t* gk, hipGraphExec_t* ek) {
   hipGraph_t g = nullptr;
   HC(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-  wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, two_way(c), c->audit, c->st);
+  enqueue_one_step(c, set);
   HC(hipStreamEndCapture(c->st, &g));
-  c->graph = g;
-  HC(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
-  c->steps_k = c->diag_every > 0 ? c->diag_every : 10;
+  *g1 = g;
+  HC(hipGraphInstantiate(e1, g, nullptr, nullptr, 0));
   g = nullptr;
   HC(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < c->steps_k; ++k) wc_enqueue_step(c->d, c->b, c->n_gblk, c->batch, two_way(c), c->audit, c->st);
+  for (int k = 0; k < c->steps_k; ++k) enqueue_one_step(c, set ^ (k & 1));
   if (c->diag_every > 0) wc_enqueue_diag(c->d, c->b, true, c->st);
   HC(hipStreamEndCapture(c->st, &g));
-  c->graph_k = g;
-  HC(hipGraphInstantiate(&c->gexec_k, c->graph_k, nullptr, nullptr, 0));
+  *gk = g;
+  HC(hipGraphInstantiate(ek, g, nullptr, nullptr, 0));
+}
+void capture(wcsph_ctx* c) {
+  drop_graphs(c);
+  c->steps_k = c->diag_every > 0 ? c->diag_every : 10;
+  capture_pair(c, 0, &c->graph, &c->gexec, &c->graph_k, &c->gexec_k);
+  // scheme 1 alternates the bucket sets from step to step
+  if (c->scheme == 1) capture_pair(c, 1, &c->graph1, &c->gexec1, &c->graph_k1, &c->gexec_k1);
 }
 
 void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   c->n_inst = n_inst;
+  c->scheme = params[0].scheme;
+  for (int i = 1; i < n_inst; ++i)
+    require(params[i].scheme == c->scheme, "every instance of a batch must use the same scheme");
   c->pin.assign(params, params + n_inst);
   c->diag_every = params[0].diag_every;
   int id0 = 0, gmap0 = 0, cell_off = 0;
@@ -575,6 +628,11 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   alloc_buf(c, c->b.Y);
   alloc_buf(c, c->b.Z);
   alloc_buf(c, c->b.W);
+  if (c->scheme == 1) {  // internal energy: the stored state (X) and the sorted state (Y)
+    c->b.X.e = dalloc_n<float>(c, c->n_slots);
+    c->b.Y.e = dalloc_n<float>(c, c->n_slots);
+    HC(hipMemsetAsync(c->b.Y.e, 0, (size_t)c->n_slots * 4, c->st));
+  }
   Dev& d = c->d;
   c->d_prm = dalloc_n<InstParams>(c, n_inst);
   // tabulated disk motion (kin_mode 3): WC_KIN_ROWS rows per instance, empty until set
@@ -626,7 +684,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.hist_dt = dalloc_n<double>(c, (size_t)n_inst * WC_HIST_CAP);
   d.hist_p = dalloc_n<float>(c, (size_t)n_inst * WC_HIST_CAP * WC_MAX_PROBES);
   d.diag = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_CAP * WC_NDIAG);
-  d.diag_part = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_BLOCKS * 8);
+  d.diag_part = dalloc_n<double>(c, (size_t)n_inst * WC_DIAG_BLOCKS * WC_DIAG_PARTS);
   d.wb_part = dalloc_n<double>(c, (size_t)n_inst * WC_MAX_RING);
   c->d_disk = dalloc_n<double>(c, 3);
   d.var = params[0].kernel_type == 1 ? 2 : 0;
@@ -634,6 +692,7 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
     if (params[i].beta > 0) d.var |= 1;
     if (params[i].eos_type == 1) d.var |= 4;
   }
+  if (c->scheme == 1) d.var |= 8;
   c->audit = !c->batch && params[0].audit != 0;
   d.audit_part = c->audit ? dalloc_n<double>(c, (size_t)wc_pair_blocks(c->n_slots) * 6) : nullptr;
   d.n_vpart = wc_pair_blocks(c->n_slots);
@@ -735,6 +794,12 @@ struct HookGuard {
   Clock* clk;
   explicit HookGuard(wcsph_ctx* cc) : c(cc), clk(&one) {
     sync(c);
+    // scheme 1 after an odd step count: the pending entries are in bucket
+    // set b; the hooks' sort reads set a, so refill it from the state
+    if (c->scheme == 1 && c->lf_set != 0) {
+      rearm(c);
+      sync(c);
+    }
     if (c->n_inst > 1) {
       many.resize(c->n_inst);
       clk = many.data();
@@ -782,6 +847,7 @@ size_t list_export_words(const wcsph_ctx* ctx) { return (size_t)ctx->hp[0].nf * 
 void list_export(wcsph_ctx* ctx, uint32_t* buf, int* count, unsigned* nbr, int max_per) {
   const size_t nf = (size_t)ctx->hp[0].nf;
   wc_enqueue_export_sort(ctx->d, ctx->b, false, ctx->st);
+  if (ctx->scheme == 1) wc_enqueue_export_dens(ctx->d, ctx->b, ctx->st);
   wc_enqueue_export_ghosts(ctx->d, ctx->b, ctx->n_gblk, ctx->st);
   HC(hipMemsetAsync(buf, 0, nf * sizeof(uint32_t), ctx->st));
   Dev dl = ctx->d;
@@ -1018,16 +1084,19 @@ wcsph_status wcsph_step(wcsph_ctx* ctx, int n_steps) {
   const int de = ctx->diag_every, K = ctx->steps_k;
   int n = n_steps;
   while (n > 0) {
+    const bool b_set = ctx->scheme == 1 && ctx->lf_set != 0;
     if (n >= K && (de <= 0 || ctx->steps % de == 0)) {
-      HC(hipGraphLaunch(ctx->gexec_k, ctx->st));
+      HC(hipGraphLaunch(b_set ? ctx->gexec_k1 : ctx->gexec_k, ctx->st));
       ctx->steps += K;
       n -= K;
+      if (ctx->scheme == 1) ctx->lf_set ^= (K & 1);
       if (de > 0)
         for (int i = 0; i < ctx->n_inst; ++i) ctx->diag_rows[i]++;
       continue;
     }
-    HC(hipGraphLaunch(ctx->gexec, ctx->st));
+    HC(hipGraphLaunch(b_set ? ctx->gexec1 : ctx->gexec, ctx->st));
     ctx->steps++;
+    if (ctx->scheme == 1) ctx->lf_set ^= 1;
     --n;
     if (de > 0 && ctx->steps % de == 0) {
       wc_enqueue_diag(ctx->d, ctx->b, true, ctx->st);
@@ -1126,6 +1195,7 @@ wcsph_status wcsph_read_diagnostics(wcsph_ctx* ctx, int inst, wcsph_diag* out, i
     o.w_ghost = v[18];
     o.w_enforce = v[19];
     o.w_clamp = v[20];
+    o.e_th = v[21];
   }
   rd += rows;
   *n_out = (int)rows;
@@ -1160,6 +1230,27 @@ wcsph_status wcsph_get_fluid(wcsph_ctx* ctx, int inst, double* t, double* x, dou
     Clock k;
     HC(hipMemcpy(&k, ctx->d_clk + inst, sizeof k, hipMemcpyDeviceToHost));
     *t = k.t_next;
+  }
+  if (state_invalid(ctx, inst)) return WCSPH_E_UNSTABLE;
+  API_END(ctx)
+}
+
+wcsph_status wcsph_get_internal_energy(wcsph_ctx* ctx, int inst, double* e, int n) {
+  API_BEGIN(ctx)
+  require(inst >= 0 && inst < ctx->n_inst, "instance out of range");
+  require(e != nullptr, "e required");
+  const InstParams& q = ctx->hp[inst];
+  if (n < q.nf) throw WcError{WCSPH_E_RANGE, "output array shorter than the fluid count"};
+  sync(ctx);
+  for (int k = 0; k < q.nf; ++k) e[k] = 0.0;
+  if (ctx->b.X.e) {
+    const size_t N = ctx->n_slots;
+    auto id = d2h(ctx, ctx->b.X.id, N);
+    auto ev = d2h(ctx, ctx->b.X.e, N);
+    for (size_t s = 0; s < N; ++s) {
+      const int k = (int)id[s] - q.id0;
+      if (k >= 0 && k < q.nf) e[k] = ev[s];
+    }
   }
   if (state_invalid(ctx, inst)) return WCSPH_E_UNSTABLE;
   API_END(ctx)
@@ -1205,13 +1296,15 @@ struct BlobHeader {
   long long n_inst, n_slots, n_cells, n_ghost, steps, batch, n_audit;
 };
 size_t audit_bytes(const wcsph_ctx* c) { return c->d.audit_part ? (size_t)c->d.n_vpart * 6 * sizeof(double) : 0; }
+// scheme 1: the internal energy per slot, after everything else
+size_t energy_bytes(const wcsph_ctx* c) { return c->b.X.e ? (size_t)c->n_slots * 4 : 0; }
 }  // namespace
 
 wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* need) {
   API_BEGIN(ctx)
   const size_t N = ctx->n_slots;
   const size_t sz = sizeof(BlobHeader) + ctx->n_inst * sizeof(Clock) + N * (4 + 4 + 16 + 16 + 2) +
-                    (size_t)ctx->n_ghost * 4 + audit_bytes(ctx);
+                    (size_t)ctx->n_ghost * 4 + audit_bytes(ctx) + energy_bytes(ctx);
   if (need) *need = sz;
   if (!buf) return WCSPH_OK;
   if (cap < sz) throw WcError{WCSPH_E_RANGE, "buffer too small for the state"};
@@ -1219,7 +1312,7 @@ wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* nee
   char* o = static_cast<char*>(buf);
   BlobHeader h;
   std::memset(&h, 0, sizeof h);
-  std::memcpy(h.magic, "WCSPHST3", 8);
+  std::memcpy(h.magic, "WCSPHST4", 8);
   h.n_inst = ctx->n_inst;
   h.n_slots = N;
   h.n_cells = ctx->n_cells;
@@ -1245,6 +1338,7 @@ wcsph_status wcsph_save_state(wcsph_ctx* ctx, void* buf, size_t cap, size_t* nee
   }
   put(ctx->d.gslot, (size_t)ctx->n_ghost * 4);
   if (ctx->d.audit_part) put(ctx->d.audit_part, audit_bytes(ctx));
+  if (ctx->b.X.e) put(ctx->b.X.e, energy_bytes(ctx));
   API_END(ctx)
 }
 
@@ -1253,14 +1347,14 @@ wcsph_status wcsph_load_state(wcsph_ctx* ctx, const void* buf, size_t n) {
   require(buf != nullptr && n >= sizeof(BlobHeader), "buffer too small");
   BlobHeader h;
   std::memcpy(&h, buf, sizeof h);
-  require(std::memcmp(h.magic, "WCSPHST3", 8) == 0, "not a state blob");
+  require(std::memcmp(h.magic, "WCSPHST4", 8) == 0, "not a state blob");
   require(h.n_inst == ctx->n_inst && h.n_slots == ctx->n_slots && h.n_cells == ctx->n_cells &&
               h.n_ghost == ctx->n_ghost && h.batch == (long long)ctx->batch &&
               h.n_audit == (long long)audit_bytes(ctx),
           "state blob does not match this context");
   const size_t N = ctx->n_slots;
   const size_t sz = sizeof(BlobHeader) + ctx->n_inst * sizeof(Clock) + N * (4 + 4 + 16 + 16 + 2) +
-                    (size_t)ctx->n_ghost * 4 + audit_bytes(ctx);
+                    (size_t)ctx->n_ghost * 4 + audit_bytes(ctx) + energy_bytes(ctx);
   require(n >= sz, "state blob truncated");
   sync(ctx);
   const char* o = static_cast<const char*>(buf) + sizeof h;
@@ -1277,6 +1371,7 @@ wcsph_status wcsph_load_state(wcsph_ctx* ctx, const void* buf, size_t n) {
   else o += N * 2;
   get(ctx->d.gslot, (size_t)ctx->n_ghost * 4);
   if (ctx->d.audit_part) get(ctx->d.audit_part, audit_bytes(ctx));
+  if (ctx->b.X.e) get(ctx->b.X.e, energy_bytes(ctx));
   rearm(ctx);
   sync(ctx);
   ctx->steps = h.steps;
@@ -1331,6 +1426,7 @@ wcsph_status wcsph_export_rates(wcsph_ctx* ctx, float* drho, float* ax, float* a
   if (n_fluid < q.nf || n_ghost < q.nw + q.nd) throw WcError{WCSPH_E_RANGE, "output arrays too small"};
   HookGuard guard(ctx);
   wc_enqueue_export_sort(ctx->d, ctx->b, false, ctx->st);
+  if (ctx->scheme == 1) wc_enqueue_export_dens(ctx->d, ctx->b, ctx->st);
   wc_enqueue_export_ghosts(ctx->d, ctx->b, ctx->n_gblk, ctx->st);
   wc_enqueue_export_pair(ctx->d, ctx->b, ctx->st);
   HC(hipGetLastError());
@@ -1355,6 +1451,29 @@ wcsph_status wcsph_export_rates(wcsph_ctx* ctx, float* drho, float* ax, float* a
       if (gvx) gvx[g] = pv[s].z;
       if (gvy) gvy[g] = pv[s].w;
     }
+  }
+  guard.restore();
+  API_END(ctx)
+}
+
+wcsph_status wcsph_export_density(wcsph_ctx* ctx, float* rho, float* p, int n_fluid) {
+  API_BEGIN(ctx)
+  require(!ctx->batch, "single-instance contexts only");
+  const InstParams& q = ctx->hp[0];
+  if (n_fluid < q.nf) throw WcError{WCSPH_E_RANGE, "output arrays too small"};
+  HookGuard guard(ctx);
+  wc_enqueue_export_sort(ctx->d, ctx->b, false, ctx->st);
+  if (ctx->scheme == 1) wc_enqueue_export_dens(ctx->d, ctx->b, ctx->st);
+  HC(hipGetLastError());
+  sync(ctx);
+  const size_t N = ctx->n_slots;
+  auto id = d2h(ctx, ctx->b.Y.id, N);
+  auto aux = d2h(ctx, ctx->b.Y.aux, N);
+  for (size_t s = 0; s < N; ++s) {
+    const int k = (int)id[s] - q.id0;
+    if (k < 0 || k >= q.nf) continue;
+    if (rho) rho[k] = aux[s].x;
+    if (p) p[k] = aux[s].y * aux[s].x * aux[s].x;
   }
   guard.restore();
   API_END(ctx)
@@ -1418,6 +1537,7 @@ wcsph_status wcsph_export_neighbour_lists_noalloc(wcsph_ctx* ctx, int* count, un
 wcsph_status wcsph_time_pair_kernel(wcsph_ctx* ctx, int reps, float* avg_ms) {
   API_BEGIN(ctx)
   require(reps >= 1 && reps <= 1000 && avg_ms != nullptr, "reps must lie in [1, 1000]");
+  require(ctx->scheme == 0, "the timing hook times the predictor pass of scheme 0");
   HookGuard guard(ctx);
   wc_enqueue_export_sort(ctx->d, ctx->b, ctx->batch, ctx->st);
   if (!ctx->batch) wc_enqueue_export_ghosts(ctx->d, ctx->b, ctx->n_gblk, ctx->st);
@@ -1480,6 +1600,7 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   require(ctx->pin[0].beta == 0, "the reverse sweep supports the linear artificial viscosity only (beta = 0)");
   require(ctx->pin[0].eos_type == 0, "the reverse sweep supports the Tait EOS only");
   require(ctx->pin[0].kernel_type == 0, "the reverse sweep supports the Wendland C2 kernel only");
+  require(ctx->scheme == 0, "the reverse sweep supports scheme 0 only");
   require(n_steps >= 1 && ckpt_every >= 1, "n_steps and ckpt_every must be >= 1");
   const long long k0 = ctx->steps - ctx->d.dt_step0;
   require(ctx->d.n_dt > 0 && k0 >= 0 && k0 + n_steps <= ctx->d.n_dt,

@@ -15,7 +15,7 @@
 #define WC_MAX_PROBES 16
 #define WC_HIST_CAP 65536
 #define WC_DIAG_CAP 4096
-#define WC_NDIAG 21
+#define WC_NDIAG 22
 #define WC_BLOCK 256
 #define WC_GHOST_BLOCK 256
 #define WC_GHOST_LANES 16      // lanes per ghost or probe in the ghost kernel
@@ -69,6 +69,14 @@ struct InstParams {
   // kin_mode 3: the instance's table of prescribed motion, kin_tab_n rows (t, x, v, a) (device)
   const double* kin_tab;
   int kin_tab_n;
+  // scheme 0: continuity + delta term, predictor-corrector; 1: the paper as
+  // published (summation density over fluid and ghosts with the density
+  // band, leapfrog, the specific internal energy heated by the artificial
+  // viscosity, and with the Mie-Grueneisen law its energy term (gamma0 +
+  // mg_a mu) rho e). Scheme 1 masses are lattice-normalised (m_fluid etc.).
+  int scheme;
+  float mg_a, mg_g0;
+  double mg_ad, mg_g0d;
 };
 
 // Per-instance clock and accumulators (device-resident, FP64 time).
@@ -84,6 +92,7 @@ struct Clock {
   double v_work;      // coupled disk: mean velocity of the step (boundary work)
   double w_boundary;  // integrated work of the disk ghosts on the fluid
   double vmax_used;   // v_max that set dt
+  double dt_prev;     // scheme 1: dt of the previous step (0 before the first), for the merged kick
   long long step;     // index of the current step (-1 before the first)
   long long diag_row; // diagnostic records written so far
   unsigned long long n_clamp, n_enforce;
@@ -100,6 +109,7 @@ struct Buf {
   float4* pv;       // (ox, oy, vx, vy): offset inside the cell, velocity
   float4* aux;      // (rho, P = p / rho^2, c, m) ; m < 0 marks a ghost
   uint16_t* inst;   // instance (batched contexts only)
+  float* e;         // scheme 1: specific internal energy (NULL otherwise)
 };
 
 // Everything a kernel may touch (passed by value).
@@ -133,13 +143,15 @@ struct Dev {
   int n_dt;
   long long dt_step0;
   double* diag;               // [n_inst][WC_DIAG_CAP][WC_NDIAG]
-  double* diag_part;          // [n_inst][WC_DIAG_BLOCKS][8] partial sums
+  double* diag_part;          // [n_inst][WC_DIAG_BLOCKS][WC_DIAG_PARTS] partial sums
   double* wb_part;            // [n_inst][WC_MAX_RING] x force of each ring ghost on the fluid
   float* vmax_part;           // single instance: per corrector pair wave, max |v| of its new fluid
                               // state (folded into the clock by the next first-evaluation sort)
   int n_vpart;                // entries of vmax_part and audit_part (waves of the pair pass)
   int var;                    // pass variants: bit 0 quadratic AV (some beta > 0), bit 1 cubic spline,
                               // bit 2 some instance uses the Mie-Grueneisen EOS (sort pass)
+  int lf_set;                 // scheme 1: the bucket set (0 a, 1 b) this step's sort reads; its
+                              // pair pass fills the other
   double* audit_part;         // energy audit (single instance, or NULL): per corrector pair wave,
                               // running sums of d_av, d_visc, w_delta, w_ghost, w_enforce, w_clamp
   float* xr;                  // export: [5][n_slots] rates per slot
@@ -175,6 +187,10 @@ struct AdjPtrs {
   int n_ghost_probe;
 };
 
-enum { EV_A = 0, EV_B = 1, EV_EXPORT = 2 };
+// Passes: EV_A / EV_B the predictor / corrector evaluation, EV_EXPORT an
+// evaluation of the newest state that changes nothing (test hooks), EV_L the
+// single evaluation of a scheme-1 (leapfrog) step.
+enum { EV_A = 0, EV_B = 1, EV_EXPORT = 2, EV_L = 3 };
+#define WC_DIAG_PARTS 9  // M, px, py, ke, e_el, e_pot, n_cav, bad, e_th
 
 

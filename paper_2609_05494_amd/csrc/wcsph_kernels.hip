@@ -92,12 +92,17 @@ __device__ __forceinline__ void mg_eos(const InstParams& P, float x, float& p, f
 }
 
 // MG: some instance uses the Mie-Grueneisen law (else the check is compiled out).
+// e: the specific internal energy (scheme 1; 0 otherwise), which adds the
+// energy term of eq. eos to the Mie-Grueneisen pressure, (gamma0 + a mu)
+// rho0 (1 + mu) e at the capped mu in compression, gamma0 rho e in tension.
 template <bool MG>
-__device__ __forceinline__ void fluid_eos(const InstParams& P, float rho, float& Pq, float& c) {
+__device__ __forceinline__ void fluid_eos(const InstParams& P, float rho, float& Pq, float& c, float e = 0.0f) {
   const float x = (rho - P.rho0) / P.rho0;
   float p;
   if (MG && P.eos_type == 1) {
     mg_eos(P, x, p, c);
+    const float mu = fminf(x, P.mg_mu_max);
+    p += (mu >= 0.0f ? P.mg_g0 + P.mg_a * mu : P.mg_g0) * (P.rho0 * (1.0f + mu)) * e;
   } else if (P.gamma == 7.0f) {
     const float y = 1.0f + x;
     p = P.B * (x * (7.0f + x * (21.0f + x * (35.0f + x * (35.0f + x * (21.0f + x * (7.0f + x)))))));
@@ -303,7 +308,10 @@ __device__ __forceinline__ uint32_t dx_code(uint32_t j, const RowRange& r) {
 // (symmetric form), laminar (Lo-Shao), XSPH. Branch-free: a ghost neighbour
 // (m < 0) contributes nothing to the delta and XSPH terms through m_fl = 0,
 // and the AV switch is min(v_ij . r_ij, 0).
-// VAR: bit 0 the quadratic AV term, bit 1 the cubic spline kernel.
+// VAR: bit 0 the quadratic AV term, bit 1 the cubic spline kernel, bit 2
+// (scheme 1) D takes the internal-energy rate (1/2) m_j Pi_ij F v_ij . r_ij
+// instead of the continuity and delta terms, bit 3 (scheme 1 density pass)
+// D takes m_j W_ij and nothing else is summed.
 template <bool AUD, int VAR, class PP>
 __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float rhoi, float Pi,
                                           float ci, float rx, float ry, float r2, const float4& pj,
@@ -311,6 +319,10 @@ __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float r
   float W, F;
   if constexpr ((VAR & 2) != 0) cubic_spline(P, r2, W, F);
   else wendland(P, r2, W, F);
+  if constexpr ((VAR & 8) != 0) {  // summation density: |m_j| W_ij over fluid and ghosts
+    acc.D += fabsf(aj.w) * W;
+    return;
+  }
   const float vxij = pi.z - pj.z, vyij = pi.w - pj.w;
   const float vr = vxij * rx + vyij * ry;
   const float mj = fabsf(aj.w);
@@ -326,7 +338,8 @@ __device__ __forceinline__ void pair_body(const PP& P, const float4& pi, float r
   const float mF = mj * F;
   // continuity + delta diffusion 2 delta h c0 (m_j / rho_j)(rho_i - rho_j) F (fluid pairs)
   const float dd = (0.5f * P.two_delta_h_c0) * mfl2 * fast_rcp(aj.x) * (rhoi - aj.x) * F;
-  acc.D += mF * vr + dd;
+  if constexpr ((VAR & 4) != 0) acc.D += 0.5f * mF * piav * vr;
+  else acc.D += mF * vr + dd;
   const float sp = Pi + aj.y + piav;
   // laminar (Lo-Shao): 4 nu0 m_j F r^2 / ((rho_i + rho_j)(r^2 + eta^2 h^2)) v_ij
   const float lam = P.four_nu0 * mF * r2 * inv;
@@ -683,7 +696,7 @@ __device__ void clock_commit(const Dev& d, int i) {
   const InstParams& P = d.prm[i];
   Clock& C = d.clk[i];
   double te;
-  if (MODE == EV_A) {
+  if (MODE == EV_A || MODE == EV_L) {
     C.t = C.t_next;
     C.step += 1;
     te = C.t;
@@ -856,7 +869,7 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
 struct Loaded {
   uint32_t cell, id;
   float4 pv;
-  float rho;
+  float rho, e;  // e: scheme 1 internal energy
   int inst;  // -1: corrupted bucket entry
 };
 // One particle moved by the sort: its state with the per-particle EOS
@@ -864,6 +877,7 @@ struct Loaded {
 struct Gathered {
   uint32_t cell, id;
   float4 pv, aux;
+  float e;
   int inst, ghost;  // ghost: -1 for fluid, else the ghost index g of its instance
 };
 // (branch-free: an entry outside the slot range reads slot 0 and is marked)
@@ -877,6 +891,7 @@ __device__ __forceinline__ Loaded sort_load(const Dev& d, const Buf& pre, uint32
   v.id = pre.id[x];
   v.pv = pre.pv[x];
   v.rho = pre.aux[x].x;
+  v.e = pre.e ? pre.e[x] : 0.0f;
   if (!ok) v.inst = -1;
   return v;
 }
@@ -889,10 +904,12 @@ __device__ __forceinline__ Gathered sort_finish(const Dev& d, const Loaded& l) {
   v.cell = l.cell;
   v.id = l.id;
   v.pv = l.pv;
+  v.e = l.e;
   const int local = (int)l.id - P.id0;
   if (local < P.nf) {
-    float Pq, c;
-    fluid_eos<MG>(P, l.rho, Pq, c);
+    float Pq = 0.0f, c = 0.0f;
+    // (scheme 1: the density pass that follows sums the density and applies the EOS)
+    if (P.scheme == 0) fluid_eos<MG>(P, l.rho, Pq, c);
     v.aux = make_float4(l.rho, Pq, c, P.m_fluid);
     v.ghost = -1;
   } else {
@@ -919,6 +936,7 @@ __device__ __forceinline__ void sort_store(const Dev& d, const Buf& out, uint32_
   out.pv[dst] = v.pv;
   out.aux[dst] = v.aux;
   if constexpr (BATCH) out.inst[dst] = (uint16_t)v.inst;
+  if (out.e) out.e[dst] = v.e;
   d.perm[dst] = e;
 }
 
@@ -929,7 +947,10 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
   __shared__ uint32_t s_base;        // sorted slots before this tile
   __shared__ uint32_t s_raw[T * WC_BUCKET];
   const int t = threadIdx.x, tile = blockIdx.x;
-  const uint32_t* bucket = MODE == EV_B ? d.bucket_b : d.bucket_a;
+  // the bucket set this sort reads: b for the corrector, the step's set for
+  // a leapfrog step, else a
+  const bool set_b = MODE == EV_B || (MODE == EV_L && d.lf_set != 0);
+  const uint32_t* bucket = set_b ? d.bucket_b : d.bucket_a;
   // cell lanes: lane sub of cell c owns the entries sub + 4 u of its bucket
   const int ct = t - 64, c = ct >> 2, sub = ct & 3;
   uint32_t n = 0u, e[SORT_SPEC], r[SORT_SPEC];
@@ -939,7 +960,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     // the tile's local offsets, and the sorted slots before the tile: the
     // entry totals of the tiles before it (filled with the buckets)
     const int K = tile * T + t;
-    const uint32_t* tot = MODE == EV_B ? d.tot_b : d.tot_a;
+    const uint32_t* tot = set_b ? d.tot_b : d.tot_a;
     uint32_t excl = 0u;
     for (int u = t; u < tile; u += 64) excl += tot[u];
     const uint32_t cnt = K < d.n_cells ? min(d.count[K], (uint32_t)WC_BUCKET) : 0u;  // overflow was flagged
@@ -953,7 +974,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     if (t == 63) s_off[T] = total;
     for (int o = 32; o > 0; o >>= 1) excl += __shfl_xor(excl, o);
     // re-arm the other bucket set's total of this tile
-    if (t == 0) (MODE == EV_B ? d.tot_a : d.tot_b)[tile] = d.wall_tot[tile];
+    if (t == 0) (set_b ? d.tot_a : d.tot_b)[tile] = d.wall_tot[tile];
     if (t == 0) s_base = excl;
     if (K < d.n_cells) d.start[K] = excl + (incl - cnt);
     if (K == d.n_cells - 1) d.start[d.n_cells] = excl + incl;
@@ -964,7 +985,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     // [64 F k, 64 F (k + 1)) of the previous corrector's per-block fluid
     // maxima (F = SORT_FOLD per lane, loads in flight during the sort) into
     // the clock with one atomic at the end
-    const bool fold = MODE == EV_A && !BATCH && ct < 64 && tile * 64 * SORT_FOLD < d.n_vpart;
+    const bool fold = (MODE == EV_A || MODE == EV_L) && !BATCH && ct < 64 && tile * 64 * SORT_FOLD < d.n_vpart;
     float vp = 0.0f;
     if (fold) {
 #pragma unroll
@@ -1024,7 +1045,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     // filled with inert entries (no particle id, zero mass, the tile's last
     // cell, old slot 0) so that every sorted slot holds a valid cell key and
     // a finite state that no later kernel moves or counts
-    const uint32_t* tot = MODE == EV_B ? d.tot_b : d.tot_a;
+    const uint32_t* tot = set_b ? d.tot_b : d.tot_a;
     const uint32_t stored = s_off[T];
     const uint32_t end = tile == (int)gridDim.x - 1 ? (uint32_t)d.n_slots - s_base : tot[tile];
     const uint32_t kin = (uint32_t)min(tile * T + T - 1, d.n_cells - 1);
@@ -1036,6 +1057,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
       out.pv[dst] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       out.aux[dst] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
       if constexpr (BATCH) out.inst[dst] = 0;
+      if (out.e) out.e[dst] = 0.0f;
       d.perm[dst] = 0u;
     }
     return;
@@ -1069,10 +1091,11 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
   // first evaluation: the stored v_max (the fluid part is already in) read
   // now, so that its latency is hidden; a wave whose ghost maximum is not
   // above it skips the atomic
-  const uint32_t vcheck = MODE == EV_A && kind != 2 ? __atomic_load_n(&C.vmax_bits, __ATOMIC_RELAXED) : 0u;
+  constexpr bool FIRST = MODE == EV_A || MODE == EV_L;  // the step's first (or only) evaluation
+  const uint32_t vcheck = FIRST && kind != 2 ? __atomic_load_n(&C.vmax_bits, __ATOMIC_RELAXED) : 0u;
   if (kind == 2) {
     // probes: Shepard average of the fluid pressure at fixed wall points
-    if (MODE == EV_A && act) {
+    if (FIRST && act) {
       const int k = blk.y + item;
       const Shep S = shepard<GL, CUB>(d, P, sb, P.probe_cell[k], P.probe_ox[k], P.probe_oy[k], lane);
       if (lane == 0) {
@@ -1130,7 +1153,7 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
       sb.aux[s] = make_float4(rg, Pg, cg, -m);
       vmag = fast_sqrt(vgx * vgx + vgy * vgy);
     }
-    if (MODE == EV_B && disk) {
+    if ((MODE == EV_B || MODE == EV_L) && disk) {
       // x force of this ring ghost on its fluid neighbours (pressure + AV)
       float fx = 0.0f;
       for_candidates<GL>(d, P, sb, K, lane, [&](const float4& pj, const float4& aj, uint32_t code) __attribute__((always_inline)) {
@@ -1155,7 +1178,7 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
       if (lane == 0) d.wb_part[inst * WC_MAX_RING + (g - P.nw)] = f;
     }
   }
-  if (MODE == EV_A) {
+  if (FIRST) {
     // the items of a block belong to one instance
     const float w = wave_max(vmag);
     if ((t & 63) == 0 && w > 0.0f && __float_as_uint(w) > vcheck) atomicMax(&C.vmax_bits, __float_as_uint(w));
@@ -1314,15 +1337,19 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
   const bool fluid = inr && h_m[threadIdx.x] > 0.0f;
   const uint32_t eb = h_eb[threadIdx.x];
   const int gid = (int)id_i - P.id0 - P.nf;  // ghost index (an inert entry has none)
+  // the bucket set this pass fills for the next sort
+  const Fill next_fill = (MODE == EV_A || (MODE == EV_L && d.lf_set == 0)) ? fill_b(d) : fill_a(d);
   if (MODE != EV_EXPORT && inr && !fluid && gid >= 0 && gid < P.nw + P.nd) {
     // ghosts: wall ghosts are carried, the disk ring is placed at the time of
-    // the next evaluation (t + dt/2 after eval A, t + dt after eval B)
+    // the next evaluation (t + dt/2 after eval A, t + dt after eval B or a
+    // leapfrog step)
     const uint32_t id = id_i;
     const int ring = (int)id - P.id0 - P.nf - P.nw;
     out.id[s] = id;
     out.aux[s] = make_float4(rho_i, 0.0f, 0.0f, 0.0f);
     if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
-    const Fill bucket = MODE == EV_A ? fill_b(d) : fill_a(d);
+    if (out.e) out.e[s] = 0.0f;
+    const Fill bucket = next_fill;
     if (ring >= 0) {
       double xc = C.xd_next;
       if (MODE == EV_A) {  // disk at t + dt/2
@@ -1363,7 +1390,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     uint32_t Kb;
     float4 pb;
     float rb;
-    if (MODE == EV_A) {
+    if (MODE == EV_A || MODE == EV_L) {
       Kb = K;
       pb = pi;
       rb = rho_i;
@@ -1374,14 +1401,29 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       pb = at32(base.pv, eb);
       rb = at32(base.aux, eb).x;
     }
-    float rn = rb + hdt * acc.D;
-    const float rn_free = rn;
-    if (rn < P.rho_lo) { rn = P.rho_lo; clamp_hit = true; }
-    if (rn > P.rho_hi) { rn = P.rho_hi; clamp_hit = true; }
-    float vx = pb.z + hdt * acc.ax;
-    float vy = pb.w + hdt * (acc.ay + P.gy);
-    float ox = pb.x + hdt * (pi.z + acc.Vx);
-    float oy = pb.y + hdt * (pi.w + acc.Vy);
+    float rn, rn_free, vx, vy, ox, oy, e_new = 0.0f;
+    if constexpr (MODE == EV_L) {
+      // leapfrog (scheme 1): merged kick v^(n+1/2) = v^(n-1/2) + (dt^(n-1) +
+      // dt^n)/2 a^n, drift with the new velocity plus the XSPH correction,
+      // internal energy by its rate (D); rho is the step's summed density
+      const float kick = (float)(0.5 * (C.dt_prev + dt)), fdt = (float)dt;
+      rn = rb;
+      rn_free = rn;
+      vx = pb.z + kick * acc.ax;
+      vy = pb.w + kick * (acc.ay + P.gy);
+      ox = pb.x + fdt * (vx + acc.Vx);
+      oy = pb.y + fdt * (vy + acc.Vy);
+      e_new = sb.e[s] + fdt * acc.D;
+    } else {
+      rn = rb + hdt * acc.D;
+      rn_free = rn;
+      if (rn < P.rho_lo) { rn = P.rho_lo; clamp_hit = true; }
+      if (rn > P.rho_hi) { rn = P.rho_hi; clamp_hit = true; }
+      vx = pb.z + hdt * acc.ax;
+      vy = pb.w + hdt * (acc.ay + P.gy);
+      ox = pb.x + hdt * (pi.z + acc.Vx);
+      oy = pb.y + hdt * (pi.w + acc.Vy);
+    }
     int cx, cy;
     cell_xy(P, Kb, cx, cy);
     renorm(ox, cx, P.dc);
@@ -1440,9 +1482,10 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
     out.aux[s] = make_float4(rn, 0.0f, 0.0f, 0.0f);
     out.id[s] = id_i;
     if constexpr (BATCH) out.inst[s] = (uint16_t)inst;
+    if constexpr (MODE == EV_L) out.e[s] = e_new;
     newkey = Kn;
     vnew = fast_sqrt(vx * vx + vy * vy);
-    if (!(rn == rn) || !(vnew <= 3.0e38f)) atomicOr(&clk[inst].bad, 1u);
+    if (!(rn == rn) || !(vnew <= 3.0e38f) || !(fabsf(e_new) <= 3.0e38f)) atomicOr(&clk[inst].bad, 1u);
     if constexpr (AUD && MODE == EV_B) {
       // the energy the enforcement and the density clamp add to the new state
       const double m = (double)h_m[threadIdx.x];
@@ -1471,8 +1514,18 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       a[5] += tot[5];
     }
   }
-  bucket_put_wave(d, MODE == EV_A ? fill_b(d) : fill_a(d), lead, newkey, (uint32_t)s);
+  bucket_put_wave(d, next_fill, lead, newkey, (uint32_t)s);
   count_hits<BATCH>(clk, inst, clamp_hit, enf_hit);
+  if (MODE == EV_L) {
+    // as after a corrector: this block's max |v| of the new state for the
+    // next step's dt (the clock pass has already closed this step)
+    if constexpr (BATCH) {
+      vmax_update<BATCH>(clk, inst, lead, vnew);
+    } else {
+      const float w = wave_max(lead ? vnew : 0.0f);
+      if (threadIdx.x == 0) d.vmax_part[blockIdx.x] = w;
+    }
+  }
   if (MODE == EV_B) {
     if constexpr (BATCH) {
       vmax_update<BATCH>(clk, inst, lead, vnew);
@@ -1499,6 +1552,82 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
       }
     }
   }
+}
+
+// Summation density of scheme 1 (eq. density-sum), in place on the sorted
+// state: per fluid slot, the pair-sum machinery above sums |m_j| W_ij over
+// the fluid and ghosts in support (the ring already at this step's time),
+// the particle's own m_i W(0) is added, the result is clamped to the density
+// band (counted), and the EOS with the internal energy fills (rho, P, c). A
+// neighbour's aux is read only for its mass, which this pass does not
+// change. count: add the clamp hits to the clock (0 for the test hooks).
+template <bool BATCH, int VAR>
+__global__ __launch_bounds__(PAIR_BLOCK) void k_dens(Dev d, Buf sb, int count) {
+  __shared__ float4 uni[PAIR_BLOCK / 64][UCAP];
+  __shared__ uint8_t lst[LCAP * PAIR_BLOCK];
+  const int s0 = xcd_block(blockIdx.x, gridDim.x) * PAIR_SLOTS;
+  const int q = (int)(threadIdx.x % PAIR_G);
+  const int s = s0 + (int)(threadIdx.x / PAIR_G);
+  const bool inr = s < d.n_slots;
+  const int inst = inr ? inst_at<BATCH>(sb, s) : 0;
+  uint32_t K = 0;
+  float4 pi = make_float4(0, 0, 0, 0), ai = make_float4(0, 0, 0, 0);
+  if (inr) {
+    K = sb.cell[s];
+    pi = sb.pv[s];
+    ai = sb.aux[s];
+  }
+  const bool fluid = inr && ai.w > 0.0f;
+  PairAcc acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  AudAcc aud = {0.0f, 0.0f, 0.0f, 0.0f};
+  pair_sums_wave<BATCH, false, VAR | 8>(d, sb, s, inst, K, fluid, pi, ai, q, uni[threadIdx.x >> 6],
+                                        lst + threadIdx.x, acc, aud);
+  const float sum = slot_sum(acc.D);
+  bool clamp_hit = false;
+  if (q == 0 && fluid) {
+    const InstParams& P = d.prm[inst];
+    float W0, F0;
+    if constexpr ((VAR & 2) != 0) cubic_spline(P, 0.0f, W0, F0);
+    else wendland(P, 0.0f, W0, F0);
+    float rho = sum + ai.w * W0;
+    if (rho < P.rho_lo) { rho = P.rho_lo; clamp_hit = true; }
+    if (rho > P.rho_hi) { rho = P.rho_hi; clamp_hit = true; }
+    float Pq, c;
+    fluid_eos<true>(P, rho, Pq, c, sb.e[s]);
+    sb.aux[s] = make_float4(rho, Pq, c, ai.w);
+    if (!(rho == rho) || !(fabsf(Pq) <= 3.0e38f)) atomicOr(&d.clk[inst].bad, 1u);
+  }
+  if (count) count_hits<BATCH>(d.clk, inst, clamp_hit, false);
+}
+
+// The clock of a scheme-1 step (one wave per instance, after the ghost
+// pass): dt from v_max (fluid of the stored state and ghosts) or the fixed
+// table, the previous step's dt kept for the merged kick, the probe row's
+// (t, dt), the disk at t + dt for the enforcement and the ring of the next
+// step, the ring's work over the step (its x force at t times the disk
+// velocity at t times dt, a fixed-order sum) and the new state's time.
+__global__ __launch_bounds__(64) void k_clock_lf(Dev d) {
+  const int i = blockIdx.x;
+  const InstParams& P = d.prm[i];
+  Clock& C = d.clk[i];
+  double f = 0.0;
+  for (int k = (int)threadIdx.x; k < P.nd; k += 64) f += d.wb_part[i * WC_MAX_RING + k];
+  f = wave_sum(f);
+  if (threadIdx.x != 0) return;
+  const double dt = step_dt(d, P, C);
+  C.dt_prev = C.dt;
+  C.dt = dt;
+  C.vmax_used = (double)__uint_as_float(C.vmax_bits);
+  C.vmax_bits = 0u;
+  const long long row = (long long)i * WC_HIST_CAP + (C.step % WC_HIST_CAP);
+  d.hist_t[row] = C.t;
+  d.hist_dt[row] = dt;
+  double xn, vn, an;
+  kinematics(P, C.t + dt, xn, vn, an);
+  C.xd_next = xn;
+  C.vd_next = vn;
+  C.w_boundary += dt * f * C.vd;
+  C.t_next = C.t + dt;
 }
 
 // Two-way coupled disk (kin_mode 2), one wave per instance between the
@@ -1581,12 +1710,14 @@ __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
   const int a = lo + b * chunk, e = min(hi, a + chunk);
   const double g = P.gammad, r0 = P.rho0d, B = P.Bd, m = P.m_fluidd;
   const double rc = P.diag_rc, k1 = P.diag_k1, r0g1 = P.diag_r0g1, erc = P.diag_erc, inv_r0g = P.diag_inv_r0g;
-  double M = 0, px = 0, py = 0, ke = 0, eel = 0, epot = 0, ncav = 0, bad = 0;
+  double M = 0, px = 0, py = 0, ke = 0, eel = 0, epot = 0, ncav = 0, bad = 0, eth = 0;
   for (int s = a + (int)threadIdx.x; s < e; s += 256) {
     const int local = (int)X.id[s] - P.id0;
     if (local < 0 || local >= P.nf) continue;
     const float4 pv = X.pv[s];
     const double r = (double)X.aux[s].x;
+    const double ei = X.e ? (double)X.e[s] : 0.0;  // scheme 1: specific internal energy
+    eth += m * ei;
     int cx, cy;
     cell_xy(P, X.cell[s], cx, cy);
     const double y = P.y_lo + (double)cy * P.dcd + (double)pv.y;
@@ -1598,7 +1729,8 @@ __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
     if (P.eos_type == 1) {
       eel += m * mg_e_el(P, r);
       const double mu = r / r0 - 1.0;
-      ncav += (mu < 0.0 && P.mg_Kd * mu <= P.p_cavd) ? 1.0 : 0.0;
+      // (scheme 1: with the energy term gamma0 rho e of the tension branch)
+      ncav += (mu < 0.0 && P.mg_Kd * mu + P.mg_g0d * r * ei <= P.p_cavd) ? 1.0 : 0.0;
     } else {
       const double rg1 = pow_gm1(r, g);
       // specific elastic energy of the Tait law, cutoff branch below rho_c
@@ -1608,17 +1740,18 @@ __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
     epot += m * (-(double)P.gy) * y;
     if (!(r == r) || !(fabs(u) < 1e30) || !(fabs(w) < 1e30)) bad += 1.0;
   }
-  const double v[8] = {M, px, py, ke, eel, epot, ncav, bad};
-  __shared__ double ws[4][8];
+  const double v[WC_DIAG_PARTS] = {M, px, py, ke, eel, epot, ncav, bad, eth};
+  __shared__ double ws[4][WC_DIAG_PARTS];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < WC_DIAG_PARTS; ++k) {
     const double x = wave_sum(v[k]);
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6][k] = x;
   }
   __syncthreads();
-  if (threadIdx.x < 8) {
+  if (threadIdx.x < WC_DIAG_PARTS) {
     const int k = threadIdx.x;
-    d.diag_part[((long long)i * WC_DIAG_BLOCKS + b) * 8 + k] = ((ws[0][k] + ws[1][k]) + ws[2][k]) + ws[3][k];
+    d.diag_part[((long long)i * WC_DIAG_BLOCKS + b) * WC_DIAG_PARTS + k] =
+        ((ws[0][k] + ws[1][k]) + ws[2][k]) + ws[3][k];
   }
 }
 
@@ -1628,14 +1761,15 @@ __global__ __launch_bounds__(64) void k_diag_final(Dev d) {
   // in order, then a butterfly over the wave
   static_assert(WC_DIAG_BLOCKS % 64 == 0, "whole waves of block partials");
   constexpr int NB = WC_DIAG_BLOCKS / 64;
-  double part[NB][8];  // every load in flight before the sums
+  double part[NB][WC_DIAG_PARTS];  // every load in flight before the sums
 #pragma unroll
   for (int j = 0; j < NB; ++j)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) part[j][k] = d.diag_part[((long long)i * WC_DIAG_BLOCKS + threadIdx.x + 64 * j) * 8 + k];
-  double tot[8];
+    for (int k = 0; k < WC_DIAG_PARTS; ++k)
+      part[j][k] = d.diag_part[((long long)i * WC_DIAG_BLOCKS + threadIdx.x + 64 * j) * WC_DIAG_PARTS + k];
+  double tot[WC_DIAG_PARTS];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < WC_DIAG_PARTS; ++k) {
     double v = 0.0;
 #pragma unroll
     for (int j = 0; j < NB; ++j) v += part[j][k];
@@ -1674,6 +1808,7 @@ __global__ __launch_bounds__(64) void k_diag_final(Dev d) {
   o[14] = (double)C.n_enforce;
 #pragma unroll
   for (int k = 0; k < 6; ++k) o[15 + k] = aud[k];
+  o[21] = tot[8];
   if (tot[7] > 0.0 || !(tot[3] == tot[3])) C.bad |= 1u;
 }
 
@@ -1726,16 +1861,35 @@ static void launch_ghost(const Dev& d, int n_gblk, const Buf& sb, hipStream_t st
 }
 
 // The pair pass of the context's scheme variant: bit 0 the quadratic AV
-// term (some instance has beta > 0), bit 1 the cubic spline kernel.
-template <int MODE, bool BATCH, bool AUD = false>
-static void launch_pair(const Dev& d, const Buf& sb, const Buf& base, const Buf& out, hipStream_t st) {
+// term (some instance has beta > 0), bit 1 the cubic spline kernel; scheme 1
+// (d.var bit 3) sums the internal-energy rate in place of the density rate.
+template <int MODE, bool BATCH, bool AUD, int V4>
+static void launch_pair_v(const Dev& d, const Buf& sb, const Buf& base, const Buf& out, hipStream_t st) {
   const dim3 g(NQ(d.n_slots)), b(PAIR_BLOCK);
   switch (d.var & 3) {
-    case 0: k_pair<MODE, BATCH, AUD, 0><<<g, b, 0, st>>>(d, sb, base, out); break;
-    case 1: k_pair<MODE, BATCH, AUD, 1><<<g, b, 0, st>>>(d, sb, base, out); break;
-    case 2: k_pair<MODE, BATCH, AUD, 2><<<g, b, 0, st>>>(d, sb, base, out); break;
-    default: k_pair<MODE, BATCH, AUD, 3><<<g, b, 0, st>>>(d, sb, base, out); break;
+    case 0: k_pair<MODE, BATCH, AUD, V4 | 0><<<g, b, 0, st>>>(d, sb, base, out); break;
+    case 1: k_pair<MODE, BATCH, AUD, V4 | 1><<<g, b, 0, st>>>(d, sb, base, out); break;
+    case 2: k_pair<MODE, BATCH, AUD, V4 | 2><<<g, b, 0, st>>>(d, sb, base, out); break;
+    default: k_pair<MODE, BATCH, AUD, V4 | 3><<<g, b, 0, st>>>(d, sb, base, out); break;
   }
+}
+template <int MODE, bool BATCH, bool AUD = false>
+static void launch_pair(const Dev& d, const Buf& sb, const Buf& base, const Buf& out, hipStream_t st) {
+  if constexpr (MODE == EV_L) launch_pair_v<MODE, BATCH, AUD, 4>(d, sb, base, out, st);
+  else if constexpr (MODE == EV_EXPORT) {
+    if (d.var & 8) launch_pair_v<MODE, BATCH, AUD, 4>(d, sb, base, out, st);
+    else launch_pair_v<MODE, BATCH, AUD, 0>(d, sb, base, out, st);
+  } else {
+    launch_pair_v<MODE, BATCH, AUD, 0>(d, sb, base, out, st);
+  }
+}
+
+// The summation-density pass (scheme 1) of the context's kernel.
+template <bool BATCH>
+static void launch_dens(const Dev& d, const Buf& sb, bool count, hipStream_t st) {
+  const dim3 g(NQ(d.n_slots)), b(PAIR_BLOCK);
+  if (d.var & 2) k_dens<BATCH, 2><<<g, b, 0, st>>>(d, sb, count ? 1 : 0);
+  else k_dens<BATCH, 0><<<g, b, 0, st>>>(d, sb, count ? 1 : 0);
 }
 
 template <bool BATCH>
@@ -1744,10 +1898,12 @@ static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, co
   if (d.var & 4) {
     if (mode == EV_A) k_sort<EV_A, BATCH, true><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
     else if (mode == EV_B) k_sort<EV_B, BATCH, true><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+    else if (mode == EV_L) k_sort<EV_L, BATCH, true><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
     else k_sort<EV_EXPORT, BATCH, true><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
   } else {
     if (mode == EV_A) k_sort<EV_A, BATCH, false><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
     else if (mode == EV_B) k_sort<EV_B, BATCH, false><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
+    else if (mode == EV_L) k_sort<EV_L, BATCH, false><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
     else k_sort<EV_EXPORT, BATCH, false><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
   }
 }
@@ -1764,10 +1920,34 @@ static void enqueue_step_t(const Dev& d, const Bufs& b, int n_gblk, bool two_way
   else launch_pair<EV_B, BATCH>(d, b.W, b.Y, b.X, st);
 }
 
+// One leapfrog step (scheme 1) reading bucket set `set`: sort X into Y,
+// summation density and EOS, ghosts and probes, the clock, then the pair
+// pass with the update, back into X.
+template <bool BATCH>
+static void enqueue_lf_t(const Dev& d, const Bufs& b, int n_gblk, int set, hipStream_t st) {
+  Dev dl = d;
+  dl.lf_set = set;
+  eval_sort<BATCH>(dl, st, EV_L, b.X, b.Y);
+  launch_dens<BATCH>(dl, b.Y, true, st);
+  launch_ghost<EV_L, BATCH>(dl, n_gblk, b.Y, st);
+  k_clock_lf<<<d.n_inst, 64, 0, st>>>(dl);
+  launch_pair<EV_L, BATCH>(dl, b.Y, b.Y, b.X, st);
+}
+
 void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, bool two_way, bool audit,
                      hipStream_t st) {
   if (batch) enqueue_step_t<true>(d, b, n_gblk, two_way, false, st);
   else enqueue_step_t<false>(d, b, n_gblk, two_way, audit, st);
+}
+
+void wc_enqueue_step_lf(const Dev& d, const Bufs& b, int n_gblk, bool batch, int set, hipStream_t st) {
+  if (batch) enqueue_lf_t<true>(d, b, n_gblk, set, st);
+  else enqueue_lf_t<false>(d, b, n_gblk, set, st);
+}
+
+// Summation density of the export sort's state (scheme 1 test hooks).
+void wc_enqueue_export_dens(const Dev& d, const Bufs& b, hipStream_t st) {
+  launch_dens<false>(d, b.Y, false, st);
 }
 
 void wc_enqueue_disk_query(const Dev& d, int inst, double* out, hipStream_t st) {

@@ -16,6 +16,11 @@ struct Bufs {
 void wc_enqueue_step(const Dev& d, const Bufs& b, int n_gblk, bool batch, bool two_way, bool audit,
                      hipStream_t st);
 // Disk centre, velocity, acceleration of instance inst's newest state into out[3] (device).
+// One leapfrog step (scheme 1) whose sort reads bucket set `set` (0 a, 1 b);
+// its pair pass fills the other set.
+void wc_enqueue_step_lf(const Dev& d, const Bufs& b, int n_gblk, bool batch, int set, hipStream_t st);
+// Summation density and EOS in place on the export sort's state (scheme 1).
+void wc_enqueue_export_dens(const Dev& d, const Bufs& b, hipStream_t st);
 void wc_enqueue_disk_query(const Dev& d, int inst, double* out, hipStream_t st);
 void wc_enqueue_init(const Dev& d, const Bufs& b, bool batch, hipStream_t st);
 void wc_enqueue_diag(const Dev& d, const Bufs& b, bool sorted, hipStream_t st);
