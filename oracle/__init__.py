@@ -50,6 +50,7 @@ class Params(C.Structure):
         ("kin_coef", C.c_double), ("beta", C.c_double), ("kernel_type", C.c_int),
         ("eos_type", C.c_int), ("mg_s1", C.c_double), ("mg_gamma0", C.c_double),
         ("mg_mu_max", C.c_double), ("scheme", C.c_int), ("mg_a", C.c_double),
+        ("axisym", C.c_int),
     ]
 
 
@@ -157,7 +158,8 @@ class Oracle:
             init = f64(init).reshape(-1, 5)
             self.h = L.orc_create(C.byref(self.p), init.shape[0], dptr(init))
         if not self.h:
-            raise ValueError("scheme 1 with the coupled disk (kin_mode 2) is not built")
+            raise ValueError("not built: scheme 1 with the coupled disk (kin_mode 2), or the "
+                             "axisymmetric form with scheme 1 or with gravity")
         self.nf = L.orc_num_fluid(self.h)
         self.ng = L.orc_num_ghost(self.h)
         self.ncells = L.orc_num_cells(self.h)

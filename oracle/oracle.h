@@ -45,6 +45,11 @@ typedef struct {
                   the sum, lattice-normalised masses) with its clamp, leapfrog, and the
                   specific internal energy heated by the artificial viscosity */
   double mg_a; /* the a of eq. eos (scheme 1 with eos_type 1) */
+  int axisym;  /* 1: the axisymmetric r-z form (the extension the Conclusions rank first): x is the
+                  axial coordinate z, y >= 0 the radius r, the box's y = 0 edge the symmetry axis;
+                  fluid particles carry fixed ring masses 2 pi r0 rho0 dx^2, continuity gains the
+                  hoop term -rho v_r / r, the ghost layers below the axis mirror the fluid (slip)
+                  and are off inside the sphere; needs scheme 0 and gravity_y = 0 */
 } orc_params;
 
 /* ---- whole solver ------------------------------------------------------ */

@@ -45,6 +45,19 @@
 //    and the energy changed by the enforcement and the density clamp of the
 //    corrector (W_enforce, W_clamp). What they leave of the change of the
 //    fluid energy is the time-integration, XSPH and boundary-position part.
+//  * the axisymmetric r-z form (axisym = 1; the first of the extensions the
+//    Conclusions rank): the plane is the meridian half-plane through the
+//    tank axis, x the axial coordinate, y >= 0 the radius, the sphere's
+//    centre on the axis. Each fluid particle stands for a ring of fixed mass
+//    M_i = 2 pi r_i(0) rho0 dx^2; its planar mass in the pair sums is
+//    M_i / (2 pi r_i), so m_i / rho_i stays its area in the meridian plane.
+//    The continuity equation in cylindrical coordinates adds the hoop part
+//    of the divergence, -rho_i v_r,i / r_i (r_i held >= dx/2), to the
+//    planar sums; the pressure gradient has no hoop part. The three ghost
+//    layers below the axis are the mirror of the fluid: Shepard pressure,
+//    axial velocity kept and radial velocity reversed; those inside the
+//    sphere are off (zero mass). Mass, momentum, energies and the ring's
+//    force are the 3D values (each particle weighted by its ring mass).
 // Ghost state and rates are re-evaluated at both evaluations of a step
 // (operator split of the Pipeline Provenance section).
 
@@ -418,8 +431,12 @@ struct Sim {
   // summed density, e the specific internal energy)
   std::vector<T> x, y, vx, vy, rho, e;
   double dt_prev = 0.0;  // scheme 1: dt of the previous step (0 before the first)
-  // ghosts by ghost index: walls first, then the disk ring
+  // axisymmetric form: ring mass per radian M_i / (2 pi) = r_i(0) rho0 dx^2 by fluid id
+  std::vector<double> mring;
+  // ghosts by ghost index: walls first, then the disk ring; goff: a ghost
+  // below the axis inside the sphere, off for the current evaluation
   std::vector<double> gx, gy, gm;
+  std::vector<char> goff;
   std::vector<T> gp, grho, gvx, gvy;
   // cell list: storage order (global ids) and cell ranges
   std::vector<int> order, cell_start, key;
@@ -443,6 +460,19 @@ struct Sim {
   double xc = 0, vc = 0, ac = 0;
 
   int N() const { return Nf + Nw + Nd; }
+
+  // the radius below which the hoop term and the planar mass hold it (the
+  // first lattice row)
+  double rmin() const { return 0.5 * P.dx; }
+  // planar mass of fluid particle i in the pair sums: m_fluid, or in the
+  // axisymmetric form its ring mass over 2 pi r_i
+  double plan_mass(int i) const {
+    if (!P.axisym) return G.m_fluid;
+    return mring[i] / std::max(val(y[i]), rmin());
+  }
+  // its weight in the mass, momentum and energy sums and the ring force:
+  // m_fluid (per unit depth), or the ring mass 2 pi M_i / (2 pi)
+  double weight3(int i) const { return P.axisym ? 2.0 * M_PI * mring[i] : G.m_fluid; }
 
   void setup(const orc_params& p, int n_init, const double* init) {
     P = p;
@@ -470,6 +500,9 @@ struct Sim {
     }
     Nf = (int)x.size();
     e.assign(Nf, T(0.0));
+    mring.assign(Nf, 0.0);
+    if (p.axisym)
+      for (int i = 0; i < Nf; ++i) mring[i] = val(y[i]) * G.m_fluid;
     // wall ghosts (S2): the lattice continued ghost_layers deep around the box, j outer
     const int Lg = p.ghost_layers;
     for (int j = -Lg; j < G.ny + Lg; ++j)
@@ -481,6 +514,7 @@ struct Sim {
     // disk ring (S3)
     Nd = p.disk_R > 0 ? p.n_disk_ghosts : 0;
     for (int k = 0; k < Nd; ++k) { gx.push_back(0); gy.push_back(0); gm.push_back(G.m_disk); }
+    goff.assign(Nw + Nd, 0);
     gp.assign(Nw + Nd, T(0.0)); grho.assign(Nw + Nd, T(p.rho0));
     gvx.assign(Nw + Nd, T(0.0)); gvy.assign(Nw + Nd, T(0.0));
     order.resize(N());
@@ -589,6 +623,16 @@ struct Sim {
     for (int g = 0; g < NG; ++g) {
       double vwx = 0, awx = 0;
       if (g >= Nw) { vwx = dv; awx = da; }
+      // axisymmetric form: a wall ghost below the axis mirrors the fluid, and
+      // is off inside the sphere (whose centre is on the axis)
+      const bool axis = P.axisym && g < Nw && gy[g] < 0.0;
+      goff[g] = 0;
+      if (axis && Nd > 0 &&
+          (gx[g] - dx_c) * (gx[g] - dx_c) + (gy[g] - P.disk_y0) * (gy[g] - P.disk_y0) < P.disk_R * P.disk_R) {
+        goff[g] = 1;
+        gp[g] = T(0.0); grho[g] = T(P.rho0); gvx[g] = T(0.0); gvy[g] = T(0.0);
+        continue;
+      }
       T SW, Sp, Srx, Sry, Svx, Svy;
       shepard(gx[g], gy[g], pf, SW, Sp, Srx, Sry, Svx, Svy);
       T pg, vgx, vgy;
@@ -597,6 +641,7 @@ struct Sim {
         pg = (Sp + (0.0 - awx) * Srx + (P.gravity_y - 0.0) * Sry) / SW;
         vgx = 2.0 * vwx - Svx / SW;
         vgy = 0.0 - Svy / SW;
+        if (axis) vgx = Svx / SW;  // slip: the axial velocity is kept, the radial one reversed
       } else {
         pg = T(0.0);
         vgx = T(vwx);
@@ -617,13 +662,13 @@ struct Sim {
       v.x = x[id]; v.y = y[id]; v.vx = vx[id]; v.vy = vy[id]; v.rho = rho[id];
       v.P = pf[id] / (rho[id] * rho[id]);
       v.c = eos_c(rho[id], P, K);
-      v.m = G.m_fluid; v.kind = 0;
+      v.m = plan_mass(id); v.kind = 0;
     } else {
       int g = id - Nf;
       v.x = T(gx[g]); v.y = T(gy[g]); v.vx = gvx[g]; v.vy = gvy[g]; v.rho = grho[g];
       v.P = gp[g] / (grho[g] * grho[g]);
       v.c = eos_c(grho[g], P, K);
-      v.m = gm[g]; v.kind = g < Nw ? 1 : 2;
+      v.m = goff[g] ? 0.0 : gm[g]; v.kind = g < Nw ? 1 : 2;
     }
     return v;
   }
@@ -642,11 +687,13 @@ struct Sim {
         pair_law(a, view(j, pf), P, G, K, acc);
       });
       D[i] = P.scheme == 1 ? acc.E : acc.D;
+      // axisymmetric form: the hoop part of the divergence, -rho v_r / r
+      if (P.axisym) D[i] = D[i] - rho[i] * vy[i] / std::max(val(y[i]), rmin());
       ax[i] = acc.ax;
       ay[i] = acc.ay + P.gravity_y;
       Vx[i] = vx[i] + acc.Vx;
       Vy[i] = vy[i] + acc.Vy;
-      fdx[i] = G.m_fluid * acc.fdx;
+      fdx[i] = weight3(i) * acc.fdx;
       au[4 * (size_t)i] = acc.av;
       au[4 * (size_t)i + 1] = acc.visc;
       au[4 * (size_t)i + 2] = acc.del;
@@ -656,8 +703,8 @@ struct Sim {
     for (int i = 0; i < Nf; ++i) f += fdx[i];
     for (int q = 0; q < 4; ++q) {
       double z = 0.0;
-      for (int i = 0; i < Nf; ++i) z += au[4 * (size_t)i + q];
-      audit_rate[q] = G.m_fluid * z;
+      for (int i = 0; i < Nf; ++i) z += weight3(i) * au[4 * (size_t)i + q];
+      audit_rate[q] = z;
     }
     return f;
   }
@@ -736,13 +783,13 @@ struct Sim {
       if (val(r) < lo) { r = T(lo); n_clamp++; }
       if (val(r) > hi) { r = T(hi); n_clamp++; }
       // energy the clamp and the enforcement of the new state add (corrector)
-      if (corrector && val(r) != r_free) audit[5] += G.m_fluid * (e_el(val(r)) - e_el(r_free));
+      if (corrector && val(r) != r_free) audit[5] += weight3(i) * (e_el(val(r)) - e_el(r_free));
       T ux = vx0[i] + hdt * ax[i], uy = vy0[i] + hdt * ay[i];
       T xx = x0[i] + hdt * Vx[i], yy = y0[i] + hdt * Vy[i];
       const double k_free = val(ux) * val(ux) + val(uy) * val(uy);
       if (enforce(xx, yy, ux, uy, cx, P.disk_y0, vd)) {
         n_enforce++;
-        if (corrector) audit[4] += 0.5 * G.m_fluid * (val(ux) * val(ux) + val(uy) * val(uy) - k_free);
+        if (corrector) audit[4] += 0.5 * weight3(i) * (val(ux) * val(ux) + val(uy) * val(uy) - k_free);
       }
       x[i] = xx; y[i] = yy; vx[i] = ux; vy[i] = uy; rho[i] = r;
     }
@@ -917,7 +964,7 @@ struct Sim {
     double M = 0, px_ = 0, py_ = 0, ke = 0, eel = 0, epot = 0, eth = 0;
     long ncav = 0;
     for (int i = 0; i < Nf; ++i) {
-      double m = G.m_fluid, u = val(vx[i]), w = val(vy[i]), r = val(rho[i]);
+      double m = weight3(i), u = val(vx[i]), w = val(vy[i]), r = val(rho[i]);
       M += m;
       px_ += m * u;
       py_ += m * w;
@@ -946,6 +993,8 @@ extern "C" {
 
 void* orc_create(const orc_params* p, int n_init, const double* init) {
   if (p->scheme == 1 && p->kin_mode == 2) return nullptr;  // the coupled disk is not built for scheme 1
+  // the axisymmetric form: scheme 0, no gravity across the axis
+  if (p->axisym && (p->scheme != 0 || p->gravity_y != 0.0)) return nullptr;
   SimD* s = new SimD();
   s->P = *p;
   s->set_coef(p->alpha, p->delta, p->c0);
@@ -1246,7 +1295,8 @@ void orc_pair_rates(const orc_params* p, int n, const double* x, const double* y
 }
 
 void orc_tangent_J(const orc_params* p, int n_steps, const double* dt, double* J, double* dJ) {
-  if (p->kin_mode == 2 || p->kin_mode == 3 || p->scheme == 1) {  // coupled: not differentiated; table: not held here; scheme 1: not built
+  // coupled: not differentiated; table: not held here; scheme 1 and the axisymmetric form: not built
+  if (p->kin_mode == 2 || p->kin_mode == 3 || p->scheme == 1 || p->axisym) {
     *J = dJ[0] = dJ[1] = dJ[2] = std::nan("");
     return;
   }

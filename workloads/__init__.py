@@ -126,6 +126,22 @@ def paper_scheme(cfg: dict) -> dict:
     return dict(cfg, scheme=1, eos_type=1, c0=MG_C, kernel_type=1, cfl=0.25, delta=0.0)
 
 
+def axisymmetric(cfg: dict) -> dict:
+    """The same workload in the axisymmetric r-z form (axisym = 1), the
+    extension the Conclusions rank first: the plane is the meridian
+    half-plane through the tank axis, x the axial coordinate and y >= 0 the
+    radius, so the box is [0, L] x [0, W/2] (the planar channel's half-width
+    is the tank radius) with the axis at y = 0 and the disk's centre, now a
+    sphere's, on it. Gravity is off (across the axis it would break the
+    symmetry). The probes keep their axial stations, on the axis (the
+    paper's centreline gauges) and on the tank wall. disk_mass stays the
+    projectile's 3D mass."""
+    Rt = 0.5 * cfg["W"]
+    xs = sorted({x for x, _ in cfg["probes"]})
+    probes = [pt for x in xs for pt in ((x, 0.0), (x, Rt))]
+    return dict(cfg, W=Rt, disk_y0=0.0, gravity_y=0.0, axisym=1, probes=probes)
+
+
 def C2() -> dict:
     """300x150 mm, dx = 0.5 mm (179,552 fluid), R = 6 mm, 900 m/s, 2,000 steps,
     four wall probes at the PTn / PTf stations x = 30 and 105 mm."""
