@@ -132,7 +132,27 @@ typedef struct {
  *               the diagnostics (ke of v^(n+1/2), e_el of that rho, e_th = sum
  *               m e) and save/load see. Scheme 1 requires kin_mode != 2 and
  *               audit = 0, and every instance of a batch must share it; the
- *               reverse sweep takes scheme 0 only. */
+ *               reverse sweep takes scheme 0 only.
+ *  axisym     : 1 = the axisymmetric r-z form, the extension the Conclusions
+ *               rank first (it restores the out-of-plane relief the planar
+ *               section discards, Formulation Comparison): the plane is the
+ *               meridian half-plane through the tank axis, x the axial
+ *               coordinate and y the radius, so [0,L]x[0,W] is a tank of
+ *               radius W with its axis on y = 0, and the disk is a sphere
+ *               whose centre must lie on the axis (disk_y0 = 0). Each fluid
+ *               particle is a ring of fixed mass M = 2 pi r0 rho0 dx^2 (r0 its
+ *               radius at set-up; wcsph_set_fluid keeps these masses) and
+ *               enters the pair sums with the planar mass M / (2 pi max(r,
+ *               dx/2)); the continuity equation adds the hoop part of the
+ *               divergence, -rho v_r / max(r, dx/2); the wall-ghost layers
+ *               below the axis mirror the fluid (the Adami pressure, axial
+ *               velocity kept, radial reversed) and are switched off inside
+ *               the sphere. mass, mom, ke, e_el and w_boundary (with the
+ *               ring's force on the fluid and, for kin_mode 2, the sphere's
+ *               motion) are then 3D values: each particle weighs its ring
+ *               mass, and disk_mass is the sphere's mass (kg). Requires
+ *               scheme 0, gravity_y = 0 (gravity across the axis breaks the
+ *               symmetry) and audit = 0; the reverse sweep rejects it. */
 typedef struct {
   double L, W, dx, h_over_dx, cell_size;
   double rho0, c0, gamma, p_cav;
@@ -153,6 +173,7 @@ typedef struct {
   double mg_s1, mg_gamma0, mg_mu_max;
   int scheme;
   double mg_a;
+  int axisym;
 } wcsph_params;
 
 /* One diagnostic record (FP64 reductions over the fluid of one instance).

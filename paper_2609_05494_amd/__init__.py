@@ -70,6 +70,7 @@ class Params(C.Structure):
         ("kin_coef", C.c_double), ("audit", C.c_int), ("beta", C.c_double),
         ("kernel_type", C.c_int), ("eos_type", C.c_int), ("mg_s1", C.c_double),
         ("mg_gamma0", C.c_double), ("mg_mu_max", C.c_double), ("scheme", C.c_int), ("mg_a", C.c_double),
+        ("axisym", C.c_int),
     ]
 
 

@@ -188,9 +188,18 @@ void validate(const wcsph_params& p) {
   require(p.ghost_rho_mode == 0 || p.ghost_rho_mode == 1, "ghost_rho_mode must be 0 or 1");
   require(p.init_mode == 0 || p.init_mode == 1, "init_mode must be 0 or 1");
   require(p.disk_R >= 0, "disk_R must be >= 0");
+  require(p.axisym == 0 || p.axisym == 1, "axisym must be 0 or 1");
+  if (p.axisym) {
+    require(p.scheme == 0, "the axisymmetric form takes scheme 0 only");
+    require(p.gravity_y == 0.0, "the axisymmetric form needs gravity_y = 0");
+    require(p.audit == 0, "the axisymmetric form does not take the energy audit");
+    if (p.disk_R > 0) require(p.disk_y0 == 0.0, "the axisymmetric sphere's centre must lie on the axis (disk_y0 = 0)");
+  }
   if (p.disk_R > 0) {
+    // (axisymmetric: the sphere straddles the axis, the box holds its upper half)
+    const double y_lo = p.axisym ? -p.disk_R : 0.0;
     require(p.disk_x0 - p.disk_R >= -1e-12 && p.disk_x0 + p.disk_R <= p.L + 1e-12 &&
-                p.disk_y0 - p.disk_R >= -1e-12 && p.disk_y0 + p.disk_R <= p.W + 1e-12,
+                p.disk_y0 - p.disk_R >= y_lo - 1e-12 && p.disk_y0 + p.disk_R <= p.W + 1e-12,
             "disk must lie inside the channel");
     require(p.kin_t_ramp > 0 && p.kin_v0 >= 0 && p.kin_coef >= 0, "kinematics coefficients invalid");
   }
@@ -323,6 +332,9 @@ InstParams derive(const wcsph_params& p) {
   q.m_wall = (float)m_part;
   q.m_disk = p.n_disk_ghosts > 0 ? (float)(m_part / p.dx * 2.0 * M_PI * p.disk_R / p.n_disk_ghosts) : 0.0f;
   q.scheme = p.scheme;
+  q.axisym = p.axisym;
+  q.r_mind = 0.5 * p.dx;
+  q.r_min = (float)q.r_mind;
   q.mg_a = (float)p.mg_a;
   q.mg_g0 = (float)p.mg_gamma0;
   q.mg_ad = p.mg_a;
@@ -703,6 +715,23 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   d.n_dt = 0;
   d.dt_step0 = 0;
   d.dt_table = nullptr;
+  // axisymmetric instances: each fluid ring's mass per radian r0 m_fluid by
+  // particle id, from its set-up radius (kept through set_fluid and load)
+  d.mring = nullptr;
+  bool any_axisym = false;
+  for (int i = 0; i < n_inst; ++i) any_axisym = any_axisym || params[i].axisym;
+  if (any_axisym) {
+    std::vector<double> mr(c->n_slots, 0.0);
+    for (int i = 0; i < n_inst; ++i) {
+      const InstParams& q = c->hp[i];
+      if (!q.axisym) continue;
+      for (int k = 0; k < q.nf; ++k) mr[(size_t)q.id0 + k] = c->geo[i].fy[k] * q.m_fluidd;
+    }
+    double* dm = dalloc_n<double>(c, c->n_slots);
+    HC(hipMemcpyAsync(dm, mr.data(), (size_t)c->n_slots * 8, hipMemcpyHostToDevice, c->st));
+    sync(c);  // the host vector goes out of scope
+    d.mring = dm;
+  }
   HC(hipMemcpyAsync(c->d_prm, c->hp.data(), n_inst * sizeof(InstParams), hipMemcpyHostToDevice, c->st));
   HC(hipMemcpyAsync(c->d_wallcount, c->h_wallcount.data(), (size_t)c->n_cells * 4, hipMemcpyHostToDevice, c->st));
   HC(hipMemcpyAsync(wrank, c->h_wrank.data(), (size_t)c->n_ghost * 4, hipMemcpyHostToDevice, c->st));
@@ -1601,6 +1630,7 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   require(ctx->pin[0].eos_type == 0, "the reverse sweep supports the Tait EOS only");
   require(ctx->pin[0].kernel_type == 0, "the reverse sweep supports the Wendland C2 kernel only");
   require(ctx->scheme == 0, "the reverse sweep supports scheme 0 only");
+  require(ctx->pin[0].axisym == 0, "the reverse sweep supports the planar form only");
   require(n_steps >= 1 && ckpt_every >= 1, "n_steps and ckpt_every must be >= 1");
   const long long k0 = ctx->steps - ctx->d.dt_step0;
   require(ctx->d.n_dt > 0 && k0 >= 0 && k0 + n_steps <= ctx->d.n_dt,

@@ -77,6 +77,11 @@ struct InstParams {
   int scheme;
   float mg_a, mg_g0;
   double mg_ad, mg_g0d;
+  // axisymmetric r-z form: x axial, y the radius from the axis y = 0; the
+  // radius below which the hoop term and the planar ring mass hold (dx/2)
+  int axisym;
+  float r_min;
+  double r_mind;
 };
 
 // Per-instance clock and accumulators (device-resident, FP64 time).
@@ -158,6 +163,8 @@ struct Dev {
   int* nb_count;              // export: neighbour count per slot
   long long* nb_idsum;        // export: neighbour id sum per slot
   uint32_t* nb_ids;           // export: per fluid index, neighbour count [nf], then ids [nf][WC_NB_CAP] (or NULL)
+  const double* mring;        // axisymmetric instances: ring mass per radian M / (2 pi) by particle id
+                              // (fluid ids; NULL when no instance is axisymmetric)
   double2* tape_pos;          // reverse sweep: pre-enforcement position per fluid id (or NULL)
   float4* tape_vel;           // reverse sweep: pre-enforcement (vx, vy, rho, 0) per fluid id
 };

@@ -910,7 +910,15 @@ __device__ __forceinline__ Gathered sort_finish(const Dev& d, const Loaded& l) {
     float Pq = 0.0f, c = 0.0f;
     // (scheme 1: the density pass that follows sums the density and applies the EOS)
     if (P.scheme == 0) fluid_eos<MG>(P, l.rho, Pq, c);
-    v.aux = make_float4(l.rho, Pq, c, P.m_fluid);
+    float m = P.m_fluid;
+    if (P.axisym) {
+      // the ring's planar mass M / (2 pi r), r held >= dx/2
+      int cx, cy;
+      cell_xy(P, l.cell, cx, cy);
+      const double r = P.y_lo + (double)cy * P.dcd + (double)l.pv.y;
+      m = (float)(d.mring[l.id] / fmax(r, P.r_mind));
+    }
+    v.aux = make_float4(l.rho, Pq, c, m);
     v.ghost = -1;
   } else {
     v.ghost = local - P.nf;
@@ -1112,70 +1120,96 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
     const uint32_t s = d.gslot[P.gmap0 + g];
     const uint32_t K = d.gcell[P.gmap0 + g];
     const float2 pg = d.gpos[P.gmap0 + g];
-    const Shep S = shepard<GL, CUB>(d, P, sb, K, pg.x, pg.y, lane);
-    const float vwx = disk ? (float)C.vd : 0.0f;
-    const float awx = disk ? (float)C.ad : 0.0f;
-    float p, vgx, vgy;
-    if (S.W > 0.0f) {
-      const float inv = 1.0f / S.W;
-      // body-force term (g - a_w) . sum rho_j (r_g - r_j) W
-      p = (S.p + (0.0f - awx) * S.rx + P.gy * S.ry) * inv;
-      vgx = 2.0f * vwx - S.vx * inv;
-      vgy = -S.vy * inv;
+    // axisymmetric form: a wall ghost below the axis mirrors the fluid (slip)
+    // and is off (zero mass, at rest) inside the sphere
+    bool axis = false, off = false;
+    if (P.axisym && !disk) {
+      int gcx, gcy;
+      cell_xy(P, K, gcx, gcy);
+      const double yg = P.y_lo + (double)gcy * P.dcd + (double)pg.y;
+      axis = yg < 0.0;
+      if (axis && P.nd > 0) {
+        const double xg = P.x_lo + (double)gcx * P.dcd + (double)pg.x;
+        const double ux = xg - C.xd, uy = yg - P.disk_y0;
+        off = ux * ux + uy * uy < P.R * P.R;  // the same on every lane of the item
+      }
+    }
+    if (off) {
+      if (lane == 0) {
+        sb.pv[s] = make_float4(pg.x, pg.y, 0.0f, 0.0f);
+        sb.aux[s] = make_float4(P.rho0, 0.0f, P.c0, -0.0f);
+      }
     } else {
-      p = 0.0f;
-      vgx = vwx;
-      vgy = 0.0f;
-    }
-    p = fmaxf(p, P.p_cav);
-    float rg, cg;
-    if (P.eos_type == 1) {
-      // Mie-Grueneisen inverse: tension line, or the root in [0, 1/b) of
-      // s (1 - b mu)^2 = mu (1 + k1 mu), s = p / K; capped at mu_max
-      const float sp = p / P.mg_K;
-      float mu = sp;
-      if (P.ghost_rho_mode != 0 && sp > 0.0f)
-        mu = fminf(2.0f * sp / ((1.0f + 2.0f * P.mg_b * sp) + sqrtf(1.0f + 4.0f * sp * (P.mg_b + P.mg_k1))),
-                   P.mg_mu_max);
-      rg = P.rho0 * (1.0f + mu);
-      float pu;
-      mg_eos(P, mu, pu, cg);
-    } else {
-      if (P.ghost_rho_mode == 0) rg = P.rho0 * (1.0f + p * P.inv_rho0c02);
-      else rg = P.rho0 * expf(P.inv_gamma * log1pf(p / P.B));
-      const float xg = (rg - P.rho0) / P.rho0, yg = 1.0f + xg;
-      cg = P.gamma == 7.0f ? P.c0 * (yg * yg * yg) : P.c0 * expf(P.c_exp * log1pf(xg));
-    }
-    const float Pg = p / (rg * rg);
-    const float m = disk ? P.m_disk : P.m_wall;
-    if (lane == 0) {
-      sb.pv[s] = make_float4(pg.x, pg.y, vgx, vgy);
-      sb.aux[s] = make_float4(rg, Pg, cg, -m);
-      vmag = fast_sqrt(vgx * vgx + vgy * vgy);
-    }
-    if ((MODE == EV_B || MODE == EV_L) && disk) {
-      // x force of this ring ghost on its fluid neighbours (pressure + AV)
-      float fx = 0.0f;
-      for_candidates<GL>(d, P, sb, K, lane, [&](const float4& pj, const float4& aj, uint32_t code) __attribute__((always_inline)) {
-        if (!(aj.w > 0.0f)) return;
-        float rx, ry;
-        rel_pos(P, pg.x, pg.y, pj, code, rx, ry);
-        rx = -rx;  // r_i - r_g
-        ry = -ry;
-        const float r2 = rx * rx + ry * ry;
-        if (!(r2 < P.four_h2)) return;
-        float W, F;
-        if constexpr (CUB) cubic_spline(P, r2, W, F);
-        else wendland(P, r2, W, F);
-        const float vr = (pj.z - vgx) * rx + (pj.w - vgy) * ry;
-        const float rsum = aj.x + rg, den = r2 + P.eta2h2;
-        const float inv = fast_rcp(den * rsum);
-        const float piav =
-            vr < 0.0f ? -P.alpha * (aj.z + cg) * P.h * vr * inv + P.beta2h2 * vr * vr * inv * (rsum * inv) : 0.0f;
-        fx -= aj.w * m * (aj.y + Pg + piav) * F * rx;
-      });
-      const double f = group_sum<GL>((double)fx);
-      if (lane == 0) d.wb_part[inst * WC_MAX_RING + (g - P.nw)] = f;
+      const Shep S = shepard<GL, CUB>(d, P, sb, K, pg.x, pg.y, lane);
+      const float vwx = disk ? (float)C.vd : 0.0f;
+      const float awx = disk ? (float)C.ad : 0.0f;
+      float p, vgx, vgy;
+      if (S.W > 0.0f) {
+        const float inv = 1.0f / S.W;
+        // body-force term (g - a_w) . sum rho_j (r_g - r_j) W
+        p = (S.p + (0.0f - awx) * S.rx + P.gy * S.ry) * inv;
+        vgx = axis ? S.vx * inv : 2.0f * vwx - S.vx * inv;  // axis: the axial velocity is kept
+        vgy = -S.vy * inv;
+      } else {
+        p = 0.0f;
+        vgx = vwx;
+        vgy = 0.0f;
+      }
+      p = fmaxf(p, P.p_cav);
+      float rg, cg;
+      if (P.eos_type == 1) {
+        // Mie-Grueneisen inverse: tension line, or the root in [0, 1/b) of
+        // s (1 - b mu)^2 = mu (1 + k1 mu), s = p / K; capped at mu_max
+        const float sp = p / P.mg_K;
+        float mu = sp;
+        if (P.ghost_rho_mode != 0 && sp > 0.0f)
+          mu = fminf(2.0f * sp / ((1.0f + 2.0f * P.mg_b * sp) + sqrtf(1.0f + 4.0f * sp * (P.mg_b + P.mg_k1))),
+                     P.mg_mu_max);
+        rg = P.rho0 * (1.0f + mu);
+        float pu;
+        mg_eos(P, mu, pu, cg);
+      } else {
+        if (P.ghost_rho_mode == 0) rg = P.rho0 * (1.0f + p * P.inv_rho0c02);
+        else rg = P.rho0 * expf(P.inv_gamma * log1pf(p / P.B));
+        const float xg = (rg - P.rho0) / P.rho0, yg = 1.0f + xg;
+        cg = P.gamma == 7.0f ? P.c0 * (yg * yg * yg) : P.c0 * expf(P.c_exp * log1pf(xg));
+      }
+      const float Pg = p / (rg * rg);
+      const float m = disk ? P.m_disk : P.m_wall;
+      if (lane == 0) {
+        sb.pv[s] = make_float4(pg.x, pg.y, vgx, vgy);
+        sb.aux[s] = make_float4(rg, Pg, cg, -m);
+        vmag = fast_sqrt(vgx * vgx + vgy * vgy);
+      }
+      if ((MODE == EV_B || MODE == EV_L) && disk) {
+        // x force of this ring ghost on its fluid neighbours (pressure + AV)
+        float fx = 0.0f;
+        int rcx, rcy;
+        cell_xy(P, K, rcx, rcy);
+        const float yg = (float)(P.y_lo + (double)rcy * P.dcd) + pg.y;  // the ghost's radius (axisymmetric)
+        for_candidates<GL>(d, P, sb, K, lane, [&](const float4& pj, const float4& aj, uint32_t code) __attribute__((always_inline)) {
+          if (!(aj.w > 0.0f)) return;
+          float rx, ry;
+          rel_pos(P, pg.x, pg.y, pj, code, rx, ry);
+          rx = -rx;  // r_i - r_g
+          ry = -ry;
+          const float r2 = rx * rx + ry * ry;
+          if (!(r2 < P.four_h2)) return;
+          float W, F;
+          if constexpr (CUB) cubic_spline(P, r2, W, F);
+          else wendland(P, r2, W, F);
+          const float vr = (pj.z - vgx) * rx + (pj.w - vgy) * ry;
+          const float rsum = aj.x + rg, den = r2 + P.eta2h2;
+          const float inv = fast_rcp(den * rsum);
+          const float piav =
+              vr < 0.0f ? -P.alpha * (aj.z + cg) * P.h * vr * inv + P.beta2h2 * vr * vr * inv * (rsum * inv) : 0.0f;
+          // (axisymmetric: the fluid particle's ring mass 2 pi m r in place of m)
+          const float mi = P.axisym ? aj.w * (6.283185307f * fmaxf(yg + ry, P.r_min)) : aj.w;
+          fx -= mi * m * (aj.y + Pg + piav) * F * rx;
+        });
+        const double f = group_sum<GL>((double)fx);
+        if (lane == 0) d.wb_part[inst * WC_MAX_RING + (g - P.nw)] = f;
+      }
     }
   }
   if (FIRST) {
@@ -1370,6 +1404,13 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Bu
   acc.Vx = sacc[3][threadIdx.x];
   acc.Vy = sacc[4][threadIdx.x];
   const bool lead = fluid;
+  if (P.axisym && lead) {
+    // axisymmetric form: the hoop part of the divergence, -rho v_r / r (r >= dx/2)
+    int cx, cy;
+    cell_xy(P, K, cx, cy);
+    const float r = fmaxf((float)(P.y_lo + (double)cy * P.dcd) + pi.y, P.r_min);
+    acc.D -= rho_i * pi.w / r;
+  }
   if (MODE == EV_EXPORT) {
     if (lead) {
       d.xr[s] = acc.D;
@@ -1708,12 +1749,14 @@ __global__ __launch_bounds__(256) void k_diag_part(Dev d, Buf X, int sorted) {
   }
   const int chunk = (hi - lo + WC_DIAG_BLOCKS - 1) / WC_DIAG_BLOCKS;
   const int a = lo + b * chunk, e = min(hi, a + chunk);
-  const double g = P.gammad, r0 = P.rho0d, B = P.Bd, m = P.m_fluidd;
+  const double g = P.gammad, r0 = P.rho0d, B = P.Bd, m_plan = P.m_fluidd;
   const double rc = P.diag_rc, k1 = P.diag_k1, r0g1 = P.diag_r0g1, erc = P.diag_erc, inv_r0g = P.diag_inv_r0g;
   double M = 0, px = 0, py = 0, ke = 0, eel = 0, epot = 0, ncav = 0, bad = 0, eth = 0;
   for (int s = a + (int)threadIdx.x; s < e; s += 256) {
     const int local = (int)X.id[s] - P.id0;
     if (local < 0 || local >= P.nf) continue;
+    // (axisymmetric: each particle weighs its ring mass 2 pi M / (2 pi))
+    const double m = P.axisym ? 6.283185307179586 * d.mring[X.id[s]] : m_plan;
     const float4 pv = X.pv[s];
     const double r = (double)X.aux[s].x;
     const double ei = X.e ? (double)X.e[s] : 0.0;  // scheme 1: specific internal energy

@@ -46,6 +46,11 @@ def test_invalid_parameters_rejected_before_allocation():
         assert st == wc.E_INVALID, bad
         assert out.value is None
         assert L.wcsph_last_error(None)
+    # the axisymmetric form: scheme 0, no gravity, no audit, the sphere on the axis
+    rz = workloads.axisymmetric(workloads.C1())
+    for bad in (dict(axisym=2), dict(scheme=1), dict(gravity_y=-9.81), dict(audit=1), dict(disk_y0=1e-3)):
+        st = L.wcsph_create(C.byref(wc.params(dict(rz, **bad))), None, fake_stream, C.byref(out))
+        assert st == wc.E_INVALID, bad
     st = L.wcsph_create(C.byref(wc.params(workloads.C1())), None, None, C.byref(out))
     assert st == wc.E_INVALID  # NULL stream refused
     assert L.wcsph_step(None, 1) == wc.E_STATE
