@@ -1,5 +1,5 @@
 """Autotuner for the scan shapes of the pair pass (union pass size UCAP, hit
-list length LCAP, candidates per scan step PU).
+list length LCAP, unroll RU of a lane's walk along one of its rows).
 
 Every shape sums each particle's pairs in the same order, so every variant
 must give the same state bit for bit; the tuner checks that and keeps the
@@ -27,20 +27,20 @@ import sys
 
 from . import build as _build
 
-DEFAULT = {"UCAP": 192, "LCAP": 16, "PU": 4}
+DEFAULT = {"UCAP": 128, "LCAP": 16, "RU": 2}
 # shapes whose LDS and list bounds hold: the byte hit list indexes a pass
-# (UCAP <= 256), a scan step fits the list (PU <= LCAP - PU)
-SPACE = [dict(UCAP=u, LCAP=l, PU=p) for u, l, p in itertools.product((128, 192, 256), (16, 24), (4, 8))]
+# (UCAP <= 256), the list holds at least a few hits (LCAP >= 8)
+SPACE = [dict(UCAP=u, LCAP=l, RU=r) for u, l, r in itertools.product((128, 192, 256), (16, 24), (1, 2, 4))]
 HEADER = os.path.join(_build.CSRC, "wcsph_tuned.h")
 REPS = 3
 
 
 def tag(shape: dict) -> str:
-    return "u{UCAP}_l{LCAP}_p{PU}".format(**shape)
+    return "u{UCAP}_l{LCAP}_r{RU}".format(**shape)
 
 
 def valid(shape: dict) -> bool:
-    return 64 <= shape["UCAP"] <= 256 and 1 <= shape["PU"] <= shape["LCAP"] - shape["PU"]
+    return 64 <= shape["UCAP"] <= 256 and 8 <= shape["LCAP"] <= 64 and shape["RU"] in (1, 2, 4, 8)
 
 
 def build_variants(out_dir: str) -> list:
@@ -123,7 +123,7 @@ def write_header(path: str, shape: dict, workload: str, steps: int, results: lis
     lines.append("// A shape given on the command line (-DUCAP=... when the tuner builds its")
     lines.append("// variants) takes precedence over the one recorded here.")
     lines.append("#pragma once")
-    for k in ("UCAP", "LCAP", "PU"):
+    for k in ("UCAP", "LCAP", "RU"):
         lines += [f"#ifndef {k}", f"#define {k} {int(shape[k])}", "#endif"]
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")

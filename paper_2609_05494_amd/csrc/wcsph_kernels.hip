@@ -19,7 +19,7 @@
 #include "wcsph_launch.h"
 #include "wcsph_kin.h"
 
-// Scan shapes of the pair pass (UCAP, LCAP, PU) picked for this GPU by the
+// Scan shapes of the pair pass (UCAP, LCAP, RU) picked for this GPU by the
 // autotuner (paper_2609_05494_amd/autotune.py), when it has been run; the
 // defaults below otherwise. They change speed only: every shape sums each
 // particle's pairs in the same order.
@@ -412,12 +412,11 @@ __device__ __forceinline__ PairC pair_c(const InstParams& P) {
 #ifndef LCAP
 #define LCAP 16   // entries of a lane's hit list
 #endif
-#ifndef PU
-#define PU 4      // candidates per lane per scan step
+#ifndef RU
+#define RU 2      // unroll of a lane's walk along one of its rows
 #endif
-#ifndef PAIR_ONEPASS
-#define PAIR_ONEPASS 1  // separate scan loop for a union that fits one pass
-#endif
+#define PAIR_STR2(x) #x
+#define PAIR_STR(x) PAIR_STR2(x)
 
 // Order the wave's LDS accesses: stores before this point are seen by every
 // lane's loads after it (accesses of one wave are performed in order; the
@@ -433,12 +432,12 @@ __device__ __forceinline__ void wave_sync() {
 // instance and one cell row form a group; the union of their 3x3 blocks is
 // one slot range per row, which the wave stages in LDS in passes of UCAP entries:
 // offset x, offset y seen from the group's row, cell column, slot. Each
-// lane then walks its own particle's candidates (rows bottom to top, cells
-// left to right in sorted order, dealt round-robin to the slot's lanes)
-// through LDS, keeps the in-support ones in a lane-private list and sums
-// the pair law over the list. A lane's candidate order and every operand
-// of a pair depend on the particle and its neighbours only, not on the
-// other slots of the wave.
+// lane then walks its own particle's three rows of candidates (rows bottom
+// to top; in each row, the row's cells left to right in sorted order, entry
+// q, q + PAIR_G, ... for lane q) through LDS, keeps the in-support ones in a
+// lane-private list and sums the pair law over the list. A lane's candidate
+// order and every operand of a pair depend on the particle and its
+// neighbours only, not on the other slots of the wave.
 // EXP (export hook, single instance): every in-support neighbour's id also
 // goes to the export buffer d.nb_ids by fluid index f: the count at [f]
 // (zeroed by the host), the ids at [nf + f * WC_NB_CAP + k].
@@ -497,8 +496,12 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
       adj2 = ub2 + (ors[2] - urs[2]) - p2;
     }
     const float cxi = (float)(cx - cxa);
-    uint32_t c = (uint32_t)q;  // this lane's next own candidate
     int cnt = 0;
+    // own row r is the union range [p_r + adj_r, p_r + adj_r + on_r); lane q
+    // walks entries q, q + G, ... of each own row in turn (row, next union
+    // index u, end of the row), carried from pass to pass
+    int row = 0;
+    uint32_t u = adj0 + (uint32_t)q, uend = adj0 + p1;
     // sum the pair law over the list, two entries in flight (buffers a, b)
     auto fetch = [&](int k, float4& E, float4& pj, float4& aj) __attribute__((always_inline)) {
       E = U[my[min(k, cnt - 1) * PAIR_BLOCK]];
@@ -547,49 +550,32 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
       }
       wave_sync();
       if (mem) {
-        // ONE: the whole union is in this pass, so every own candidate is in it
-        auto scan = [&](auto one) __attribute__((always_inline)) {
-          constexpr bool ONE = decltype(one)::value;
-          while (c < no) {
-            uint32_t ix[PU];
-            bool v[PU];
-            int nv = 0;
-#pragma unroll
-            for (int k = 0; k < PU; ++k) {
-              const uint32_t cc = c + (uint32_t)(PAIR_G * k);
-              const uint32_t u = cc + (cc < p1 ? adj0 : (cc < p2 ? adj1 : adj2));
-              if constexpr (ONE) {
-                v[k] = cc < no;
-                ix[k] = v[k] ? u : 0u;
-              } else {
-                v[k] = (cc < no) & (u - u0 < m);  // inside this pass (unsigned: both bounds)
-                ix[k] = v[k] ? u - u0 : 0u;
-                nv += v[k] ? 1 : 0;
-              }
-            }
-#pragma unroll
-            for (int k = 0; k < PU; ++k) {
-              const float4 E = U[ix[k]];
+        // a lane walks a row up to the nearer of the row's end, the pass's
+        // end and the room left in its list; then it flushes the list, moves
+        // to its next own row, or leaves the rest of the row to the next pass
+        const uint32_t pe = u0 + m;
+        for (;;) {
+          const uint32_t lim = min(uend, pe);
+          while (u < lim) {
+            // the row's candidates in this pass, as many as the list has room for
+            const uint32_t ue = u + PAIR_G * min((lim - u + PAIR_G - 1) / PAIR_G, (uint32_t)(LCAP - cnt));
+            _Pragma(PAIR_STR(unroll RU))
+            for (; u < ue; u += PAIR_G) {
+              const float4 E = U[u - u0];
               const float rx = (pi.x - E.x) - (E.z - cxi) * P.dc;
               const float ry = pi.y - E.y;
-              const bool hit = v[k] & (rx * rx + ry * ry < P.four_h2) & (__float_as_uint(E.w) != (uint32_t)s);
-              my[cnt * PAIR_BLOCK] = (uint8_t)ix[k];
+              const bool hit = (rx * rx + ry * ry < P.four_h2) & (__float_as_uint(E.w) != (uint32_t)s);
+              my[cnt * PAIR_BLOCK] = (uint8_t)(u - u0);
               cnt += hit ? 1 : 0;
             }
-            if (cnt > LCAP - PU) flush();
-            if constexpr (ONE) {
-              c += (uint32_t)(PAIR_G * PU);
-            } else {
-              c += (uint32_t)(PAIR_G * nv);
-              if (nv < PU) break;
-            }
+            if (cnt == LCAP) flush();
           }
-        };
-#if PAIR_ONEPASS
-        if (n <= UCAP) scan(std::true_type());
-        else
-#endif
-          scan(std::false_type());
+          if (u < uend || row == 2) break;  // the pass ends inside this row, or every row is done
+          ++row;  // this own row is done: the next one
+          const uint32_t a = row == 1 ? p1 + adj1 : p2 + adj2;
+          u = a + (uint32_t)q;
+          uend = a + (row == 1 ? p2 - p1 : no - p2);
+        }
         flush();
       }
     }
@@ -1276,12 +1262,17 @@ __device__ __forceinline__ double eos_e_el(const InstParams& P, double r) {
   return P.eos_type == 1 ? mg_e_el(P, r) : tait_e_el(P, r);
 }
 
-template <int MODE, bool BATCH, bool AUD, int VAR>
-#ifdef PAIR_MINW
-__global__ __launch_bounds__(PAIR_BLOCK, PAIR_MINW) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
-#else
-__global__ __launch_bounds__(PAIR_BLOCK) void k_pair(Dev d, Buf sb, Buf base, Buf out) {
+// Blocks per compute unit the register budget of the single-instance pair
+// pass is held to: seven (seven waves per SIMD, at most 72 VGPRs), which it
+// meets without spills; left to itself the compiler took 79 VGPRs (six waves
+// per SIMD) and the pass ran 6 % slower (C2). The batched, audit, export
+// and cubic-kernel variants keep the compiler's budget (they would spill).
+#ifndef PAIR_MINW
+#define PAIR_MINW 7
 #endif
+template <int MODE, bool BATCH, bool AUD, int VAR>
+__global__ __launch_bounds__(PAIR_BLOCK, (BATCH || AUD || MODE == EV_EXPORT || (VAR & 2)) ? 1 : PAIR_MINW)
+void k_pair(Dev d, Buf sb, Buf base, Buf out) {
   __shared__ float4 uni[PAIR_BLOCK / 64][UCAP];
   __shared__ uint8_t lst[LCAP * PAIR_BLOCK];
   // hand-over of each slot from the first phase to the second
