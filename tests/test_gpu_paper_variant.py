@@ -86,12 +86,27 @@ def test_mixed_kernels_in_a_batch_rejected():
 def test_paper_geometry_matches_oracle():
     """The paper's 750x150 mm channel at dx = 1.5 mm with its kernel and
     single-line walls, 300 steps (the pulse reaches the near station after
-    step 200): probe histories within 3e-3 of the largest probe peak, the
-    CFL step within 2e-4. The bars are looser than at C1 (1e-3, 1e-5): at
-    R/dx = 4 the disk's enforcement events, where FP32 and FP64 trajectories
-    part first, weigh more (measured: 1.8e-3 and 8e-5)."""
+    step 200). Bars from the committed oracle-only measurement at this
+    workload (tests/golden/chaos_floor.py: the FP64 oracle against itself
+    with its state rounded to FP32 every step, with and without FP32-sized
+    noise on each step's change), twice the largest value it shows:
+    * near-station probes, history over each probe's own peak: floor 1.8e-3,
+      bar 3.6e-3;
+    * the CFL step: floor 1.5e-4, bar 3.0e-4 (dt follows the single
+      fastest particle, next to the disk at R/dx = 4);
+    * far-station probes: within 300 steps they see only the hydrostatic
+      compression (about 525 Pa), below what a float32 density resolves at
+      rho0 (one ulp is about 130 Pa); the rounded oracle loses it whole
+      (floor 1.0 of the signal), so the bar there is twice the oracle's
+      own peak as an absolute difference."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "chaos_floor.json")) as f:
+        fl = json.load(f)["paper"]
+    runs = (fl["rounded"], fl["rounded_noise"])
     cfg = workloads.paper_geometry()
     n = 300
+    assert fl["steps"] == n and not fl["replay_dt"]
     print(f"[gpu] paper geometry, {n} steps", flush=True)
     s = wc.Solver(cfg, "cuda:0")
     assert s.nf == 49947
@@ -103,17 +118,20 @@ def test_paper_geometry_matches_oracle():
     o.step(n)
     _, dto, po = o.probes()
     do = o.diags()
-    scale = np.abs(po).max()
-    assert scale > 1e5  # the near station has seen the pulse
     for k in range(po.shape[1]):
-        err = np.abs(pg[:, k] - po[:, k]).max() / scale
-        print(f"probe {k}: max err {err:.3e} of the largest peak")
-        assert err <= 3e-3
-    # dt follows the largest particle speed, which sits next to the disk at
-    # R/dx = 4 with single-line walls: one particle's FP32 speed, not a sum
+        peak = np.abs(po[:, k]).max()
+        floor = max(r["history_over_peak"][k] for r in runs)
+        err = np.abs(pg[:, k] - po[:, k]).max() / peak
+        print(f"probe {k}: own peak {peak:.4g} Pa, max err / own peak {err:.3e} (floor {floor:.3e})")
+        if floor < 0.5:  # the pulse has reached the station
+            assert peak > 1e5
+            assert err <= 2.0 * floor
+        else:  # hydrostatic only: below the FP32 density's resolution
+            assert np.abs(pg[:, k] - po[:, k]).max() <= 2.0 * peak
     dterr = np.abs(dtg / dto - 1).max()
-    print(f"dt: max rel err {dterr:.2e}")
-    assert dterr < 2e-4
+    dt_bar = 2.0 * max(r["dt_rel"] for r in runs)
+    print(f"dt: max rel err {dterr:.2e} (bar {dt_bar:.2e})")
+    assert dterr <= dt_bar
     assert np.abs(dg["mass"] - dg["mass"][0]).max() <= 1e-12 * dg["mass"][0]
     for k in ("ke", "e_el", "w_boundary"):
         assert abs(dg[k][-1] - do[k][-1]) <= 1e-3 * abs(do[k][-1]), k
