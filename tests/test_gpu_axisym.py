@@ -55,7 +55,7 @@ def test_one_evaluation_C1(steps):
 
 
 def test_one_evaluation_full_size_C2():
-    """The 300 mm x 75 mm tank at dx 0.5 mm (89,718 fluid rings): many
+    """The 300 mm x 75 mm tank at dx 0.5 mm (89,776 fluid rings): many
     pair-kernel tiles and a ragged last block."""
     e = _one_evaluation(workloads.axisymmetric(workloads.C2()), 20)
     assert max(e.values()) <= 1e-4
