@@ -346,6 +346,43 @@ def mg_run(wc, workloads, steps: int, tait_value: float):
                 probe_peak_pa=float(np.abs(p).max()), unstable=unstable)
 
 
+def axisymmetric_run(wc, workloads, steps: int, planar_peaks):
+    """The headline workload in the axisymmetric r-z form (a 300 mm tank of
+    radius 75 mm, 89,776 fluid rings, the sphere on the axis), `steps` steps
+    from t = 0: its rate, and its wall-probe peaks against the planar run's
+    at the same stations (75 mm from the projectile's path): the
+    out-of-plane relief the planar section discards."""
+    import torch
+    cfg = workloads.axisymmetric(workloads.C2())
+    s = wc.Solver(cfg, "cuda:0")
+    blob = s.save_state()
+    s.step(20)
+    s.synchronize()
+    s.load_state(blob)
+    s.read_probes()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.synchronize()
+    el = time.perf_counter() - t0
+    _, _, p = s.read_probes()
+    d = s.read_diagnostics(check=False)
+    nf = s.nf
+    s.close()
+    peaks = np.abs(p).max(0)  # probes: (30 mm, axis), (30 mm, wall), (105 mm, axis), (105 mm, wall)
+    wall = [float(peaks[1]), float(peaks[3])]
+    out = dict(workload="300 mm tank of radius 75 mm (r-z), dx 0.5 mm, 89,776 fluid rings, sphere R 6 mm "
+                        "on the axis at 900 m/s",
+               steps=steps, value=nf * steps / el, unit="fluid ring-steps/s",
+               ms_per_step=round(el / steps * 1e3, 5),
+               probe_peaks_pa={"axis_30mm": float(peaks[0]), "wall_30mm": wall[0],
+                               "axis_105mm": float(peaks[2]), "wall_105mm": wall[1]},
+               mass_3d_kg=float(d["mass"][-1]), unstable=bool(d.get("unstable", False)))
+    if planar_peaks is not None:
+        out["planar_over_rz_wall_peak"] = [round(planar_peaks[k] / wall[k], 3) for k in range(2)]
+    return out
+
+
 def paper_production_run(wc, workloads, t_end: float = 150e-6):
     """The paper's production case in its own geometry (750x150 mm channel,
     dx = 1.5 mm, 49,947 fluid, 900 m/s) with the paper's kernel, alpha and
@@ -400,6 +437,8 @@ def main():
                     help="steps of the quadratic-viscosity run (0 skips it)")
     ap.add_argument("--mg-steps", type=int, default=2000,
                     help="steps of the Mie-Grueneisen run (0 skips it)")
+    ap.add_argument("--axisym-steps", type=int, default=2000,
+                    help="steps of the axisymmetric r-z run (0 skips it)")
     ap.add_argument("--paper-run", type=int, default=1,
                     help="1: time the paper's production case to 150 us (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -470,6 +509,9 @@ def main():
     audit = audit_run(wc, workloads, args.audit_steps, value) if args.audit_steps > 0 else None
     qav = qav_run(wc, workloads, args.qav_steps, value) if args.qav_steps > 0 else None
     mg = mg_run(wc, workloads, args.mg_steps, value) if args.mg_steps > 0 else None
+    # planar wall-probe peaks at the 30 and 105 mm stations (probes on y = 0)
+    planar_wall = [float(np.abs(p[:, 0]).max()), float(np.abs(p[:, 2]).max())] if p.size else None
+    axisym = axisymmetric_run(wc, workloads, args.axisym_steps, planar_wall) if args.axisym_steps > 0 else None
     paper = paper_production_run(wc, workloads) if args.paper_run else None
     cpu = None if args.no_cpu else cpu_baseline()
     out = {
@@ -497,6 +539,7 @@ def main():
         "energy_audit": audit,
         "quadratic_av": qav,
         "mie_grueneisen": mg,
+        "axisymmetric": axisym,
         "paper_production_run": paper,
         "unstable": unstable,
         "probe_peak_pa": float(np.abs(p).max()) if p.size else None,
