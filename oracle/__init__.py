@@ -118,6 +118,7 @@ def lib():
                                 + [_D, _D, _D]),
             "orc_pair_rates": (None, [P, C.c_int] + [_D] * 7 + [_I] + [_D] * 5),
             "orc_tangent_J": (None, [P, C.c_int, _D, _D, _D]),
+            "orc_tangent_J_f32": (None, [P, C.c_int, _D, _D, _D]),
             "orc_eval_density": (None, [C.c_void_p, _D, _D]),
             "orc_get_energy": (None, [C.c_void_p, _D]),
             "orc_eos_pe": (C.c_double, [P, C.c_double, C.c_double]),
@@ -349,11 +350,15 @@ def pair_rates(cfg: dict, x, y, vx, vy, rho, pres, m, kind):
     return dict(zip(("drho", "ax", "ay", "Vx", "Vy"), out))
 
 
-def tangent_J(cfg: dict, dt):
+def tangent_J(cfg: dict, dt, round_f32: bool = False):
+    """J and dJ/d(alpha, delta, c0) by the FP64 forward-mode tangent on a
+    fixed dt table; round_f32: the state's values rounded to the hot path's
+    FP32 representation after every step (tangents kept)."""
     dt = f64(dt)
     J = C.c_double()
     dJ = np.empty(3)
-    lib().orc_tangent_J(C.byref(params(cfg)), dt.size, dptr(dt), C.byref(J), dptr(dJ))
+    fn = lib().orc_tangent_J_f32 if round_f32 else lib().orc_tangent_J
+    fn(C.byref(params(cfg)), dt.size, dptr(dt), C.byref(J), dptr(dJ))
     return J.value, dJ
 
 

@@ -142,6 +142,10 @@ void orc_pair_rates(const orc_params* p, int n, const double* x, const double* y
 /* Runs n_steps from the set-up state with the given dt table and returns
  * J and dJ/d(alpha, delta, c0). */
 void orc_tangent_J(const orc_params* p, int n_steps, const double* dt, double* J, double* dJ);
+/* The same with the state's values rounded to the FP32 representation of the
+ * hot path after every step (cell + float32 offset, float32 v and rho; the
+ * tangents are kept): how far FP32 storage alone moves J and its gradient. */
+void orc_tangent_J_f32(const orc_params* p, int n_steps, const double* dt, double* J, double* dJ);
 
 #ifdef __cplusplus
 }

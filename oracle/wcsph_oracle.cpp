@@ -1294,7 +1294,25 @@ void orc_pair_rates(const orc_params* p, int n, const double* x, const double* y
   }
 }
 
-void orc_tangent_J(const orc_params* p, int n_steps, const double* dt, double* J, double* dJ) {
+}  // extern "C"
+
+// The value of a state component rounded to float32 (the tangent is kept).
+template <class T>
+void round_value_f32(T& x) {
+  x.v = (double)(float)x.v;
+}
+// A position rounded to the FP32 representation of the hot path: the index
+// of its cell of edge dc from lo, plus a float32 offset inside the cell.
+template <class T>
+void round_position_f32(T& x, double lo, double dc) {
+  const double c = std::floor((x.v - lo) / dc);
+  double o = (double)(float)(x.v - lo - c * dc);
+  double cc = c;
+  if (o >= (double)(float)dc) { cc += 1.0; o = 0.0; }
+  x.v = lo + cc * dc + o;
+}
+
+void tangent_run(const orc_params* p, int n_steps, const double* dt, bool round_f32, double* J, double* dJ) {
   // coupled: not differentiated; table: not held here; scheme 1 and the axisymmetric form: not built
   if (p->kin_mode == 2 || p->kin_mode == 3 || p->scheme == 1 || p->axisym) {
     *J = dJ[0] = dJ[1] = dJ[2] = std::nan("");
@@ -1308,9 +1326,32 @@ void orc_tangent_J(const orc_params* p, int n_steps, const double* dt, double* J
   s.set_coef(a, d, c);
   s.setup(*p, 0, nullptr);
   s.dt_table.assign(dt, dt + n_steps);
-  for (int k = 0; k < n_steps; ++k) s.one_step();
+  auto round_state = [&]() {
+    for (int i = 0; i < s.Nf; ++i) {
+      round_position_f32(s.x[i], s.G.x_lo, s.G.dc);
+      round_position_f32(s.y[i], s.G.y_lo, s.G.dc);
+      round_value_f32(s.vx[i]);
+      round_value_f32(s.vy[i]);
+      round_value_f32(s.rho[i]);
+    }
+  };
+  if (round_f32) round_state();
+  for (int k = 0; k < n_steps; ++k) {
+    s.one_step();
+    if (round_f32) round_state();
+  }
   *J = s.J.v;
   for (int k = 0; k < 3; ++k) dJ[k] = s.J.d[k];
+}
+
+extern "C" {
+
+void orc_tangent_J(const orc_params* p, int n_steps, const double* dt, double* J, double* dJ) {
+  tangent_run(p, n_steps, dt, false, J, dJ);
+}
+
+void orc_tangent_J_f32(const orc_params* p, int n_steps, const double* dt, double* J, double* dJ) {
+  tangent_run(p, n_steps, dt, true, J, dJ);
 }
 
 }  // extern "C"

@@ -17,7 +17,14 @@ the largest history difference over the probe's own peak, the peak
 difference and the impulse (sum p dt) difference, and the largest relative
 difference of dt where the run keeps its own step.
 
-python -m tests.golden.chaos_floor [c2|paper|all]
+For the adjoint form the file records the same comparison for the FP64
+forward-mode tangent of the summed probe impulse: J and dJ/d(alpha, delta,
+c0) on the oracle's dt table with and without the per-step rounding. For
+the precision form (C3, 1,000 steps) it records runs B and C's FP64
+diagnostics (x momentum, ke, e_el, w_boundary) against run A's, stored by
+tests/golden/c3_reference.py.
+
+python -m tests.golden.chaos_floor [c2|paper|c5_adjoint|c3_diag|all]
 """
 from __future__ import annotations
 
@@ -92,11 +99,69 @@ def floor(cfg: dict, steps: int, replay_dt: bool) -> dict:
     return out
 
 
+def tangent_floor(cfg: dict, steps: int) -> dict:
+    """The FP64 forward-mode tangent of the summed probe impulse J on the
+    oracle's own dt table, with and without the state rounded to the FP32
+    representation after every step (tangents kept): how far FP32 storage
+    alone moves J and dJ/d(alpha, delta, c0)."""
+    t0 = time.perf_counter()
+    a = oracle.Oracle(cfg)
+    a.step(steps)
+    _, dt, _ = a.probes()
+    J, g = oracle.tangent_J(cfg, dt)
+    Jr, gr = oracle.tangent_J(cfg, dt, round_f32=True)
+    return dict(steps=steps, J=J, grad=g.tolist(), J_rounded=Jr, grad_rounded=gr.tolist(),
+                J_rel=abs(Jr / J - 1), grad_rel=(np.abs(gr / g - 1)).tolist(),
+                wall_s=round(time.perf_counter() - t0, 1))
+
+
+DIAG_KEYS = ("momx", "ke", "e_el", "w_boundary")
+
+
+def diag_floor(cfg: dict, ref_file: str) -> dict:
+    """The FP64 diagnostics (records every 10 steps) of runs B and C against
+    the oracle's own run A stored in ref_file (by tests/golden/c3_reference.py),
+    on A's dt table: per quantity, the largest difference over the records
+    divided by the largest value."""
+    t0 = time.perf_counter()
+    ref = np.load(os.path.join(HERE, ref_file))
+    steps = int(ref["steps"])
+    out = dict(steps=steps, replay_dt=True, ref=ref_file, noise=NOISE)
+    for name, noise in (("rounded", 0.0), ("rounded_noise", NOISE)):
+        rng = np.random.default_rng(SEED)
+        b = oracle.Oracle(cfg)
+        b.set_dt_table(ref["dt"])
+
+        def store(prev):
+            t_, f = b.fluid()
+            if noise > 0.0 and prev is not None:
+                f = [p + (c - p) * (1.0 + noise * rng.uniform(-1.0, 1.0, c.size)) for c, p in zip(f, prev)]
+            r = round_state(cfg, *f)
+            b.set_fluid(t_, *r)
+            return r
+
+        prev = store(None)
+        for n in range(steps):
+            b.step(1)
+            prev = store(prev)
+            if n % 100 == 99:
+                print(f"  {name} step {n + 1}/{steps}", flush=True)
+        d = b.diags()
+        out[name] = {k: float(np.abs(d[k][1:] - ref["diag_" + k][1:]).max() / np.abs(ref["diag_" + k][1:]).max())
+                     for k in DIAG_KEYS}
+    out["wall_s"] = round(time.perf_counter() - t0, 1)
+    return out
+
+
 CASES = {
     # the whole 300x150 mm run on one time-step table
     "c2": lambda: floor(workloads.C2(), workloads.C2()["steps"], True),
     # the paper's 750x150 mm channel at dx 1.5 mm, each run on its own CFL step
     "paper": lambda: floor(workloads.paper_geometry(), 300, False),
+    # the adjoint form (120x60 mm, 500 steps): the gradient's FP32-storage floor
+    "c5_adjoint": lambda: tangent_floor(workloads.C5(), workloads.C5()["steps"]),
+    # the precision form's 1,000 steps (600x300 mm): its FP64 diagnostics
+    "c3_diag": lambda: diag_floor(workloads.C3(), "c3_1000.npz"),
 }
 
 
@@ -106,6 +171,8 @@ def main(which: str = "all") -> None:
             res = json.load(f)
     except (OSError, ValueError):
         res = {}
+    if which != "all" and which not in CASES:
+        raise SystemExit(f"unknown case {which}; one of {sorted(CASES)} or all")
     for k, fn in CASES.items():
         if which in ("all", k):
             print(f"[floor] {k}", flush=True)
