@@ -81,7 +81,15 @@ def test_autograd_function_matches_reverse_sweep():
 
 def test_adjoint_C5_full_size():
     """120x60 mm at dx 0.5 mm (28,352 fluid), 900 m/s, 500 steps,
-    checkpoint every 50 steps."""
+    checkpoint every 50 steps. Bars per component: twice the oracle's own
+    FP32 floor at this workload, the FP64 tangent run with its state rounded
+    to the FP32 representation after every step against the plain FP64
+    tangent (tests/golden/chaos_floor.py, case c5_adjoint: relative
+    differences 1.5e-2, 1.2e-3 and 2.0e-4 for alpha, delta and c0)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "chaos_floor.json")) as f:
+        floor = np.array(json.load(f)["c5_adjoint"]["grad_rel"])
     cfg = workloads.C5()
     n = cfg["steps"]
     dt = _table(cfg, n)
@@ -89,8 +97,9 @@ def test_adjoint_C5_full_size():
     J, g = _gpu_grad(cfg, dt, 50)
     Jo, go = oracle.tangent_J(cfg, dt)
     rel = _report("C5", J, g, Jo, go)
+    print(f"C5 bars (2x the FP32 floor): {2.0 * floor}")
     assert abs(J - Jo) <= 1e-3 * abs(Jo)
-    assert np.all(rel <= 2e-2)
+    assert np.all(rel <= 2.0 * floor)
 
 
 def test_adjoint_matches_central_differences_of_the_gpu_forward():

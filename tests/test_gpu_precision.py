@@ -3,7 +3,8 @@ FP64 time, kinematics and diagnostics) against the FP64 oracle at full
 size, with the error of every result printed.
 
 * 600x300 mm channel at dx 0.5 mm (719,552 fluid): one evaluation from a
-  shared state, and 100 steps from t = 0 (fields and FP64 diagnostics).
+  shared state, 100 steps from t = 0 (fields and FP64 diagnostics), and
+  the configured 1,000 steps against the stored oracle run.
 * 300x150 mm channel (179,552 fluid): the whole 2,000-step run on the
   oracle's time-step table, wall-probe histories (the entry pulse reaches
   the near probes after about 1,100 steps and the far ones near the end).
@@ -68,6 +69,71 @@ def test_C3_one_evaluation_and_100_steps():
     for k in ("momx", "ke", "e_el", "w_boundary"):
         assert e2[k] <= 1e-3, k
     s.close()
+
+
+def test_C3_1000_steps_against_the_stored_oracle_run():
+    """The precision form's whole configured run (600x300 mm, dx 0.5 mm,
+    719,552 fluid, 1,000 steps) on the oracle's time-step table, against the
+    oracle's run stored by tests/golden/c3_reference.py (too long to repeat
+    here): mass to the FP64 sum's rounding at every record (every 10
+    steps); momx, ke, e_el and w_boundary, each as the largest difference
+    over the records relative to the largest record, within twice the
+    oracle's own FP32 floor at this workload (the FP64 oracle against itself
+    with its state rounded to the FP32 representation every step, with and
+    without FP32-sized noise on each step's change: tests/golden/
+    chaos_floor.py, case c3_diag; floors momx 1.6e-3, ke 6.8e-3, e_el
+    2.9e-3, w_boundary 4.2e-3); e_disk (the prescribed disk's kinetic
+    energy) to 1e-12. Within 1,000 steps the entry pulse has not reached the
+    wall probes (75 mm and more from the path): they read the hydrostatic
+    compression of a few hundred Pa, below what a float32 density resolves
+    (one ulp of rho0 is about 130 Pa), so they are bounded as an absolute
+    difference of twice the oracle's peak."""
+    import os
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "c3_1000.npz"))
+    cfg = workloads.C3()
+    n = cfg["steps"]
+    assert int(ref["steps"]) == n
+    print(f"[gpu] C3 {n} steps on the stored oracle dt table", flush=True)
+    s = wc.Solver(cfg, "cuda:0")
+    assert s.nf == int(ref["n_fluid"])
+    s.set_dt_table(ref["dt"])
+    s.step(n)
+    _, dtg, pg = s.read_probes()
+    dg = s.read_diagnostics()
+    s.close()
+    assert np.array_equal(dtg, ref["dt"])
+    # records of the same steps on both sides (every 10 steps, the last at step 1,000)
+    steps_g = np.asarray(dg["step"], np.int64)
+    steps_o = np.asarray(ref["diag_step"], np.int64)
+    common = np.intersect1d(steps_g[steps_g > 0], steps_o[steps_o > 0])
+    assert common.size >= 99 and common.max() == n
+    ig = np.searchsorted(steps_g, common)
+    io = np.searchsorted(steps_o, common)
+    e = {}
+    e["mass"] = float(np.abs(dg["mass"][ig] / ref["diag_mass"][io] - 1).max())
+    for k in ("momx", "ke", "e_el", "w_boundary", "e_disk"):
+        o = ref["diag_" + k][io]
+        e[k] = float(np.abs(dg[k][ig] - o).max() / np.abs(o).max())
+    peaks = np.abs(ref["p"]).max(0)
+    e["probe_abs_over_peak"] = (np.abs(pg - ref["p"]).max(0) / peaks).tolist()
+    fl = _floor_c3()
+    print("C3 1,000 steps, errors vs the stored FP64 run:", e)
+    print("C3 bars (2x the FP32 floor):", fl)
+    assert e["mass"] <= 2 * s.nf * 2.0 ** -53
+    for k in ("momx", "ke", "e_el", "w_boundary"):
+        assert e[k] <= fl[k], k
+    assert e["e_disk"] <= 1e-12
+    assert peaks.max() < 1e4  # the pulse has not arrived: hydrostatic only
+    assert max(e["probe_abs_over_peak"]) <= 2.0
+
+
+def _floor_c3():
+    """Twice the larger of the two floor runs per C3 diagnostic."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "chaos_floor.json")) as f:
+        fl = json.load(f)["c3_diag"]
+    return {k: 2.0 * max(fl["rounded"][k], fl["rounded_noise"][k]) for k in ("momx", "ke", "e_el", "w_boundary")}
 
 
 def _floor(case):
