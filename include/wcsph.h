@@ -376,9 +376,13 @@ wcsph_status wcsph_set_coefficients(wcsph_ctx* ctx, int inst, double alpha, doub
  * fixed time-step table (wcsph_set_dt_table must
  * cover the run, so dt does not depend on c0).
  * adj_forward advances n_steps from the current state, keeps a device
- * checkpoint every ckpt_every steps and returns J. adj_backward walks the
+ * checkpoint every ckpt_every steps and returns J. With ckpt_every >=
+ * n_steps (and no energy audit) the forward itself tapes every evaluation
+ * (about 2 * (40 n_slots + 32 n_fluid) bytes per step, one allocation, kept
+ * for later calls) and the backward replays nothing; the tape is bitwise
+ * that of a replay. Otherwise adj_backward walks the
  * segments last to first: it restores a checkpoint, replays the segment
- * taping each evaluation's sorted state and pre-enforcement state, and runs
+ * taping each evaluation's sorted state and pre-enforcement state. It runs
  * the hand-written transpose of the step (enforcement, pair sums, Adami ghost
  * Shepard sums, probes, Tait EOS) in FP32 with FP64 coefficient
  * accumulators; grad[3] = dJ * dJ/d(alpha, delta, c0). The state is left at

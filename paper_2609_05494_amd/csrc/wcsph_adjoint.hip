@@ -15,7 +15,8 @@
 // Adjoints are FP32 per fluid particle (indexed by particle id); the
 // coefficient gradients are reduced per block in FP64 in a fixed order.
 // The sorted states, cell lists and pre-enforcement states of each
-// evaluation come from a taped replay of the checkpoint segment.
+// evaluation come from the tape: written by the forward run itself when one
+// segment covers it, else by a replay of each checkpoint segment.
 
 #include "wcsph_adjoint.h"
 #include "wcsph_launch.h"

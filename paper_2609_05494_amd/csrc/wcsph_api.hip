@@ -128,6 +128,7 @@ struct wcsph_ctx {
     std::vector<char*> ckpt_dev;       // state at each segment start, then the end state
     size_t ckpt_bytes = 0;
     int tape_steps = 0;                // taped steps allocated
+    bool taped = false;                // the forward taped the whole run (no replay)
     std::vector<TapeEval> tA, tB;
     std::vector<double2*> pA, pB;
     std::vector<float4*> vA, vB;
@@ -918,22 +919,35 @@ void ckpt_copy(wcsph_ctx* c, char* blob, bool save) {
   if (!save) rearm(c);
 }
 
+// The tape of steps [tape_steps, steps): one device block for all of them,
+// carved into the evaluations' arrays (256-byte aligned), so that a long
+// tape costs one allocation.
 void alloc_tape(wcsph_ctx* c, int steps) {
   auto& A = c->adj;
   if (A.tape_steps >= steps) return;
   const size_t N = c->n_slots, nf = c->hp[0].nf;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t per_eval = 2 * al(N * 4) + 2 * al(N * 16) + al(((size_t)c->n_cells + 1) * 4) +
+                          al((size_t)c->n_ghost * 4) + 2 * al(nf * 16);
+  char* slab = static_cast<char*>(dalloc(c, per_eval * 2 * (size_t)(steps - A.tape_steps)));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = slab + off;
+    off += al(bytes);
+    return q;
+  };
   for (int k = A.tape_steps; k < steps; ++k) {
     for (int e = 0; e < 2; ++e) {
       TapeEval t;
-      t.cell = dalloc_n<uint32_t>(c, N);
-      t.id = dalloc_n<uint32_t>(c, N);
-      t.pv = dalloc_n<float4>(c, N);
-      t.aux = dalloc_n<float4>(c, N);
-      t.start = dalloc_n<uint32_t>(c, (size_t)c->n_cells + 1);
-      t.gslot = dalloc_n<uint32_t>(c, (size_t)c->n_ghost);
+      t.cell = reinterpret_cast<uint32_t*>(take(N * 4));
+      t.id = reinterpret_cast<uint32_t*>(take(N * 4));
+      t.pv = reinterpret_cast<float4*>(take(N * 16));
+      t.aux = reinterpret_cast<float4*>(take(N * 16));
+      t.start = reinterpret_cast<uint32_t*>(take(((size_t)c->n_cells + 1) * 4));
+      t.gslot = reinterpret_cast<uint32_t*>(take((size_t)c->n_ghost * 4));
       (e == 0 ? A.tA : A.tB).push_back(t);
-      (e == 0 ? A.pA : A.pB).push_back(dalloc_n<double2>(c, nf));
-      (e == 0 ? A.vA : A.vB).push_back(dalloc_n<float4>(c, nf));
+      (e == 0 ? A.pA : A.pB).push_back(reinterpret_cast<double2*>(take(nf * 16)));
+      (e == 0 ? A.vA : A.vB).push_back(reinterpret_cast<float4*>(take(nf * 16)));
     }
   }
   A.tape_steps = steps;
@@ -1638,8 +1652,13 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   auto& A = ctx->adj;
   A.fwd_done = false;
   A.n_steps = n_steps;
-  A.ckpt = ckpt_every;
-  A.n_seg = (n_steps + ckpt_every - 1) / ckpt_every;
+  A.ckpt = std::min(ckpt_every, n_steps);
+  A.n_seg = (n_steps + A.ckpt - 1) / A.ckpt;
+  // one segment: the forward itself writes the whole tape (the same kernels
+  // as the step graph, launched one by one with the tape's buffers), and the
+  // backward replays nothing. (With the energy audit the step graph's
+  // corrector also sums the audit terms, so that run keeps the graph.)
+  A.taped = A.n_seg == 1 && !ctx->audit;
   A.step0 = ctx->steps;
   std::vector<double> tab(ctx->d.n_dt);
   sync(ctx);
@@ -1657,11 +1676,18 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   A.ckpt_bytes = ckpt_size(ctx);
   while ((int)A.ckpt_dev.size() < A.n_seg + 1) A.ckpt_dev.push_back(static_cast<char*>(dalloc(ctx, A.ckpt_bytes)));
   ctx->hist_read[0] = ctx->steps;
-  for (int g = 0; g < A.n_seg; ++g) {
-    ckpt_copy(ctx, A.ckpt_dev[g], true);
-    const int n = std::min(ckpt_every, n_steps - g * ckpt_every);
-    for (int k = 0; k < n; ++k) HC(hipGraphLaunch(ctx->gexec, ctx->st));
-    ctx->steps += n;
+  if (A.taped) {
+    alloc_tape(ctx, n_steps);
+    ckpt_copy(ctx, A.ckpt_dev[0], true);
+    replay_taped(ctx, n_steps);
+    ctx->steps += n_steps;
+  } else {
+    for (int g = 0; g < A.n_seg; ++g) {
+      ckpt_copy(ctx, A.ckpt_dev[g], true);
+      const int n = std::min(A.ckpt, n_steps - g * A.ckpt);
+      for (int k = 0; k < n; ++k) HC(hipGraphLaunch(ctx->gexec, ctx->st));
+      ctx->steps += n;
+    }
   }
   ckpt_copy(ctx, A.ckpt_dev[A.n_seg], true);
   // J = sum_n sum_k p_k^n dt_n (probe rows of this run)
@@ -1710,8 +1736,10 @@ wcsph_status wcsph_adj_backward(wcsph_ctx* ctx, double dJ, double* grad) {
   const long long steps_after = ctx->steps;
   for (int g = A.n_seg - 1; g >= 0; --g) {
     const int n = std::min(A.ckpt, A.n_steps - g * A.ckpt);
-    ckpt_copy(ctx, A.ckpt_dev[g], false);
-    replay_taped(ctx, n);
+    if (!A.taped) {
+      ckpt_copy(ctx, A.ckpt_dev[g], false);
+      replay_taped(ctx, n);
+    }
     for (int k = n - 1; k >= 0; --k) {
       const int st = g * A.ckpt + k;
       const double t = A.t[st], dt = A.dt[st];
