@@ -67,9 +67,11 @@ WC_HD inline void pair_forward(const PairIn<T>& in, const PairK<T>& k, T& D, T& 
   Vy = -w * in.vy;
 }
 
+// (rcp_fn: the reciprocal the caller's precision calls for; the device
+// passes the hardware reciprocal, as the step kernels use)
 template <class T>
 WC_HD inline void pair_vjp(const PairIn<T>& in, const PairK<T>& k, T lD, T lax, T lay, T lVx, T lVy,
-                           PairGrad<T>& g, T (*sqrt_fn)(T)) {
+                           PairGrad<T>& g, T (*sqrt_fn)(T), T (*rcp_fn)(T)) {
   const T rx = in.rx, ry = in.ry, vx = in.vx, vy = in.vy;
   const T r2 = rx * rx + ry * ry;
   const T rr = sqrt_fn(r2);
@@ -79,35 +81,36 @@ WC_HD inline void pair_vjp(const PairIn<T>& in, const PairK<T>& k, T lD, T lax, 
   const T F = -k.fgrad * s2 * s;
   const T dF = T(1.5) * k.fgrad * s2 * k.inv_h;  // dF / d|r|
   const T vr = vx * rx + vy * ry;
-  const T R2 = in.ra + in.rb, den = r2 + k.eta2h2, inv = T(1) / (den * R2);
+  const T R2 = in.ra + in.rb, den = r2 + k.eta2h2, inv = rcp_fn(den * R2);
+  const T iR2 = rcp_fn(R2), iden = inv * R2, irb = rcp_fn(in.rb);
   const T C2 = in.ca + in.cb;
   const T mv = wc_min0(vr);
   const T Pi = -k.alpha * k.h * C2 * mv * inv;
   const T Pv = vr < T(0) ? -k.alpha * k.h * C2 * inv : T(0);  // dPi / dvr
   const T mF = in.mb * F;
   const T kd = in.fl * k.delta * k.two_h_c0 * in.mb;
-  const T drho = (in.ra - in.rb) / in.rb;
+  const T drho = (in.ra - in.rb) * irb;
   const T sp = in.Pa + in.Pb + Pi;
   const T lam = k.four_nu0 * mF * r2 * inv;
   const T Lv = lax * vx + lay * vy;
   const T Lr = lax * rx + lay * ry;
   const T LV = lVx * vx + lVy * vy;
-  const T GLV = -in.fl * k.eps * in.mb * T(2) / R2 * W;  // dL / d(lV . v)
-  const T GW = -in.fl * k.eps * in.mb * T(2) / R2 * LV;  // dL / dW
+  const T GLV = -in.fl * k.eps * in.mb * T(2) * iR2 * W;  // dL / d(lV . v)
+  const T GW = -in.fl * k.eps * in.mb * T(2) * iR2 * LV;  // dL / dW
   const T GF = lD * in.mb * vr + lD * kd * drho + Lv * k.four_nu0 * in.mb * r2 * inv - in.mb * sp * Lr;
   const T dvr = lD * mF - mF * Lr * Pv;
-  const T dden = (-Lv * lam + mF * Lr * Pi) / den;
+  const T dden = (-Lv * lam + mF * Lr * Pi) * iden;
   const T dr2 = Lv * k.four_nu0 * mF * inv + dden;
   const T dLr = -mF * sp;
-  const T fr = rr > T(0) ? GF * dF / rr : T(0);
+  const T fr = rr > T(0) ? GF * dF * rcp_fn(rr) : T(0);
   g.rx = fr * rx + GW * F * rx + dvr * vx + T(2) * dr2 * rx + dLr * lax;
   g.ry = fr * ry + GW * F * ry + dvr * vy + T(2) * dr2 * ry + dLr * lay;
   g.vx = dvr * rx + lam * lax + GLV * lVx;
   g.vy = dvr * ry + lam * lay + GLV * lVy;
   const T T5 = GLV * LV;
-  const T dR2 = (-Lv * lam + mF * Lr * Pi - T5) / R2;
-  g.ra = dR2 + lD * kd * F / in.rb;
-  g.rb = dR2 - lD * kd * F * in.ra / (in.rb * in.rb);
+  const T dR2 = (-Lv * lam + mF * Lr * Pi - T5) * iR2;
+  g.ra = dR2 + lD * kd * F * irb;
+  g.rb = dR2 - lD * kd * F * in.ra * irb * irb;
   g.P = -mF * Lr;
   g.c = -mF * Lr * (-k.alpha * k.h * mv * inv);
   g.alpha = -mF * Lr * (-k.h * C2 * mv * inv);

@@ -25,6 +25,7 @@
 namespace {
 
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ float d_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float d_pow(float a, float b) { return powf(a, b); }
 
 __device__ __forceinline__ PairK<float> pair_k(const InstParams& P) {
@@ -217,7 +218,10 @@ __device__ __forceinline__ void tcand(const TRow& r0, const TRow& r1, const TRow
   dx = j < r.ms ? -1 : (j < r.me ? 0 : 1);
 }
 #ifndef ADJ_FG
-#define ADJ_FG 4  // lanes per fluid slot in the fluid adjoint kernel
+#define ADJ_FG 8  // lanes per fluid slot in the fluid adjoint kernel
+#endif
+#ifndef ADJ_LCAP
+#define ADJ_LCAP 16  // entries of a lane's hit list in the fluid adjoint kernel
 #endif
 
 template <int G>
@@ -231,7 +235,9 @@ __device__ __forceinline__ float gsum(float v) {
 // density these become the adjoint of the ghost pressure (zero when the
 // cavitation cutoff is active) and of c0. The ghost's Shepard sums are
 // stored for the fluid pass. Extra threads compute the probes' Shepard sums.
-#define AG_L 16  // lanes per ghost or probe
+#ifndef AG_L
+#define AG_L 32  // lanes per ghost or probe
+#endif
 __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te, double t_eval, int n_gb) {
   __shared__ double shd[4];
   const InstParams& P = d.prm[0];
@@ -264,8 +270,8 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
       int dx, dy;
       tcand(r0, r1, r2, blk, c, j, dx, dy);
       const float4 aj = te.aux[j];
+      const float4 pj = te.pv[j];  // (loaded with aux: one round trip per candidate)
       if (!(aj.w > 0.0f)) continue;
-      const float4 pj = te.pv[j];
       // r_i - r_g for the pair phi(i, g)
       const float rx = (pj.x + (float)dx * P.dc) - pg.x, ry = (pj.y + (float)dy * P.dc) - pg.y;
       const float r2 = rx * rx + ry * ry;
@@ -276,7 +282,7 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
       in.mb = mg; in.fl = 0.0f;
       PairGrad<float> g;
       const float4 lj = reinterpret_cast<const float4*>(ls)[j];
-      pair_vjp(in, k, lj.x, lj.y, lj.z, lj.w, ls[4 * N + j], g, d_sqrt);
+      pair_vjp(in, k, lj.x, lj.y, lj.z, lj.w, ls[4 * N + j], g, d_sqrt, d_rcp);
       gr += g.rb;
       gP += g.P;
       gc += g.c;
@@ -373,8 +379,9 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
 // (added, or set when accumulate == 0).
 __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te, float probe_seed,
                                                     int accumulate, int block0) {
-  // four lanes per slot (quad lane g) share its 3x3 candidates
+  // ADJ_FG lanes per slot (lane g of the group) share its 3x3 candidates
   __shared__ double shd[4];
+  __shared__ uint32_t s_hits[ADJ_LCAP * 256];
   const InstParams& P = d.prm[0];
   const int s = (int)((blockIdx.x * 256 + threadIdx.x) / ADJ_FG);
   const int g = (int)(threadIdx.x % ADJ_FG);
@@ -397,61 +404,90 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
       int cx, cy;
       cxy(P, K, cx, cy);
       const TRow r0 = trow(te, P, cx, cy, -1), r1 = trow(te, P, cx, cy, 0), r2 = trow(te, P, cx, cy, 1);
-    const TCount blk = tcount(r0, r1, r2);
-      for (uint32_t c = (uint32_t)g; c < blk.n; c += ADJ_FG) {
-        uint32_t j;
-        int dx, dy;
-        tcand(r0, r1, r2, blk, c, j, dx, dy);
-        if (j == (uint32_t)s) continue;
-        const float4 pj = te.pv[j];
-        const float rx = (pi.x - pj.x) - (float)dx * P.dc;  // r_s - r_j
-        const float ry = (pi.y - pj.y) - (float)dy * P.dc;
-        const float r2 = rx * rx + ry * ry;
-        if (!(r2 < P.four_h2)) continue;
-        const float4 aj = te.aux[j];
-        const bool jfl = aj.w > 0.0f;
-        // own rates: phi(s, j)
-        PairIn<float> in;
-        in.rx = rx; in.ry = ry; in.vx = pi.z - pj.z; in.vy = pi.w - pj.w;
-        in.ra = ai.x; in.rb = aj.x; in.Pa = ai.y; in.Pb = aj.y; in.ca = ai.z; in.cb = aj.z;
-        in.mb = fabsf(aj.w); in.fl = jfl ? 1.0f : 0.0f;
-        PairGrad<float> gg;
-        pair_vjp(in, k, lD, lax, lay, lVx, lVy, gg, d_sqrt);
-        urx += gg.rx; ury += gg.ry; uvx += gg.vx; uvy += gg.vy; ur += gg.ra; uP += gg.P; uc += gg.c;
-        th_a += (double)gg.alpha;
-        th_d += (double)gg.delta;
-        th_c += (double)gg.c0x;
-        if (jfl) {
-          // the neighbour's rates: phi(j, s), r = r_j - r_s
-          PairIn<float> jn;
-          jn.rx = -rx; jn.ry = -ry; jn.vx = pj.z - pi.z; jn.vy = pj.w - pi.w;
-          jn.ra = aj.x; jn.rb = ai.x; jn.Pa = aj.y; jn.Pb = ai.y; jn.ca = aj.z; jn.cb = ai.z;
-          jn.mb = ai.w; jn.fl = 1.0f;
-          PairGrad<float> h;
-          const float4 lj = reinterpret_cast<const float4*>(ls)[j];
-          pair_vjp(jn, k, lj.x, lj.y, lj.z, lj.w, ls[4 * N + j], h, d_sqrt);
-          urx -= h.rx; ury -= h.ry; uvx -= h.vx; uvy -= h.vy; ur += h.rb; uP += h.P; uc += h.c;
-        } else {
-          // ghost j: this particle enters the ghost's Shepard sums
-          const float* gq = a.gadj + (size_t)j * 10;
-          const float SW = gq[3];
-          if (SW > 0.0f) {
-            const float pbar = gq[0], vbx = gq[1], vby = gq[2], pt = gq[4], vax = gq[5], vay = gq[6];
-            const float gx = gq[7], gy = gq[8];
-            const float ddx = -rx, ddy = -ry;  // d = r_g - r_s
-            const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
-            const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
-            const float F = -P.fgrad * s2 * sq;
-            const float ad_ = gx * ddx + gy * ddy;
-            const float iw = 1.0f / SW;
-            ur += pbar * (ei.dp + ad_) * W * iw;
-            const float cf = -(ei.p + ai.x * ad_ - pt) * F * iw;
-            const float vv = vbx * (pi.z - vax) + vby * (pi.w - vay);
-            urx += pbar * (cf * ddx - ai.x * W * iw * gx) + vv * F * ddx * iw;
-            ury += pbar * (cf * ddy - ai.x * W * iw * gy) + vv * F * ddy * iw;
-            uvx -= vbx * W * iw;
-            uvy -= vby * W * iw;
-            uc0 += pbar * ei.dpdc0 * W * iw;
+      const TCount blk = tcount(r0, r1, r2);
+      // the in-support candidates go into a lane-private list in LDS (slot,
+      // cell shift); the pair terms run over the list, so a wave runs them as
+      // often as its longest list, not once per candidate position. Chunks of
+      // ADJ_LCAP candidates per lane keep every list within its room; the
+      // terms are summed in candidate order
+      uint32_t* my = s_hits + threadIdx.x;
+      const float4* ls4 = reinterpret_cast<const float4*>(ls);
+      for (uint32_t c0 = (uint32_t)g; c0 < blk.n; c0 += ADJ_FG * ADJ_LCAP) {
+        int cnt = 0;
+        const uint32_t c1 = min(blk.n, c0 + ADJ_FG * ADJ_LCAP);
+        for (uint32_t c = c0; c < c1; c += ADJ_FG) {
+          uint32_t jc;
+          int dxc, dyc;
+          tcand(r0, r1, r2, blk, c, jc, dxc, dyc);
+          const float4 pc = te.pv[jc];
+          const float rxc = (pi.x - pc.x) - (float)dxc * P.dc;
+          const float ryc = (pi.y - pc.y) - (float)dyc * P.dc;
+          const bool hit = jc != (uint32_t)s && rxc * rxc + ryc * ryc < P.four_h2;
+          my[cnt * 256] = (jc << 4) | ((uint32_t)(dyc + 1) << 2) | (uint32_t)(dxc + 1);
+          cnt += hit ? 1 : 0;
+        }
+        // the next hit's state is loaded while this one's terms are computed
+        // (an empty list loads the lane's own slot, always in range)
+        uint32_t cn = cnt > 0 ? my[0] : ((uint32_t)s << 4);
+        float4 pn = te.pv[cn >> 4], an = te.aux[cn >> 4], ln = ls4[cn >> 4];
+        float lyn = ls[4 * N + (cn >> 4)];
+        for (int kk = 0; kk < cnt; ++kk) {
+          const uint32_t code = cn;
+          const uint32_t j = code >> 4;
+          const int dx = (int)(code & 3u) - 1, dy = (int)((code >> 2) & 3u) - 1;
+          const float4 pj = pn, aj = an, lj = ln;
+          const float lyj = lyn;
+          cn = my[min(kk + 1, cnt - 1) * 256];
+          pn = te.pv[cn >> 4];
+          an = te.aux[cn >> 4];
+          ln = ls4[cn >> 4];
+          lyn = ls[4 * N + (cn >> 4)];
+          const float rx = (pi.x - pj.x) - (float)dx * P.dc;  // r_s - r_j
+          const float ry = (pi.y - pj.y) - (float)dy * P.dc;
+          const float r2 = rx * rx + ry * ry;
+          const bool jfl = aj.w > 0.0f;
+          // own rates: phi(s, j)
+          PairIn<float> in;
+          in.rx = rx; in.ry = ry; in.vx = pi.z - pj.z; in.vy = pi.w - pj.w;
+          in.ra = ai.x; in.rb = aj.x; in.Pa = ai.y; in.Pb = aj.y; in.ca = ai.z; in.cb = aj.z;
+          in.mb = fabsf(aj.w); in.fl = jfl ? 1.0f : 0.0f;
+          PairGrad<float> gg;
+          pair_vjp(in, k, lD, lax, lay, lVx, lVy, gg, d_sqrt, d_rcp);
+          urx += gg.rx; ury += gg.ry; uvx += gg.vx; uvy += gg.vy; ur += gg.ra; uP += gg.P; uc += gg.c;
+          th_a += (double)gg.alpha;
+          th_d += (double)gg.delta;
+          th_c += (double)gg.c0x;
+          if (jfl) {
+            // the neighbour's rates: phi(j, s), r = r_j - r_s
+            PairIn<float> jn;
+            jn.rx = -rx; jn.ry = -ry; jn.vx = pj.z - pi.z; jn.vy = pj.w - pi.w;
+            jn.ra = aj.x; jn.rb = ai.x; jn.Pa = aj.y; jn.Pb = ai.y; jn.ca = aj.z; jn.cb = ai.z;
+            jn.mb = ai.w; jn.fl = 1.0f;
+            PairGrad<float> h;
+            pair_vjp(jn, k, lj.x, lj.y, lj.z, lj.w, lyj, h, d_sqrt, d_rcp);
+            urx -= h.rx; ury -= h.ry; uvx -= h.vx; uvy -= h.vy; ur += h.rb; uP += h.P; uc += h.c;
+          } else {
+            // ghost j: this particle enters the ghost's Shepard sums
+            const float* gq = a.gadj + (size_t)j * 10;
+            const float SW = gq[3];
+            if (SW > 0.0f) {
+              const float pbar = gq[0], vbx = gq[1], vby = gq[2], pt = gq[4], vax = gq[5], vay = gq[6];
+              const float gx = gq[7], gy = gq[8];
+              const float ddx = -rx, ddy = -ry;  // d = r_g - r_s
+              const float q = sqrtf(r2) * P.inv_h, sq = 1.0f - 0.5f * q, s2 = sq * sq;
+              const float W = P.sigma * s2 * s2 * (2.0f * q + 1.0f);
+              const float F = -P.fgrad * s2 * sq;
+              const float ad_ = gx * ddx + gy * ddy;
+              const float iw = 1.0f / SW;
+              ur += pbar * (ei.dp + ad_) * W * iw;
+              const float cf = -(ei.p + ai.x * ad_ - pt) * F * iw;
+              const float vv = vbx * (pi.z - vax) + vby * (pi.w - vay);
+              urx += pbar * (cf * ddx - ai.x * W * iw * gx) + vv * F * ddx * iw;
+              ury += pbar * (cf * ddy - ai.x * W * iw * gy) + vv * F * ddy * iw;
+              uvx -= vbx * W * iw;
+              uvy -= vby * W * iw;
+              uc0 += pbar * ei.dpdc0 * W * iw;
+            }
           }
         }
       }

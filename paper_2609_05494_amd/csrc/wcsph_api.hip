@@ -129,6 +129,11 @@ struct wcsph_ctx {
     size_t ckpt_bytes = 0;
     int tape_steps = 0;                // taped steps allocated
     bool taped = false;                // the forward taped the whole run (no replay)
+    std::vector<hipGraph_t> tg_graph;  // the taping forward of tg_n steps, in graphs of a few steps
+    std::vector<hipGraphExec_t> tg_exec;
+    int tg_n = 0;
+    Dev tg_dev{};                      // ... captured for this device state and these buffers
+    Bufs tg_bufs{};
     std::vector<TapeEval> tA, tB;
     std::vector<double2*> pA, pB;
     std::vector<float4*> vA, vB;
@@ -756,9 +761,11 @@ void build(wcsph_ctx* c, const wcsph_params* params, int n_inst) {
   capture(c);
 }
 
+void drop_tape_graphs(wcsph_ctx* c);
 void release(wcsph_ctx* c) {
   if (c->st) hipStreamSynchronize(c->st);
   drop_graphs(c);
+  drop_tape_graphs(c);
   for (void* p : c->blocks) {
     if (c->custom_alloc) c->al.free(p, (void*)c->st, c->al.user);
     else hipFree(p);
@@ -969,27 +976,63 @@ Buf tape_buf(const Buf& work, const TapeEval& t) {
 // state, cell ranges, ghost slots); the enforcement kernels tape the
 // pre-enforcement state. The corrector's pair kernel reads the predictor's
 // sorted state from the tape as well.
-void replay_taped(wcsph_ctx* c, int n) {
+void replay_taped_step(wcsph_ctx* c, int k) {
   auto& A = c->adj;
-  for (int k = 0; k < n; ++k) {
-    Bufs bt = c->b;
-    bt.Y = tape_buf(c->b.Y, A.tA[k]);
-    bt.W = tape_buf(c->b.W, A.tB[k]);
-    Dev dA = c->d;
-    dA.start = A.tA[k].start;
-    dA.gslot = A.tA[k].gslot;
-    dA.tape_pos = A.pA[k];
-    dA.tape_vel = A.vA[k];
-    wc_enqueue_eval(dA, bt, c->n_gblk, EV_A, c->st);
-    HC(hipGetLastError());
-    Dev dB = c->d;
-    dB.start = A.tB[k].start;
-    dB.gslot = A.tB[k].gslot;
-    dB.tape_pos = A.pB[k];
-    dB.tape_vel = A.vB[k];
-    wc_enqueue_eval(dB, bt, c->n_gblk, EV_B, c->st);
-    HC(hipGetLastError());
+  Bufs bt = c->b;
+  bt.Y = tape_buf(c->b.Y, A.tA[k]);
+  bt.W = tape_buf(c->b.W, A.tB[k]);
+  Dev dA = c->d;
+  dA.start = A.tA[k].start;
+  dA.gslot = A.tA[k].gslot;
+  dA.tape_pos = A.pA[k];
+  dA.tape_vel = A.vA[k];
+  wc_enqueue_eval(dA, bt, c->n_gblk, EV_A, c->st);
+  HC(hipGetLastError());
+  Dev dB = c->d;
+  dB.start = A.tB[k].start;
+  dB.gslot = A.tB[k].gslot;
+  dB.tape_pos = A.pB[k];
+  dB.tape_vel = A.vB[k];
+  wc_enqueue_eval(dB, bt, c->n_gblk, EV_B, c->st);
+  HC(hipGetLastError());
+}
+void replay_taped(wcsph_ctx* c, int n) {
+  for (int k = 0; k < n; ++k) replay_taped_step(c, k);
+}
+
+// The forward's taping of n steps through graphs of WC_TAPE_GRAPH_STEPS
+// steps each (the same launches as replay_taped), captured once and kept
+// while the step count, the device state handed to the kernels and the
+// buffers stay as they were.
+#define WC_TAPE_GRAPH_STEPS 10
+void drop_tape_graphs(wcsph_ctx* c) {
+  auto& A = c->adj;
+  for (hipGraphExec_t e : A.tg_exec) hipGraphExecDestroy(e);
+  for (hipGraph_t g : A.tg_graph) hipGraphDestroy(g);
+  A.tg_exec.clear();
+  A.tg_graph.clear();
+  A.tg_n = 0;
+}
+void taped_forward(wcsph_ctx* c, int n) {
+  auto& A = c->adj;
+  if (A.tg_n != n || std::memcmp(&A.tg_dev, &c->d, sizeof(Dev)) != 0 ||
+      std::memcmp(&A.tg_bufs, &c->b, sizeof(Bufs)) != 0) {
+    drop_tape_graphs(c);
+    for (int k0 = 0; k0 < n; k0 += WC_TAPE_GRAPH_STEPS) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t e = nullptr;
+      HC(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+      for (int k = k0; k < std::min(n, k0 + WC_TAPE_GRAPH_STEPS); ++k) replay_taped_step(c, k);
+      HC(hipStreamEndCapture(c->st, &g));
+      A.tg_graph.push_back(g);
+      HC(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+      A.tg_exec.push_back(e);
+    }
+    A.tg_n = n;
+    std::memcpy(&A.tg_dev, &c->d, sizeof(Dev));
+    std::memcpy(&A.tg_bufs, &c->b, sizeof(Bufs));
   }
+  for (hipGraphExec_t e : A.tg_exec) HC(hipGraphLaunch(e, c->st));
 }
 
 }  // namespace
@@ -1646,6 +1689,7 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   require(ctx->scheme == 0, "the reverse sweep supports scheme 0 only");
   require(ctx->pin[0].axisym == 0, "the reverse sweep supports the planar form only");
   require(n_steps >= 1 && ckpt_every >= 1, "n_steps and ckpt_every must be >= 1");
+  require(n_steps <= WC_HIST_CAP, "n_steps beyond the probe history's capacity");
   const long long k0 = ctx->steps - ctx->d.dt_step0;
   require(ctx->d.n_dt > 0 && k0 >= 0 && k0 + n_steps <= ctx->d.n_dt,
           "a fixed dt table covering the run is required (wcsph_set_dt_table)");
@@ -1679,7 +1723,7 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   if (A.taped) {
     alloc_tape(ctx, n_steps);
     ckpt_copy(ctx, A.ckpt_dev[0], true);
-    replay_taped(ctx, n_steps);
+    taped_forward(ctx, n_steps);
     ctx->steps += n_steps;
   } else {
     for (int g = 0; g < A.n_seg; ++g) {
@@ -1693,14 +1737,17 @@ wcsph_status wcsph_adj_forward(wcsph_ctx* ctx, int n_steps, int ckpt_every, doub
   // J = sum_n sum_k p_k^n dt_n (probe rows of this run)
   sync(ctx);
   const int np = ctx->hp[0].n_probes;
+  // (the run's rows in one copy, two where the history ring wraps)
   std::vector<float> pr((size_t)n_steps * WC_MAX_PROBES);
+  const size_t r0 = (size_t)(A.step0 % WC_HIST_CAP), n1 = std::min((size_t)n_steps, (size_t)WC_HIST_CAP - r0);
+  HC(hipMemcpy(pr.data(), ctx->d.hist_p + r0 * WC_MAX_PROBES, n1 * WC_MAX_PROBES * sizeof(float),
+               hipMemcpyDeviceToHost));
+  if (n1 < (size_t)n_steps)
+    HC(hipMemcpy(pr.data() + n1 * WC_MAX_PROBES, ctx->d.hist_p, ((size_t)n_steps - n1) * WC_MAX_PROBES * sizeof(float),
+                 hipMemcpyDeviceToHost));
   double Jv = 0.0;
-  for (int k = 0; k < n_steps; ++k) {
-    const size_t row = (size_t)((A.step0 + k) % WC_HIST_CAP);
-    float v[WC_MAX_PROBES];
-    HC(hipMemcpy(v, ctx->d.hist_p + row * WC_MAX_PROBES, sizeof v, hipMemcpyDeviceToHost));
-    for (int j = 0; j < np; ++j) Jv += (double)v[j] * A.dt[k];
-  }
+  for (int k = 0; k < n_steps; ++k)
+    for (int j = 0; j < np; ++j) Jv += (double)pr[(size_t)k * WC_MAX_PROBES + j] * A.dt[k];
   ctx->hist_read[0] = ctx->steps;
   A.J = Jv;
   if (J) *J = Jv;
