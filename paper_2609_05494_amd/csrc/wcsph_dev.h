@@ -18,7 +18,9 @@
 #define WC_NDIAG 22
 #define WC_BLOCK 256
 #define WC_GHOST_BLOCK 256
+#ifndef WC_GHOST_LANES
 #define WC_GHOST_LANES 16      // lanes per ghost or probe in the ghost kernel
+#endif
 #define WC_MAX_RING 256        // disk-ring ghosts per instance
 #define WC_DIAG_BLOCKS 256     // diagnostic partial sums per instance
 #define WC_BUCKET 64           // capacity of one cell bucket (particles per cell)

@@ -96,7 +96,8 @@ def test_autograd_function_matches_reverse_sweep():
 
 def test_adjoint_C5_full_size():
     """120x60 mm at dx 0.5 mm (28,352 fluid), 900 m/s, 500 steps,
-    checkpoint every 50 steps. Bars per component: twice the oracle's own
+    checkpoint every 50 steps, and the same with the whole run taped by the
+    forward (bitwise equal). Bars per component: twice the oracle's own
     FP32 floor at this workload, the FP64 tangent run with its state rounded
     to the FP32 representation after every step against the plain FP64
     tangent (tests/golden/chaos_floor.py, case c5_adjoint: relative
@@ -110,6 +111,10 @@ def test_adjoint_C5_full_size():
     dt = _table(cfg, n)
     print(f"[gpu] adjoint C5, {n} steps, checkpoint 50", flush=True)
     J, g = _gpu_grad(cfg, dt, 50)
+    # the whole run taped by the forward (about 2.2 GB, nothing replayed):
+    # bitwise the checkpointed sweep's J and gradient
+    Jt, gt = _gpu_grad(cfg, dt, n)
+    assert Jt == J and np.array_equal(gt, g)
     Jo, go = oracle.tangent_J(cfg, dt)
     rel = _report("C5", J, g, Jo, go)
     print(f"C5 bars (2x the FP32 floor): {2.0 * floor}")
