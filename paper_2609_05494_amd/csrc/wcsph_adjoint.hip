@@ -5,13 +5,15 @@
 // One step is U* = E_A(U^n + dt/2 f(U^n)), U^{n+1} = E_B(U^n + dt f(U*)),
 // f = rates (pair sums over fluid and Adami ghosts, ghosts from Shepard sums
 // of the fluid), E = density band + wall / disk enforcement. Given the
-// adjoint of U^{n+1} the sweep runs, per step and in reverse:
-//   k_adj_enforce (B)  transpose of E_B; adjoint of U^n (direct part) and of f(U*)
-//   k_adj_gather       rate adjoints into the sorted slot order of U*
-//   k_adj_ghost        ghost-state adjoints (pair terms seen by the fluid)
-//   k_adj_fluid        pull-form transpose of the rates at U* -> adjoint of U*
-//   k_adj_enforce (A), k_adj_gather, k_adj_ghost, k_adj_fluid at U^n with the
-//                      probe terms of step n
+// adjoint of U^{n+1} the sweep runs, per step and in reverse, two launches
+// per evaluation:
+//   k_adj_ghost (B)    transpose of E_B (adjoint of U^n, direct part, and the
+//                      rate adjoints in the sorted slot order of U*), in the
+//                      same launch as the ghost-state adjoints (pair terms
+//                      seen by the fluid)
+//   k_adj_fluid (B)    pull-form transpose of the rates at U* -> adjoint of U*
+//   k_adj_ghost (A), k_adj_fluid (A) the same at U^n with the probe terms of
+//                      step n
 // Adjoints are FP32 per fluid particle (indexed by particle id); the
 // coefficient gradients are reduced per block in FP64 in a fixed order.
 // The sorted states, cell lists and pre-enforcement states of each
@@ -88,10 +90,12 @@ __device__ __forceinline__ GhostD ghost_d(const InstParams& P, float p) {
 // i (by id). lam_out: adjoint of the evaluation's output state
 // (x, y, vx, vy, rho); pre: pre-enforcement state taped by the forward
 // kernel; te: time of the enforcement; hdt: dt/2 (eval A) or dt (eval B).
-// Writes lam_base (+= when accumulate) and returns the rate adjoints
-// lf = hdt * (lam_pre_rho -> D, lam_pre_v -> a, lam_pre_r -> V).
-__device__ __forceinline__ void adj_enforce_one(const InstParams& P, const AdjPtrs& a, int i, double te, float hdt,
-                                                int accumulate, float* lf) {
+// (xd, vd): the disk at te (from the caller, the same for every particle).
+// With WRITE, writes lam_base (+= when accumulate); returns the rate
+// adjoints lf = hdt * (lam_pre_rho -> D, lam_pre_v -> a, lam_pre_r -> V).
+template <bool WRITE>
+__device__ __forceinline__ void adj_enforce_one(const InstParams& P, const AdjPtrs& a, int i, double xd, double vd,
+                                                float hdt, int accumulate, float* lf) {
   const int n = P.nf;
   float lx = a.lam_out[i], ly = a.lam_out[n + i], lvx = a.lam_out[2 * n + i], lvy = a.lam_out[3 * n + i],
         lr = a.lam_out[4 * n + i];
@@ -110,8 +114,6 @@ __device__ __forceinline__ void adj_enforce_one(const InstParams& P, const AdjPt
   if (yw > P.W - e) { yw = P.W - e; vyw = -vyw; hy = true; }
   // disk: radial pull-out and reflection of the inward relative velocity
   if (P.nd > 0) {
-    double xd, vd, ad;
-    kinematics(P, te, xd, vd, ad);
     const double dx = xw - xd, dy = yw - P.disk_y0;
     const double d2 = dx * dx + dy * dy;
     if (d2 < P.R * P.R) {
@@ -149,11 +151,13 @@ __device__ __forceinline__ void adj_enforce_one(const InstParams& P, const AdjPt
   }
   if (hx) { lx = 0.0f; lvx = -lvx; }
   if (hy) { ly = 0.0f; lvy = -lvy; }
-  float* lb = a.lam_base;
-  if (accumulate) {
-    lb[i] += lx; lb[n + i] += ly; lb[2 * n + i] += lvx; lb[3 * n + i] += lvy; lb[4 * n + i] += lr;
-  } else {
-    lb[i] = lx; lb[n + i] = ly; lb[2 * n + i] = lvx; lb[3 * n + i] = lvy; lb[4 * n + i] = lr;
+  if constexpr (WRITE) {
+    float* lb = a.lam_base;
+    if (accumulate) {
+      lb[i] += lx; lb[n + i] += ly; lb[2 * n + i] += lvx; lb[3 * n + i] += lvy; lb[4 * n + i] += lr;
+    } else {
+      lb[i] = lx; lb[n + i] = ly; lb[2 * n + i] = lvx; lb[3 * n + i] = lvy; lb[4 * n + i] = lr;
+    }
   }
   // rates: rho' = rho + h D, v' = v + h a, r' = r + h V
   lf[0] = hdt * lr;
@@ -163,18 +167,18 @@ __device__ __forceinline__ void adj_enforce_one(const InstParams& P, const AdjPt
   lf[4] = hdt * ly;
 }
 
-// The enforcement transpose of every fluid particle, written straight into
-// the sorted slot order of the taped evaluation (each fluid id holds one
-// slot; ghost slots get zero): lam_base by id, the rate adjoints lam_s by
-// slot.
-__global__ __launch_bounds__(256) void k_adj_enforce_gather(Dev d, AdjPtrs a, TapeEval te, double t_enf, float hdt,
-                                                            int accumulate) {
-  const int s = blockIdx.x * 256 + threadIdx.x;
+// The enforcement transpose of fluid slot s, written straight into the
+// sorted slot order of the taped evaluation (each fluid id holds one slot;
+// ghost slots get zero): lam_base by id, the rate adjoints lam_s by slot.
+__device__ __forceinline__ void adj_enforce_slot(const Dev& d, const AdjPtrs& a, const TapeEval& te, int s,
+                                                 double t_enf, float hdt, int accumulate) {
   if (s >= d.n_slots) return;
   const InstParams& P = d.prm[0];
+  double xd = 0.0, vd = 0.0, ad;
+  if (P.nd > 0) kinematics(P, t_enf, xd, vd, ad);
   const int id = (int)te.id[s] - P.id0;
   float lf[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  if (id >= 0 && id < P.nf) adj_enforce_one(P, a, id, t_enf, hdt, accumulate, lf);
+  if (id >= 0 && id < P.nf) adj_enforce_one<true>(P, a, id, xd, vd, hdt, accumulate, lf);
   reinterpret_cast<float4*>(a.lam_s)[s] = make_float4(lf[0], lf[1], lf[2], lf[3]);
   a.lam_s[4 * d.n_slots + s] = lf[4];
 }
@@ -238,8 +242,18 @@ __device__ __forceinline__ float gsum(float v) {
 #ifndef AG_L
 #define AG_L 32  // lanes per ghost or probe
 #endif
-__global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te, double t_eval, int n_gb) {
+// One launch per evaluation carries both this pass (its first n_gb blocks)
+// and the enforcement transpose of every slot (the blocks after them): the
+// ghost items take their fluid neighbours' rate adjoints from the
+// enforcement transpose recomputed per neighbour (a: the enforcement's
+// adjoint pointers, t_enf, hdt), so neither waits for the other.
+__global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te, double t_eval, int n_gb,
+                                                   double t_enf, float hdt, int acc_enf) {
   __shared__ double shd[4];
+  if ((int)blockIdx.x >= n_gb) {
+    adj_enforce_slot(d, a, te, ((int)blockIdx.x - n_gb) * 256 + (int)threadIdx.x, t_enf, hdt, acc_enf);
+    return;
+  }
   const InstParams& P = d.prm[0];
   const int item = (int)((blockIdx.x * 256 + threadIdx.x) / AG_L);
   const int lane = (int)(threadIdx.x % AG_L);
@@ -256,6 +270,8 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
     double xd, vd, ad;
     kinematics(P, t_eval, xd, vd, ad);
     const float awx = disk ? (float)ad : 0.0f;
+    double xe = 0.0, ve = 0.0, ae_;  // the disk at the enforcement's time
+    if (P.nd > 0) kinematics(P, t_enf, xe, ve, ae_);
     const float mg = -ag.w;
     int cx, cy;
     cxy(P, K, cx, cy);
@@ -263,14 +279,13 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
     const TCount blk = tcount(r0, r1, r2);
     float gr = 0, gP = 0, gc = 0, gvx = 0, gvy = 0;
     float SW = 0, Sp = 0, Srx = 0, Sry = 0, Svx = 0, Svy = 0;
-    const float* ls = a.lam_s;
-    const int N = d.n_slots;
     for (uint32_t c = (uint32_t)lane; c < blk.n; c += AG_L) {
       uint32_t j;
       int dx, dy;
       tcand(r0, r1, r2, blk, c, j, dx, dy);
       const float4 aj = te.aux[j];
       const float4 pj = te.pv[j];  // (loaded with aux: one round trip per candidate)
+      const uint32_t idr = te.id[j];
       if (!(aj.w > 0.0f)) continue;
       // r_i - r_g for the pair phi(i, g)
       const float rx = (pj.x + (float)dx * P.dc) - pg.x, ry = (pj.y + (float)dy * P.dc) - pg.y;
@@ -281,8 +296,10 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
       in.ra = aj.x; in.rb = ag.x; in.Pa = aj.y; in.Pb = ag.y; in.ca = aj.z; in.cb = ag.z;
       in.mb = mg; in.fl = 0.0f;
       PairGrad<float> g;
-      const float4 lj = reinterpret_cast<const float4*>(ls)[j];
-      pair_vjp(in, k, lj.x, lj.y, lj.z, lj.w, ls[4 * N + j], g, d_sqrt, d_rcp);
+      // the neighbour's rate adjoints (its slot's lam_s entry)
+      float lf[5];
+      adj_enforce_one<false>(P, a, (int)idr - P.id0, xe, ve, hdt, 0, lf);
+      pair_vjp(in, k, lf[0], lf[1], lf[2], lf[3], lf[4], g, d_sqrt, d_rcp);
       gr += g.rb;
       gP += g.P;
       gc += g.c;
@@ -575,17 +592,14 @@ int wc_adj_partial_blocks(int n_ghost_probe, int n_slots) {
   return adj_ghost_blocks(n_ghost_probe) + adj_fluid_blocks(n_slots);
 }
 
-void wc_enqueue_adj_rates(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_eval, float probe_seed,
-                          bool accumulate, hipStream_t st) {
-  const int ngb = adj_ghost_blocks(a.n_ghost_probe);
-  k_adj_ghost<<<ngb, 256, 0, st>>>(d, a, te, t_eval, ngb);
+void wc_enqueue_adj_eval(const Dev& d, const AdjPtrs& ae, const AdjPtrs& ar, const TapeEval& te, double t_enf,
+                         float hdt, bool acc_enf, double t_eval, float probe_seed, bool acc_rates, hipStream_t st) {
+  const int ngb = adj_ghost_blocks(ae.n_ghost_probe);
+  const int neb = (d.n_slots + 255) / 256;
+  k_adj_ghost<<<ngb + neb, 256, 0, st>>>(d, ae, te, t_eval, ngb, t_enf, hdt, acc_enf ? 1 : 0);
   const int nfb = adj_fluid_blocks(d.n_slots);
-  k_adj_fluid<<<nfb, 256, 0, st>>>(d, a, te, probe_seed, accumulate ? 1 : 0, ngb);
+  k_adj_fluid<<<nfb, 256, 0, st>>>(d, ar, te, probe_seed, acc_rates ? 1 : 0, ngb);
 }
 
 void wc_enqueue_adj_theta(const AdjPtrs& a, int nblk, hipStream_t st) { k_adj_theta<<<1, 64, 0, st>>>(a, nblk); }
 
-void wc_enqueue_adj_enforce_gather(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_enf, float hdt,
-                                   bool accumulate, hipStream_t st) {
-  k_adj_enforce_gather<<<(d.n_slots + 255) / 256, 256, 0, st>>>(d, a, te, t_enf, hdt, accumulate ? 1 : 0);
-}

@@ -1791,21 +1791,23 @@ wcsph_status wcsph_adj_backward(wcsph_ctx* ctx, double dJ, double* grad) {
       const int st = g * A.ckpt + k;
       const double t = A.t[st], dt = A.dt[st];
       AdjPtrs a = A.a;
-      // corrector: U^{n+1} = E_B(U^n + dt f(U*))
+      // corrector: U^{n+1} = E_B(U^n + dt f(U*)); the enforcement transpose
+      // into L0 (direct part of U^n), the rates' adjoint into Ls (U*)
       a.lam_out = A.L1;
       a.lam_base = A.L0;
       a.pre_pos = A.pB[k];
       a.pre_vel = A.vB[k];
-      wc_enqueue_adj_enforce_gather(ctx->d, a, A.tB[k], t + dt, (float)dt, false, ctx->st);
-      a.lam_base = A.Ls;
-      wc_enqueue_adj_rates(ctx->d, a, A.tB[k], t + 0.5 * dt, 0.0f, false, ctx->st);
-      // predictor: U* = E_A(U^n + dt/2 f(U^n)); probes of step n
+      AdjPtrs ar = a;
+      ar.lam_base = A.Ls;
+      wc_enqueue_adj_eval(ctx->d, a, ar, A.tB[k], t + dt, (float)dt, false, t + 0.5 * dt, 0.0f, false, ctx->st);
+      // predictor: U* = E_A(U^n + dt/2 f(U^n)); probes of step n; both
+      // parts added into L0
       a.lam_out = A.Ls;
       a.lam_base = A.L0;
       a.pre_pos = A.pA[k];
       a.pre_vel = A.vA[k];
-      wc_enqueue_adj_enforce_gather(ctx->d, a, A.tA[k], t + 0.5 * dt, (float)(0.5 * dt), true, ctx->st);
-      wc_enqueue_adj_rates(ctx->d, a, A.tA[k], t, (float)(dJ * dt), true, ctx->st);
+      wc_enqueue_adj_eval(ctx->d, a, a, A.tA[k], t + 0.5 * dt, (float)(0.5 * dt), true, t, (float)(dJ * dt), true,
+                          ctx->st);
       HC(hipGetLastError());
       std::swap(A.L0, A.L1);
     }

@@ -38,10 +38,12 @@ void wc_enqueue_eval(const Dev& d, const Bufs& b, int n_gblk, int mode, hipStrea
 int wc_pair_blocks(int n_slots);
 // number of per-block theta partials one adjoint rate evaluation writes
 int wc_adj_partial_blocks(int n_ghost_probe, int n_slots);
-void wc_enqueue_adj_rates(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_eval, float probe_seed,
-                          bool accumulate, hipStream_t st);
-// the enforcement transpose of one evaluation, written into the taped slot order
-void wc_enqueue_adj_enforce_gather(const Dev& d, const AdjPtrs& a, const TapeEval& te, double t_enf, float hdt,
-                                   bool accumulate, hipStream_t st);
+// The reverse of one evaluation: the enforcement transpose (adjoint
+// pointers ae: lam_out -> lam_base, added when acc_enf; the rate adjoints
+// into the taped slot order) in one launch with the ghost adjoints, then
+// the fluid adjoints (pointers ar: into ar.lam_base, added when acc_rates;
+// probe terms when probe_seed != 0).
+void wc_enqueue_adj_eval(const Dev& d, const AdjPtrs& ae, const AdjPtrs& ar, const TapeEval& te, double t_enf,
+                         float hdt, bool acc_enf, double t_eval, float probe_seed, bool acc_rates, hipStream_t st);
 // theta += the per-block running sums of the coefficient partials (after the sweep)
 void wc_enqueue_adj_theta(const AdjPtrs& a, int nblk, hipStream_t st);
