@@ -240,7 +240,7 @@ __device__ __forceinline__ float gsum(float v) {
 // cavitation cutoff is active) and of c0. The ghost's Shepard sums are
 // stored for the fluid pass. Extra threads compute the probes' Shepard sums.
 #ifndef AG_L
-#define AG_L 32  // lanes per ghost or probe
+#define AG_L 64  // lanes per ghost or probe (at most a wave: the sums are in-wave shuffles)
 #endif
 // One launch per evaluation carries both this pass (its first n_gb blocks)
 // and the enforcement transpose of every slot (the blocks after them): the
