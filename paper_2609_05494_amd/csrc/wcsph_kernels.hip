@@ -833,8 +833,10 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
 // The cell-list build of one evaluation in one launch: a stable counting
 // sort of the slots by cell key. The previous evaluation left every slot in
 // the bucket of its new cell (bucket order arbitrary, from atomics), and
-// counted the entries per cell and per tile of WC_SORT_TILE cells. Block b
-// owns cells [b T, (b+1) T) (T = WC_SORT_TILE). Its first wave turns the
+// counted the entries per cell and per tile of WC_SORT_TILE cells. Block 0
+// advances the clocks (a chain of dependent FP64 loads and stores that no
+// tile waits for); block b > 0 owns the cells of tile b - 1, [(b-1) T, b T)
+// (T = WC_SORT_TILE). Its first wave turns the
 // cells' counts into local offsets and finds the tile's first sorted slot as
 // the sum of the totals of the tiles before it (a few loads per lane, no
 // waiting on other blocks) -> start[]. Meanwhile the other waves, four lanes per cell,
@@ -842,14 +844,16 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
 // entry by old slot within its bucket (rank = number of smaller entries: the
 // sort is stable with respect to the current order). After one block
 // barrier every entry is stored at its sorted place with the per-particle
-// EOS; ghost slots and perm[new] = old are recorded. The first block also
-// advances the clocks. Each block re-arms its tile's total of the other
+// EOS; ghost slots and perm[new] = old are recorded. Each tile re-arms its tile's total of the other
 // bucket set with the static wall-ghost entries, for the fills of the
 // evaluation that follows.
 #define SORT_CELL_WAVES (WC_SORT_TILE / 16)     // four lanes per cell
 #define SORT_BLOCK (64 * (1 + SORT_CELL_WAVES))  // plus the offsets wave
 #define SORT_SPEC 3  // bucket entries per lane fetched with the counts
-#define SORT_FOLD 8  // per-block v_max entries per lane folded by a tile
+#ifndef SORT_PRE
+#define SORT_PRE 8  // tile totals per lane in flight at once in the tile prefix
+#endif
+#define SORT_FOLD 16  // per-block v_max entries per lane in flight in the fold
 
 // State of one particle at its old slot e, as loaded (before the EOS).
 struct Loaded {
@@ -940,7 +944,31 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
   __shared__ uint32_t s_off[T + 1];  // exclusive offsets of the tile's cells, total at [T]
   __shared__ uint32_t s_base;        // sorted slots before this tile
   __shared__ uint32_t s_raw[T * WC_BUCKET];
-  const int t = threadIdx.x, tile = blockIdx.x;
+  const int t = threadIdx.x;
+  if (blockIdx.x == 0) {
+    if (t < 64) {
+      for (int i = t; i < d.n_inst; i += 64) clock_commit<MODE>(d, i);
+    } else if ((MODE == EV_A || MODE == EV_L) && !BATCH) {
+      // meanwhile, single instance: the other waves fold the previous
+      // corrector's per-block fluid maxima into the clock (SORT_FOLD loads
+      // per lane in flight at once; a clamped index reads an entry again,
+      // which leaves the maximum as it is), one atomic per wave; the commit
+      // of a first evaluation does not read v_max
+      constexpr int FL = SORT_BLOCK - 64;
+      float vp = 0.0f;
+      for (int i0 = t - 64; i0 < d.n_vpart; i0 += FL * SORT_FOLD) {
+        float v[SORT_FOLD];
+#pragma unroll
+        for (int k = 0; k < SORT_FOLD; ++k) v[k] = d.vmax_part[min(i0 + FL * k, d.n_vpart - 1)];
+#pragma unroll
+        for (int k = 0; k < SORT_FOLD; ++k) vp = fmaxf(vp, v[k]);
+      }
+      const float w = wave_max(vp);
+      if ((t & 63) == 0 && w > 0.0f) atomicMax(&d.clk[0].vmax_bits, __float_as_uint(w));
+    }
+    return;
+  }
+  const int tile = blockIdx.x - 1;
   // the bucket set this sort reads: b for the corrector, the step's set for
   // a leapfrog step, else a
   const bool set_b = MODE == EV_B || (MODE == EV_L && d.lf_set != 0);
@@ -955,9 +983,19 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     // entry totals of the tiles before it (filled with the buckets)
     const int K = tile * T + t;
     const uint32_t* tot = set_b ? d.tot_b : d.tot_a;
+    const uint32_t cnt_raw = d.count[min(K, d.n_cells - 1)];  // in flight during the prefix
+    // SORT_PRE loads in flight per lane and round (an index past the
+    // preceding tiles reads the last of them and adds nothing), so the last
+    // tiles wait for one round of latency, not one per 64 tiles
     uint32_t excl = 0u;
-    for (int u = t; u < tile; u += 64) excl += tot[u];
-    const uint32_t cnt = K < d.n_cells ? min(d.count[K], (uint32_t)WC_BUCKET) : 0u;  // overflow was flagged
+    for (int u0 = t; u0 < tile; u0 += 64 * SORT_PRE) {
+      uint32_t v[SORT_PRE];
+#pragma unroll
+      for (int k = 0; k < SORT_PRE; ++k) v[k] = tot[min(u0 + 64 * k, tile - 1)];
+#pragma unroll
+      for (int k = 0; k < SORT_PRE; ++k) excl += u0 + 64 * k < tile ? v[k] : 0u;
+    }
+    const uint32_t cnt = K < d.n_cells ? min(cnt_raw, (uint32_t)WC_BUCKET) : 0u;  // overflow was flagged
     uint32_t incl = cnt;
     for (int o = 1; o < 64; o <<= 1) {
       const uint32_t u = __shfl_up(incl, o);
@@ -973,21 +1011,6 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     if (K < d.n_cells) d.start[K] = excl + (incl - cnt);
     if (K == d.n_cells - 1) d.start[d.n_cells] = excl + incl;
   } else {
-    if (tile == 0)
-      for (int i = ct; i < d.n_inst; i += SORT_BLOCK - 64) clock_commit<MODE>(d, i);
-    // single instance: the first cell wave of tile k folds entries
-    // [64 F k, 64 F (k + 1)) of the previous corrector's per-block fluid
-    // maxima (F = SORT_FOLD per lane, loads in flight during the sort) into
-    // the clock with one atomic at the end
-    const bool fold = (MODE == EV_A || MODE == EV_L) && !BATCH && ct < 64 && tile * 64 * SORT_FOLD < d.n_vpart;
-    float vp = 0.0f;
-    if (fold) {
-#pragma unroll
-      for (int k = 0; k < SORT_FOLD; ++k) {
-        const int i = (tile * SORT_FOLD + k) * 64 + ct;
-        vp = fmaxf(vp, i < d.n_vpart ? d.vmax_part[i] : 0.0f);
-      }
-    }
     const int K = tile * T + c;
     if (K < d.n_cells) {
       n = min(d.count[K], (uint32_t)WC_BUCKET);
@@ -1024,10 +1047,6 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     }
 #pragma unroll
     for (int u = 0; u < SORT_SPEC; ++u) gv[u] = sort_finish<MG>(d, lv[u]);  // EOS while the offsets are found
-    if (fold) {
-      const float w = wave_max(vp);
-      if (ct == 0 && w > 0.0f) atomicMax(&d.clk[0].vmax_bits, __float_as_uint(w));
-    }
   }
   __syncthreads();  // offsets and the tile's base
   if (t < 64) {
@@ -1041,7 +1060,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
     // a finite state that no later kernel moves or counts
     const uint32_t* tot = set_b ? d.tot_b : d.tot_a;
     const uint32_t stored = s_off[T];
-    const uint32_t end = tile == (int)gridDim.x - 1 ? (uint32_t)d.n_slots - s_base : tot[tile];
+    const uint32_t end = tile == (int)gridDim.x - 2 ? (uint32_t)d.n_slots - s_base : tot[tile];
     const uint32_t kin = (uint32_t)min(tile * T + T - 1, d.n_cells - 1);
     for (uint32_t g = stored + (uint32_t)t; g < end; g += 64) {
       const uint32_t dst = s_base + g;
@@ -1928,7 +1947,7 @@ static void launch_dens(const Dev& d, const Buf& sb, bool count, hipStream_t st)
 
 template <bool BATCH>
 static void eval_sort(const Dev& d, hipStream_t st, int mode, const Buf& pre, const Buf& out) {
-  const int nt = (d.n_cells + WC_SORT_TILE - 1) / WC_SORT_TILE;
+  const int nt = (d.n_cells + WC_SORT_TILE - 1) / WC_SORT_TILE + 1;  // the clock block, then the tiles
   if (d.var & 4) {
     if (mode == EV_A) k_sort<EV_A, BATCH, true><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
     else if (mode == EV_B) k_sort<EV_B, BATCH, true><<<nt, SORT_BLOCK, 0, st>>>(d, pre, out);
