@@ -587,6 +587,10 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
 // round-robin to a group of G lanes (lane l takes c = l, l + G, ...) with
 // SCAN_UNROLL loads in flight. fn gets the candidate's pv and aux and its
 // cell-shift code (row << 2) | column.
+// The empty asm statement takes every loaded value (as an operand it may
+// change), so the group's loads all complete there, together: otherwise the compiler defers
+// the loads of the fields that fn reads only in support into fn's branches,
+// and a lane waits for them one candidate at a time.
 template <int G, class Fn>
 __device__ __forceinline__ void for_candidates(const Dev& d, const InstParams& P, const Buf& sb, uint32_t K,
                                                int lane, Fn&& fn) {
@@ -608,6 +612,10 @@ __device__ __forceinline__ void for_candidates(const Dev& d, const InstParams& P
       pq[u] = at32(sb.pv, j);
       aq[u] = at32(sb.aux, j);
     }
+#pragma unroll
+    for (int u = 0; u < SCAN_UNROLL; ++u)
+      asm("" : "+v"(pq[u].x), "+v"(pq[u].y), "+v"(pq[u].z), "+v"(pq[u].w), "+v"(aq[u].x), "+v"(aq[u].y),
+          "+v"(aq[u].z), "+v"(aq[u].w));
 #pragma unroll
     for (int u = 0; u < SCAN_UNROLL; ++u)
       if (c0 + G * u < n) fn(pq[u], aq[u], code[u]);
