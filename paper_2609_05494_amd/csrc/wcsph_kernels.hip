@@ -451,6 +451,10 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
   const uint32_t lane = threadIdx.x & 63u;
   int cx = 0, cy = 0;
   if (fluid) cell_xy(IP, K, cx, cy);
+  // a single instance's grid, read once (the wave fences in the loop below
+  // keep the compiler from hoisting these loads out of it)
+  const int incx = IP.ncx, incy = IP.ncy, ioff = IP.cell_off;
+  const float idc = IP.dc;
   uint64_t pending = __ballot(fluid);
   while (pending) {
     const int L = __builtin_ctzll(pending);
@@ -461,33 +465,50 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
     pending &= ~mb;
     const int cxa = __builtin_amdgcn_readlane(cx, L);
     const int cxb = __builtin_amdgcn_readlane(cx, 63 - __builtin_clzll(mb));
-    const InstParams& G = d.prm[ginst];
-    const int gncx = G.ncx, gncy = G.ncy, goff = G.cell_off;
-    const float gdc = G.dc;
-    // union rows: first slot, first cell key; union index bases ub1, ub2
-    uint32_t urs[3] = {0u, 0u, 0u}, un[3] = {0u, 0u, 0u};
-    int k0[3] = {0, 0, 0};
+    const int gncx = BATCH ? d.prm[ginst].ncx : incx, gncy = BATCH ? d.prm[ginst].ncy : incy,
+              goff = BATCH ? d.prm[ginst].cell_off : ioff;
+    const float gdc = BATCH ? d.prm[ginst].dc : idc;
+    // union rows: first slot, first cell key; union index bases ub1, ub2.
+    // The cell-start loads of the union's rows complete together, then
+    // those of the lane's own rows (the empty asm statements take them as
+    // operands), without branches: a row outside the grid reads the nearest
+    // row and its values are then replaced. Otherwise the compiler waits for
+    // each row's loads before it issues the next row's.
+    uint32_t va[3], vb[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int kc = goff + min(max(gcy + r - 1, 0), gncy - 1) * gncx;
+      va[r] = at32(d.start, (uint32_t)(kc + max(cxa - 1, 0)));
+      vb[r] = at32(d.start, (uint32_t)(kc + min(cxb + 1, gncx - 1) + 1));
+    }
+    asm("" : "+v"(va[0]), "+v"(va[1]), "+v"(va[2]), "+v"(vb[0]), "+v"(vb[1]), "+v"(vb[2]));
+    uint32_t urs[3], un[3];
+    int k0[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       const int yy = gcy + r - 1;
-      if (yy >= 0 && yy < gncy) {
-        k0[r] = goff + yy * gncx;
-        urs[r] = at32(d.start, (uint32_t)(k0[r] + max(cxa - 1, 0)));
-        un[r] = at32(d.start, (uint32_t)(k0[r] + min(cxb + 1, gncx - 1) + 1)) - urs[r];
-      }
+      const bool ok = yy >= 0 && yy < gncy;
+      k0[r] = ok ? goff + yy * gncx : 0;
+      urs[r] = ok ? __builtin_amdgcn_readfirstlane(va[r]) : 0u;
+      un[r] = ok ? __builtin_amdgcn_readfirstlane(vb[r]) - __builtin_amdgcn_readfirstlane(va[r]) : 0u;
+    }
+    uint32_t ors[3], on[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int kc = goff + min(max(gcy + r - 1, 0), gncy - 1) * gncx;
+      ors[r] = at32(d.start, (uint32_t)(kc + min(max(cx - 1, 0), gncx - 1)));  // (any lane's cx: clamped)
+      on[r] = at32(d.start, (uint32_t)(kc + min(cx + 1, gncx - 1) + 1));
+    }
+    asm("" : "+v"(ors[0]), "+v"(ors[1]), "+v"(ors[2]), "+v"(on[0]), "+v"(on[1]), "+v"(on[2]));
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      on[r] = un[r] != 0u ? on[r] - ors[r] : 0u;
+      ors[r] = un[r] != 0u ? ors[r] : 0u;
     }
     const uint32_t ub1 = un[0], ub2 = un[0] + un[1], n = ub2 + un[2];
     // own rows: candidate c of row r has union index c + adj[r]
     uint32_t p1 = 0u, p2 = 0u, no = 0u, adj0 = 0u, adj1 = 0u, adj2 = 0u;
     if (mem) {
-      uint32_t ors[3] = {0u, 0u, 0u}, on[3] = {0u, 0u, 0u};
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        if (un[r] != 0u) {
-          ors[r] = at32(d.start, (uint32_t)(k0[r] + max(cx - 1, 0)));
-          on[r] = at32(d.start, (uint32_t)(k0[r] + min(cx + 1, gncx - 1) + 1)) - ors[r];
-        }
-      }
       p1 = on[0];
       p2 = on[0] + on[1];
       no = p2 + on[2];
@@ -538,15 +559,29 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
     for (uint32_t u0 = 0; u0 < n; u0 += UCAP) {
       const uint32_t m = min(n - u0, (uint32_t)UCAP);
       wave_sync();  // the previous pass is no longer read
-      for (uint32_t t = lane; t < m; t += 64) {
-        const uint32_t u = u0 + t;
+      // a lane's entries of the pass: every load first (past the pass's end
+      // a lane reads its last entry again and stores nothing)
+      constexpr int SPL = (UCAP + 63) / 64;
+      uint32_t sj[SPL];
+      int skr[SPL];
+      float ssy[SPL];
+      float4 spj[SPL];
+      uint32_t scl[SPL];
+#pragma unroll
+      for (int e = 0; e < SPL; ++e) {
+        const uint32_t u = u0 + min(lane + 64u * (uint32_t)e, m - 1u);
         const bool a0 = u < ub1, a1 = u < ub2;
-        const uint32_t j = a0 ? urs[0] + u : (a1 ? urs[1] + (u - ub1) : urs[2] + (u - ub2));
-        const int kr = a0 ? k0[0] : (a1 ? k0[1] : k0[2]);
-        const float sy = a0 ? -gdc : (a1 ? 0.0f : gdc);
-        const float4 pj = at32(sb.pv, j);
-        const int cxj = (int)at32(sb.cell, j) - kr;
-        U[t] = make_float4(pj.x, pj.y + sy, (float)(cxj - cxa), __uint_as_float(j));
+        sj[e] = a0 ? urs[0] + u : (a1 ? urs[1] + (u - ub1) : urs[2] + (u - ub2));
+        skr[e] = a0 ? k0[0] : (a1 ? k0[1] : k0[2]);
+        ssy[e] = a0 ? -gdc : (a1 ? 0.0f : gdc);
+        spj[e] = at32(sb.pv, sj[e]);
+        scl[e] = at32(sb.cell, sj[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < SPL; ++e) {
+        const uint32_t t = lane + 64u * (uint32_t)e;
+        const int cxj = (int)scl[e] - skr[e];
+        if (t < m) U[t] = make_float4(spj[e].x, spj[e].y + ssy[e], (float)(cxj - cxa), __uint_as_float(sj[e]));
       }
       wave_sync();
       if (mem) {
