@@ -1344,6 +1344,19 @@ void k_pair(Dev d, Buf sb, Buf base, Buf out) {
   __shared__ float h_rho[PAIR_SLOTS], h_m[PAIR_SLOTS];
   __shared__ int h_inst[PAIR_SLOTS];
   __shared__ float h_aud[AUD ? 4 : 1][PAIR_SLOTS];
+  // a single instance's constants and clock, copied for the second phase:
+  // the compiler cannot move global loads above the phase's global stores,
+  // and waited for each field in turn; from LDS it loads them together
+  // (no block writes a clock field that a second phase reads)
+  __shared__ InstParams sP;
+  __shared__ Clock sC;
+  if constexpr (!BATCH) {
+    constexpr int NP = (int)(sizeof(InstParams) / 4), NC = (int)(sizeof(Clock) / 4);
+    static_assert(sizeof(InstParams) % 4 == 0 && sizeof(Clock) % 4 == 0 && NP + NC <= PAIR_BLOCK, "copy");
+    const int t = (int)threadIdx.x;
+    if (t < NP) reinterpret_cast<uint32_t*>(&sP)[t] = reinterpret_cast<const uint32_t*>(d.prm)[t];
+    else if (t < NP + NC) reinterpret_cast<uint32_t*>(&sC)[t - NP] = reinterpret_cast<const uint32_t*>(d.clk)[t - NP];
+  }
   // blocks map to XCDs in contiguous slot ranges
   const int s0 = xcd_block(blockIdx.x, gridDim.x) * PAIR_SLOTS;
   {
@@ -1413,10 +1426,10 @@ void k_pair(Dev d, Buf sb, Buf base, Buf out) {
   if (threadIdx.x >= PAIR_SLOTS) return;
   const int s = s0 + (int)threadIdx.x;
   const bool inr = s < d.n_slots;
-  const int inst = h_inst[threadIdx.x];
-  const InstParams& P = d.prm[inst];
+  const int inst = BATCH ? h_inst[threadIdx.x] : 0;
+  const InstParams& P = *(BATCH ? &d.prm[inst] : &sP);
   Clock* clk = d.clk;
-  const Clock& C = clk[inst];
+  const Clock& C = *(BATCH ? &clk[inst] : &sC);
   const uint32_t K = h_K[threadIdx.x];
   const float4 pi = h_pv[threadIdx.x];
   const float rho_i = h_rho[threadIdx.x];
