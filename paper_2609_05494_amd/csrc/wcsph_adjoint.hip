@@ -154,7 +154,10 @@ __device__ __forceinline__ void adj_enforce_one(const InstParams& P, const AdjPt
   if constexpr (WRITE) {
     float* lb = a.lam_base;
     if (accumulate) {
-      lb[i] += lx; lb[n + i] += ly; lb[2 * n + i] += lvx; lb[3 * n + i] += lvy; lb[4 * n + i] += lr;
+      // the five loads before any store (a store might otherwise alias the
+      // next load, and each sum would wait for the one before it)
+      const float b0 = lb[i], b1 = lb[n + i], b2 = lb[2 * n + i], b3 = lb[3 * n + i], b4 = lb[4 * n + i];
+      lb[i] = b0 + lx; lb[n + i] = b1 + ly; lb[2 * n + i] = b2 + lvx; lb[3 * n + i] = b3 + lvy; lb[4 * n + i] = b4 + lr;
     } else {
       lb[i] = lx; lb[n + i] = ly; lb[2 * n + i] = lvx; lb[3 * n + i] = lvy; lb[4 * n + i] = lr;
     }
@@ -170,10 +173,10 @@ __device__ __forceinline__ void adj_enforce_one(const InstParams& P, const AdjPt
 // The enforcement transpose of fluid slot s, written straight into the
 // sorted slot order of the taped evaluation (each fluid id holds one slot;
 // ghost slots get zero): lam_base by id, the rate adjoints lam_s by slot.
-__device__ __forceinline__ void adj_enforce_slot(const Dev& d, const AdjPtrs& a, const TapeEval& te, int s,
+__device__ __forceinline__ void adj_enforce_slot(const Dev& d, const InstParams& P, const AdjPtrs& a,
+                                                 const TapeEval& te, int s,
                                                  double t_enf, float hdt, int accumulate) {
   if (s >= d.n_slots) return;
-  const InstParams& P = d.prm[0];
   double xd = 0.0, vd = 0.0, ad;
   if (P.nd > 0) kinematics(P, t_enf, xd, vd, ad);
   const int id = (int)te.id[s] - P.id0;
@@ -250,11 +253,22 @@ __device__ __forceinline__ float gsum(float v) {
 __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te, double t_eval, int n_gb,
                                                    double t_enf, float hdt, int acc_enf) {
   __shared__ double shd[4];
+  // the instance's constants in LDS: read there in the candidate loop and
+  // the enforcement transpose, where from global memory the compiler waited
+  // for each field in turn
+  __shared__ InstParams sP;
+  {
+    constexpr int NP = (int)(sizeof(InstParams) / 4);
+    static_assert(sizeof(InstParams) % 4 == 0 && NP <= 256, "copy");
+    if ((int)threadIdx.x < NP)
+      reinterpret_cast<uint32_t*>(&sP)[threadIdx.x] = reinterpret_cast<const uint32_t*>(d.prm)[threadIdx.x];
+    __syncthreads();
+  }
+  const InstParams& P = sP;
   if ((int)blockIdx.x >= n_gb) {
-    adj_enforce_slot(d, a, te, ((int)blockIdx.x - n_gb) * 256 + (int)threadIdx.x, t_enf, hdt, acc_enf);
+    adj_enforce_slot(d, P, a, te, ((int)blockIdx.x - n_gb) * 256 + (int)threadIdx.x, t_enf, hdt, acc_enf);
     return;
   }
-  const InstParams& P = d.prm[0];
   const int item = (int)((blockIdx.x * 256 + threadIdx.x) / AG_L);
   const int lane = (int)(threadIdx.x % AG_L);
   const int ng = P.nw + P.nd;
@@ -283,9 +297,13 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
       uint32_t j;
       int dx, dy;
       tcand(r0, r1, r2, blk, c, j, dx, dy);
-      const float4 aj = te.aux[j];
-      const float4 pj = te.pv[j];  // (loaded with aux: one round trip per candidate)
-      const uint32_t idr = te.id[j];
+      float4 aj = te.aux[j];
+      float4 pj = te.pv[j];
+      uint32_t idr = te.id[j];
+      // one round trip per candidate: the empty asm takes the loaded values,
+      // so the compiler cannot defer the loads of pj and idr past the test
+      asm("" : "+v"(aj.x), "+v"(aj.y), "+v"(aj.z), "+v"(aj.w), "+v"(pj.x), "+v"(pj.y), "+v"(pj.z), "+v"(pj.w),
+          "+v"(idr));
       if (!(aj.w > 0.0f)) continue;
       // r_i - r_g for the pair phi(i, g)
       const float rx = (pj.x + (float)dx * P.dc) - pg.x, ry = (pj.y + (float)dy * P.dc) - pg.y;
@@ -366,9 +384,10 @@ __global__ __launch_bounds__(256) void k_adj_ghost(Dev d, AdjPtrs a, TapeEval te
       uint32_t j;
       int dx, dy;
       tcand(r0, r1, r2, blk, c, j, dx, dy);
-      const float4 aj = te.aux[j];
+      float4 aj = te.aux[j];
+      float4 pj = te.pv[j];
+      asm("" : "+v"(aj.x), "+v"(aj.y), "+v"(aj.z), "+v"(aj.w), "+v"(pj.x), "+v"(pj.y), "+v"(pj.z), "+v"(pj.w));
       if (!(aj.w > 0.0f)) continue;
-      const float4 pj = te.pv[j];
       const float rx = P.probe_ox[kk] - (pj.x + (float)dx * P.dc), ry = P.probe_oy[kk] - (pj.y + (float)dy * P.dc);
       const float r2 = rx * rx + ry * ry;
       if (!(r2 < P.four_h2)) continue;
