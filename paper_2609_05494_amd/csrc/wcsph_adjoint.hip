@@ -451,16 +451,30 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
       for (uint32_t c0 = (uint32_t)g; c0 < blk.n; c0 += ADJ_FG * ADJ_LCAP) {
         int cnt = 0;
         const uint32_t c1 = min(blk.n, c0 + ADJ_FG * ADJ_LCAP);
-        for (uint32_t c = c0; c < c1; c += ADJ_FG) {
-          uint32_t jc;
-          int dxc, dyc;
-          tcand(r0, r1, r2, blk, c, jc, dxc, dyc);
-          const float4 pc = te.pv[jc];
-          const float rxc = (pi.x - pc.x) - (float)dxc * P.dc;
-          const float ryc = (pi.y - pc.y) - (float)dyc * P.dc;
-          const bool hit = jc != (uint32_t)s && rxc * rxc + ryc * ryc < P.four_h2;
-          my[cnt * 256] = (jc << 4) | ((uint32_t)(dyc + 1) << 2) | (uint32_t)(dxc + 1);
-          cnt += hit ? 1 : 0;
+        // four candidates' positions in flight at once (past the chunk's
+        // end a lane reads its first candidate again and records nothing)
+        for (uint32_t cb = c0; cb < c1; cb += ADJ_FG * 4) {
+          uint32_t jq[4];
+          int dxq[4], dyq[4];
+          float2 pq[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t c = cb + ADJ_FG * (uint32_t)u;
+            tcand(r0, r1, r2, blk, c < c1 ? c : c0, jq[u], dxq[u], dyq[u]);
+            const float4 pc = te.pv[jq[u]];
+            pq[u] = make_float2(pc.x, pc.y);
+          }
+          asm("" : "+v"(pq[0].x), "+v"(pq[0].y), "+v"(pq[1].x), "+v"(pq[1].y), "+v"(pq[2].x), "+v"(pq[2].y),
+              "+v"(pq[3].x), "+v"(pq[3].y));
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (cb + ADJ_FG * (uint32_t)u >= c1) break;
+            const float rxc = (pi.x - pq[u].x) - (float)dxq[u] * P.dc;
+            const float ryc = (pi.y - pq[u].y) - (float)dyq[u] * P.dc;
+            const bool hit = jq[u] != (uint32_t)s && rxc * rxc + ryc * ryc < P.four_h2;
+            my[cnt * 256] = (jq[u] << 4) | ((uint32_t)(dyq[u] + 1) << 2) | (uint32_t)(dxq[u] + 1);
+            cnt += hit ? 1 : 0;
+          }
         }
         // the next hit's state is loaded while this one's terms are computed
         // (an empty list loads the lane's own slot, always in range)
@@ -565,7 +579,10 @@ __global__ __launch_bounds__(256) void k_adj_fluid(Dev d, AdjPtrs a, TapeEval te
         const int n = P.nf;
         float* lb = a.lam_base;
         if (accumulate) {
-          lb[id] += urx; lb[n + id] += ury; lb[2 * n + id] += uvx; lb[3 * n + id] += uvy; lb[4 * n + id] += ur;
+          // the five loads before any store (as in the enforcement transpose)
+          const float b0 = lb[id], b1 = lb[n + id], b2 = lb[2 * n + id], b3 = lb[3 * n + id], b4 = lb[4 * n + id];
+          lb[id] = b0 + urx; lb[n + id] = b1 + ury; lb[2 * n + id] = b2 + uvx; lb[3 * n + id] = b3 + uvy;
+          lb[4 * n + id] = b4 + ur;
         } else {
           lb[id] = urx; lb[n + id] = ury; lb[2 * n + id] = uvx; lb[3 * n + id] = uvy; lb[4 * n + id] = ur;
         }
