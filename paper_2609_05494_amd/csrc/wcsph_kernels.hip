@@ -1138,9 +1138,17 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(Dev d, Buf pre, Buf out) {
 #define GL WC_GHOST_LANES
 template <int MODE, bool BATCH, bool CUB>
 __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
-  const int4 blk = d.gblk[blockIdx.x];
-  const int inst = blk.x, kind = blk.w;
+  // the table entry in one load, and (single instance) the offset of the
+  // instance's ghost arrays with it: left to itself the compiler loads each
+  // field where it is first used, one after the other
+  int4 blk = d.gblk[blockIdx.x];
+  int gm = BATCH ? 0 : d.prm[0].gmap0;
+  const uint32_t *gslot = d.gslot, *gcell = d.gcell;
+  const float2* gpos = d.gpos;
+  asm("" : "+s"(blk.x), "+s"(blk.y), "+s"(blk.z), "+s"(blk.w), "+s"(gm), "+s"(gslot), "+s"(gcell), "+s"(gpos));
+  const int inst = BATCH ? blk.x : 0, kind = blk.w;
   const InstParams& P = d.prm[inst];
+  if constexpr (BATCH) gm = P.gmap0;
   Clock& C = d.clk[inst];
   const int t = threadIdx.x, item = t / GL, lane = t % GL;
   const bool act = item < blk.z;
@@ -1165,9 +1173,9 @@ __global__ __launch_bounds__(WC_GHOST_BLOCK) void k_ghost(Dev d, Buf sb) {
   float vmag = 0.0f;
   if (act) {
     const int g = blk.y + item;
-    const uint32_t s = d.gslot[P.gmap0 + g];
-    const uint32_t K = d.gcell[P.gmap0 + g];
-    const float2 pg = d.gpos[P.gmap0 + g];
+    const uint32_t s = gslot[gm + g];
+    const uint32_t K = gcell[gm + g];
+    const float2 pg = gpos[gm + g];
     // axisymmetric form: a wall ghost below the axis mirrors the fluid (slip)
     // and is off (zero mass, at rest) inside the sphere
     bool axis = false, off = false;
