@@ -559,29 +559,15 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
     for (uint32_t u0 = 0; u0 < n; u0 += UCAP) {
       const uint32_t m = min(n - u0, (uint32_t)UCAP);
       wave_sync();  // the previous pass is no longer read
-      // a lane's entries of the pass: every load first (past the pass's end
-      // a lane reads its last entry again and stores nothing)
-      constexpr int SPL = (UCAP + 63) / 64;
-      uint32_t sj[SPL];
-      int skr[SPL];
-      float ssy[SPL];
-      float4 spj[SPL];
-      uint32_t scl[SPL];
-#pragma unroll
-      for (int e = 0; e < SPL; ++e) {
-        const uint32_t u = u0 + min(lane + 64u * (uint32_t)e, m - 1u);
+      for (uint32_t t = lane; t < m; t += 64) {
+        const uint32_t u = u0 + t;
         const bool a0 = u < ub1, a1 = u < ub2;
-        sj[e] = a0 ? urs[0] + u : (a1 ? urs[1] + (u - ub1) : urs[2] + (u - ub2));
-        skr[e] = a0 ? k0[0] : (a1 ? k0[1] : k0[2]);
-        ssy[e] = a0 ? -gdc : (a1 ? 0.0f : gdc);
-        spj[e] = at32(sb.pv, sj[e]);
-        scl[e] = at32(sb.cell, sj[e]);
-      }
-#pragma unroll
-      for (int e = 0; e < SPL; ++e) {
-        const uint32_t t = lane + 64u * (uint32_t)e;
-        const int cxj = (int)scl[e] - skr[e];
-        if (t < m) U[t] = make_float4(spj[e].x, spj[e].y + ssy[e], (float)(cxj - cxa), __uint_as_float(sj[e]));
+        const uint32_t j = a0 ? urs[0] + u : (a1 ? urs[1] + (u - ub1) : urs[2] + (u - ub2));
+        const int kr = a0 ? k0[0] : (a1 ? k0[1] : k0[2]);
+        const float sy = a0 ? -gdc : (a1 ? 0.0f : gdc);
+        const float4 pj = at32(sb.pv, j);
+        const int cxj = (int)at32(sb.cell, j) - kr;
+        U[t] = make_float4(pj.x, pj.y + sy, (float)(cxj - cxa), __uint_as_float(j));
       }
       wave_sync();
       if (mem) {
