@@ -609,9 +609,9 @@ __device__ __forceinline__ void pair_sums_wave(const Dev& d, const Buf& sb, int 
 // SCAN_UNROLL loads in flight. fn gets the candidate's pv and aux and its
 // cell-shift code (row << 2) | column.
 // The empty asm statement takes every loaded value (as an operand it may
-// change), so the group's loads all complete there, together: otherwise the compiler defers
-// the loads of the fields that fn reads only in support into fn's branches,
-// and a lane waits for them one candidate at a time.
+// change), so the group's loads all complete there, together: otherwise
+// the compiler defers the loads of the fields that fn reads only in support
+// into fn's branches, and a lane waits for them one candidate at a time.
 template <int G, class Fn>
 __device__ __forceinline__ void for_candidates(const Dev& d, const InstParams& P, const Buf& sb, uint32_t K,
                                                int lane, Fn&& fn) {
@@ -873,9 +873,9 @@ __device__ __forceinline__ void place_ring(const Dev& d, const InstParams& P, in
 // entry by old slot within its bucket (rank = number of smaller entries: the
 // sort is stable with respect to the current order). After one block
 // barrier every entry is stored at its sorted place with the per-particle
-// EOS; ghost slots and perm[new] = old are recorded. Each tile re-arms its tile's total of the other
-// bucket set with the static wall-ghost entries, for the fills of the
-// evaluation that follows.
+// EOS; ghost slots and perm[new] = old are recorded. Each tile re-arms its
+// tile's total of the other bucket set with the static wall-ghost entries,
+// for the fills of the evaluation that follows.
 #define SORT_CELL_WAVES (WC_SORT_TILE / 16)     // four lanes per cell
 #define SORT_BLOCK (64 * (1 + SORT_CELL_WAVES))  // plus the offsets wave
 #define SORT_SPEC 3  // bucket entries per lane fetched with the counts
