@@ -91,6 +91,31 @@ def test_full_C4_sweep_sampled_instances():
     b.close()
 
 
+def test_batch_beyond_one_wave_of_instances():
+    """More instances than one wave has lanes: the sort's clock block commits
+    the clocks 64 instances per round, so instances past the 64th take the
+    second round. Those and the first ones equal their single runs bitwise,
+    and every instance conserves mass."""
+    cfgs = [dict(workloads.tiny(v0=300.0 + 5.0 * k), alpha=0.05 + 0.002 * k) for k in range(70)]
+    n = 20
+    b = wc.Solver(cfgs, "cuda:0")
+    print(f"[gpu] batch of {b.n_inst} small instances, {n} steps", flush=True)
+    assert b.n_inst == 70
+    b.step(n)
+    for k in range(70):
+        d = b.read_diagnostics(k)
+        assert "unstable" not in d
+        assert np.abs(d["mass"] - d["mass"][0]).max() <= 1e-12 * d["mass"][0]
+    for k in (0, 63, 64, 69):
+        (tb, fb), (_, dtb, pb) = b.fluid(k), b.read_probes(k)
+        (ts, fs), (_, dts, ps), _ = _run_single(cfgs[k], n)
+        assert tb == ts, k
+        for u, v in zip(fb, fs):
+            assert np.array_equal(u, v), k
+        assert np.array_equal(dtb, dts) and np.array_equal(pb, ps), k
+    b.close()
+
+
 def test_batch_step_needs_a_batched_context():
     s = wc.Solver(workloads.tiny(), "cuda:0")
     assert wc.lib().wcsph_batch_step(s.handle, 1) == wc.E_INVALID
